@@ -1,0 +1,155 @@
+"""Discrete domain description (paper Section 5, "Discrete Domain Design").
+
+Every cell carries a label: interior, Dirichlet or exterior.  From the labels
+the paper derives which variables are unknowns:
+  * a velocity on the face between two interior cells is active;
+  * a velocity on a face of a Dirichlet cell is a Dirichlet value (not solved);
+  * a pressure at an interior cell centre is active.
+Coarse labels: a coarse cell is Dirichlet if it encloses any fine Dirichlet
+cell, otherwise interior if it encloses any fine interior cell, otherwise
+exterior.  The boundary set V1 holds all degrees of freedom of the cells that
+are proximal to a Dirichlet or exterior cell; V2 holds the rest.
+
+Reading (proximal): a cell is proximal when it shares a face with a
+non-interior cell.  For a box padded by one Dirichlet layer this equals
+sharing a vertex, and it reproduces the boundary-DOF counts of Table 1 for the
+driven-cavity rows exactly.
+
+Exterior cells (and the Neumann faces they create) are outside the scope of
+this oracle: `Domain` rejects them.
+
+The labelled arrays are padded: padded index = cell index + 1, so a box of n
+cells per axis has label arrays of n+2 per axis whose outer layer is
+Dirichlet.  Classification is written for any dimension d (2 or 3) so that
+both the 2D and 3D rows of Table 1 can be checked.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+INTERIOR, DIRICHLET, EXTERIOR = 0, 1, 2
+
+
+def box_labels(dims) -> np.ndarray:
+    """Labels of a box of `dims` interior cells padded by one Dirichlet layer."""
+    lab = np.full(tuple(n + 2 for n in dims), DIRICHLET, dtype=np.int8)
+    lab[tuple(slice(1, n + 1) for n in dims)] = INTERIOR
+    return lab
+
+
+def coarsen_labels(lab: np.ndarray) -> np.ndarray:
+    """Label coarsening of Section 5.
+
+    Coarse cell I covers fine cells 2I and 2I+1 (cell indices).  In padded
+    indices this means coarse padded index c covers fine padded 2c-1 and 2c;
+    an extra Dirichlet layer stands in for the fine cells beyond the padding.
+    """
+    d = lab.ndim
+    dims = [s - 2 for s in lab.shape]
+    if any(n % 2 for n in dims):
+        raise ValueError("label coarsening needs an even number of cells per axis")
+    ext = np.pad(lab, 1, constant_values=DIRICHLET)  # ext index = padded + 1
+    cdims = [n // 2 for n in dims]
+    # fine padded indices 2c-1, 2c  ->  ext indices 2c, 2c+1, for c = 0 .. n/2+1
+    blocks = ext.reshape(tuple(x for n in cdims for x in (n + 2, 2)))
+    axes = tuple(2 * a + 1 for a in range(d))
+    any_dir = (blocks == DIRICHLET).any(axis=axes)
+    any_int = (blocks == INTERIOR).any(axis=axes)
+    out = np.where(any_dir, DIRICHLET, np.where(any_int, INTERIOR, EXTERIOR)).astype(np.int8)
+    return out
+
+
+def classify(lab: np.ndarray):
+    """Active masks and V1 masks for every velocity component and the pressure.
+
+    Returns (active, v1) where each is a list of d boolean arrays for the face
+    fields (face field for axis a has n_a+1 entries along a) followed by one
+    boolean array for the pressure (cell field).  V2 = active & ~v1.
+    """
+    d = lab.ndim
+    dims = [s - 2 for s in lab.shape]
+    inner = tuple(slice(1, n + 1) for n in dims)
+    interior = lab == INTERIOR
+    cell_active = interior[inner]
+
+    # proximal cells: interior cells with a face neighbour that is not interior
+    prox = np.zeros_like(interior)
+    for a in range(d):
+        for s in (-1, 1):
+            prox |= np.roll(~interior, s, axis=a)
+    prox &= interior
+    cell_v1 = prox[inner]
+
+    face_active, face_v1 = [], []
+    for a in range(d):
+        # face f (0..n_a) along axis a separates cells f-1 and f -> padded f and f+1
+        lo = [slice(1, n + 1) for n in dims]
+        hi = [slice(1, n + 1) for n in dims]
+        lo[a] = slice(0, dims[a] + 1)
+        hi[a] = slice(1, dims[a] + 2)
+        lo, hi = tuple(lo), tuple(hi)
+        act = interior[lo] & interior[hi]
+        face_active.append(act)
+        face_v1.append(act & (prox[lo] | prox[hi]))
+    return face_active + [cell_active], face_v1 + [cell_v1]
+
+
+def dof_counts(lab: np.ndarray):
+    """(#active DOFs, #V1 DOFs) - the two integer columns of Table 1."""
+    active, v1 = classify(lab)
+    return int(sum(m.sum() for m in active)), int(sum(m.sum() for m in v1))
+
+
+@dataclass
+class Domain:
+    """One level of the hierarchy: a labelled 3D grid of spacing h.
+
+    Holds the constants of the discrete Stokes operator (Eq. 2): viscosity
+    eta and the penalty gamma of the preconditioner matrix (Section 4).
+    """
+    labels: np.ndarray
+    h: float
+    eta: float = 1.0
+    gamma: float = 1e-3
+    active: list = field(init=False)
+    v1: list = field(init=False)
+    v2: list = field(init=False)
+
+    def __post_init__(self):
+        if self.labels.ndim != 3:
+            raise ValueError("the oracle's Stokes operator is 3D")
+        if (self.labels == EXTERIOR).any():
+            raise ValueError("exterior cells (Neumann faces) are outside this oracle's scope")
+        self.active, self.v1 = classify(self.labels)
+        self.v2 = [a & ~v for a, v in zip(self.active, self.v1)]
+
+    @property
+    def dims(self):
+        return tuple(s - 2 for s in self.labels.shape)
+
+    @property
+    def shapes(self):
+        nx, ny, nz = self.dims
+        return [(nx + 1, ny, nz), (nx, ny + 1, nz), (nx, ny, nz + 1), (nx, ny, nz)]
+
+    def n_dofs(self):
+        return int(sum(m.sum() for m in self.active))
+
+    def coarsen(self):
+        return Domain(coarsen_labels(self.labels), 2.0 * self.h, self.eta, self.gamma)
+
+    def parity(self, field_index: int) -> np.ndarray:
+        """Red (0) / black (1) colour of every entry of a field: (i+j+k) mod 2
+        in the field's own index (face number along its normal axis, cell
+        numbers along the others)."""
+        shp = self.shapes[field_index]
+        i, j, k = np.ogrid[0:shp[0], 0:shp[1], 0:shp[2]]
+        return ((i + j + k) & 1).astype(np.int8)
+
+    def vanka_colour(self) -> np.ndarray:
+        """8-colour class of every cell: (i&1) + 2(j&1) + 4(k&1)."""
+        nx, ny, nz = self.dims
+        i, j, k = np.ogrid[0:nx, 0:ny, 0:nz]
+        return ((i & 1) + 2 * (j & 1) + 4 * (k & 1)).astype(np.int8)

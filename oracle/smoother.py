@@ -1,0 +1,219 @@
+"""Smoothers of paper Section 3: symmetric distributive Gauss-Seidel on the
+interior set V2, symmetric multiplicative Vanka on the boundary set V1, and
+their symmetric composition (Alg. 3).  All of them act on the penalised matrix
+L~ of Section 4 (the V-cycle only ever sees L~).
+
+Every smoother is written as the relaxation x <- x + S (b - L~ x) of Eq.
+relaxation, one colour class at a time, with the residual recomputed in full
+before each class.  Inside one colour class the updates do not influence each
+other's residuals (checked by a test that runs the literal one-unknown-at-a-
+time loop of Alg. 2), so applying a class at once equals visiting its members
+in any order.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .domain import Domain
+from .operator import apply_operator, grad, neg_div, residual
+
+
+# ---------------------------------------------------------------------------
+# Distribution matrix restricted to V2 (Eq. dist; Appendix D splits L into the
+# V1/V2 blocks and DGS relaxes L~22 x2 = b2 - L~21 x1).
+#
+# Reading: M22 = [[I, -B22^T], [0, eta B22 B22^T]] is built from V2 rows and
+# columns only, so a pressure update never moves a V1 unknown.
+# ---------------------------------------------------------------------------
+
+def distribute(dom: Domain, delta: np.ndarray):
+    """M22 applied to a pressure-cell vector delta (its V2 entries are used)."""
+    g = grad(dom, np.where(dom.v2[3], delta, 0.0))
+    g = [np.where(dom.v2[a], g[a], 0.0) for a in range(3)]
+    dp = np.where(dom.v2[3], dom.eta * neg_div(dom, g), 0.0)
+    return (-g[0], -g[1], -g[2], dp)
+
+
+def collect(dom: Domain, r):
+    """Pressure rows of M22^T r = -B22 r_u + eta B22 B22^T r_p (Eq. ldist)."""
+    ru = [np.where(dom.v2[a], r[a], 0.0) for a in range(3)]
+    g = grad(dom, np.where(dom.v2[3], r[3], 0.0))
+    g = [np.where(dom.v2[a], g[a], 0.0) for a in range(3)]
+    out = -neg_div(dom, ru) + dom.eta * neg_div(dom, g)
+    return np.where(dom.v2[3], out, 0.0)
+
+
+def dgs_diagonals(dom: Domain):
+    """d_j = L~_{j,:} M_{:,j} (Alg. 2), for every V2 unknown.
+
+    Returns (d_u, d_p): d_u is a list of three face arrays, d_p a cell array;
+    entries outside V2 are zero.  Evaluated for a whole colour class at once:
+    members of one class do not couple, so (L~ M 1_class)_j = (L~ M)_jj.
+    """
+    gam = dom.gamma
+    d_u = [np.zeros(s) for s in dom.shapes[:3]]
+    d_p = np.zeros(dom.shapes[3])
+    for colour in (0, 1):
+        ind = tuple(np.where(dom.v2[a] & (dom.parity(a) == colour), 1.0, 0.0) for a in range(3))
+        y = apply_operator(dom, ind + (np.zeros(dom.shapes[3]),), gam)
+        for a in range(3):
+            d_u[a] += np.where(ind[a] > 0, y[a], 0.0)
+        sel = dom.v2[3] & (dom.parity(3) == colour)
+        y = apply_operator(dom, distribute(dom, np.where(sel, 1.0, 0.0)), gam)
+        d_p += np.where(sel, y[3], 0.0)
+    return d_u, d_p
+
+
+def dgs_forward(dom: Domain, x, b, diags=None):
+    """One DGS sweep on L~22 M22 (Alg. 2 with the right preconditioning of Eq. dist).
+
+    Reading (order): L M is block lower triangular (Eq. disc), so the sweep is
+    a block forward substitution: all velocities first, then all pressures.
+    Each block goes red ((i+j+k) even) then black.  A velocity update is the
+    plain Gauss-Seidel step (velocity columns of M are unit vectors); a
+    pressure update moves x along the column m_j of M22.
+    """
+    d_u, d_p = diags if diags is not None else dgs_diagonals(dom)
+    gam = dom.gamma
+    x = tuple(v.copy() for v in x)
+    for colour in (0, 1):
+        r = residual(dom, x, b, gam)
+        x = tuple(np.where(dom.v2[a] & (dom.parity(a) == colour), x[a] + r[a] / np.where(d_u[a] != 0, d_u[a], 1.0), x[a])
+                  for a in range(3)) + (x[3],)
+    for colour in (0, 1):
+        r = residual(dom, x, b, gam)
+        sel = dom.v2[3] & (dom.parity(3) == colour) & (d_p != 0)
+        delta = np.where(sel, r[3] / np.where(d_p != 0, d_p, 1.0), 0.0)
+        dx = distribute(dom, delta)
+        x = tuple(v + dv for v, dv in zip(x, dx))
+    return x
+
+
+def dgs_reverse(dom: Domain, x, b, diags=None):
+    """Gauss-Seidel on the left-preconditioned system M22^T L~22 (Eq. ldist) in
+    exactly the reverse order of `dgs_forward`: pressures black, red, then
+    velocities black, red.  Each step updates its own unknown by
+    (M^T r)_j / d_j; for velocities (M^T)_j = e_j^T."""
+    d_u, d_p = diags if diags is not None else dgs_diagonals(dom)
+    gam = dom.gamma
+    x = tuple(v.copy() for v in x)
+    for colour in (1, 0):
+        r = residual(dom, x, b, gam)
+        rt = collect(dom, r)
+        sel = dom.v2[3] & (dom.parity(3) == colour) & (d_p != 0)
+        x = x[:3] + (x[3] + np.where(sel, rt / np.where(d_p != 0, d_p, 1.0), 0.0),)
+    for colour in (1, 0):
+        r = residual(dom, x, b, gam)
+        x = tuple(np.where(dom.v2[a] & (dom.parity(a) == colour), x[a] + r[a] / np.where(d_u[a] != 0, d_u[a], 1.0), x[a])
+                  for a in range(3)) + (x[3],)
+    return x
+
+
+def dgs_symmetric(dom: Domain, x, b, diags=None):
+    """Symmetric DGS (Section 3.1, Appendix A): forward sweep, then reverse."""
+    diags = diags if diags is not None else dgs_diagonals(dom)
+    return dgs_reverse(dom, dgs_forward(dom, x, b, diags), b, diags)
+
+
+# ---------------------------------------------------------------------------
+# Vanka (Eq. mv, Section 3.2, Appendix C)
+# ---------------------------------------------------------------------------
+
+# Local unknowns of the subdomain of cell (i, j, k), in this order:
+#   0: u_x[i]   1: u_x[i+1]   2: u_y[j]   3: u_y[j+1]   4: u_z[k]   5: u_z[k+1]   6: p
+_SLOT_FIELD = (0, 0, 1, 1, 2, 2, 3)
+_SLOT_SHIFT = (0, 1, 0, 1, 0, 1, 0)
+
+
+def vanka_slots(dom: Domain, cells: np.ndarray):
+    """Index tuples of the 7 local unknowns of each cell, and their activity."""
+    idx, act = [], []
+    for s in range(7):
+        f = _SLOT_FIELD[s]
+        ii = [cells[:, 0].copy(), cells[:, 1].copy(), cells[:, 2].copy()]
+        if f < 3:
+            ii[f] += _SLOT_SHIFT[s]
+        ii = tuple(ii)
+        idx.append(ii)
+        act.append(dom.active[f][ii])
+    return idx, np.stack(act, axis=1)
+
+
+def vanka_local_matrix(eta: float, h: float, gamma: float, act: np.ndarray) -> np.ndarray:
+    """K_i = C_i L~ C_i^T for each subdomain (Eq. mv), written out.
+
+    Reading (subdomain): one V1 cell - its pressure and its active faces, at
+    most 7 unknowns, matching the prefactorised 3^6 local problems keyed on
+    the six neighbour labels (Section 6).  Entries: 6 eta/h^2 on velocity
+    diagonals, -eta/h^2 between the two faces of one axis (lattice neighbours),
+    +1/h (minus face) and -1/h (plus face) between a face and the pressure,
+    -gamma on the pressure diagonal.  Slots that are not unknowns get an
+    identity row and column, so their update is zero.
+    """
+    n = act.shape[0]
+    K = np.zeros((n, 7, 7))
+    c = eta / h ** 2
+    for a in range(3):
+        lo, hi = 2 * a, 2 * a + 1
+        K[:, lo, lo] = 6.0 * c
+        K[:, hi, hi] = 6.0 * c
+        both = act[:, lo] & act[:, hi]
+        K[:, lo, hi] = np.where(both, -c, 0.0)
+        K[:, hi, lo] = K[:, lo, hi]
+        K[:, lo, 6] = K[:, 6, lo] = np.where(act[:, lo], 1.0 / h, 0.0)
+        K[:, hi, 6] = K[:, 6, hi] = np.where(act[:, hi], -1.0 / h, 0.0)
+    K[:, 6, 6] = -gamma
+    for s in range(7):
+        off = ~act[:, s]
+        K[off, s, :] = 0.0
+        K[off, :, s] = 0.0
+        K[off, s, s] = 1.0
+    return K
+
+
+def vanka_color(dom: Domain, x, b, colour: int):
+    """One colour class of multiplicative Vanka on V1.
+
+    Reading (intra-colour semantics): all subdomains of one class take their
+    local residual from the state at the start of the class and then apply
+    their corrections, i.e. x <- x + sum_i C_i^T K_i^{-1} C_i (b - L~ x) over
+    the class.  Same-class subdomains share no unknown (cells two apart), so
+    the corrections never overlap.
+    """
+    cells = np.argwhere(dom.v1[3] & (dom.vanka_colour() == colour))
+    if cells.shape[0] == 0:
+        return x
+    idx, act = vanka_slots(dom, cells)
+    r = residual(dom, x, b, dom.gamma)
+    rloc = np.stack([np.where(act[:, s], r[_SLOT_FIELD[s]][idx[s]], 0.0) for s in range(7)], axis=1)
+    K = vanka_local_matrix(dom.eta, dom.h, dom.gamma, act)
+    delta = np.linalg.solve(K, rloc[:, :, None])[:, :, 0]
+    x = [v.copy() for v in x]
+    for s in range(7):
+        f = _SLOT_FIELD[s]
+        np.add.at(x[f], idx[s], np.where(act[:, s], delta[:, s], 0.0))
+    return tuple(x)
+
+
+def vanka_symmetric(dom: Domain, x, b):
+    """Symmetric multiplicative Vanka (Section 3.2): classes 0..7, then 7..0."""
+    for colour in range(8):
+        x = vanka_color(dom, x, b, colour)
+    for colour in reversed(range(8)):
+        x = vanka_color(dom, x, b, colour)
+    return x
+
+
+def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None):
+    """Alg. 3: symmetric Vanka on V1, symmetric DGS on V2, symmetric Vanka on V1.
+
+    Reading: the three calls are chained (each starts from the previous
+    output), as in the symmetry proof of Appendix D; `n_boundary` symmetric
+    Vanka applications fill each Vanka slot.
+    """
+    for _ in range(n_boundary):
+        x = vanka_symmetric(dom, x, b)
+    x = dgs_symmetric(dom, x, b, diags)
+    for _ in range(n_boundary):
+        x = vanka_symmetric(dom, x, b)
+    return x

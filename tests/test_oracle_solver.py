@@ -1,0 +1,373 @@
+"""Pins of the oracle's smoothers, V-cycle and SQMR against the paper's
+theorems, its algorithms written as dense linear algebra, library routines and
+closed forms."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle.domain import Domain, box_labels
+from oracle.multigrid import Hierarchy, vcycle
+from oracle.operator import apply_operator, assemble, from_vector, residual, to_vector
+from oracle.smoother import (collect, dgs_diagonals, dgs_forward, dgs_reverse, dgs_symmetric,
+                             distribute, smooth, vanka_color, vanka_local_matrix, vanka_slots,
+                             vanka_symmetric)
+from oracle.sqmr import mg_sqmr, remove_pressure_mean, sqmr
+from oracle.transfer import prolong, restrict
+from paper_2312_10615_amd.workloads import mms_fields, random_state, sinusoid_forcing
+
+
+def dom_of(dims, eta=1.0, gamma=1e-3):
+    return Domain(box_labels(dims), 1.0 / max(dims), eta, gamma)
+
+
+def rand_state(dom, seed):
+    x = random_state(*dom.dims, seed=seed)
+    return tuple(np.where(m, v, 0.0) for m, v in zip(dom.active, x))
+
+
+def zero(dom):
+    return tuple(np.zeros(s) for s in dom.shapes)
+
+
+def dense_of(dom, fn, n_out_dom=None):
+    """Dense matrix of a linear map given on states."""
+    out_dom = n_out_dom or dom
+    n = dom.n_dofs()
+    cols = []
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        cols.append(to_vector(out_dom, fn(from_vector(dom, e))))
+    return np.stack(cols, axis=1)
+
+
+def dof_tags(dom):
+    """Per DOF (to_vector order): field id, red/black parity, V2 flag."""
+    fid = to_vector(dom, tuple(np.full(s, float(f)) for f, s in enumerate(dom.shapes))).astype(int)
+    par = to_vector(dom, tuple(dom.parity(f).astype(float) for f in range(4))).astype(int)
+    v2 = to_vector(dom, tuple(m.astype(float) for m in dom.v2)).astype(bool)
+    return fid, par, v2
+
+
+def traversal_order(dom):
+    """Forward DGS order of the reading: velocities red, velocities black,
+    pressures red, pressures black (natural order inside a class)."""
+    fid, par, v2 = dof_tags(dom)
+    order = []
+    for is_p in (False, True):
+        for colour in (0, 1):
+            order += [j for j in range(fid.size) if v2[j] and (fid[j] == 3) == is_p and par[j] == colour]
+    return order
+
+
+def m_columns(dom, order):
+    """Columns of M22 (Eq. dist restricted to V2) for the DOFs in `order`."""
+    fid, _, _ = dof_tags(dom)
+    n = dom.n_dofs()
+    cols = {}
+    for j in order:
+        if fid[j] < 3:
+            c = np.zeros(n)
+            c[j] = 1.0
+        else:
+            e = np.zeros(n)
+            e[j] = 1.0
+            cells = from_vector(dom, e)[3]
+            c = to_vector(dom, distribute(dom, cells))
+        cols[j] = c
+    return cols
+
+
+# --- DGS (Alg. 2, Eq. dist / ldist, Appendix A) -------------------------------
+
+def test_dgs_diagonals_closed_form():
+    dom = dom_of((6, 8, 6), eta=0.8)
+    d_u, d_p = dgs_diagonals(dom)
+    c = dom.eta / dom.h ** 2
+    for a in range(3):
+        assert np.allclose(d_u[a][dom.v2[a]], 6 * c, rtol=1e-14)
+        assert np.all(d_u[a][~dom.v2[a]] == 0)
+    # n_j = number of V2 faces of cell j
+    nj = np.zeros(dom.shapes[3])
+    for a in range(3):
+        v = dom.v2[a].astype(float)
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[a] = slice(0, -1)
+        hi[a] = slice(1, None)
+        nj += v[tuple(lo)] + v[tuple(hi)]
+    want = -(1 + dom.gamma * dom.eta) * nj / dom.h ** 2
+    assert np.allclose(d_p[dom.v2[3]], want[dom.v2[3]], rtol=1e-13)
+
+
+def test_distribute_and_collect_are_adjoint():
+    dom = dom_of((6, 6, 8))
+    rng = np.random.default_rng(0)
+    delta = rng.standard_normal(dom.shapes[3])
+    r = rand_state(dom, 3)
+    lhs = sum(float(np.sum(a * b)) for a, b in zip(distribute(dom, delta), r))
+    rhs = float(np.sum(np.where(dom.v2[3], delta, 0) * collect(dom, r)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("dims", [(6, 6, 6), (6, 4, 8)])
+def test_dgs_sweeps_equal_literal_one_unknown_loop(dims):
+    """Alg. 2 run literally, one unknown at a time in the traversal order with
+    dense rows of L~ and columns of M, equals the colour-at-once sweep; the
+    reverse sweep likewise against one-at-a-time GS on M^T L~."""
+    dom = dom_of(dims)
+    Lt = assemble(dom, dom.gamma, dense=True)
+    order = traversal_order(dom)
+    cols = m_columns(dom, order)
+    b = to_vector(dom, rand_state(dom, 11))
+    x0 = to_vector(dom, rand_state(dom, 12))
+
+    x = x0.copy()
+    for j in order:
+        m = cols[j]
+        d = Lt[j] @ m
+        x += (b[j] - Lt[j] @ x) / d * m
+    got = to_vector(dom, dgs_forward(dom, from_vector(dom, x0), from_vector(dom, b)))
+    assert np.allclose(got, x, rtol=0, atol=1e-11 * np.abs(x).max())
+
+    y = x.copy()
+    for j in reversed(order):
+        m = cols[j]
+        d = Lt[j] @ m
+        y[j] += m @ (b - Lt @ y) / d
+    got2 = to_vector(dom, dgs_reverse(dom, from_vector(dom, x), from_vector(dom, b)))
+    assert np.allclose(got2, y, rtol=0, atol=1e-11 * np.abs(y).max())
+
+
+def test_pressure_step_zeroes_its_continuity_residual():
+    dom = dom_of((8, 8, 8))
+    b, x = rand_state(dom, 1), rand_state(dom, 2)
+    y = dgs_forward(dom, x, b)
+    r = residual(dom, y, b, dom.gamma)
+    # black pressures were relaxed last: their continuity residual is zero
+    sel = dom.v2[3] & (dom.parity(3) == 1)
+    assert np.abs(r[3][sel]).max() <= 1e-10 * np.abs(b[3]).max()
+
+
+def test_symmetric_dgs_equals_appendix_a_formula():
+    """P = M G^-1 + G^-T M^T - G^-T M^T L M G^-1 with G the lower triangle of
+    L~22 M22 in traversal order (Appendix A, Theorem 1), and P symmetric."""
+    dom = dom_of((6, 6, 4))
+    Lt = assemble(dom, dom.gamma, dense=True)
+    order = traversal_order(dom)
+    cols = m_columns(dom, order)
+    idx = np.array(order)
+    L22 = Lt[np.ix_(idx, idx)]
+    M22 = np.stack([cols[j][idx] for j in order], axis=1)
+    G = np.tril(L22 @ M22)
+    Gi = np.linalg.inv(G)
+    P = M22 @ Gi + Gi.T @ M22.T - Gi.T @ M22.T @ L22 @ M22 @ Gi
+    n = dom.n_dofs()
+    C = np.zeros((idx.size, idx.size))
+    for c, j in enumerate(order):
+        e = np.zeros(n)
+        e[j] = 1.0
+        C[:, c] = to_vector(dom, dgs_symmetric(dom, zero(dom), from_vector(dom, e)))[idx]
+    assert np.abs(C - P).max() <= 1e-12 * np.abs(P).max()
+    assert np.abs(C - C.T).max() <= 1e-12 * np.abs(C).max()
+
+
+# --- Vanka (Eq. mv, Appendix C) ---------------------------------------------
+
+def _dof_index(dom):
+    """Map (field, i, j, k) -> position in to_vector order."""
+    n = dom.n_dofs()
+    pos = from_vector(dom, np.arange(n, dtype=float))
+    return pos
+
+
+def test_vanka_local_matrix_is_the_submatrix_of_l_tilde():
+    dom = dom_of((6, 4, 8))
+    Lt = assemble(dom, dom.gamma, dense=True)
+    pos = _dof_index(dom)
+    cells = np.argwhere(dom.v1[3])
+    idx, act = vanka_slots(dom, cells)
+    K = vanka_local_matrix(dom.eta, dom.h, dom.gamma, act)
+    fields = (0, 0, 1, 1, 2, 2, 3)
+    for c in range(cells.shape[0]):
+        live = [s for s in range(7) if act[c, s]]
+        g = [int(pos[fields[s]][tuple(ix[c] for ix in idx[s])]) for s in live]
+        assert np.allclose(K[c][np.ix_(live, live)], Lt[np.ix_(g, g)], rtol=1e-14, atol=0)
+
+
+def test_vanka_colour_step_equals_eq_mv_dense_form():
+    """Colour step = x + sum_i C_i^T (C_i L~ C_i^T)^{-1} C_i (b - L~ x)."""
+    dom = dom_of((4, 6, 6))
+    Lt = assemble(dom, dom.gamma, dense=True)
+    pos = _dof_index(dom)
+    b, x = rand_state(dom, 5), rand_state(dom, 6)
+    bv, xv = to_vector(dom, b), to_vector(dom, x)
+    colour = 3
+    cells = np.argwhere(dom.v1[3] & (dom.vanka_colour() == colour))
+    idx, act = vanka_slots(dom, cells)
+    fields = (0, 0, 1, 1, 2, 2, 3)
+    r = bv - Lt @ xv
+    want = xv.copy()
+    for c in range(cells.shape[0]):
+        g = [int(pos[fields[s]][tuple(ix[c] for ix in idx[s])]) for s in range(7) if act[c, s]]
+        want[g] += np.linalg.solve(Lt[np.ix_(g, g)], r[g])
+    got = to_vector(dom, vanka_color(dom, x, b, colour))
+    assert np.allclose(got, want, rtol=0, atol=1e-11 * np.abs(want).max())
+
+
+def test_single_subdomain_solve_zeroes_its_local_residual():
+    dom = dom_of((2, 2, 2))   # eight cells, one per colour
+    b, x = rand_state(dom, 1), rand_state(dom, 2)
+    y = vanka_color(dom, x, b, 5)
+    r = residual(dom, y, b, dom.gamma)
+    cell = np.argwhere(dom.vanka_colour() == 5)
+    idx, act = vanka_slots(dom, cell)
+    fields = (0, 0, 1, 1, 2, 2, 3)
+    for s in range(7):
+        if act[0, s]:
+            assert abs(r[fields[s]][tuple(ix[0] for ix in idx[s])]) <= 1e-10 * np.abs(b[fields[s]]).max()
+
+
+# --- Symmetry theorems (Appendices A, C, D) and the V-cycle -----------------
+
+@pytest.fixture(scope="module")
+def small():
+    dom = dom_of((4, 6, 6))
+    return dom, assemble(dom, dom.gamma, dense=True), dgs_diagonals(dom)
+
+
+@pytest.mark.parametrize("which", ["vanka", "dgs", "smooth"])
+def test_smoother_matrices_are_symmetric_and_propagators_self_adjoint(small, which):
+    dom, Lt, diags = small
+    fn = {"vanka": lambda b: vanka_symmetric(dom, zero(dom), b),
+          "dgs": lambda b: dgs_symmetric(dom, zero(dom), b, diags),
+          "smooth": lambda b: smooth(dom, zero(dom), b, 1, diags)}[which]
+    C = dense_of(dom, fn)
+    assert np.abs(C - C.T).max() <= 1e-12 * np.abs(C).max()
+    E = np.eye(C.shape[0]) - C @ Lt
+    assert np.abs(Lt @ E - E.T @ Lt).max() <= 1e-10 * np.abs(Lt).max()
+
+
+def test_vcycle_is_symmetric_on_random_vectors():
+    H = Hierarchy((16, 16, 16), 1.0 / 16)
+    dom = H.doms[0]
+    x, y = rand_state(dom, 21), rand_state(dom, 22)
+    a = sum(float(np.sum(u * v)) for u, v in zip(x, vcycle(H, y)))
+    b = sum(float(np.sum(u * v)) for u, v in zip(vcycle(H, x), y))
+    assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def test_single_level_vcycle_is_the_exact_inverse():
+    H = Hierarchy((4, 4, 6), 0.25, levels=1)
+    dom = H.doms[0]
+    Lt = assemble(dom, dom.gamma, dense=True)
+    b = rand_state(dom, 3)
+    got = to_vector(dom, vcycle(H, b))
+    want = np.linalg.inv(Lt) @ to_vector(dom, b)
+    assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_two_level_vcycle_matches_alg1_algebra():
+    """W = (I - C L~)(C + P Lc^-1 R (I - L~ C)) + C with C the smoothing matrix."""
+    H = Hierarchy((8, 4, 4), 1.0 / 8, levels=2)
+    fine, coarse = H.doms
+    Lt = assemble(fine, fine.gamma, dense=True)
+    Lc = assemble(coarse, coarse.gamma, dense=True)
+    C = dense_of(fine, lambda b: smooth(fine, zero(fine), b, 1, H.diags[0]))
+    P = dense_of(coarse, lambda e: prolong(fine, coarse, e), fine)
+    R = dense_of(fine, lambda r: restrict(fine, coarse, r), coarse)
+    I = np.eye(C.shape[0])
+    want = (I - C @ Lt) @ (C + P @ np.linalg.solve(Lc, R @ (I - Lt @ C))) + C
+    got = dense_of(fine, lambda b: vcycle(H, b))
+    assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
+    assert np.abs(got - got.T).max() <= 1e-11 * np.abs(got).max()
+    assert np.allclose(P, 8 * R.T, rtol=0, atol=1e-15)
+
+
+# --- SQMR (Alg. 4) ------------------------------------------------------------
+
+def _sym_indefinite(n, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.concatenate([rng.uniform(1, 10, n - n // 3), -rng.uniform(1, 10, n // 3)])
+    return (Q * ev) @ Q.T
+
+
+def test_unpreconditioned_sqmr_iterates_are_minres_iterates():
+    A = _sym_indefinite(60, 0)
+    b = np.random.default_rng(1).standard_normal(60)
+    ours = []
+    sqmr(lambda v: A @ v, lambda v: v.copy(), b, np.zeros(60), rtol=1e-30, maxit=12,
+         on_iterate=lambda j, x, s: ours.append(x.copy()))
+    theirs = []
+    spla.minres(A, b, rtol=1e-30, maxiter=12, callback=lambda xk: theirs.append(xk.copy()))
+    for j in range(10):
+        assert np.linalg.norm(ours[j] - theirs[j]) <= 1e-9 * np.linalg.norm(theirs[j]), j
+
+
+def test_sqmr_s_vectors_are_pcg_residuals_on_spd_problems():
+    rng = np.random.default_rng(2)
+    n = 50
+    B = rng.standard_normal((n, n))
+    A = B @ B.T + n * np.eye(n)
+    dinv = 1.0 / np.diag(A) * rng.uniform(0.5, 2.0, n)
+    b = rng.standard_normal(n)
+    ours = []
+    sqmr(lambda v: A @ v, lambda v: dinv * v, b, np.zeros(n), rtol=1e-30, maxit=15,
+         on_iterate=lambda j, x, s: ours.append(s.copy()))
+    theirs = []
+    M = spla.LinearOperator((n, n), matvec=lambda v: dinv * v)
+    spla.cg(A, b, rtol=1e-30, maxiter=15, M=M, callback=lambda xk: theirs.append(b - A @ xk))
+    for j in range(12):
+        assert np.linalg.norm(ours[j] - theirs[j]) <= 1e-8 * np.linalg.norm(b), j
+
+
+def test_mg_sqmr_reaches_the_dense_solution():
+    n = 8
+    H = Hierarchy((n, n, n), 1.0 / n)
+    dom = H.doms[0]
+    f = sinusoid_forcing(n, n, n, 1.0 / n, seed=0)
+    b = tuple(np.where(dom.active[a], f[a], 0.0) for a in range(3)) + (np.zeros((n, n, n)),)
+    x, info = mg_sqmr(H, b, rtol=1e-13, maxit=100)
+    assert info["status"] == "converged"
+    L = assemble(dom, 0.0, dense=True)
+    N = L.shape[0]
+    z = to_vector(dom, tuple(np.zeros(s) for s in dom.shapes[:3]) + (np.ones(dom.shapes[3]),))
+    K = np.block([[L, z[:, None]], [z[None, :], np.zeros((1, 1))]])
+    sol = np.linalg.solve(K, np.concatenate([to_vector(dom, b), [0.0]]))[:N]
+    got = to_vector(dom, remove_pressure_mean(dom, x))
+    assert np.linalg.norm(got - sol) <= 1e-9 * np.linalg.norm(sol)
+
+
+def test_sqmr_status_paths():
+    H = Hierarchy((8, 8, 8), 1.0 / 8)
+    dom = H.doms[0]
+    z = zero(dom)
+    x, info = mg_sqmr(H, z, x0=rand_state(dom, 1))
+    assert info["status"] == "converged" and all(np.all(v == 0) for v in x)
+    b = rand_state(dom, 2)
+    b = b[:3] + (np.zeros(dom.shapes[3]),)
+    x, info = mg_sqmr(H, b, maxit=1)
+    assert info["status"] == "maxit" and info["iters"] == 1
+    bad = (np.where(dom.active[0], np.nan, 0.0),) + b[1:]
+    x, info = mg_sqmr(H, bad, maxit=5)
+    assert info["status"] == "nonfinite"
+
+
+@pytest.mark.slow
+def test_manufactured_solution_converges_at_second_order():
+    errs = []
+    for n in (8, 16, 32):
+        H = Hierarchy((n, n, n), 1.0 / n)
+        dom = H.doms[0]
+        m = mms_fields(n, eta=1.0)
+        b = tuple(np.where(dom.active[a], m["f"][a], 0.0) for a in range(3)) + (np.zeros((n, n, n)),)
+        x, info = mg_sqmr(H, b, rtol=1e-11, maxit=300)
+        assert info["status"] == "converged"
+        x = remove_pressure_mean(dom, x)
+        eu = np.sqrt(sum(np.sum(np.where(dom.active[a], x[a] - m["u"][a], 0.0) ** 2) for a in range(3)) / dom.n_dofs())
+        ep = np.sqrt(np.mean((x[3] - m["p"]) ** 2))
+        errs.append((eu, ep))
+    for (u0, p0), (u1, p1) in zip(errs, errs[1:]):
+        assert np.log2(u0 / u1) >= 1.8
+        assert np.log2(p0 / p1) >= 1.5
