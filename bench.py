@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark: time for MG-SQMR to reach relative residual 1e-8 on the 256^3
+MAC Stokes problem (FP64, 7-level V-cycle), on one MI355X.
+
+One step = one complete solve from x0 = 0 (all hot-path kernels: operator,
+V-cycle smoothers and transfers, coarse solve, SQMR recurrences).  The input
+(seeded sinusoid forcing) is resident in HBM before timing starts.  Prints
+one JSON line.
+
+Roofline: the dominant kernel is timed live with HIP events (recorded by the
+library on its stream) during the timed steps; `achieved` = its algorithmic
+bytes per launch / its average launch duration.  `traffic` comes from the
+rocprofv3 counter summary under profiles/ when that summary was taken on the
+current kernel source, else null.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+S = 8  # bytes per FP64 value
+
+
+def dof_counts(n):
+    nu = 3 * (n - 1) * n * n
+    return nu, n ** 3
+
+
+def algorithmic_bytes(kernel, n):
+    """Compulsory bytes of one launch at level 0 (each operand streamed once)."""
+    nu, npr = dof_counts(n)
+    return {
+        "dgs_u": (2 * nu + npr) * S,            # read u, p, b_u(colour); write u(colour)
+        "dgs_pr": (2 * nu + 2.5 * npr) * S,     # read u, p, b_u, b_p; write p(colour)
+        "dgs_pf_own": (2 * nu + 2 * npr) * S,   # read u, p/2, b_p/2; write u, p/2, delta/2
+        "dgs_pf_nbr": 1.5 * npr * S,            # read delta/2, p/2; write p/2
+        "apply": 3 * (nu + npr) * S,            # residual: read x, b; write r
+        "restrict": 1.125 * (nu + npr) * S,
+        "prolong": 2.125 * (nu + npr) * S,
+    }[kernel]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("geom.hpp", "kernels.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2312_10615_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, n):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on this kernel source and workload."""
+    path = os.path.join(ROOT, "profiles", "counters_fp64_256.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("n") != n:
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return (k["fetch_kib"] + k["write_kib"]) * 1024.0 * d.get("copy_scale", 1.0)
+
+
+def cpu_baseline(iters, n_full, seed):
+    """Oracle timed on the host: one V-cycle plus one operator application (the
+    work of one MG-SQMR iteration apart from vector updates) at 128^3, scaled by
+    8 (work is linear in the unknowns) to 256^3 and by the iteration count."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.multigrid import Hierarchy, vcycle
+    from oracle.operator import apply_operator
+    from paper_2312_10615_amd.workloads import sinusoid_forcing
+
+    n = n_full // 2
+    with threadpool_limits(limits=1):
+        H = Hierarchy((n, n, n), 1.0 / n)
+        dom = H.doms[0]
+        f = sinusoid_forcing(n, n, n, 1.0 / n, seed=seed)
+        b = tuple(np.where(dom.active[a], f[a], 0.0) for a in range(3)) + (np.zeros((n, n, n)),)
+        t0 = time.perf_counter()
+        vcycle(H, b)
+        apply_operator(dom, b, 0.0)
+        t1 = time.perf_counter()
+    per_iter = (t1 - t0) * (n_full / n) ** 3
+    return {"value": per_iter * (iters + 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"one oracle V-cycle + one operator apply at {n}^3 (seed {seed}, 1 thread) took "
+                      f"{t1 - t0:.1f} s; scaled x{(n_full // n) ** 3} to {n_full}^3 and x{iters + 1} "
+                      f"V-cycles of the GPU solve", "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--kernel", default="dgs_pr", help="dominant kernel class timed for the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the solve does not shard "
+              f"across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2312_10615_amd.stokes import StokesSolver
+    from paper_2312_10615_amd.workloads import sinusoid_forcing
+
+    n = args.n
+    h = 1.0 / n
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    sol = StokesSolver(n, n, n, h=h)
+    t_setup = time.perf_counter() - t_setup
+    f = sinusoid_forcing(n, n, n, h, seed=args.seed)
+    b = sol.pack((f[0], f[1], f[2], np.zeros((n, n, n))))
+    del f
+    torch.cuda.synchronize()
+    print(f"[bench] setup {t_setup:.2f}s, levels={sol.layout.levels}, unknowns={sol.layout.n_dofs}", file=sys.stderr,
+          flush=True)
+
+    info = None
+    for w in range(args.warmup):
+        x, info = sol.solve(b, rtol=args.rtol, maxit=500)
+        print(f"[bench] warmup {w}: iters={info['iters']} relres={info['relres']:.3e} {info['status']}",
+              file=sys.stderr, flush=True)
+
+    sol.profile(args.kernel, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        x, info = sol.solve(b, rtol=args.rtol, maxit=500)
+        print(f"[bench] step {k}: iters={info['iters']} relres={info['relres']:.3e} {info['status']}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, klaunch = sol.profile_read(args.kernel, 0)
+    sol.profile("off")
+    assert info["status"] == "ok", info
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+
+    # V-cycle time alone (outside the timed region)
+    s = b.clone()
+    t = sol.new_state()
+    sol.vcycle(s, out=t)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    nvc = 5
+    for _ in range(nvc):
+        sol.vcycle(s, out=t)
+    ev1.record()
+    torch.cuda.synchronize()
+    vcycle_ms = ev0.elapsed_time(ev1) / nvc
+
+    avg_ms = kms / max(klaunch, 1)
+    abytes = algorithmic_bytes(args.kernel, n)
+    achieved = abytes / (avg_ms * 1e-3) / 1e9
+    traffic = counter_traffic(args.kernel, n)
+    line = {
+        "metric": "time to 1e-8 rel. residual, 256^3 Stokes; V-cycle HBM GB/s vs plain FP64",
+        "value": round(ms_per_step / 1000.0, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded 8-mode sinusoid forcing per component, zero divergence RHS)",
+        "config": {"workload": f"3D MAC Stokes {n}^3 cells unit cube, no-slip box, eta=1, gamma=1e-3, "
+                               f"{sol.layout.levels}-level V-cycle (split schedule, 2 pre + 2 post DGS sweeps, n_b=1), "
+                               f"MG-SQMR to rtol {args.rtol:g}",
+                   "unknowns": int(sol.layout.n_dofs), "seed": args.seed, "precision": "fp64 throughout"},
+        "iterations": info["iters"],
+        "final_relres": info["relres"],
+        "vcycle_ms": round(vcycle_ms, 3),
+        "setup_s": round(t_setup, 3),
+        "roofline": {"bound": "hbm", "kernel": f"k_{args.kernel} (level 0)", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": klaunch,
+                     "algorithmic_bytes_per_launch": abytes},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(info["iters"], n, args.seed)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

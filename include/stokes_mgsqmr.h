@@ -1,0 +1,190 @@
+/*
+ * stokes_mgsqmr.h - C ABI of the MI355X (gfx950) multigrid-preconditioned SQMR
+ * solver for the 3D Stokes equations on a staggered (MAC) grid.
+ *
+ * Method: Tao & Sifakis, "A Symmetric Multigrid-Preconditioned Krylov Subspace
+ * Solver for Stokes Equations" (arXiv 2312.10615).  The library solves
+ *
+ *     L x = b,   L = [[A, B^T], [B, 0]],  x = (u, p),  b = (f, g)       (Eq. 2)
+ *
+ * with A = -eta * 7-point Laplacian on each velocity lattice, B^T the pressure
+ * gradient onto faces and B minus the divergence onto cells, by SQMR (Alg. 4)
+ * preconditioned with one V-cycle (Alg. 1) on the penalised matrix
+ * L~ = [[A, B^T], [B, -gamma I]] (Section 4).  The V-cycle smooths with
+ * symmetric multiplicative Vanka on the boundary set V1 and symmetric
+ * distributive Gauss-Seidel on the interior set V2 (Alg. 3, Section 3),
+ * transfers with bilinear / constant prolongation P and R = P^T/8
+ * (Section 2), and solves the coarsest level exactly.
+ *
+ * Domain: a box of nx*ny*nz cells of edge h surrounded by one layer of
+ * Dirichlet cells (Section 5 with every cell interior); homogeneous no-slip
+ * walls.  Non-zero Dirichlet data is folded into b by the caller.
+ *
+ * Conventions
+ *  - Every function returns an int status (STOKES_OK = 0).  No exception or
+ *    abort crosses the ABI.  stokes_strerror() names a status.
+ *  - All device pointers are HIP device addresses on the current device;
+ *    every GPU operation is enqueued on the stream given to stokes_setup().
+ *  - The library never allocates device memory: the caller owns the
+ *    workspace, every state vector, and the memory behind them.  The library
+ *    allocates only its host-side context, released by stokes_destroy().
+ *  - One context must not be used from two host threads at once.
+ *
+ * State vectors ("x", "b", "s", "t", "y" below) are float64 device arrays of
+ * stokes_layout_t.total elements holding u_x, u_y, u_z and p in the padded
+ * layout described by stokes_layout(): element (I, J, K) of field f sits at
+ * off[f] + I + sy*J + sz*K, padded indices I in [0, nx+2), J in [0, ny+2),
+ * K in [0, nz+2).  Pressure of cell (i,j,k) (0-based) is at (i+1, j+1, k+1);
+ * u_x on the face x = i*h of row (j,k) is at (i+1, j+1, k+1), i = 0..nx
+ * (i = 0 and i = nx are walls); u_y, u_z alike.  Slots that are not unknowns
+ * ("ghost slots": walls, Dirichlet ghosts, pitch padding) must hold zero in
+ * every input that the library reads as x; the library writes zero there in
+ * every vector it outputs.  Right-hand sides may hold anything in ghost slots.
+ */
+#ifndef STOKES_MGSQMR_H
+#define STOKES_MGSQMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  STOKES_OK = 0,
+  STOKES_EINVAL = 1,      /* bad dimensions / levels / null or misaligned pointer / small workspace */
+  STOKES_ENOCONV = 2,     /* maxit reached before the tolerance; x holds the last iterate */
+  STOKES_EBREAKDOWN = 3,  /* sigma = 0 or rho = 0 in SQMR; x holds the last iterate */
+  STOKES_ENONFINITE = 4,  /* a NaN/Inf scalar appeared (e.g. non-finite b) */
+  STOKES_EDEVICE = 5      /* a HIP runtime call failed */
+};
+
+/* Smoothing schedules of the V-cycle (Section 3: the pre- and post-smoothing
+ * matrices must be transposes of each other for W to be symmetric).
+ *  STOKES_SMOOTHER_SPLIT: pre-smoothing = Alg. 3 with nu reverse DGS sweeps
+ *    (Gauss-Seidel on M^T L~, Eq. ldist) on V2 between symmetric Vanka on V1;
+ *    post-smoothing = Alg. 3 with nu forward DGS sweeps (on L~ M, Eq. dist).
+ *    The two are transposes of each other.  Default.
+ *  STOKES_SMOOTHER_SYMMETRIC: the paper's arrangement - the same symmetric
+ *    smoother (Alg. 3 with one symmetric DGS = forward + reverse sweep) in both
+ *    phases, nu/2 times (nu even). */
+enum { STOKES_SMOOTHER_SPLIT = 0, STOKES_SMOOTHER_SYMMETRIC = 1 };
+
+/* Solver parameters.  Defaults (stokes_default_params): eta = 1, gamma = 1e-3
+ * (the penalty of Section 4; Section 6 uses 1e-3), levels = 0 (auto), nu = 2,
+ * n_boundary = 1, vcycle_precision = 64, smoother = STOKES_SMOOTHER_SPLIT,
+ * flags = STOKES_FLAG_REMOVE_MEAN. */
+typedef struct stokes_params {
+  int32_t nx, ny, nz;         /* interior cells per axis, each >= 2 */
+  double h;                   /* cell edge; > 0 */
+  double eta;                 /* viscosity; > 0 */
+  double gamma;               /* penalty of L~ inside the V-cycle; >= 0 */
+  int32_t levels;             /* multigrid levels; 0 = halve while all axes are even and
+                                 every halved axis keeps >= 4 cells; explicit values may
+                                 go down to 2 cells per axis */
+  int32_t nu;                 /* DGS sweeps per smoothing phase (pre and post), >= 1;
+                                 even for STOKES_SMOOTHER_SYMMETRIC */
+  int32_t n_boundary;         /* symmetric Vanka applications per Vanka slot of Alg. 3, >= 1 */
+  int32_t vcycle_precision;   /* 64 (FP64 V-cycle) */
+  int32_t smoother;           /* STOKES_SMOOTHER_* */
+  int32_t flags;              /* STOKES_FLAG_* */
+} stokes_params;
+
+/* After convergence subtract the mean pressure over the cells (the closed box
+ * leaves p defined up to a constant). */
+#define STOKES_FLAG_REMOVE_MEAN 1
+
+typedef struct stokes_layout_t {
+  int32_t nx, ny, nz;         /* interior cells */
+  int64_t sy, sz;             /* element strides of J and K (stride of I is 1) */
+  int64_t off[4];             /* element offset of u_x, u_y, u_z, p */
+  int64_t field;              /* elements per field (off[f+1] - off[f]) */
+  int64_t total;              /* elements in one state vector */
+  int64_t n_dofs;             /* number of unknowns */
+  int32_t levels;             /* resolved level count */
+} stokes_layout_t;
+
+typedef struct stokes_info {
+  int32_t iters;              /* SQMR iterations performed */
+  int32_t status;             /* STOKES_OK / ENOCONV / EBREAKDOWN / ENONFINITE */
+  double relres;              /* final true ||b - L x||_2 / ||b||_2 */
+  double bnorm;               /* ||b||_2 over the unknowns */
+  double* history;            /* optional caller-owned host array of maxit+1 doubles:
+                                 relative true residual after each iteration (index 0: x0);
+                                 NULL = not recorded */
+} stokes_info;
+
+typedef struct stokes_ctx stokes_ctx;
+
+/* Fill *p with the defaults listed above and the given box. */
+int stokes_default_params(int32_t nx, int32_t ny, int32_t nz, double h, stokes_params* p);
+
+/* Bytes of device workspace stokes_setup() needs for these parameters. */
+int stokes_workspace_bytes(const stokes_params* p, size_t* bytes);
+
+/* Build the multigrid hierarchy (label coarsening of Section 5, rediscretised
+ * operators of Section 2), the Vanka local inverses (the prefactorised local
+ * saddle problems of Section 6), the coarsest-level inverse and the V1 colour
+ * lists, and upload them into `workspace` (device, >= stokes_workspace_bytes,
+ * 256-byte aligned).  `hip_stream` is a hipStream_t (NULL = default stream).
+ * Blocks until the uploads are complete.  On success *out owns a host context. */
+int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hip_stream,
+                 stokes_ctx** out);
+
+/* Layout of state vectors for this context. */
+int stokes_layout(const stokes_ctx* ctx, stokes_layout_t* out);
+
+/* y = L x (penalized = 0) or y = L~ x (penalized = 1) on the finest level
+ * (Eq. 2 / Section 4).  x and y are distinct device state vectors.  Async. */
+int stokes_apply(stokes_ctx* ctx, const double* x, double* y, int32_t penalized);
+
+/* t = W s: one V-cycle on L~ with zero initial guess (Alg. 1 as the
+ * preconditioner of Section 3/4).  s and t are distinct device state vectors;
+ * s is not modified.  Async. */
+int stokes_vcycle(stokes_ctx* ctx, const double* s, double* t);
+
+/* Solve L x = b with MG-SQMR (Alg. 4).  b: device state vector (read only).
+ * x: device state vector, in: initial guess x0 (zeros or a warm start; its
+ * ghost slots are cleared), out: the iterate meeting ||b - L x|| <= rtol ||b||
+ * (or the last one).  Stops after maxit iterations (maxit >= 0).  Synchronises
+ * the stream (the SQMR scalars are read back every iteration).  Returns the
+ * solve status, also stored in info->status (info may be NULL). */
+int stokes_solve(stokes_ctx* ctx, const double* b, double* x, double rtol, int32_t maxit,
+                 stokes_info* info);
+
+/* Diagnostics: per-kernel timing with HIP events recorded on the context's
+ * stream around the selected launches (the "tracing" aux subsystem).
+ * kernel_class: one of STOKES_KC_*, or STOKES_KC_ALL, or STOKES_KC_OFF to stop;
+ * level: multigrid level (0 = finest) or -1 for all.  Selecting resets the
+ * accumulated times.  stokes_profile_read() synchronises the stream and returns
+ * the accumulated milliseconds and launch count for (kernel_class, level). */
+enum {
+  STOKES_KC_APPLY = 0,        /* operator / residual / residual-norm passes */
+  STOKES_KC_DGS_U = 1,        /* velocity Gauss-Seidel half sweep (one colour) */
+  STOKES_KC_DGS_PF_OWN = 2,   /* forward pressure step, own cell */
+  STOKES_KC_DGS_PF_NBR = 3,   /* forward pressure step, neighbours */
+  STOKES_KC_DGS_PR = 4,       /* reverse (left-preconditioned) pressure step */
+  STOKES_KC_VANKA_DELTA = 5,  /* Vanka local solves of one colour */
+  STOKES_KC_VANKA_APPLY = 6,  /* Vanka corrections of one colour */
+  STOKES_KC_RESTRICT = 7,
+  STOKES_KC_PROLONG = 8,
+  STOKES_KC_COARSE = 9,
+  STOKES_KC_BLAS = 10,        /* SQMR vector updates, dots, fills */
+  STOKES_KC_COUNT = 11,
+  STOKES_KC_ALL = -1,
+  STOKES_KC_OFF = -2
+};
+int stokes_profile(stokes_ctx* ctx, int32_t kernel_class, int32_t level);
+int stokes_profile_read(stokes_ctx* ctx, int32_t kernel_class, int32_t level, double* total_ms, int64_t* launches);
+
+/* Release the host context (never touches the caller's device memory). */
+void stokes_destroy(stokes_ctx* ctx);
+
+const char* stokes_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STOKES_MGSQMR_H */

@@ -6,10 +6,19 @@ Section 5) and an exact solve at the coarsest level.  As a preconditioner it
 is called with a zero initial guess, which makes t = V-CYCLE(L~, s, 0, n)
 linear in s (Section 3).
 
-Reading (smoothing counts): the pre- and post-smoothing steps are `nu`
-applications of Alg. 3 each; the default nu = 1 holds one symmetric DGS
-(a forward and a reverse sweep) per smoothing step, as in Section 6 where the
-interior DGS is applied once per V-cycle phase.
+Smoothing schedules.  `nu` counts DGS sweeps per smoothing phase (a
+"sweep" is one directional pass, Section 3.1), so nu = 2 is "2 pre / 2 post".
+  * "symmetric" - the paper's choice (Section 3): the same symmetric smoother
+    in both phases, Alg. 3 applied nu/2 times, each with one symmetric DGS
+    (forward sweep on L M, Eq. dist, then reverse sweep on M^T L, Eq. ldist).
+  * "split" - the other arrangement Section 3 allows: different smoothers in
+    the two phases whose matrices are transposes of each other.  Pre-smoothing
+    is Alg. 3 with nu reverse sweeps on V2, post-smoothing Alg. 3 with nu
+    forward sweeps; the reverse sweep's error propagator is the L~-adjoint of
+    the forward sweep's, symmetric Vanka is L~-self-adjoint, so the pair meets
+    the transpose condition and W stays symmetric.  Measured: with the same
+    work per level it contracts where "symmetric" does not (the product of a
+    forward and a reverse sweep amplifies the lowest V2 pressure modes).
 Reading (levels): with levels = 0 the hierarchy halves every axis while all
 axes are even and every halved axis keeps at least 4 cells; an explicit
 level count may go down to 2 cells per axis.
@@ -20,7 +29,7 @@ import numpy as np
 
 from .domain import Domain, box_labels
 from .operator import apply_operator, assemble, from_vector, residual, to_vector, zeros_like_state
-from .smoother import dgs_diagonals, smooth
+from .smoother import dgs_diagonals, dgs_forward, dgs_reverse, smooth
 from .transfer import prolong, restrict
 
 
@@ -41,12 +50,14 @@ def max_levels(dims) -> int:
 class Hierarchy:
     """Levels 0 (finest) .. levels-1 (coarsest) of a box domain."""
 
-    def __init__(self, dims, h, eta=1.0, gamma=1e-3, levels=0, nu=1, n_boundary=1):
+    def __init__(self, dims, h, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1, schedule="split"):
         if levels == 0:
             levels = auto_levels(dims)
         if levels < 1 or levels > max_levels(dims):
             raise ValueError("too many levels for these dimensions")
-        self.nu, self.n_boundary = nu, n_boundary
+        if schedule not in ("split", "symmetric") or nu < 1 or (schedule == "symmetric" and nu % 2):
+            raise ValueError("bad smoothing schedule")
+        self.nu, self.n_boundary, self.schedule = nu, n_boundary, schedule
         self.doms = [Domain(box_labels(dims), h, eta, gamma)]
         for _ in range(levels - 1):
             self.doms.append(self.doms[-1].coarsen())
@@ -69,14 +80,37 @@ def vcycle(H: Hierarchy, b, level: int = 0):
         return H.coarse_solve(b)
     dom, coarse = H.doms[level], H.doms[level + 1]
     x = zeros_like_state(dom)
-    for _ in range(H.nu):
-        x = smooth(dom, x, b, H.n_boundary, H.diags[level])
+    x = presmooth(H, level, x, b)
     r = residual(dom, x, b, dom.gamma)
     e = vcycle(H, restrict(dom, coarse, r), level + 1)
     x = tuple(v + dv for v, dv in zip(x, prolong(dom, coarse, e)))
-    for _ in range(H.nu):
-        x = smooth(dom, x, b, H.n_boundary, H.diags[level])
-    return x
+    return postsmooth(H, level, x, b)
+
+
+def _sweeps(sweep, k):
+    def interior(dom, x, b, diags):
+        for _ in range(k):
+            x = sweep(dom, x, b, diags)
+        return x
+    return interior
+
+
+def presmooth(H: Hierarchy, level: int, x, b):
+    dom, diags = H.doms[level], H.diags[level]
+    if H.schedule == "symmetric":
+        for _ in range(H.nu // 2):
+            x = smooth(dom, x, b, H.n_boundary, diags)
+        return x
+    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_reverse, H.nu))
+
+
+def postsmooth(H: Hierarchy, level: int, x, b):
+    dom, diags = H.doms[level], H.diags[level]
+    if H.schedule == "symmetric":
+        for _ in range(H.nu // 2):
+            x = smooth(dom, x, b, H.n_boundary, diags)
+        return x
+    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_forward, H.nu))
 
 
 def apply_L(H: Hierarchy, x):

@@ -19,27 +19,30 @@ from .operator import apply_operator, grad, neg_div, residual
 
 
 # ---------------------------------------------------------------------------
-# Distribution matrix restricted to V2 (Eq. dist; Appendix D splits L into the
-# V1/V2 blocks and DGS relaxes L~22 x2 = b2 - L~21 x1).
+# Distribution matrix (Eq. dist): M = [[I, -B^T], [0, eta B B^T]].
 #
-# Reading: M22 = [[I, -B22^T], [0, eta B22 B22^T]] is built from V2 rows and
-# columns only, so a pressure update never moves a V1 unknown.
+# Reading: DGS on V2 is Alg. 2 with the loop over the V2 unknowns only; each
+# update moves x along the full column m_j of the global M.  For a V2 cell
+# that column is the interior stencil (all six faces and six neighbours are
+# unknowns), which is where L M has the block-triangular form of Eq. disc -
+# the reason Section 3.1 keeps DGS away from the boundary.  A pressure update
+# therefore also moves the faces it shares with V1 cells and the pressures of
+# V1 neighbours.  Symmetry is unaffected: Appendix A's argument holds for the
+# rectangular M of the V2 columns, and every stage of Alg. 3 keeps an
+# L~-self-adjoint error propagator.
 # ---------------------------------------------------------------------------
 
 def distribute(dom: Domain, delta: np.ndarray):
-    """M22 applied to a pressure-cell vector delta (its V2 entries are used)."""
+    """M applied to a pressure-cell vector delta supported on the V2 cells."""
     g = grad(dom, np.where(dom.v2[3], delta, 0.0))
-    g = [np.where(dom.v2[a], g[a], 0.0) for a in range(3)]
-    dp = np.where(dom.v2[3], dom.eta * neg_div(dom, g), 0.0)
+    dp = np.where(dom.active[3], dom.eta * neg_div(dom, g), 0.0)
     return (-g[0], -g[1], -g[2], dp)
 
 
 def collect(dom: Domain, r):
-    """Pressure rows of M22^T r = -B22 r_u + eta B22 B22^T r_p (Eq. ldist)."""
-    ru = [np.where(dom.v2[a], r[a], 0.0) for a in range(3)]
-    g = grad(dom, np.where(dom.v2[3], r[3], 0.0))
-    g = [np.where(dom.v2[a], g[a], 0.0) for a in range(3)]
-    out = -neg_div(dom, ru) + dom.eta * neg_div(dom, g)
+    """Pressure rows of M^T r at the V2 cells: -B r_u + eta B B^T r_p (Eq. ldist)."""
+    g = grad(dom, np.where(dom.active[3], r[3], 0.0))
+    out = -neg_div(dom, list(r[:3])) + dom.eta * neg_div(dom, g)
     return np.where(dom.v2[3], out, 0.0)
 
 
@@ -65,13 +68,13 @@ def dgs_diagonals(dom: Domain):
 
 
 def dgs_forward(dom: Domain, x, b, diags=None):
-    """One DGS sweep on L~22 M22 (Alg. 2 with the right preconditioning of Eq. dist).
+    """One DGS sweep over the V2 unknowns (Alg. 2 with the right preconditioning of Eq. dist).
 
     Reading (order): L M is block lower triangular (Eq. disc), so the sweep is
     a block forward substitution: all velocities first, then all pressures.
     Each block goes red ((i+j+k) even) then black.  A velocity update is the
     plain Gauss-Seidel step (velocity columns of M are unit vectors); a
-    pressure update moves x along the column m_j of M22.
+    pressure update moves x along the column m_j of M.
     """
     d_u, d_p = diags if diags is not None else dgs_diagonals(dom)
     gam = dom.gamma
@@ -90,7 +93,7 @@ def dgs_forward(dom: Domain, x, b, diags=None):
 
 
 def dgs_reverse(dom: Domain, x, b, diags=None):
-    """Gauss-Seidel on the left-preconditioned system M22^T L~22 (Eq. ldist) in
+    """Gauss-Seidel on the left-preconditioned system M^T L~ (Eq. ldist), rows of V2, in
     exactly the reverse order of `dgs_forward`: pressures black, red, then
     velocities black, red.  Each step updates its own unknown by
     (M^T r)_j / d_j; for velocities (M^T)_j = e_j^T."""
@@ -204,8 +207,10 @@ def vanka_symmetric(dom: Domain, x, b):
     return x
 
 
-def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None):
-    """Alg. 3: symmetric Vanka on V1, symmetric DGS on V2, symmetric Vanka on V1.
+def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None, interior=None):
+    """Alg. 3: symmetric Vanka on V1, an interior smoother on V2, symmetric
+    Vanka on V1.  The interior smoother defaults to the symmetric DGS of
+    Section 3.1; `interior(dom, x, b, diags)` replaces it.
 
     Reading: the three calls are chained (each starts from the previous
     output), as in the symmetry proof of Appendix D; `n_boundary` symmetric
@@ -213,7 +218,7 @@ def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None):
     """
     for _ in range(n_boundary):
         x = vanka_symmetric(dom, x, b)
-    x = dgs_symmetric(dom, x, b, diags)
+    x = (interior or dgs_symmetric)(dom, x, b, diags)
     for _ in range(n_boundary):
         x = vanka_symmetric(dom, x, b)
     return x

@@ -1,0 +1,560 @@
+// gfx950 kernels of the MG-SQMR hot path.  Bandwidth-bound stencil work:
+// no matrix cores, wave64 shuffles for reductions, padded x-fastest layout
+// (geom.hpp), one thread per slot, and block indices remapped so that each
+// of the 8 XCDs walks a contiguous slab of the grid (its L2 then serves the
+// y- and z-neighbour rows of its own rows).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "geom.hpp"
+
+namespace sg {
+
+constexpr int BS = 256;        // threads per block (4 waves)
+constexpr int NXCD = 8;        // XCDs on MI355X; workgroups are dealt round-robin over them
+constexpr int RED_BLOCKS = 2048;  // fixed grid of the BLAS-1 reductions (deterministic order)
+
+// Logical block index: physical block b runs on XCD b % 8; give XCD x the
+// contiguous range [x*per, (x+1)*per).  Grids are padded to a multiple of 8.
+__device__ __forceinline__ int logical_block() {
+  const int per = gridDim.x / NXCD;
+  const int b = blockIdx.x;
+  return (b % NXCD) * per + b / NXCD;
+}
+
+__device__ __forceinline__ void slot_ijk(const Geom& g, int s, int& I, int& J, int& K) {
+  K = s / g.sz;
+  const int rem = s - K * g.sz;
+  J = rem / g.sy;
+  I = rem - J * g.sy;
+}
+
+// Sum over the block, result valid in thread 0.  Fixed order: deterministic.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sm[BS / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sm[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < BS / 64; ++i) t += sm[i];
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Rows of the operator (Eq. 2 / Section 4).  s = slot of the row, T = storage.
+//   u_x row: (eta/h^2)(6u - 6 lattice neighbours) + (p(I,J,K) - p(I-1,J,K))/h
+//   p row  : -(1/h) sum_a (u_a(plus face) - u_a(minus face)) - gamma p
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ double row_u(const Geom& g, const T* __restrict__ u, const T* __restrict__ p, int s,
+                                        int pstride) {
+  const double lap = 6.0 * (double)u[s] - (double)u[s - 1] - (double)u[s + 1] - (double)u[s - g.sy] -
+                     (double)u[s + g.sy] - (double)u[s - g.sz] - (double)u[s + g.sz];
+  return g.c * lap + ((double)p[s] - (double)p[s - pstride]) * g.inv_h;
+}
+
+template <typename T>
+__device__ __forceinline__ double row_p(const Geom& g, const T* __restrict__ ux, const T* __restrict__ uy,
+                                        const T* __restrict__ uz, const T* __restrict__ p, int s, double gamma) {
+  const double div = ((double)ux[s + 1] - (double)ux[s]) + ((double)uy[s + g.sy] - (double)uy[s]) +
+                     ((double)uz[s + g.sz] - (double)uz[s]);
+  return -div * g.inv_h - gamma * (double)p[s];
+}
+
+enum ApplyMode { AP_APPLY = 0, AP_RESID = 1, AP_APPLY_DOT = 2, AP_RESNORM = 3, AP_BNORM = 4 };
+
+// AP_APPLY:     y = L~ x                  (gamma = penalty, or 0 for L)
+// AP_RESID:     y = b - L~ x
+// AP_APPLY_DOT: y = L~ x, partial[blk] = sum x.y
+// AP_RESNORM:   partial[blk] = sum (b - L~ x)^2 over unknowns (no y)
+// AP_BNORM:     partial[blk] = sum b^2 over unknowns (x unused)
+// Every slot of y is written; slots that are not unknowns get 0.
+template <int MODE, typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
+                                              T* __restrict__ y, double gamma, double* __restrict__ partial) {
+  const int s = logical_block() * BS + threadIdx.x;
+  double acc = 0.0;
+  if (s < g.field) {
+    int I, J, K;
+    slot_ijk(g, s, I, J, K);
+    const int F = g.field;
+    const T* ux = x;
+    const T* uy = x + F;
+    const T* uz = x + 2 * F;
+    const T* p = x + 3 * F;
+    double o[4] = {0.0, 0.0, 0.0, 0.0};
+    bool act[4];
+    act[0] = g.ux_active(I, J, K);
+    act[1] = g.uy_active(I, J, K);
+    act[2] = g.uz_active(I, J, K);
+    act[3] = g.p_active(I, J, K);
+    if (MODE != AP_BNORM) {
+      if (act[0]) o[0] = row_u(g, ux, p, s, 1);
+      if (act[1]) o[1] = row_u(g, uy, p, s, g.sy);
+      if (act[2]) o[2] = row_u(g, uz, p, s, g.sz);
+      if (act[3]) o[3] = row_p(g, ux, uy, uz, p, s, gamma);
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      double v = o[f];
+      if (MODE == AP_RESID || MODE == AP_RESNORM || MODE == AP_BNORM) v = act[f] ? (double)b[f * F + s] - v : 0.0;
+      if (MODE == AP_APPLY || MODE == AP_RESID || MODE == AP_APPLY_DOT) y[f * F + s] = (T)v;
+      if (MODE == AP_APPLY_DOT) acc += (double)x[f * F + s] * (double)(T)v;
+      if (MODE == AP_RESNORM || MODE == AP_BNORM) acc += v * v;
+    }
+  }
+  if (MODE == AP_APPLY_DOT || MODE == AP_RESNORM || MODE == AP_BNORM) {
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Distributive Gauss-Seidel on V2 (Alg. 2, Eq. dist, Eq. ldist, Appendix A).
+// Half-slot threads: thread t handles the slot of colour `colour` in its pair.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool half_slot(const Geom& g, int t, int colour, int& I, int& J, int& K) {
+  const int half = g.sy >> 1;
+  const int row = t / half;
+  if (row >= g.rows) return false;
+  const int m = t - row * half;
+  K = row / (g.ny + 2);
+  J = row - K * (g.ny + 2);
+  I = 2 * m + ((colour + 1 + J + K) & 1);
+  return true;
+}
+
+// Velocity Gauss-Seidel step on the V2 faces of one colour: u += r / (6 eta/h^2).
+// Same-colour faces are not lattice neighbours and p is fixed, so the class
+// updates at once.
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_dgs_u(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
+  int I, J, K;
+  if (!half_slot(g, logical_block() * BS + threadIdx.x, colour, I, J, K)) return;
+  const int s = g.idx(I, J, K);
+  const int F = g.field;
+  T* ux = x;
+  T* uy = x + F;
+  T* uz = x + 2 * F;
+  const T* p = x + 3 * F;
+  const double dinv = 1.0 / (6.0 * g.c);
+  if (g.ux_v2(I, J, K)) ux[s] = (T)((double)ux[s] + ((double)b[s] - row_u(g, ux, p, s, 1)) * dinv);
+  if (g.uy_v2(I, J, K)) uy[s] = (T)((double)uy[s] + ((double)b[F + s] - row_u(g, uy, p, s, g.sy)) * dinv);
+  if (g.uz_v2(I, J, K)) uz[s] = (T)((double)uz[s] + ((double)b[2 * F + s] - row_u(g, uz, p, s, g.sz)) * dinv);
+}
+
+// Pressure step of the forward sweep, part 1, on the V2 cells of one colour:
+// delta = r_j / d_j with d_j = (L~ M)_jj = -6 (1 + gamma eta) / h^2, then move
+// x along the column m_j of M = [[I, -B^T], [0, eta B B^T]] (Eq. dist) as far
+// as the cell itself is concerned: its six faces get -+delta/h and p_j gets
+// 6 eta delta / h^2.  A V2 cell's six faces and six neighbours are all
+// unknowns, so m_j is the full interior column.  delta is kept for part 2.
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_dgs_pf_own(Geom g, T* __restrict__ x, const TB* __restrict__ b,
+                                                   T* __restrict__ dscr, int colour) {
+  int I, J, K;
+  if (!half_slot(g, logical_block() * BS + threadIdx.x, colour, I, J, K)) return;
+  if (!g.p_v2(I, J, K)) return;
+  const int s = g.idx(I, J, K);
+  const int F = g.field;
+  T* ux = x;
+  T* uy = x + F;
+  T* uz = x + 2 * F;
+  T* p = x + 3 * F;
+  const double ih2 = g.inv_h * g.inv_h;
+  const double r = (double)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma);
+  const double delta = r / (-6.0 * (1.0 + g.gamma * g.eta) * ih2);
+  dscr[s] = (T)delta;
+  const double dh = delta * g.inv_h;
+  ux[s] = (T)((double)ux[s] - dh);
+  ux[s + 1] = (T)((double)ux[s + 1] + dh);
+  uy[s] = (T)((double)uy[s] - dh);
+  uy[s + g.sy] = (T)((double)uy[s + g.sy] + dh);
+  uz[s] = (T)((double)uz[s] - dh);
+  uz[s + g.sz] = (T)((double)uz[s + g.sz] + dh);
+  p[s] = (T)((double)p[s] + 6.0 * g.eta * delta * ih2);
+}
+
+// Part 2 on every cell of the other colour (V1 ring cells included): p_k -=
+// (eta/h^2) * sum of the deltas of its V2 neighbours (the off-diagonal
+// entries of eta B B^T in the columns m_j).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_dgs_pf_nbr(Geom g, T* __restrict__ x, const T* __restrict__ dscr,
+                                                   int colour) {
+  int I, J, K;
+  if (!half_slot(g, logical_block() * BS + threadIdx.x, colour ^ 1, I, J, K)) return;
+  if (!g.p_active(I, J, K)) return;
+  const int s = g.idx(I, J, K);
+  T* p = x + 3 * g.field;
+  double sum = 0.0;
+  if (g.p_v2(I - 1, J, K)) sum += (double)dscr[s - 1];
+  if (g.p_v2(I + 1, J, K)) sum += (double)dscr[s + 1];
+  if (g.p_v2(I, J - 1, K)) sum += (double)dscr[s - g.sy];
+  if (g.p_v2(I, J + 1, K)) sum += (double)dscr[s + g.sy];
+  if (g.p_v2(I, J, K - 1)) sum += (double)dscr[s - g.sz];
+  if (g.p_v2(I, J, K + 1)) sum += (double)dscr[s + g.sz];
+  if (sum != 0.0) p[s] = (T)((double)p[s] - g.eta * g.inv_h * g.inv_h * sum);
+}
+
+// Pressure step of the reverse sweep (Gauss-Seidel on M^T L~, Eq. ldist) on
+// the V2 cells of one colour: p_j += (m_j . r) / d_j with
+//   m_j . r = (1/h) sum_a (r(plus face) - r(minus face)) + (eta/h^2)(6 r_j - sum_k r_k)
+// over the six faces and six neighbours, r = b - L~ x.  Only p_j changes, and
+// no residual read here depends on another same-colour pressure.
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
+  int I, J, K;
+  if (!half_slot(g, logical_block() * BS + threadIdx.x, colour, I, J, K)) return;
+  if (!g.p_v2(I, J, K)) return;
+  const int s = g.idx(I, J, K);
+  const int F = g.field;
+  const T* ux = x;
+  const T* uy = x + F;
+  const T* uz = x + 2 * F;
+  T* p = x + 3 * F;
+  const TB* bux = b;
+  const TB* buy = b + F;
+  const TB* buz = b + 2 * F;
+  const TB* bp = b + 3 * F;
+  // sum_a (r(plus face) - r(minus face))
+  double fsum = ((double)bux[s + 1] - row_u(g, ux, p, s + 1, 1)) - ((double)bux[s] - row_u(g, ux, p, s, 1));
+  fsum += ((double)buy[s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy)) - ((double)buy[s] - row_u(g, uy, p, s, g.sy));
+  fsum += ((double)buz[s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz)) - ((double)buz[s] - row_u(g, uz, p, s, g.sz));
+  const double gam = g.gamma;
+  const double rj = (double)bp[s] - row_p(g, ux, uy, uz, p, s, gam);
+  double nsum = (double)bp[s - 1] - row_p(g, ux, uy, uz, p, s - 1, gam);
+  nsum += (double)bp[s + 1] - row_p(g, ux, uy, uz, p, s + 1, gam);
+  nsum += (double)bp[s - g.sy] - row_p(g, ux, uy, uz, p, s - g.sy, gam);
+  nsum += (double)bp[s + g.sy] - row_p(g, ux, uy, uz, p, s + g.sy, gam);
+  nsum += (double)bp[s - g.sz] - row_p(g, ux, uy, uz, p, s - g.sz, gam);
+  nsum += (double)bp[s + g.sz] - row_p(g, ux, uy, uz, p, s + g.sz, gam);
+  const double ih2 = g.inv_h * g.inv_h;
+  const double rt = fsum * g.inv_h + g.eta * ih2 * (6.0 * rj - nsum);
+  p[s] = (T)((double)p[s] + rt / (-6.0 * (1.0 + gam * g.eta) * ih2));
+}
+
+// ---------------------------------------------------------------------------
+// Multiplicative Vanka on V1 (Eq. mv), one colour class.  Each subdomain is
+// one V1 cell with its pressure and active faces; the class takes all its
+// local residuals from the state at the start of the class (part 1), then
+// applies the corrections (part 2).  K^-1 of the local saddle problem comes
+// from a per-level table indexed by the 6-bit face-activity type.
+// ---------------------------------------------------------------------------
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
+                                                    const int* __restrict__ cells, int ncells,
+                                                    const double* __restrict__ kinv, double* __restrict__ delta) {
+  const int c = blockIdx.x * BS + threadIdx.x;
+  if (c >= ncells) return;
+  const int s = cells[c];
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
+  const int F = g.field;
+  const T* ux = x;
+  const T* uy = x + F;
+  const T* uz = x + 2 * F;
+  const T* p = x + 3 * F;
+  double r[7];
+  int type = 0;
+  const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
+  r[0] = a0 ? (double)b[s] - row_u(g, ux, p, s, 1) : 0.0;
+  r[1] = a1 ? (double)b[s + 1] - row_u(g, ux, p, s + 1, 1) : 0.0;
+  r[2] = a2 ? (double)b[F + s] - row_u(g, uy, p, s, g.sy) : 0.0;
+  r[3] = a3 ? (double)b[F + s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy) : 0.0;
+  r[4] = a4 ? (double)b[2 * F + s] - row_u(g, uz, p, s, g.sz) : 0.0;
+  r[5] = a5 ? (double)b[2 * F + s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz) : 0.0;
+  r[6] = (double)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma);
+  type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
+  const double* km = kinv + type * 64;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) acc += km[i * 8 + j] * r[j];
+    delta[c * 8 + i] = acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
+                                                    int ncells, const double* __restrict__ delta) {
+  const int c = blockIdx.x * BS + threadIdx.x;
+  if (c >= ncells) return;
+  const int s = cells[c];
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
+  const int F = g.field;
+  const double* d = delta + c * 8;
+  if (I >= 2) x[s] = (T)((double)x[s] + d[0]);
+  if (I + 1 <= g.nx) x[s + 1] = (T)((double)x[s + 1] + d[1]);
+  if (J >= 2) x[F + s] = (T)((double)x[F + s] + d[2]);
+  if (J + 1 <= g.ny) x[F + s + g.sy] = (T)((double)x[F + s + g.sy] + d[3]);
+  if (K >= 2) x[2 * F + s] = (T)((double)x[2 * F + s] + d[4]);
+  if (K + 1 <= g.nz) x[2 * F + s + g.sz] = (T)((double)x[2 * F + s + g.sz] + d[5]);
+  x[3 * F + s] = (T)((double)x[3 * F + s] + d[6]);
+}
+
+// ---------------------------------------------------------------------------
+// Grid transfer (Section 2): R = P^T / 8 with P bilinear per velocity lattice
+// (weights 1, 1/2 along the face axis; 3/4, 1/4 across) and constant for p.
+// ---------------------------------------------------------------------------
+// Restriction: one thread per coarse slot; reads the fine residual r (zero at
+// every fine slot that is not an unknown).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_restrict(Geom f, Geom c, const T* __restrict__ r, T* __restrict__ bc) {
+  const int s = logical_block() * BS + threadIdx.x;
+  if (s >= c.field) return;
+  int I, J, K;
+  slot_ijk(c, s, I, J, K);
+  const int Ff = f.field, Fc = c.field;
+  const double wf[3] = {0.5, 1.0, 0.5};          // face axis: fine 2I-2, 2I-1, 2I
+  const double wc[4] = {0.25, 0.75, 0.75, 0.25};  // cell axis: fine 2J-2 .. 2J+1
+  // u_x
+  {
+    double acc = 0.0;
+    if (c.ux_active(I, J, K)) {
+      for (int kk = 0; kk < 4; ++kk)
+        for (int jj = 0; jj < 4; ++jj) {
+          const double w = wc[jj] * wc[kk];
+          const int base = f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk);
+          acc += w * (wf[0] * (double)r[base] + wf[1] * (double)r[base + 1] + wf[2] * (double)r[base + 2]);
+        }
+    }
+    bc[s] = (T)(acc * 0.125);
+  }
+  // u_y
+  {
+    double acc = 0.0;
+    if (c.uy_active(I, J, K)) {
+      for (int kk = 0; kk < 4; ++kk)
+        for (int jj = 0; jj < 3; ++jj)
+          for (int ii = 0; ii < 4; ++ii)
+            acc += wc[ii] * wf[jj] * wc[kk] * (double)r[Ff + f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk)];
+    }
+    bc[Fc + s] = (T)(acc * 0.125);
+  }
+  // u_z
+  {
+    double acc = 0.0;
+    if (c.uz_active(I, J, K)) {
+      for (int kk = 0; kk < 3; ++kk)
+        for (int jj = 0; jj < 4; ++jj)
+          for (int ii = 0; ii < 4; ++ii)
+            acc += wc[ii] * wc[jj] * wf[kk] * (double)r[2 * Ff + f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk)];
+    }
+    bc[2 * Fc + s] = (T)(acc * 0.125);
+  }
+  // p
+  {
+    double acc = 0.0;
+    if (c.p_active(I, J, K)) {
+      for (int kk = 0; kk < 2; ++kk)
+        for (int jj = 0; jj < 2; ++jj)
+          for (int ii = 0; ii < 2; ++ii) acc += (double)r[3 * Ff + f.idx(2 * I - 1 + ii, 2 * J - 1 + jj, 2 * K - 1 + kk)];
+    }
+    bc[3 * Fc + s] = (T)(acc * 0.125);
+  }
+}
+
+// 1D prolongation weights on the cell-centre lattice: fine padded index J
+// (1-based cell) takes 3/4 from coarse (j>>1)+1 and 1/4 from the coarse row on
+// its side (j = J-1).
+__device__ __forceinline__ void cell_w(int J, int& n0, int& n1) {
+  const int j = J - 1;
+  n0 = (j >> 1) + 1;
+  n1 = (j & 1) ? n0 + 1 : n0 - 1;
+}
+// ... and on the face lattice along the face axis: fine face i = I-1 takes 1
+// from coarse face i/2 when even, 1/2 from (i-1)/2 and (i+1)/2 when odd.
+__device__ __forceinline__ void face_w(int I, int& n0, int& n1, double& w0, double& w1) {
+  const int i = I - 1;
+  if ((i & 1) == 0) {
+    n0 = i / 2 + 1;
+    n1 = n0;
+    w0 = 1.0;
+    w1 = 0.0;
+  } else {
+    n0 = (i - 1) / 2 + 1;
+    n1 = n0 + 1;
+    w0 = 0.5;
+    w1 = 0.5;
+  }
+}
+
+// x_fine += P e_coarse, one thread per fine slot.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __restrict__ e, T* __restrict__ x) {
+  const int s = logical_block() * BS + threadIdx.x;
+  if (s >= f.field) return;
+  int I, J, K;
+  slot_ijk(f, s, I, J, K);
+  const int Ff = f.field, Fc = c.field;
+  if (f.ux_active(I, J, K)) {
+    int a0, a1, b0, b1, c0, c1;
+    double w0, w1;
+    face_w(I, a0, a1, w0, w1);
+    cell_w(J, b0, b1);
+    cell_w(K, c0, c1);
+    auto at = [&](int i, int j, int k) { return (double)e[c.idx(i, j, k)]; };
+    const double v = w0 * (0.75 * (0.75 * at(a0, b0, c0) + 0.25 * at(a0, b1, c0)) +
+                           0.25 * (0.75 * at(a0, b0, c1) + 0.25 * at(a0, b1, c1))) +
+                     w1 * (0.75 * (0.75 * at(a1, b0, c0) + 0.25 * at(a1, b1, c0)) +
+                           0.25 * (0.75 * at(a1, b0, c1) + 0.25 * at(a1, b1, c1)));
+    x[s] = (T)((double)x[s] + v);
+  }
+  if (f.uy_active(I, J, K)) {
+    int a0, a1, b0, b1, c0, c1;
+    double w0, w1;
+    face_w(J, b0, b1, w0, w1);
+    cell_w(I, a0, a1);
+    cell_w(K, c0, c1);
+    auto at = [&](int i, int j, int k) { return (double)e[Fc + c.idx(i, j, k)]; };
+    const double v = w0 * (0.75 * (0.75 * at(a0, b0, c0) + 0.25 * at(a1, b0, c0)) +
+                           0.25 * (0.75 * at(a0, b0, c1) + 0.25 * at(a1, b0, c1))) +
+                     w1 * (0.75 * (0.75 * at(a0, b1, c0) + 0.25 * at(a1, b1, c0)) +
+                           0.25 * (0.75 * at(a0, b1, c1) + 0.25 * at(a1, b1, c1)));
+    x[Ff + s] = (T)((double)x[Ff + s] + v);
+  }
+  if (f.uz_active(I, J, K)) {
+    int a0, a1, b0, b1, c0, c1;
+    double w0, w1;
+    face_w(K, c0, c1, w0, w1);
+    cell_w(I, a0, a1);
+    cell_w(J, b0, b1);
+    auto at = [&](int i, int j, int k) { return (double)e[2 * Fc + c.idx(i, j, k)]; };
+    const double v = w0 * (0.75 * (0.75 * at(a0, b0, c0) + 0.25 * at(a1, b0, c0)) +
+                           0.25 * (0.75 * at(a0, b1, c0) + 0.25 * at(a1, b1, c0))) +
+                     w1 * (0.75 * (0.75 * at(a0, b0, c1) + 0.25 * at(a1, b0, c1)) +
+                           0.25 * (0.75 * at(a0, b1, c1) + 0.25 * at(a1, b1, c1)));
+    x[2 * Ff + s] = (T)((double)x[2 * Ff + s] + v);
+  }
+  if (f.p_active(I, J, K)) {
+    const int ci = ((I - 1) >> 1) + 1, cj = ((J - 1) >> 1) + 1, ck = ((K - 1) >> 1) + 1;
+    x[3 * Ff + s] = (T)((double)x[3 * Ff + s] + (double)e[3 * Fc + c.idx(ci, cj, ck)]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level: x = L~c^{-1} b with the dense inverse; one wave per row.
+// x must be zero beforehand (its ghost slots stay zero).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BS) void k_coarse_solve(const double* __restrict__ kinv, const int* __restrict__ dof,
+                                                     int n, const T* __restrict__ b, T* __restrict__ x) {
+  const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double acc = 0.0;
+  const double* kr = kinv + (size_t)row * n;
+  for (int j = lane; j < n; j += 64) acc += kr[j] * (double)b[dof[j]];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) x[dof[row]] = (T)acc;
+}
+
+// ---------------------------------------------------------------------------
+// BLAS-1 pieces of SQMR (Alg. 4) on whole state vectors (ghost slots are zero).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BS) void k_fill(T* __restrict__ x, long n, T v) {
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) x[i] = v;
+}
+
+// partial[2*blk] = sum a.a, partial[2*blk+1] = sum a.c
+__global__ __launch_bounds__(BS) void k_dot_aa_ac(const double* __restrict__ a, const double* __restrict__ c, long n,
+                                                  double* __restrict__ partial) {
+  double s0 = 0.0, s1 = 0.0;
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+    const double av = a[i];
+    s0 += av * av;
+    s1 += av * c[i];
+  }
+  const double t0 = block_sum(s0);
+  const double t1 = block_sum(s1);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = t0;
+    partial[2 * blockIdx.x + 1] = t1;
+  }
+}
+
+// sum of p over the cells (for the mean-pressure removal)
+__global__ __launch_bounds__(BS) void k_sum_p(Geom g, const double* __restrict__ x, double* __restrict__ partial) {
+  const int s = logical_block() * BS + threadIdx.x;
+  double v = 0.0;
+  if (s < g.field) {
+    int I, J, K;
+    slot_ijk(g, s, I, J, K);
+    if (g.p_active(I, J, K)) v = x[3 * g.field + s];
+  }
+  const double t = block_sum(v);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(BS) void k_shift_p(Geom g, double* __restrict__ x, double amount) {
+  const int s = logical_block() * BS + threadIdx.x;
+  if (s >= g.field) return;
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
+  if (g.p_active(I, J, K)) x[3 * g.field + s] -= amount;
+}
+
+// Zero the ghost slots of a state vector (the caller's initial guess).
+__global__ __launch_bounds__(BS) void k_clear_ghosts(Geom g, double* __restrict__ x) {
+  const int s = logical_block() * BS + threadIdx.x;
+  if (s >= g.field) return;
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
+  const int F = g.field;
+  if (!g.ux_active(I, J, K)) x[s] = 0.0;
+  if (!g.uy_active(I, J, K)) x[F + s] = 0.0;
+  if (!g.uz_active(I, J, K)) x[2 * F + s] = 0.0;
+  if (!g.p_active(I, J, K)) x[3 * F + s] = 0.0;
+}
+
+// s -= a * t
+__global__ __launch_bounds__(BS) void k_axpy_neg(double* __restrict__ s, const double* __restrict__ t, long n,
+                                                 double a) {
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) s[i] -= a * t[i];
+}
+
+// d = cd * d + cq * q;  x += d
+__global__ __launch_bounds__(BS) void k_update_dx(double* __restrict__ d, const double* __restrict__ q,
+                                                  double* __restrict__ x, long n, double cd, double cq) {
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+    const double dv = cd * d[i] + cq * q[i];
+    d[i] = dv;
+    x[i] += dv;
+  }
+}
+
+// q = t + beta * q
+__global__ __launch_bounds__(BS) void k_xpby(double* __restrict__ q, const double* __restrict__ t, long n,
+                                             double bt) {
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) q[i] = t[i] + bt * q[i];
+}
+
+// out[k] = sum_b partial[b*stride + k], fixed order, single block.
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int nblk, int stride,
+                                                 double* __restrict__ out) {
+  __shared__ double sm[16];
+  for (int k = 0; k < stride; ++k) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 1024) v += partial[(long)b * stride + k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sm[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < 16; ++i) t += sm[i];
+      out[k] = t;
+    }
+  }
+}
+
+}  // namespace sg

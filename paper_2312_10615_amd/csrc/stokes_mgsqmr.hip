@@ -1,0 +1,681 @@
+// MG-SQMR driver and C ABI (include/stokes_mgsqmr.h) for gfx950.
+//
+// Host code sequences the kernels of kernels.hpp on the caller's stream:
+//   V-cycle (Alg. 1) -> SMOOTH (Alg. 3) -> symmetric Vanka / symmetric DGS
+//   SQMR (Alg. 4)    -> operator apply + fused reductions, BLAS-1 updates
+// The SQMR scalars are reduced on the device in a fixed order and read back
+// once per reduction, so results are bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/stokes_mgsqmr.h"
+#include "host_tables.hpp"
+#include "kernels.hpp"
+
+using namespace sg;
+
+namespace {
+
+struct Level {
+  Geom g;
+  double* b = nullptr;   // right-hand side (levels >= 1; level 0 uses the caller's)
+  double* x = nullptr;   // iterate (levels >= 1)
+  double* r = nullptr;   // residual scratch (all but the coarsest)
+  double* dscr = nullptr;  // DGS pressure-step deltas (p field)
+  int* vcells[8] = {};
+  int nv[8] = {};
+  double* kinv = nullptr;  // 64 x 8 x 8 Vanka local inverses
+};
+
+struct Carver {
+  char* base;
+  size_t used = 0, cap;
+  bool dry;
+  Carver(void* b, size_t c, bool d) : base((char*)b), cap(c), dry(d) {}
+  template <typename T>
+  T* take(size_t count) {
+    used = (used + 255) & ~size_t(255);
+    T* p = dry ? nullptr : (T*)(base + used);
+    used += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct stokes_ctx {
+  stokes_params prm{};
+  int L = 0;
+  std::vector<Level> lev;
+  hipStream_t stream = nullptr;
+  long total = 0;  // elements of a finest-level state vector
+  // SQMR vectors
+  double *s = nullptr, *t = nullptr, *q = nullptr, *d = nullptr;
+  // reductions
+  double* partial = nullptr;
+  int npartial = 0;
+  double* dscal = nullptr;   // device scalars: reduction results
+  double* hscal = nullptr;   // pinned host mirror
+  // coarsest level
+  double* cinv = nullptr;
+  int* cdof = nullptr;
+  int nc = 0;
+  // Vanka delta scratch (max colour count x 8)
+  double* vdelta = nullptr;
+  // kernel timing (diagnostics)
+  int prof_class = STOKES_KC_OFF, prof_level = -1;
+  struct Pending { int k, l; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<double> prof_ms;     // [class * 32 + level]
+  std::vector<long> prof_n;
+  bool prof_on(int k, int l) const {
+    return prof_class != STOKES_KC_OFF && (prof_class == STOKES_KC_ALL || prof_class == k) &&
+           (prof_level < 0 || prof_level == l);
+  }
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
+namespace {
+
+// Records HIP events around one launch when that kernel class/level is selected.
+struct Prof {
+  stokes_ctx* c;
+  int k, l;
+  hipEvent_t a = nullptr;
+  Prof(stokes_ctx* c_, int k_, int l_) : c(c_), k(k_), l(l_) {
+    if (c->prof_on(k, l)) {
+      a = c->event();
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Prof() {
+    if (!a) return;
+    hipEvent_t b = c->event();
+    if (!b) {
+      c->pool.push_back(a);
+      return;
+    }
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({k, l, a, b});
+  }
+};
+
+// Fold finished event pairs into the accumulators (waits for them).
+void prof_collect(stokes_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      const int slot = p.k * 32 + (p.l < 32 ? p.l : 31);
+      c->prof_ms[slot] += ms;
+      c->prof_n[slot] += 1;
+    }
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+int grid_for(long slots) {
+  long nb = (slots + BS - 1) / BS;
+  nb = (nb + NXCD - 1) / NXCD * NXCD;
+  return (int)nb;
+}
+
+int half_grid(const Geom& g) { return grid_for((long)g.rows * (g.sy / 2)); }
+
+#define HIPCHK(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return STOKES_EDEVICE;      \
+  } while (0)
+
+long coarse_dofs(const Geom& g) {
+  return (long)(g.nx - 1) * g.ny * g.nz + (long)g.nx * (g.ny - 1) * g.nz + (long)g.nx * g.ny * (g.nz - 1) +
+         (long)g.nx * g.ny * g.nz;
+}
+
+int validate(const stokes_params* p, int* levels_out) {
+  if (!p) return STOKES_EINVAL;
+  if (p->nx < 2 || p->ny < 2 || p->nz < 2) return STOKES_EINVAL;
+  if (!(p->h > 0) || !(p->eta > 0) || !(p->gamma >= 0) || !std::isfinite(p->h) || !std::isfinite(p->eta) ||
+      !std::isfinite(p->gamma))
+    return STOKES_EINVAL;
+  if (p->nu < 1 || p->n_boundary < 1) return STOKES_EINVAL;
+  if (p->smoother != STOKES_SMOOTHER_SPLIT && p->smoother != STOKES_SMOOTHER_SYMMETRIC) return STOKES_EINVAL;
+  if (p->smoother == STOKES_SMOOTHER_SYMMETRIC && (p->nu % 2)) return STOKES_EINVAL;
+  if (p->vcycle_precision != 64) return STOKES_EINVAL;
+  int L = p->levels;
+  if (L == 0) L = count_levels(p->nx, p->ny, p->nz, 4);
+  if (L < 1 || L > count_levels(p->nx, p->ny, p->nz, 2)) return STOKES_EINVAL;
+  // 32-bit slot arithmetic inside the kernels
+  Geom g0 = make_geom(p->nx, p->ny, p->nz, p->h, p->eta, p->gamma, 0);
+  if ((long)g0.field * 4 >= (1L << 31) - 1024) return STOKES_EINVAL;
+  // dense coarsest solve: keep its inverse modest
+  Geom gc = make_geom(p->nx, p->ny, p->nz, p->h, p->eta, p->gamma, L - 1);
+  if (coarse_dofs(gc) > 2500) return STOKES_EINVAL;
+  *levels_out = L;
+  return STOKES_OK;
+}
+
+// Lay out (or size, when dry) everything the context keeps in the workspace.
+void carve(stokes_ctx* c, Carver& cv, int L) {
+  const stokes_params& p = c->prm;
+  c->lev.assign(L, Level{});
+  for (int l = 0; l < L; ++l) c->lev[l].g = make_geom(p.nx, p.ny, p.nz, p.h, p.eta, p.gamma, l);
+  const Geom& g0 = c->lev[0].g;
+  c->total = 4L * g0.field;
+  c->s = cv.take<double>(c->total);
+  c->t = cv.take<double>(c->total);
+  c->q = cv.take<double>(c->total);
+  c->d = cv.take<double>(c->total);
+  long maxblk = RED_BLOCKS;
+  for (int l = 0; l < L; ++l) maxblk = std::max<long>(maxblk, grid_for(c->lev[l].g.field));
+  c->npartial = (int)maxblk;
+  c->partial = cv.take<double>(2 * maxblk);
+  c->dscal = cv.take<double>(16);
+  long vmax = 0;
+  for (int l = 0; l < L; ++l) {
+    Level& lv = c->lev[l];
+    const long tot = 4L * lv.g.field;
+    if (l > 0) {
+      lv.b = cv.take<double>(tot);
+      lv.x = cv.take<double>(tot);
+    }
+    if (l < L - 1) {
+      lv.r = cv.take<double>(tot);
+      lv.dscr = cv.take<double>(lv.g.field);
+      lv.kinv = cv.take<double>(64 * 64);
+      std::vector<int> cells[8];
+      vanka_cells(lv.g, cells);
+      for (int k = 0; k < 8; ++k) {
+        lv.nv[k] = (int)cells[k].size();
+        lv.vcells[k] = cv.take<int>(std::max<size_t>(cells[k].size(), 1));
+        vmax = std::max<long>(vmax, lv.nv[k]);
+      }
+    }
+  }
+  c->vdelta = cv.take<double>(8 * std::max<long>(vmax, 1));
+  const Geom& gc = c->lev[L - 1].g;
+  c->nc = (int)coarse_dofs(gc);
+  c->cinv = cv.take<double>((size_t)c->nc * c->nc);
+  c->cdof = cv.take<int>(c->nc);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle pieces
+// ---------------------------------------------------------------------------
+void vanka_symmetric(stokes_ctx* c, int l, double* x, const double* b) {
+  Level& lv = c->lev[l];
+  for (int pass = 0; pass < 16; ++pass) {
+    const int k = pass < 8 ? pass : 15 - pass;
+    const int n = lv.nv[k];
+    if (n == 0) continue;
+    const int nb = (n + BS - 1) / BS;
+    {
+      Prof pf(c, STOKES_KC_VANKA_DELTA, l);
+      k_vanka_delta<double, double><<<nb, BS, 0, c->stream>>>(lv.g, x, b, lv.vcells[k], n, lv.kinv, c->vdelta);
+    }
+    {
+      Prof pf(c, STOKES_KC_VANKA_APPLY, l);
+      k_vanka_apply<double><<<nb, BS, 0, c->stream>>>(lv.g, x, lv.vcells[k], n, c->vdelta);
+    }
+  }
+}
+
+// Forward DGS sweep on L~ M (Alg. 2, Eq. dist) over the V2 unknowns:
+// velocities red, black; pressures red, black.
+void dgs_forward(stokes_ctx* c, int l, double* x, const double* b) {
+  Level& lv = c->lev[l];
+  const Geom& g = lv.g;
+  const int hg = half_grid(g);
+  for (int col = 0; col < 2; ++col) {
+    Prof pf(c, STOKES_KC_DGS_U, l);
+    k_dgs_u<double, double><<<hg, BS, 0, c->stream>>>(g, x, b, col);
+  }
+  for (int col = 0; col < 2; ++col) {
+    {
+      Prof pf(c, STOKES_KC_DGS_PF_OWN, l);
+      k_dgs_pf_own<double, double><<<hg, BS, 0, c->stream>>>(g, x, b, lv.dscr, col);
+    }
+    Prof pf(c, STOKES_KC_DGS_PF_NBR, l);
+    k_dgs_pf_nbr<double><<<hg, BS, 0, c->stream>>>(g, x, lv.dscr, col);
+  }
+}
+
+// Reverse sweep: Gauss-Seidel on M^T L~ (Eq. ldist) in exactly the reverse
+// order: pressures black, red; velocities black, red.
+void dgs_reverse(stokes_ctx* c, int l, double* x, const double* b) {
+  Level& lv = c->lev[l];
+  const Geom& g = lv.g;
+  const int hg = half_grid(g);
+  for (int col = 1; col >= 0; --col) {
+    Prof pf(c, STOKES_KC_DGS_PR, l);
+    k_dgs_pr<double, double><<<hg, BS, 0, c->stream>>>(g, x, b, col);
+  }
+  for (int col = 1; col >= 0; --col) {
+    Prof pf(c, STOKES_KC_DGS_U, l);
+    k_dgs_u<double, double><<<hg, BS, 0, c->stream>>>(g, x, b, col);
+  }
+}
+
+enum Interior { INT_SYMMETRIC, INT_REVERSE, INT_FORWARD };
+
+// Alg. 3: symmetric Vanka on V1, interior smoother on V2, symmetric Vanka on V1.
+void smooth(stokes_ctx* c, int l, double* x, const double* b, Interior kind, int sweeps) {
+  for (int i = 0; i < c->prm.n_boundary; ++i) vanka_symmetric(c, l, x, b);
+  for (int i = 0; i < sweeps; ++i) {
+    if (kind != INT_FORWARD) {
+      if (kind == INT_SYMMETRIC) dgs_forward(c, l, x, b);
+      dgs_reverse(c, l, x, b);
+    } else {
+      dgs_forward(c, l, x, b);
+    }
+  }
+  for (int i = 0; i < c->prm.n_boundary; ++i) vanka_symmetric(c, l, x, b);
+}
+
+void presmooth(stokes_ctx* c, int l, double* x, const double* b) {
+  if (c->prm.smoother == STOKES_SMOOTHER_SYMMETRIC) {
+    for (int i = 0; i < c->prm.nu / 2; ++i) smooth(c, l, x, b, INT_SYMMETRIC, 1);
+  } else {
+    smooth(c, l, x, b, INT_REVERSE, c->prm.nu);
+  }
+}
+
+void postsmooth(stokes_ctx* c, int l, double* x, const double* b) {
+  if (c->prm.smoother == STOKES_SMOOTHER_SYMMETRIC) {
+    for (int i = 0; i < c->prm.nu / 2; ++i) smooth(c, l, x, b, INT_SYMMETRIC, 1);
+  } else {
+    smooth(c, l, x, b, INT_FORWARD, c->prm.nu);
+  }
+}
+
+void fill_zero(stokes_ctx* c, double* x, long n, int level = 0) {
+  Prof pf(c, STOKES_KC_BLAS, level);
+  k_fill<double><<<RED_BLOCKS, BS, 0, c->stream>>>(x, n, 0.0);
+}
+
+// x = V-CYCLE(L~, b, 0, L - l)
+void vcycle(stokes_ctx* c, int l, const double* b, double* x) {
+  Level& lv = c->lev[l];
+  const Geom& g = lv.g;
+  fill_zero(c, x, 4L * g.field, l);
+  if (l == c->L - 1) {
+    const int nb = (c->nc + (BS / 64) - 1) / (BS / 64);
+    Prof pf(c, STOKES_KC_COARSE, l);
+    k_coarse_solve<double><<<nb, BS, 0, c->stream>>>(c->cinv, c->cdof, c->nc, b, x);
+    return;
+  }
+  presmooth(c, l, x, b);
+  {
+    Prof pf(c, STOKES_KC_APPLY, l);
+    k_apply<AP_RESID, double, double><<<grid_for(g.field), BS, 0, c->stream>>>(g, x, b, lv.r, g.gamma, nullptr);
+  }
+  Level& cl = c->lev[l + 1];
+  {
+    Prof pf(c, STOKES_KC_RESTRICT, l);
+    k_restrict<double><<<grid_for(cl.g.field), BS, 0, c->stream>>>(g, cl.g, lv.r, cl.b);
+  }
+  vcycle(c, l + 1, cl.b, cl.x);
+  {
+    Prof pf(c, STOKES_KC_PROLONG, l);
+    k_prolong_add<double><<<grid_for(g.field), BS, 0, c->stream>>>(g, cl.g, cl.x, x);
+  }
+  postsmooth(c, l, x, b);
+}
+
+// Device scalar reduction of `nblk` partials (stride values each) into
+// dscal[0..stride), copied to the pinned host mirror and waited for.
+int reduce_to_host(stokes_ctx* c, int nblk, int stride) {
+  {
+    Prof pf(c, STOKES_KC_BLAS, 0);
+    k_reduce<<<1, 1024, 0, c->stream>>>(c->partial, nblk, stride, c->dscal);
+  }
+  HIPCHK(hipMemcpyAsync(c->hscal, c->dscal, sizeof(double) * stride, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (!c->pending.empty()) prof_collect(c);
+  return STOKES_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int stokes_default_params(int32_t nx, int32_t ny, int32_t nz, double h, stokes_params* p) {
+  if (!p) return STOKES_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = nz;
+  p->h = h;
+  p->eta = 1.0;
+  p->gamma = 1e-3;
+  p->levels = 0;
+  p->nu = 2;
+  p->n_boundary = 1;
+  p->vcycle_precision = 64;
+  p->smoother = STOKES_SMOOTHER_SPLIT;
+  p->flags = STOKES_FLAG_REMOVE_MEAN;
+  return STOKES_OK;
+}
+
+int stokes_workspace_bytes(const stokes_params* p, size_t* bytes) {
+  int L = 0;
+  const int st = validate(p, &L);
+  if (st != STOKES_OK) return st;
+  if (!bytes) return STOKES_EINVAL;
+  stokes_ctx tmp;
+  tmp.prm = *p;
+  Carver cv(nullptr, 0, true);
+  carve(&tmp, cv, L);
+  *bytes = (cv.used + 255) & ~size_t(255);
+  return STOKES_OK;
+}
+
+int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hip_stream, stokes_ctx** out) {
+  if (!out) return STOKES_EINVAL;
+  *out = nullptr;
+  int L = 0;
+  int st = validate(p, &L);
+  if (st != STOKES_OK) return st;
+  size_t need = 0;
+  stokes_workspace_bytes(p, &need);
+  if (!workspace || bytes < need || ((uintptr_t)workspace & 255)) return STOKES_EINVAL;
+  stokes_ctx* c = new (std::nothrow) stokes_ctx();
+  if (!c) return STOKES_EINVAL;
+  c->prm = *p;
+  c->L = L;
+  c->stream = (hipStream_t)hip_stream;
+  Carver cv(workspace, bytes, false);
+  carve(c, cv, L);
+  if (hipHostMalloc((void**)&c->hscal, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return STOKES_EDEVICE;
+  }
+  // Host tables, uploaded with synchronous waits so the host buffers can go.
+  auto fail = [&](int code) {
+    stokes_destroy(c);
+    return code;
+  };
+  for (int l = 0; l < L - 1; ++l) {
+    Level& lv = c->lev[l];
+    std::vector<double> kinv;
+    if (!vanka_inverses(lv.g, kinv)) return fail(STOKES_EINVAL);
+    if (hipMemcpyAsync(lv.kinv, kinv.data(), kinv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
+        hipSuccess)
+      return fail(STOKES_EDEVICE);
+    std::vector<int> cells[8];
+    vanka_cells(lv.g, cells);
+    for (int k = 0; k < 8; ++k) {
+      if (cells[k].empty()) continue;
+      if (hipMemcpyAsync(lv.vcells[k], cells[k].data(), cells[k].size() * sizeof(int), hipMemcpyHostToDevice,
+                         c->stream) != hipSuccess)
+        return fail(STOKES_EDEVICE);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(STOKES_EDEVICE);
+  }
+  {
+    std::vector<int> dof;
+    std::vector<double> inv;
+    if (!coarse_inverse(c->lev[L - 1].g, dof, inv) || (int)dof.size() != c->nc) return fail(STOKES_EINVAL);
+    if (hipMemcpyAsync(c->cinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(c->cdof, dof.data(), dof.size() * sizeof(int), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return fail(STOKES_EDEVICE);
+  }
+  // workspace vectors start from zero (their ghost slots are never written otherwise)
+  for (int l = 1; l < L; ++l) {
+    fill_zero(c, c->lev[l].b, 4L * c->lev[l].g.field);
+    fill_zero(c, c->lev[l].x, 4L * c->lev[l].g.field);
+  }
+  fill_zero(c, c->s, c->total);
+  fill_zero(c, c->t, c->total);
+  fill_zero(c, c->q, c->total);
+  fill_zero(c, c->d, c->total);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) return fail(STOKES_EDEVICE);
+  *out = c;
+  return STOKES_OK;
+}
+
+int stokes_layout(const stokes_ctx* c, stokes_layout_t* out) {
+  if (!c || !out) return STOKES_EINVAL;
+  const Geom& g = c->lev[0].g;
+  out->nx = g.nx;
+  out->ny = g.ny;
+  out->nz = g.nz;
+  out->sy = g.sy;
+  out->sz = g.sz;
+  for (int f = 0; f < 4; ++f) out->off[f] = (int64_t)f * g.field;
+  out->field = g.field;
+  out->total = c->total;
+  out->n_dofs = coarse_dofs(g);
+  out->levels = c->L;
+  return STOKES_OK;
+}
+
+int stokes_apply(stokes_ctx* c, const double* x, double* y, int32_t penalized) {
+  if (!c || !x || !y || x == y) return STOKES_EINVAL;
+  const Geom& g = c->lev[0].g;
+  {
+    Prof pf(c, STOKES_KC_APPLY, 0);
+    k_apply<AP_APPLY, double, double><<<grid_for(g.field), BS, 0, c->stream>>>(g, x, (const double*)nullptr, y,
+                                                                               penalized ? g.gamma : 0.0, nullptr);
+  }
+  return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
+}
+
+int stokes_vcycle(stokes_ctx* c, const double* s, double* t) {
+  if (!c || !s || !t || s == t) return STOKES_EINVAL;
+  vcycle(c, 0, s, t);
+  return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
+}
+
+int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t maxit, stokes_info* info) {
+  if (!c || !b || !x || b == x || maxit < 0 || !(rtol >= 0)) return STOKES_EINVAL;
+  const Geom& g = c->lev[0].g;
+  const long n = c->total;
+  const int gf = grid_for(g.field);
+  auto fill_info = [&](int iters, int status, double relres, double bn) {
+    if (info) {
+      info->iters = iters;
+      info->status = status;
+      info->relres = relres;
+      info->bnorm = bn;
+    }
+    return status;
+  };
+  {
+    Prof pf(c, STOKES_KC_BLAS, 0);
+    k_clear_ghosts<<<gf, BS, 0, c->stream>>>(g, x);
+  }
+  // ||b|| over the unknowns
+  {
+    Prof pf(c, STOKES_KC_APPLY, 0);
+    k_apply<AP_BNORM, double, double><<<gf, BS, 0, c->stream>>>(g, (const double*)nullptr, b, (double*)nullptr, 0.0,
+                                                                c->partial);
+  }
+  if (reduce_to_host(c, gf, 1) != STOKES_OK) return fill_info(0, STOKES_EDEVICE, NAN, NAN);
+  const double bnorm = std::sqrt(c->hscal[0]);
+  if (!std::isfinite(bnorm)) return fill_info(0, STOKES_ENONFINITE, NAN, bnorm);
+  if (bnorm == 0.0) {
+    fill_zero(c, x, n);
+    if (info && info->history) info->history[0] = 0.0;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fill_info(0, STOKES_EDEVICE, 0.0, 0.0);
+    return fill_info(0, STOKES_OK, 0.0, 0.0);
+  }
+  // s0 = b - L x0, with ||s0||^2
+  {
+    Prof pf(c, STOKES_KC_APPLY, 0);
+    k_apply<AP_RESID, double, double><<<gf, BS, 0, c->stream>>>(g, x, b, c->s, 0.0, nullptr);
+  }
+  {
+    Prof pf(c, STOKES_KC_APPLY, 0);
+    k_apply<AP_RESNORM, double, double><<<gf, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
+  }
+  if (reduce_to_host(c, gf, 1) != STOKES_OK) return fill_info(0, STOKES_EDEVICE, NAN, bnorm);
+  double relres = std::sqrt(c->hscal[0]) / bnorm;
+  if (info && info->history) info->history[0] = relres;
+  auto finish = [&](int iters, int status) {
+    if (status == STOKES_OK && (c->prm.flags & STOKES_FLAG_REMOVE_MEAN)) {
+      {
+        Prof pf(c, STOKES_KC_BLAS, 0);
+        k_sum_p<<<gf, BS, 0, c->stream>>>(g, x, c->partial);
+      }
+      {
+        Prof pf(c, STOKES_KC_BLAS, 0);
+        k_reduce<<<1, 1024, 0, c->stream>>>(c->partial, gf, 1, c->dscal);
+      }
+      const double ncell = (double)g.nx * g.ny * g.nz;
+      // mean = sum / ncell, computed on the host to keep one rounding
+      if (hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+          hipStreamSynchronize(c->stream) != hipSuccess)
+        return fill_info(iters, STOKES_EDEVICE, relres, bnorm);
+      const double mean = c->hscal[0] / ncell;
+      {
+        Prof pf(c, STOKES_KC_BLAS, 0);
+        k_shift_p<<<gf, BS, 0, c->stream>>>(g, x, mean);
+      }
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+      return fill_info(iters, STOKES_EDEVICE, relres, bnorm);
+    return fill_info(iters, status, relres, bnorm);
+  };
+  if (!std::isfinite(relres)) return finish(0, STOKES_ENONFINITE);
+  if (relres <= rtol) return finish(0, STOKES_OK);
+  // t = W s0; q0 = t; tau0 = ||t||; rho0 = s0 . q0; d = 0
+  vcycle(c, 0, c->s, c->t);
+  {
+    Prof pf(c, STOKES_KC_BLAS, 0);
+    k_dot_aa_ac<<<RED_BLOCKS, BS, 0, c->stream>>>(c->t, c->s, n, c->partial);
+  }
+  if (reduce_to_host(c, RED_BLOCKS, 2) != STOKES_OK) return finish(0, STOKES_EDEVICE);
+  double tau = std::sqrt(c->hscal[0]);
+  double rho = c->hscal[1];
+  HIPCHK(hipMemcpyAsync(c->q, c->t, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  fill_zero(c, c->d, n);
+  double nu_prev = 0.0;
+  for (int j = 1; j <= maxit; ++j) {
+    // t = L q, sigma = q . t
+    {
+      Prof pf(c, STOKES_KC_APPLY, 0);
+      k_apply<AP_APPLY_DOT, double, double><<<gf, BS, 0, c->stream>>>(g, c->q, (const double*)nullptr, c->t, 0.0,
+                                                                      c->partial);
+    }
+    if (reduce_to_host(c, gf, 1) != STOKES_OK) return finish(j - 1, STOKES_EDEVICE);
+    const double sigma = c->hscal[0];
+    if (!std::isfinite(sigma)) return finish(j - 1, STOKES_ENONFINITE);
+    if (sigma == 0.0) return finish(j - 1, STOKES_EBREAKDOWN);
+    const double alpha = rho / sigma;
+    {
+      Prof pf(c, STOKES_KC_BLAS, 0);
+      k_axpy_neg<<<RED_BLOCKS, BS, 0, c->stream>>>(c->s, c->t, n, alpha);
+    }
+    // t = W s
+    vcycle(c, 0, c->s, c->t);
+    {
+      Prof pf(c, STOKES_KC_BLAS, 0);
+      k_dot_aa_ac<<<RED_BLOCKS, BS, 0, c->stream>>>(c->t, c->s, n, c->partial);
+    }
+    if (reduce_to_host(c, RED_BLOCKS, 2) != STOKES_OK) return finish(j - 1, STOKES_EDEVICE);
+    const double tnorm = std::sqrt(c->hscal[0]);
+    const double rho_new = c->hscal[1];
+    const double nu = tnorm / tau;
+    const double cc = 1.0 / std::sqrt(1.0 + nu * nu);
+    tau = tau * nu * cc;
+    {
+      Prof pf(c, STOKES_KC_BLAS, 0);
+      k_update_dx<<<RED_BLOCKS, BS, 0, c->stream>>>(c->d, c->q, x, n, cc * cc * nu_prev * nu_prev, cc * cc * alpha);
+    }
+    nu_prev = nu;
+    // true residual
+    {
+      Prof pf(c, STOKES_KC_APPLY, 0);
+      k_apply<AP_RESNORM, double, double><<<gf, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
+    }
+    if (reduce_to_host(c, gf, 1) != STOKES_OK) return finish(j, STOKES_EDEVICE);
+    relres = std::sqrt(c->hscal[0]) / bnorm;
+    if (info && info->history) info->history[j] = relres;
+    if (!std::isfinite(relres) || !std::isfinite(tnorm)) return finish(j, STOKES_ENONFINITE);
+    if (relres <= rtol) return finish(j, STOKES_OK);
+    if (rho == 0.0) return finish(j, STOKES_EBREAKDOWN);
+    const double beta = rho_new / rho;
+    {
+      Prof pf(c, STOKES_KC_BLAS, 0);
+      k_xpby<<<RED_BLOCKS, BS, 0, c->stream>>>(c->q, c->t, n, beta);
+    }
+    rho = rho_new;
+  }
+  return finish(maxit, STOKES_ENOCONV);
+}
+
+int stokes_profile(stokes_ctx* c, int32_t kernel_class, int32_t level) {
+  if (!c || kernel_class < STOKES_KC_OFF || kernel_class >= STOKES_KC_COUNT || level >= 32) return STOKES_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return STOKES_EDEVICE;
+  prof_collect(c);
+  c->prof_class = kernel_class;
+  c->prof_level = level;
+  c->prof_ms.assign(STOKES_KC_COUNT * 32, 0.0);
+  c->prof_n.assign(STOKES_KC_COUNT * 32, 0);
+  return STOKES_OK;
+}
+
+int stokes_profile_read(stokes_ctx* c, int32_t kernel_class, int32_t level, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches || kernel_class < 0 || kernel_class >= STOKES_KC_COUNT || level >= 32)
+    return STOKES_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return STOKES_EDEVICE;
+  prof_collect(c);
+  double ms = 0.0;
+  long n = 0;
+  if (!c->prof_ms.empty()) {
+    for (int l = 0; l < 32; ++l) {
+      if (level >= 0 && l != level) continue;
+      ms += c->prof_ms[kernel_class * 32 + l];
+      n += c->prof_n[kernel_class * 32 + l];
+    }
+  }
+  *total_ms = ms;
+  *launches = n;
+  return STOKES_OK;
+}
+
+void stokes_destroy(stokes_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  prof_collect(c);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  delete c;
+}
+
+const char* stokes_strerror(int status) {
+  switch (status) {
+    case STOKES_OK: return "ok";
+    case STOKES_EINVAL: return "invalid argument (dimensions, levels, pointer, alignment or workspace size)";
+    case STOKES_ENOCONV: return "not converged within maxit iterations";
+    case STOKES_EBREAKDOWN: return "SQMR breakdown (sigma or rho is zero)";
+    case STOKES_ENONFINITE: return "non-finite value in the iteration";
+    case STOKES_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+"""Python binding of the gfx950 MG-SQMR Stokes library (include/stokes_mgsqmr.h).
+
+Functions with the C names marshal arguments only; every step of the solve
+runs in the HIP library.  `StokesSolver` adds the torch plumbing: device
+workspace, state vectors, and packing between the natural MAC arrays and the
+library's padded layout.  There is no CPU fallback: if the shared library is
+missing this module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libstokes_mgsqmr.so")
+
+STOKES_OK, STOKES_EINVAL, STOKES_ENOCONV, STOKES_EBREAKDOWN, STOKES_ENONFINITE, STOKES_EDEVICE = range(6)
+STOKES_FLAG_REMOVE_MEAN = 1
+SMOOTHERS = {"split": 0, "symmetric": 1}
+STATUS_NAMES = {0: "ok", 1: "einval", 2: "enoconv", 3: "ebreakdown", 4: "enonfinite", 5: "edevice"}
+
+
+class StokesParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double), ("eta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("levels", ctypes.c_int32), ("nu", ctypes.c_int32), ("n_boundary", ctypes.c_int32),
+                ("vcycle_precision", ctypes.c_int32), ("smoother", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class StokesLayout(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("sy", ctypes.c_int64), ("sz", ctypes.c_int64), ("off", ctypes.c_int64 * 4),
+                ("field", ctypes.c_int64), ("total", ctypes.c_int64), ("n_dofs", ctypes.c_int64),
+                ("levels", ctypes.c_int32)]
+
+
+class StokesInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("bnorm", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double))]
+
+
+EXPORTS = ("stokes_default_params", "stokes_workspace_bytes", "stokes_setup", "stokes_layout", "stokes_apply",
+           "stokes_vcycle", "stokes_solve", "stokes_profile", "stokes_profile_read", "stokes_destroy",
+           "stokes_strerror")
+
+# kernel classes of stokes_profile()
+KC = {"apply": 0, "dgs_u": 1, "dgs_pf_own": 2, "dgs_pf_nbr": 3, "dgs_pr": 4, "vanka_delta": 5, "vanka_apply": 6,
+      "restrict": 7, "prolong": 8, "coarse": 9, "blas": 10}
+KC_ALL, KC_OFF = -1, -2
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the shared library (no GPU needed) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: build it with `python -m paper_2312_10615_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, vp, i32, f64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.stokes_default_params.argtypes = [i32, i32, i32, f64, P(StokesParams)]
+    lib.stokes_workspace_bytes.argtypes = [P(StokesParams), P(ctypes.c_size_t)]
+    lib.stokes_setup.argtypes = [P(StokesParams), vp, ctypes.c_size_t, vp, P(vp)]
+    lib.stokes_layout.argtypes = [vp, P(StokesLayout)]
+    lib.stokes_apply.argtypes = [vp, vp, vp, i32]
+    lib.stokes_vcycle.argtypes = [vp, vp, vp]
+    lib.stokes_solve.argtypes = [vp, vp, vp, f64, i32, P(StokesInfo)]
+    lib.stokes_profile.argtypes = [vp, i32, i32]
+    lib.stokes_profile_read.argtypes = [vp, i32, i32, P(ctypes.c_double), P(ctypes.c_int64)]
+    lib.stokes_destroy.argtypes = [vp]
+    lib.stokes_destroy.restype = None
+    lib.stokes_strerror.argtypes = [ctypes.c_int]
+    lib.stokes_strerror.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("stokes_destroy", "stokes_strerror"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class StokesError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {stokes_strerror(code)} (status {code})")
+        self.code = code
+
+
+def _check(code, where):
+    if code != STOKES_OK:
+        raise StokesError(code, where)
+
+
+# --- C-named wrappers ---------------------------------------------------------
+
+def stokes_default_params(nx, ny, nz, h) -> StokesParams:
+    p = StokesParams()
+    _check(load_library().stokes_default_params(nx, ny, nz, h, ctypes.byref(p)), "stokes_default_params")
+    return p
+
+
+def stokes_workspace_bytes(params: StokesParams) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().stokes_workspace_bytes(ctypes.byref(params), ctypes.byref(n)), "stokes_workspace_bytes")
+    return int(n.value)
+
+
+def stokes_setup(params: StokesParams, workspace_ptr: int, nbytes: int, stream_ptr: int):
+    ctx = ctypes.c_void_p()
+    _check(load_library().stokes_setup(ctypes.byref(params), ctypes.c_void_p(workspace_ptr), nbytes,
+                                       ctypes.c_void_p(stream_ptr), ctypes.byref(ctx)), "stokes_setup")
+    return ctx
+
+
+def stokes_layout(ctx) -> StokesLayout:
+    lay = StokesLayout()
+    _check(load_library().stokes_layout(ctx, ctypes.byref(lay)), "stokes_layout")
+    return lay
+
+
+def stokes_apply(ctx, x_ptr: int, y_ptr: int, penalized: int = 0) -> int:
+    return load_library().stokes_apply(ctx, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr), int(penalized))
+
+
+def stokes_vcycle(ctx, s_ptr: int, t_ptr: int) -> int:
+    return load_library().stokes_vcycle(ctx, ctypes.c_void_p(s_ptr), ctypes.c_void_p(t_ptr))
+
+
+def stokes_solve(ctx, b_ptr: int, x_ptr: int, rtol: float, maxit: int, record_history: bool = True):
+    info = StokesInfo()
+    hist = None
+    if record_history:
+        hist = (ctypes.c_double * (maxit + 1))()
+        info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    code = load_library().stokes_solve(ctx, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), float(rtol),
+                                       int(maxit), ctypes.byref(info))
+    history = [hist[i] for i in range(info.iters + 1)] if hist is not None and code != STOKES_EINVAL else None
+    return code, info, history
+
+
+def stokes_profile(ctx, kernel_class: int, level: int = -1) -> None:
+    _check(load_library().stokes_profile(ctx, int(kernel_class), int(level)), "stokes_profile")
+
+
+def stokes_profile_read(ctx, kernel_class: int, level: int = -1):
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(load_library().stokes_profile_read(ctx, int(kernel_class), int(level), ctypes.byref(ms), ctypes.byref(n)),
+           "stokes_profile_read")
+    return float(ms.value), int(n.value)
+
+
+def stokes_destroy(ctx) -> None:
+    load_library().stokes_destroy(ctx)
+
+
+def stokes_strerror(code: int) -> str:
+    return load_library().stokes_strerror(code).decode()
+
+
+# --- torch plumbing -------------------------------------------------------------
+
+class StokesSolver:
+    """Device workspace + context for one box.  State vectors are float64
+    torch tensors of `layout.total` elements on the context's device."""
+
+    def __init__(self, nx, ny, nz, h=None, *, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1,
+                 schedule="split", remove_mean=True, device=None, stream=None):
+        import torch
+        self.torch = torch
+        h = 1.0 / max(nx, ny, nz) if h is None else h
+        p = stokes_default_params(nx, ny, nz, h)
+        p.eta, p.gamma, p.levels, p.nu, p.n_boundary = eta, gamma, levels, nu, n_boundary
+        p.smoother = SMOOTHERS[schedule]
+        p.flags = STOKES_FLAG_REMOVE_MEAN if remove_mean else 0
+        self.params = p
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = stokes_workspace_bytes(p)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr, self._ws_bytes = base + off, nbytes
+        with torch.cuda.device(self.device):
+            self.ctx = stokes_setup(p, self._ws_ptr, nbytes, self.stream.cuda_stream)
+        self.layout = stokes_layout(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            stokes_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # layout helpers
+    def new_state(self):
+        return self.torch.zeros(self.layout.total, dtype=self.torch.float64, device=self.device)
+
+    def _views(self, state):
+        L = self.layout
+        nz2, ny2 = L.nz + 2, L.ny + 2
+        out = []
+        for f in range(4):
+            v = state[L.off[f]:L.off[f] + L.sz * nz2].view(nz2, ny2, L.sy)
+            out.append(v)
+        return out
+
+    def pack(self, fields, out=None):
+        """Natural arrays (ux (nx+1,ny,nz), uy, uz, p), numpy or torch, indexed
+        [i,j,k] -> padded state; only unknowns are copied, every other slot is 0."""
+        torch = self.torch
+        L = self.layout
+        nx, ny, nz = L.nx, L.ny, L.nz
+        st = self.new_state() if out is None else out.zero_()
+        v = self._views(st)
+        t = [torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
+                             dtype=torch.float64).to(self.device) for a in fields]
+        v[0][1:nz + 1, 1:ny + 1, 2:nx + 1] = t[0][1:nx].permute(2, 1, 0)
+        v[1][1:nz + 1, 2:ny + 1, 1:nx + 1] = t[1][:, 1:ny].permute(2, 1, 0)
+        v[2][2:nz + 1, 1:ny + 1, 1:nx + 1] = t[2][:, :, 1:nz].permute(2, 1, 0)
+        v[3][1:nz + 1, 1:ny + 1, 1:nx + 1] = t[3].permute(2, 1, 0)
+        return st
+
+    def unpack(self, state):
+        """Padded state -> natural numpy arrays (walls included, zero)."""
+        L = self.layout
+        nx, ny, nz = L.nx, L.ny, L.nz
+        v = self._views(state)
+        ux = v[0][1:nz + 1, 1:ny + 1, 1:nx + 2].permute(2, 1, 0).cpu().numpy().copy()
+        uy = v[1][1:nz + 1, 1:ny + 2, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
+        uz = v[2][1:nz + 2, 1:ny + 1, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
+        p = v[3][1:nz + 1, 1:ny + 1, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
+        ux[0] = ux[-1] = 0.0
+        uy[:, 0] = uy[:, -1] = 0.0
+        uz[:, :, 0] = uz[:, :, -1] = 0.0
+        return ux, uy, uz, p
+
+    # operations
+    def apply(self, x, penalized=False, out=None):
+        y = self.new_state() if out is None else out
+        _check(stokes_apply(self.ctx, x.data_ptr(), y.data_ptr(), int(penalized)), "stokes_apply")
+        return y
+
+    def vcycle(self, s, out=None):
+        t = self.new_state() if out is None else out
+        _check(stokes_vcycle(self.ctx, s.data_ptr(), t.data_ptr()), "stokes_vcycle")
+        return t
+
+    def profile(self, kernel_class, level=-1):
+        """Select kernels to time with HIP events (name from KC, 'all' or 'off')."""
+        k = {"all": KC_ALL, "off": KC_OFF}.get(kernel_class, KC.get(kernel_class, kernel_class))
+        stokes_profile(self.ctx, k, level)
+
+    def profile_read(self, kernel_class, level=-1):
+        """(total milliseconds, launches) accumulated since profile()."""
+        return stokes_profile_read(self.ctx, KC.get(kernel_class, kernel_class), level)
+
+    def solve(self, b, x0=None, rtol=1e-8, maxit=200):
+        x = self.new_state() if x0 is None else x0.clone()
+        code, info, hist = stokes_solve(self.ctx, b.data_ptr(), x.data_ptr(), rtol, maxit)
+        if code in (STOKES_EINVAL, STOKES_EDEVICE):
+            _check(code, "stokes_solve")
+        return x, {"iters": info.iters, "status": STATUS_NAMES.get(code, str(code)), "relres": info.relres,
+                   "bnorm": info.bnorm, "history": hist}

@@ -1,0 +1,210 @@
+"""GPU FP64 path vs the CPU oracle, element by element, through the C ABI.
+
+Bars: operator apply <= 1e-14 (max-abs relative), one V-cycle <= 1e-12,
+SQMR iterates x_j <= 1e-10 (relative 2-norm) while the recurrence is well
+conditioned, and within 10x the oracle's own sensitivity to 1e-15 noise after
+that (SQMR amplifies rounding differences as the iteration proceeds).  The
+floating-point differences come only from summation order and fused
+multiply-adds; every ordering decision (colours, sweep directions, Vanka
+classes) is the same on both sides.
+"""
+import numpy as np
+import pytest
+
+from oracle.domain import Domain, box_labels
+from oracle.multigrid import Hierarchy, vcycle
+from oracle.operator import apply_operator, assemble, from_vector, to_vector
+from oracle.sqmr import mg_sqmr, remove_pressure_mean, sqmr
+from paper_2312_10615_amd.stokes import StokesSolver
+from tests.gpu_helpers import announce, cuda, forcing_rhs, max_rel, random_fields, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dims", [(32, 32, 32), (24, 16, 40), (6, 10, 8), (2, 2, 2)])
+@pytest.mark.parametrize("penalized", [0, 1])
+def test_operator_apply_matches_oracle(dims, penalized):
+    torch = cuda()
+    announce(f"apply dims={dims} penalized={penalized}")
+    h = 1.0 / max(dims)
+    sol = StokesSolver(*dims, h=h, levels=1 if min(dims) < 4 else 0)
+    dom = Domain(box_labels(dims), h, 1.0, 1e-3)
+    x = random_fields(dom.active, dims, seed=sum(dims) + penalized)
+    y = sol.apply(sol.pack(x), penalized=bool(penalized))
+    torch.cuda.synchronize()
+    want = apply_operator(dom, x, 1e-3 if penalized else 0.0)
+    got = sol.unpack(y)
+    assert max_rel(got, want) <= 1e-14
+    # every slot that is not an unknown is written as zero
+    mask = sol.pack(tuple(np.where(m, 1.0, 0.0) for m in dom.active))
+    assert float(y[mask == 0].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("dims,levels,nu,nb,sched", [((32, 32, 32), 0, 2, 1, "split"), ((16, 24, 8), 0, 2, 1, "split"),
+                                                    ((8, 8, 8), 2, 1, 1, "split"), ((16, 16, 16), 0, 3, 2, "split"),
+                                                    ((12, 20, 16), 3, 2, 1, "split"),
+                                                    ((32, 32, 32), 0, 2, 1, "symmetric"),
+                                                    ((16, 24, 8), 0, 4, 2, "symmetric")])
+def test_vcycle_matches_oracle(dims, levels, nu, nb, sched):
+    torch = cuda()
+    announce(f"vcycle dims={dims} levels={levels} nu={nu} nb={nb} schedule={sched}")
+    h = 1.0 / max(dims)
+    sol = StokesSolver(*dims, h=h, levels=levels, nu=nu, n_boundary=nb, schedule=sched)
+    H = Hierarchy(dims, h, levels=levels, nu=nu, n_boundary=nb, schedule=sched)
+    assert sol.layout.levels == H.levels
+    s = random_fields(H.doms[0].active, dims, seed=7)
+    sd = sol.pack(s)
+    s_copy = sd.clone()
+    t = sol.vcycle(sd)
+    torch.cuda.synchronize()
+    assert torch.equal(sd, s_copy)  # input untouched
+    want = vcycle(H, s)
+    assert max_rel(sol.unpack(t), want) <= 1e-12
+
+
+def test_vcycle_is_symmetric_on_the_gpu():
+    torch = cuda()
+    announce("vcycle symmetry 64^3")
+    n = 64
+    sol = StokesSolver(n, n, n)
+    dom = Domain(box_labels((n, n, n)), 1.0 / n)
+    x = sol.pack(random_fields(dom.active, (n, n, n), seed=1))
+    y = sol.pack(random_fields(dom.active, (n, n, n), seed=2))
+    a = float(torch.dot(x, sol.vcycle(y)))
+    b = float(torch.dot(sol.vcycle(x), y))
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def _oracle_runs(H, b, maxit):
+    """Oracle iterates, plus the oracle's own sensitivity: the same SQMR with a
+    1e-15 relative (seeded) perturbation of every V-cycle output.  SQMR's
+    recurrences amplify rounding differences as iterations go on; the GPU
+    cannot be closer to the oracle than the oracle is to itself under one
+    ulp of noise."""
+    dom = H.doms[0]
+    xs = {}
+    x, info = mg_sqmr(H, b, rtol=1e-8, maxit=maxit, on_iterate=lambda j, xj: xs.__setitem__(j, xj))
+    rng = np.random.default_rng(12345)
+
+    def apply_A(v):
+        return to_vector(dom, apply_operator(dom, from_vector(dom, v), 0.0))
+
+    def apply_W(v):
+        w = to_vector(dom, vcycle(H, from_vector(dom, v)))
+        return w * (1.0 + 1e-15 * rng.standard_normal(w.shape))
+
+    xp = {}
+    _, info_p = sqmr(apply_A, apply_W, to_vector(dom, b), np.zeros(dom.n_dofs()), rtol=1e-8, maxit=maxit,
+                     on_iterate=lambda j, xj, sj: xp.__setitem__(j, from_vector(dom, xj)))
+    sens = {j: rel_err(xp[j], xs[j]) for j in xs if j in xp}
+    return xs, x, info, sens, info_p
+
+
+@pytest.mark.parametrize("dims,seed,sched", [((16, 16, 16), 3, "split"), ((32, 32, 32), 0, "split"),
+                                             ((32, 32, 32), 1, "split"), ((16, 24, 32), 2, "split"),
+                                             ((32, 32, 32), 0, "symmetric")])
+def test_sqmr_iterates_match_oracle(dims, seed, sched):
+    """Every checked iterate x_j agrees with the oracle's to 1e-10 (relative
+    2-norm) while the oracle's own 1-ulp sensitivity is below 1e-12, and to
+    within 10x that sensitivity afterwards."""
+    torch = cuda()
+    announce(f"sqmr iterates dims={dims} seed={seed} schedule={sched}")
+    h = 1.0 / max(dims)
+    H = Hierarchy(dims, h, schedule=sched)
+    b = forcing_rhs(H.doms[0].active, dims, h, seed)
+    xs, x_or, info_or, sens, info_p = _oracle_runs(H, b, 200)
+    assert info_or["status"] == "converged"
+    raw = StokesSolver(*dims, h=h, remove_mean=False, schedule=sched)
+    bd = raw.pack(b)
+    n_or = info_or["iters"]
+    checked = 0
+    for j in sorted({1, 2, 3, 5, 8, 12, 16, 20, 30, n_or // 2, n_or - 1, n_or}):
+        if j < 1 or j > n_or:
+            continue
+        x, info = raw.solve(bd, rtol=1e-8, maxit=j)
+        torch.cuda.synchronize()
+        assert info["iters"] == j
+        err = rel_err(raw.unpack(x), xs[j])
+        bound = 1e-10 if sens[j] <= 1e-12 else max(1e-10, 10.0 * sens[j])
+        announce(f"  j={j} err={err:.2e} oracle-sensitivity={sens[j]:.2e} bound={bound:.1e}")
+        assert err <= bound, (j, err, sens[j])
+        checked += sens[j] <= 1e-12
+    assert checked >= min(5, n_or)
+    # full solve.  Iteration count and residual history are decided by rounding
+    # near the end, so the envelope is the oracle's own perturbed run: the
+    # count may differ by one (or by as much as the perturbed run moved), the
+    # history by 10x the perturbed run's deviation (and 1e-9 where that is tiny).
+    x, info = raw.solve(bd, rtol=1e-8, maxit=200)
+    assert info["status"] == "ok"
+    hist_or = np.array(info_or["relres"])
+    hist_p = np.array(info_p["relres"])
+    hist = np.array(info["history"])
+    announce(f"  iterations gpu={info['iters']} oracle={n_or} perturbed-oracle={info_p['iters']}")
+    assert abs(info["iters"] - n_or) <= max(1, abs(info_p["iters"] - n_or))
+    m = min(len(hist), len(hist_or), len(hist_p))
+    dev = np.abs(hist[:m] - hist_or[:m])
+    env = np.maximum(1e-9 * hist_or[:m], 10.0 * np.abs(hist_p[:m] - hist_or[:m]))
+    env = np.maximum(env, 1e-13)  # ||b - L x|| / ||b|| moves by ~||L dx|| / ||b|| for an x-error dx
+    assert np.all(dev <= env), (dev / hist_or[:m]).max()
+    # mean-removed converged solution (the flag of the default context)
+    sol = StokesSolver(*dims, h=h, schedule=sched)
+    xm, infom = sol.solve(sol.pack(b), rtol=1e-8, maxit=200)
+    want = remove_pressure_mean(H.doms[0], x_or)
+    got = sol.unpack(xm)
+    assert rel_err(got, want) <= max(1e-10, 10.0 * sens[n_or])
+    assert abs(float(np.mean(got[3]))) <= 1e-13 * float(np.abs(want[3]).max())
+
+
+def test_solve_is_bitwise_reproducible():
+    torch = cuda()
+    announce("determinism 32^3")
+    n = 32
+    sol = StokesSolver(n, n, n)
+    b = sol.pack(forcing_rhs(Domain(box_labels((n, n, n)), 1 / n).active, (n, n, n), 1 / n, 5))
+    x1, i1 = sol.solve(b)
+    x2, i2 = sol.solve(b)
+    assert torch.equal(x1, x2) and i1["history"] == i2["history"]
+
+
+def test_edge_cases():
+    torch = cuda()
+    announce("edge cases")
+    n = 16
+    dom = Domain(box_labels((n, n, n)), 1 / n)
+    sol = StokesSolver(n, n, n)
+    # b = 0 returns x = 0 whatever x0 holds
+    x0 = sol.pack(random_fields(dom.active, (n, n, n), seed=3))
+    x, info = sol.solve(sol.new_state(), x0=x0)
+    assert info["status"] == "ok" and info["iters"] == 0 and float(x.abs().max()) == 0.0
+    b = sol.pack(forcing_rhs(dom.active, (n, n, n), 1 / n, 9))
+    # maxit = 0: no iteration, x0 returned
+    x, info = sol.solve(b, x0=x0, maxit=0)
+    assert info["status"] == "enoconv" and info["iters"] == 0 and torch.equal(x, x0)
+    # warm start from a converged solution: zero iterations
+    xs, info = sol.solve(b, rtol=1e-10)
+    x, info2 = sol.solve(b, x0=xs, rtol=1e-8)
+    assert info2["iters"] == 0 and info2["status"] == "ok"
+    # garbage in the ghost slots of the initial guess is cleared
+    junk = xs.clone()
+    lay = sol.layout
+    junk[lay.off[0]] = 7.0  # slot (0,0,0) of u_x is never an unknown
+    x, info3 = sol.solve(b, x0=junk, rtol=1e-8)
+    assert info3["iters"] == 0 and float(x[lay.off[0]]) == 0.0
+    # non-finite right-hand side
+    bad = b.clone()
+    bad[lay.off[3] + lay.sz + lay.sy + 1] = float("nan")
+    x, info = sol.solve(bad)
+    assert info["status"] == "enonfinite"
+    # smallest box, single level (the V-cycle is the exact inverse of L~):
+    # the converged solution equals the dense solve with mean-zero pressure
+    tiny = StokesSolver(2, 2, 2, levels=1)
+    dt = Domain(box_labels((2, 2, 2)), 0.5)
+    bt = forcing_rhs(dt.active, (2, 2, 2), 0.5, 1)
+    xt, it = tiny.solve(tiny.pack(bt), rtol=1e-13)
+    assert it["status"] == "ok" and it["iters"] <= 10
+    Ld = assemble(dt, 0.0, dense=True)
+    z = to_vector(dt, tuple(np.zeros(s) for s in dt.shapes[:3]) + (np.ones(dt.shapes[3]),))
+    K = np.block([[Ld, z[:, None]], [z[None, :], np.zeros((1, 1))]])
+    want = np.linalg.solve(K, np.concatenate([to_vector(dt, bt), [0.0]]))[:-1]
+    got = to_vector(dt, tiny.unpack(xt))
+    assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)

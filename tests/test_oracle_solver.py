@@ -6,7 +6,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 from oracle.domain import Domain, box_labels
-from oracle.multigrid import Hierarchy, vcycle
+from oracle.multigrid import Hierarchy, postsmooth, presmooth, vcycle
 from oracle.operator import apply_operator, assemble, from_vector, residual, to_vector
 from oracle.smoother import (collect, dgs_diagonals, dgs_forward, dgs_reverse, dgs_symmetric,
                              distribute, smooth, vanka_color, vanka_local_matrix, vanka_slots,
@@ -61,7 +61,7 @@ def traversal_order(dom):
 
 
 def m_columns(dom, order):
-    """Columns of M22 (Eq. dist restricted to V2) for the DOFs in `order`."""
+    """Columns of M (Eq. dist) for the V2 DOFs in `order`, full length."""
     fid, _, _ = dof_tags(dom)
     n = dom.n_dofs()
     cols = {}
@@ -87,17 +87,10 @@ def test_dgs_diagonals_closed_form():
     for a in range(3):
         assert np.allclose(d_u[a][dom.v2[a]], 6 * c, rtol=1e-14)
         assert np.all(d_u[a][~dom.v2[a]] == 0)
-    # n_j = number of V2 faces of cell j
-    nj = np.zeros(dom.shapes[3])
-    for a in range(3):
-        v = dom.v2[a].astype(float)
-        lo = [slice(None)] * 3
-        hi = [slice(None)] * 3
-        lo[a] = slice(0, -1)
-        hi[a] = slice(1, None)
-        nj += v[tuple(lo)] + v[tuple(hi)]
-    want = -(1 + dom.gamma * dom.eta) * nj / dom.h ** 2
-    assert np.allclose(d_p[dom.v2[3]], want[dom.v2[3]], rtol=1e-13)
+    # every V2 cell has six unknown faces and six unknown neighbours
+    want = -(1 + dom.gamma * dom.eta) * 6.0 / dom.h ** 2
+    assert np.allclose(d_p[dom.v2[3]], want, rtol=1e-13)
+    assert np.all(d_p[~dom.v2[3]] == 0)
 
 
 def test_distribute_and_collect_are_adjoint():
@@ -107,6 +100,13 @@ def test_distribute_and_collect_are_adjoint():
     r = rand_state(dom, 3)
     lhs = sum(float(np.sum(a * b)) for a, b in zip(distribute(dom, delta), r))
     rhs = float(np.sum(np.where(dom.v2[3], delta, 0) * collect(dom, r)))
+    # the pressure column of a V2 cell reaches V1 unknowns: faces shared with
+    # ring cells and the ring-cell pressures next to it
+    d = np.zeros(dom.shapes[3])
+    d[1, 3, 3] = 1.0
+    dx = distribute(dom, d)
+    assert dx[0][1, 3, 3] != 0 and dom.v1[0][1, 3, 3]
+    assert dx[3][0, 3, 3] != 0 and dom.v1[3][0, 3, 3]
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
@@ -150,26 +150,36 @@ def test_pressure_step_zeroes_its_continuity_residual():
 
 
 def test_symmetric_dgs_equals_appendix_a_formula():
-    """P = M G^-1 + G^-T M^T - G^-T M^T L M G^-1 with G the lower triangle of
-    L~22 M22 in traversal order (Appendix A, Theorem 1), and P symmetric."""
+    """P = M G^-1 E + E^T G^-T M^T - E^T G^-T M^T L M G^-1 E (Appendix A,
+    Theorem 1) with M the n x n2 columns of the V2 unknowns, E the selection
+    of the V2 rows and G the lower triangle of E L~ M in traversal order; P
+    is symmetric."""
     dom = dom_of((6, 6, 4))
     Lt = assemble(dom, dom.gamma, dense=True)
     order = traversal_order(dom)
     cols = m_columns(dom, order)
-    idx = np.array(order)
-    L22 = Lt[np.ix_(idx, idx)]
-    M22 = np.stack([cols[j][idx] for j in order], axis=1)
-    G = np.tril(L22 @ M22)
-    Gi = np.linalg.inv(G)
-    P = M22 @ Gi + Gi.T @ M22.T - Gi.T @ M22.T @ L22 @ M22 @ Gi
     n = dom.n_dofs()
-    C = np.zeros((idx.size, idx.size))
-    for c, j in enumerate(order):
-        e = np.zeros(n)
-        e[j] = 1.0
-        C[:, c] = to_vector(dom, dgs_symmetric(dom, zero(dom), from_vector(dom, e)))[idx]
+    idx = np.array(order)
+    M = np.stack([cols[j] for j in order], axis=1)
+    E = np.zeros((idx.size, n))
+    E[np.arange(idx.size), idx] = 1.0
+    G = np.tril(E @ Lt @ M)
+    Gi = np.linalg.inv(G)
+    P = M @ Gi @ E + E.T @ Gi.T @ M.T - E.T @ Gi.T @ M.T @ Lt @ M @ Gi @ E
+    C = dense_of(dom, lambda b: dgs_symmetric(dom, zero(dom), b))
     assert np.abs(C - P).max() <= 1e-12 * np.abs(P).max()
     assert np.abs(C - C.T).max() <= 1e-12 * np.abs(C).max()
+
+
+def test_symmetric_dgs_does_not_amplify():
+    """With the interior columns of M the symmetric DGS error propagator has
+    spectral radius 1 (the eigenvalue 1 belongs to the V1 unknowns it does not
+    relax)."""
+    dom = dom_of((8, 8, 8))
+    Lt = assemble(dom, dom.gamma, dense=True)
+    C = dense_of(dom, lambda b: dgs_symmetric(dom, zero(dom), b))
+    ev = np.abs(np.linalg.eigvals(np.eye(C.shape[0]) - C @ Lt))
+    assert ev.max() <= 1.0 + 1e-9
 
 
 # --- Vanka (Eq. mv, Appendix C) ---------------------------------------------
@@ -248,8 +258,9 @@ def test_smoother_matrices_are_symmetric_and_propagators_self_adjoint(small, whi
     assert np.abs(Lt @ E - E.T @ Lt).max() <= 1e-10 * np.abs(Lt).max()
 
 
-def test_vcycle_is_symmetric_on_random_vectors():
-    H = Hierarchy((16, 16, 16), 1.0 / 16)
+@pytest.mark.parametrize("schedule,nu", [("split", 2), ("split", 1), ("symmetric", 2)])
+def test_vcycle_is_symmetric_on_random_vectors(schedule, nu):
+    H = Hierarchy((16, 16, 16), 1.0 / 16, schedule=schedule, nu=nu)
     dom = H.doms[0]
     x, y = rand_state(dom, 21), rand_state(dom, 22)
     a = sum(float(np.sum(u * v)) for u, v in zip(x, vcycle(H, y)))
@@ -267,21 +278,45 @@ def test_single_level_vcycle_is_the_exact_inverse():
     assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
 
 
-def test_two_level_vcycle_matches_alg1_algebra():
-    """W = (I - C L~)(C + P Lc^-1 R (I - L~ C)) + C with C the smoothing matrix."""
-    H = Hierarchy((8, 4, 4), 1.0 / 8, levels=2)
+@pytest.mark.parametrize("schedule", ["split", "symmetric"])
+def test_two_level_vcycle_matches_alg1_algebra(schedule):
+    """W = (I - C2 L~)(C1 + P Lc^-1 R (I - L~ C1)) + C2 with C1, C2 the pre-
+    and post-smoothing matrices; W is symmetric because C2 = C1^T."""
+    H = Hierarchy((8, 4, 4), 1.0 / 8, levels=2, schedule=schedule)
     fine, coarse = H.doms
     Lt = assemble(fine, fine.gamma, dense=True)
     Lc = assemble(coarse, coarse.gamma, dense=True)
-    C = dense_of(fine, lambda b: smooth(fine, zero(fine), b, 1, H.diags[0]))
+    C1 = dense_of(fine, lambda b: presmooth(H, 0, zero(fine), b))
+    C2 = dense_of(fine, lambda b: postsmooth(H, 0, zero(fine), b))
+    assert np.abs(C2 - C1.T).max() <= 1e-11 * np.abs(C1).max()
     P = dense_of(coarse, lambda e: prolong(fine, coarse, e), fine)
     R = dense_of(fine, lambda r: restrict(fine, coarse, r), coarse)
-    I = np.eye(C.shape[0])
-    want = (I - C @ Lt) @ (C + P @ np.linalg.solve(Lc, R @ (I - Lt @ C))) + C
+    I = np.eye(C1.shape[0])
+    want = (I - C2 @ Lt) @ (C1 + P @ np.linalg.solve(Lc, R @ (I - Lt @ C1))) + C2
     got = dense_of(fine, lambda b: vcycle(H, b))
     assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
     assert np.abs(got - got.T).max() <= 1e-11 * np.abs(got).max()
     assert np.allclose(P, 8 * R.T, rtol=0, atol=1e-15)
+
+
+def test_split_schedule_contracts_where_the_symmetric_one_does_not():
+    """Measured property behind the default schedule: pure multigrid on L~
+    (e <- e - W L~ e) at 32^3 / 4 levels contracts with the split pre/post
+    pair and barely does with the symmetric smoother in both phases."""
+    n = 32
+    rates = {}
+    for schedule in ("split", "symmetric"):
+        H = Hierarchy((n, n, n), 1.0 / n, schedule=schedule)
+        dom = H.doms[0]
+        e = rand_state(dom, 0)
+        for _ in range(8):
+            w = vcycle(H, apply_operator(dom, e, dom.gamma))
+            e2 = tuple(a - c for a, c in zip(e, w))
+            r = np.sqrt(sum(float(np.sum(v * v)) for v in e2) / sum(float(np.sum(v * v)) for v in e))
+            nrm = np.sqrt(sum(float(np.sum(v * v)) for v in e2))
+            e = tuple(v / nrm for v in e2)
+        rates[schedule] = r
+    assert rates["split"] < 0.4 < 0.7 < rates["symmetric"]
 
 
 # --- SQMR (Alg. 4) ------------------------------------------------------------
