@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--kernel", default="dgs_pr", help="dominant kernel class timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the solve does not shard "
@@ -169,6 +171,13 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     vcycle_ms = ev0.elapsed_time(ev1) / nvc
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     avg_ms = kms / max(klaunch, 1)
     abytes = algorithmic_bytes(args.kernel, n)

@@ -94,6 +94,11 @@ typedef struct stokes_params {
 /* After convergence subtract the mean pressure over the cells (the closed box
  * leaves p defined up to a constant). */
 #define STOKES_FLAG_REMOVE_MEAN 1
+/* Launch the V-cycle kernel by kernel instead of replaying a captured HIP
+ * graph of it (the default captures one graph per (s, t) pointer pair and
+ * profiling selection, on a private stream, and replays it on the caller's
+ * stream). */
+#define STOKES_FLAG_NO_GRAPH 2
 
 typedef struct stokes_layout_t {
   int32_t nx, ny, nz;         /* interior cells */

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <vector>
 
@@ -52,7 +53,9 @@ struct stokes_ctx {
   stokes_params prm{};
   int L = 0;
   std::vector<Level> lev;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // the caller's stream: everything runs here
+  hipStream_t ks = nullptr;       // stream the V-cycle launches go to (= stream, or cap while capturing)
+  hipStream_t cap = nullptr;      // private stream used only to capture V-cycle graphs
   long total = 0;  // elements of a finest-level state vector
   // SQMR vectors
   double *s = nullptr, *t = nullptr, *q = nullptr, *d = nullptr;
@@ -70,6 +73,24 @@ struct stokes_ctx {
   // kernel timing (diagnostics)
   int prof_class = STOKES_KC_OFF, prof_level = -1;
   struct Pending { int k, l; hipEvent_t a, b; };
+  // V-cycle graphs, keyed by input/output pointers and the profiling selection:
+  // a sequence of graph segments and eagerly launched (timed) kernels
+  struct Step {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::function<void()> fn;
+    int k = -1, l = -1;
+  };
+  struct GraphEntry {
+    const double* s;
+    double* t;
+    int pc, pl;
+    std::vector<Step> steps;
+  };
+  std::vector<GraphEntry> graphs;
+  std::vector<Step> steps;      // segments of the graph being captured
+  bool capturing = false;
+  hipError_t cap_error = hipSuccess;
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   std::vector<double> prof_ms;     // [class * 32 + level]
@@ -100,7 +121,7 @@ struct Prof {
   Prof(stokes_ctx* c_, int k_, int l_) : c(c_), k(k_), l(l_) {
     if (c->prof_on(k, l)) {
       a = c->event();
-      if (a) (void)hipEventRecord(a, c->stream);
+      if (a) (void)hipEventRecord(a, c->ks);
     }
   }
   ~Prof() {
@@ -110,7 +131,7 @@ struct Prof {
       c->pool.push_back(a);
       return;
     }
-    (void)hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, c->ks);
     c->pending.push_back({k, l, a, b});
   }
 };
@@ -130,6 +151,15 @@ void prof_collect(stokes_ctx* c) {
   c->pending.clear();
 }
 
+void drop_graphs(stokes_ctx* c) {
+  for (auto& e : c->graphs)
+    for (auto& st : e.steps) {
+      if (st.exec) (void)hipGraphExecDestroy(st.exec);
+      if (st.graph) (void)hipGraphDestroy(st.graph);
+    }
+  c->graphs.clear();
+}
+
 int grid_for(long slots) {
   long nb = (slots + BS - 1) / BS;
   nb = (nb + NXCD - 1) / NXCD * NXCD;
@@ -137,6 +167,7 @@ int grid_for(long slots) {
 }
 
 int half_grid(const Geom& g) { return grid_for((long)g.rows * (g.sy / 2)); }
+int slot_grid(const Geom& g) { return grid_for(g.field); }
 
 #define HIPCHK(call)                                  \
   do {                                                \
@@ -219,58 +250,77 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
 // ---------------------------------------------------------------------------
 // V-cycle pieces
 // ---------------------------------------------------------------------------
+
+// Every V-cycle launch goes through launch(): it runs `f` (which enqueues one
+// kernel on c->ks), timing it with events when its class/level is selected.
+// While a graph is being captured, a selected launch closes the running graph
+// segment and is stored to run eagerly (between two segment replays) so its
+// events sit on the caller's stream, outside any graph.
+void seg_open(stokes_ctx* c);
+void seg_close(stokes_ctx* c);
+
+template <class F>
+void launch(stokes_ctx* c, int cls, int level, F f) {
+  if (c->prof_on(cls, level)) {
+    if (c->capturing) {
+      seg_close(c);
+      stokes_ctx::Step st;
+      st.fn = f;
+      st.k = cls;
+      st.l = level;
+      c->steps.push_back(std::move(st));
+      seg_open(c);
+      return;
+    }
+    Prof pf(c, cls, level);
+    f();
+    return;
+  }
+  f();
+}
+
 void vanka_symmetric(stokes_ctx* c, int l, double* x, const double* b) {
-  Level& lv = c->lev[l];
+  const Level& lv = c->lev[l];
   for (int pass = 0; pass < 16; ++pass) {
     const int k = pass < 8 ? pass : 15 - pass;
     const int n = lv.nv[k];
     if (n == 0) continue;
     const int nb = (n + BS - 1) / BS;
-    {
-      Prof pf(c, STOKES_KC_VANKA_DELTA, l);
-      k_vanka_delta<double, double><<<nb, BS, 0, c->stream>>>(lv.g, x, b, lv.vcells[k], n, lv.kinv, c->vdelta);
-    }
-    {
-      Prof pf(c, STOKES_KC_VANKA_APPLY, l);
-      k_vanka_apply<double><<<nb, BS, 0, c->stream>>>(lv.g, x, lv.vcells[k], n, c->vdelta);
-    }
+    const Geom g = lv.g;
+    const int* cells = lv.vcells[k];
+    const double* kinv = lv.kinv;
+    double* vd = c->vdelta;
+    launch(c, STOKES_KC_VANKA_DELTA, l, [=] {
+      k_vanka_delta<double, double><<<nb, BS, 0, c->ks>>>(g, x, b, cells, n, kinv, vd);
+    });
+    launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_vanka_apply<double><<<nb, BS, 0, c->ks>>>(g, x, cells, n, vd); });
   }
 }
 
 // Forward DGS sweep on L~ M (Alg. 2, Eq. dist) over the V2 unknowns:
 // velocities red, black; pressures red, black.
 void dgs_forward(stokes_ctx* c, int l, double* x, const double* b) {
-  Level& lv = c->lev[l];
-  const Geom& g = lv.g;
+  const Geom g = c->lev[l].g;
+  double* dscr = c->lev[l].dscr;
   const int hg = half_grid(g);
+  for (int col = 0; col < 2; ++col)
+    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u<double, double><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
   for (int col = 0; col < 2; ++col) {
-    Prof pf(c, STOKES_KC_DGS_U, l);
-    k_dgs_u<double, double><<<hg, BS, 0, c->stream>>>(g, x, b, col);
-  }
-  for (int col = 0; col < 2; ++col) {
-    {
-      Prof pf(c, STOKES_KC_DGS_PF_OWN, l);
-      k_dgs_pf_own<double, double><<<hg, BS, 0, c->stream>>>(g, x, b, lv.dscr, col);
-    }
-    Prof pf(c, STOKES_KC_DGS_PF_NBR, l);
-    k_dgs_pf_nbr<double><<<hg, BS, 0, c->stream>>>(g, x, lv.dscr, col);
+    launch(c, STOKES_KC_DGS_PF_OWN, l,
+           [=] { k_dgs_pf_own<double, double><<<hg, BS, 0, c->ks>>>(g, x, b, dscr, col); });
+    launch(c, STOKES_KC_DGS_PF_NBR, l, [=] { k_dgs_pf_nbr<double><<<hg, BS, 0, c->ks>>>(g, x, dscr, col); });
   }
 }
 
 // Reverse sweep: Gauss-Seidel on M^T L~ (Eq. ldist) in exactly the reverse
 // order: pressures black, red; velocities black, red.
 void dgs_reverse(stokes_ctx* c, int l, double* x, const double* b) {
-  Level& lv = c->lev[l];
-  const Geom& g = lv.g;
+  const Geom g = c->lev[l].g;
   const int hg = half_grid(g);
-  for (int col = 1; col >= 0; --col) {
-    Prof pf(c, STOKES_KC_DGS_PR, l);
-    k_dgs_pr<double, double><<<hg, BS, 0, c->stream>>>(g, x, b, col);
-  }
-  for (int col = 1; col >= 0; --col) {
-    Prof pf(c, STOKES_KC_DGS_U, l);
-    k_dgs_u<double, double><<<hg, BS, 0, c->stream>>>(g, x, b, col);
-  }
+  for (int col = 1; col >= 0; --col)
+    launch(c, STOKES_KC_DGS_PR, l, [=] { k_dgs_pr<double, double><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
+  for (int col = 1; col >= 0; --col)
+    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u<double, double><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
 }
 
 enum Interior { INT_SYMMETRIC, INT_REVERSE, INT_FORWARD };
@@ -306,37 +356,104 @@ void postsmooth(stokes_ctx* c, int l, double* x, const double* b) {
 }
 
 void fill_zero(stokes_ctx* c, double* x, long n, int level = 0) {
-  Prof pf(c, STOKES_KC_BLAS, level);
-  k_fill<double><<<RED_BLOCKS, BS, 0, c->stream>>>(x, n, 0.0);
+  launch(c, STOKES_KC_BLAS, level, [=] { k_fill<double><<<RED_BLOCKS, BS, 0, c->ks>>>(x, n, 0.0); });
 }
 
 // x = V-CYCLE(L~, b, 0, L - l)
 void vcycle(stokes_ctx* c, int l, const double* b, double* x) {
-  Level& lv = c->lev[l];
-  const Geom& g = lv.g;
+  const Geom g = c->lev[l].g;
   fill_zero(c, x, 4L * g.field, l);
   if (l == c->L - 1) {
     const int nb = (c->nc + (BS / 64) - 1) / (BS / 64);
-    Prof pf(c, STOKES_KC_COARSE, l);
-    k_coarse_solve<double><<<nb, BS, 0, c->stream>>>(c->cinv, c->cdof, c->nc, b, x);
+    const double* cinv = c->cinv;
+    const int* cdof = c->cdof;
+    const int nc = c->nc;
+    launch(c, STOKES_KC_COARSE, l,
+           [=] { k_coarse_solve<double><<<nb, BS, 0, c->ks>>>(cinv, cdof, nc, b, x); });
     return;
   }
   presmooth(c, l, x, b);
-  {
-    Prof pf(c, STOKES_KC_APPLY, l);
-    k_apply<AP_RESID, double, double><<<grid_for(g.field), BS, 0, c->stream>>>(g, x, b, lv.r, g.gamma, nullptr);
-  }
-  Level& cl = c->lev[l + 1];
-  {
-    Prof pf(c, STOKES_KC_RESTRICT, l);
-    k_restrict<double><<<grid_for(cl.g.field), BS, 0, c->stream>>>(g, cl.g, lv.r, cl.b);
-  }
-  vcycle(c, l + 1, cl.b, cl.x);
-  {
-    Prof pf(c, STOKES_KC_PROLONG, l);
-    k_prolong_add<double><<<grid_for(g.field), BS, 0, c->stream>>>(g, cl.g, cl.x, x);
-  }
+  double* r = c->lev[l].r;
+  const Geom gc = c->lev[l + 1].g;
+  double* bc = c->lev[l + 1].b;
+  double* xc = c->lev[l + 1].x;
+  launch(c, STOKES_KC_APPLY, l, [=] {
+    k_apply<AP_RESID, double, double><<<slot_grid(g), BS, 0, c->ks>>>(g, x, b, r, g.gamma, nullptr);
+  });
+  launch(c, STOKES_KC_RESTRICT, l,
+         [=] { k_restrict<double><<<slot_grid(gc), BS, 0, c->ks>>>(g, gc, r, bc); });
+  vcycle(c, l + 1, bc, xc);
+  launch(c, STOKES_KC_PROLONG, l,
+         [=] { k_prolong_add<double><<<slot_grid(g), BS, 0, c->ks>>>(g, gc, xc, x); });
   postsmooth(c, l, x, b);
+}
+
+void seg_open(stokes_ctx* c) {
+  if (c->cap_error == hipSuccess) c->cap_error = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+}
+
+void seg_close(stokes_ctx* c) {
+  if (c->cap_error != hipSuccess) return;
+  hipGraph_t graph = nullptr;
+  c->cap_error = hipStreamEndCapture(c->cap, &graph);
+  if (c->cap_error != hipSuccess) return;
+  size_t nodes = 0;
+  (void)hipGraphGetNodes(graph, nullptr, &nodes);
+  if (nodes == 0) {
+    (void)hipGraphDestroy(graph);
+    return;
+  }
+  stokes_ctx::Step st;
+  st.graph = graph;
+  c->cap_error = hipGraphInstantiate(&st.exec, graph, nullptr, nullptr, 0);
+  c->steps.push_back(std::move(st));
+}
+
+// t = W s on the caller's stream.  The V-cycle (about 900 launches at 256^3)
+// is captured once per (s, t, profiling selection) into graph segments that
+// are replayed on the caller's stream; STOKES_FLAG_NO_GRAPH launches it
+// kernel by kernel instead.
+int run_vcycle(stokes_ctx* c, const double* s, double* t) {
+  if (c->prm.flags & STOKES_FLAG_NO_GRAPH) {
+    c->ks = c->stream;
+    vcycle(c, 0, s, t);
+    return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
+  }
+  stokes_ctx::GraphEntry* hit = nullptr;
+  for (auto& e : c->graphs)
+    if (e.s == s && e.t == t && e.pc == c->prof_class && e.pl == c->prof_level) hit = &e;
+  if (!hit) {
+    if (c->graphs.size() >= 4) {
+      (void)hipStreamSynchronize(c->stream);
+      drop_graphs(c);
+    }
+    c->steps.clear();
+    c->cap_error = hipSuccess;
+    c->capturing = true;
+    c->ks = c->cap;
+    seg_open(c);
+    vcycle(c, 0, s, t);
+    seg_close(c);
+    c->capturing = false;
+    c->ks = c->stream;
+    stokes_ctx::GraphEntry e{s, t, c->prof_class, c->prof_level, std::move(c->steps)};
+    c->steps.clear();
+    c->graphs.push_back(std::move(e));
+    hit = &c->graphs.back();
+    if (c->cap_error != hipSuccess || hipGetLastError() != hipSuccess) {
+      drop_graphs(c);
+      return STOKES_EDEVICE;
+    }
+  }
+  for (auto& st : hit->steps) {
+    if (st.exec) {
+      if (hipGraphLaunch(st.exec, c->stream) != hipSuccess) return STOKES_EDEVICE;
+    } else {
+      Prof pf(c, st.k, st.l);
+      st.fn();
+    }
+  }
+  return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
 }
 
 // Device scalar reduction of `nblk` partials (stride values each) into
@@ -404,9 +521,15 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
   c->prm = *p;
   c->L = L;
   c->stream = (hipStream_t)hip_stream;
+  c->ks = c->stream;
   Carver cv(workspace, bytes, false);
   carve(c, cv, L);
   if (hipHostMalloc((void**)&c->hscal, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return STOKES_EDEVICE;
+  }
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipHostFree(c->hscal);
     delete c;
     return STOKES_EDEVICE;
   }
@@ -477,7 +600,7 @@ int stokes_apply(stokes_ctx* c, const double* x, double* y, int32_t penalized) {
   const Geom& g = c->lev[0].g;
   {
     Prof pf(c, STOKES_KC_APPLY, 0);
-    k_apply<AP_APPLY, double, double><<<grid_for(g.field), BS, 0, c->stream>>>(g, x, (const double*)nullptr, y,
+    k_apply<AP_APPLY, double, double><<<slot_grid(g), BS, 0, c->stream>>>(g, x, (const double*)nullptr, y,
                                                                                penalized ? g.gamma : 0.0, nullptr);
   }
   return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
@@ -485,15 +608,15 @@ int stokes_apply(stokes_ctx* c, const double* x, double* y, int32_t penalized) {
 
 int stokes_vcycle(stokes_ctx* c, const double* s, double* t) {
   if (!c || !s || !t || s == t) return STOKES_EINVAL;
-  vcycle(c, 0, s, t);
-  return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
+  return run_vcycle(c, s, t);
 }
 
 int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t maxit, stokes_info* info) {
   if (!c || !b || !x || b == x || maxit < 0 || !(rtol >= 0)) return STOKES_EINVAL;
   const Geom& g = c->lev[0].g;
   const long n = c->total;
-  const int gf = grid_for(g.field);
+  const int gf = grid_for(g.field);  // flat kernels (ghost clearing, pressure mean)
+  const int ga = slot_grid(g);        // tiled operator kernels
   auto fill_info = [&](int iters, int status, double relres, double bn) {
     if (info) {
       info->iters = iters;
@@ -510,10 +633,10 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
   // ||b|| over the unknowns
   {
     Prof pf(c, STOKES_KC_APPLY, 0);
-    k_apply<AP_BNORM, double, double><<<gf, BS, 0, c->stream>>>(g, (const double*)nullptr, b, (double*)nullptr, 0.0,
+    k_apply<AP_BNORM, double, double><<<ga, BS, 0, c->stream>>>(g, (const double*)nullptr, b, (double*)nullptr, 0.0,
                                                                 c->partial);
   }
-  if (reduce_to_host(c, gf, 1) != STOKES_OK) return fill_info(0, STOKES_EDEVICE, NAN, NAN);
+  if (reduce_to_host(c, ga, 1) != STOKES_OK) return fill_info(0, STOKES_EDEVICE, NAN, NAN);
   const double bnorm = std::sqrt(c->hscal[0]);
   if (!std::isfinite(bnorm)) return fill_info(0, STOKES_ENONFINITE, NAN, bnorm);
   if (bnorm == 0.0) {
@@ -525,13 +648,13 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
   // s0 = b - L x0, with ||s0||^2
   {
     Prof pf(c, STOKES_KC_APPLY, 0);
-    k_apply<AP_RESID, double, double><<<gf, BS, 0, c->stream>>>(g, x, b, c->s, 0.0, nullptr);
+    k_apply<AP_RESID, double, double><<<ga, BS, 0, c->stream>>>(g, x, b, c->s, 0.0, nullptr);
   }
   {
     Prof pf(c, STOKES_KC_APPLY, 0);
-    k_apply<AP_RESNORM, double, double><<<gf, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
+    k_apply<AP_RESNORM, double, double><<<ga, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
   }
-  if (reduce_to_host(c, gf, 1) != STOKES_OK) return fill_info(0, STOKES_EDEVICE, NAN, bnorm);
+  if (reduce_to_host(c, ga, 1) != STOKES_OK) return fill_info(0, STOKES_EDEVICE, NAN, bnorm);
   double relres = std::sqrt(c->hscal[0]) / bnorm;
   if (info && info->history) info->history[0] = relres;
   auto finish = [&](int iters, int status) {
@@ -562,7 +685,7 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
   if (!std::isfinite(relres)) return finish(0, STOKES_ENONFINITE);
   if (relres <= rtol) return finish(0, STOKES_OK);
   // t = W s0; q0 = t; tau0 = ||t||; rho0 = s0 . q0; d = 0
-  vcycle(c, 0, c->s, c->t);
+  if (run_vcycle(c, c->s, c->t) != STOKES_OK) return finish(0, STOKES_EDEVICE);
   {
     Prof pf(c, STOKES_KC_BLAS, 0);
     k_dot_aa_ac<<<RED_BLOCKS, BS, 0, c->stream>>>(c->t, c->s, n, c->partial);
@@ -577,10 +700,10 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
     // t = L q, sigma = q . t
     {
       Prof pf(c, STOKES_KC_APPLY, 0);
-      k_apply<AP_APPLY_DOT, double, double><<<gf, BS, 0, c->stream>>>(g, c->q, (const double*)nullptr, c->t, 0.0,
+      k_apply<AP_APPLY_DOT, double, double><<<ga, BS, 0, c->stream>>>(g, c->q, (const double*)nullptr, c->t, 0.0,
                                                                       c->partial);
     }
-    if (reduce_to_host(c, gf, 1) != STOKES_OK) return finish(j - 1, STOKES_EDEVICE);
+    if (reduce_to_host(c, ga, 1) != STOKES_OK) return finish(j - 1, STOKES_EDEVICE);
     const double sigma = c->hscal[0];
     if (!std::isfinite(sigma)) return finish(j - 1, STOKES_ENONFINITE);
     if (sigma == 0.0) return finish(j - 1, STOKES_EBREAKDOWN);
@@ -590,7 +713,7 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
       k_axpy_neg<<<RED_BLOCKS, BS, 0, c->stream>>>(c->s, c->t, n, alpha);
     }
     // t = W s
-    vcycle(c, 0, c->s, c->t);
+    if (run_vcycle(c, c->s, c->t) != STOKES_OK) return finish(j - 1, STOKES_EDEVICE);
     {
       Prof pf(c, STOKES_KC_BLAS, 0);
       k_dot_aa_ac<<<RED_BLOCKS, BS, 0, c->stream>>>(c->t, c->s, n, c->partial);
@@ -609,9 +732,9 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
     // true residual
     {
       Prof pf(c, STOKES_KC_APPLY, 0);
-      k_apply<AP_RESNORM, double, double><<<gf, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
+      k_apply<AP_RESNORM, double, double><<<ga, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
     }
-    if (reduce_to_host(c, gf, 1) != STOKES_OK) return finish(j, STOKES_EDEVICE);
+    if (reduce_to_host(c, ga, 1) != STOKES_OK) return finish(j, STOKES_EDEVICE);
     relres = std::sqrt(c->hscal[0]) / bnorm;
     if (info && info->history) info->history[j] = relres;
     if (!std::isfinite(relres) || !std::isfinite(tnorm)) return finish(j, STOKES_ENONFINITE);
@@ -631,6 +754,7 @@ int stokes_profile(stokes_ctx* c, int32_t kernel_class, int32_t level) {
   if (!c || kernel_class < STOKES_KC_OFF || kernel_class >= STOKES_KC_COUNT || level >= 32) return STOKES_EINVAL;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return STOKES_EDEVICE;
   prof_collect(c);
+  if (kernel_class != c->prof_class || level != c->prof_level) drop_graphs(c);
   c->prof_class = kernel_class;
   c->prof_level = level;
   c->prof_ms.assign(STOKES_KC_COUNT * 32, 0.0);
@@ -659,9 +783,11 @@ int stokes_profile_read(stokes_ctx* c, int32_t kernel_class, int32_t level, doub
 
 void stokes_destroy(stokes_ctx* c) {
   if (!c) return;
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
   prof_collect(c);
+  drop_graphs(c);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   if (c->hscal) (void)hipHostFree(c->hscal);
   delete c;
 }

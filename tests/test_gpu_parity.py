@@ -208,3 +208,32 @@ def test_edge_cases():
     want = np.linalg.solve(K, np.concatenate([to_vector(dt, bt), [0.0]]))[:-1]
     got = to_vector(dt, tiny.unpack(xt))
     assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+
+
+def test_vcycle_graph_replays_match_eager_launches():
+    """The captured V-cycle graph, replayed several times with unrelated eager
+    work and synchronisations in between, gives bitwise the eager result."""
+    torch = cuda()
+    announce("graph replays vs eager, 32^3 and 24x16x40")
+    for dims in ((32, 32, 32), (24, 16, 40)):
+        h = 1.0 / max(dims)
+        g_sol = StokesSolver(*dims, h=h)
+        e_sol = StokesSolver(*dims, h=h, graphs=False)
+        dom = Domain(box_labels(dims), h)
+        s = g_sol.pack(random_fields(dom.active, dims, seed=4))
+        want = e_sol.vcycle(s)
+        torch.cuda.synchronize()
+        t = g_sol.new_state()
+        for rep in range(4):
+            g_sol.vcycle(s, out=t)
+            torch.cuda.synchronize()
+            assert torch.equal(t, want), rep
+            # unrelated eager work between replays
+            junk = e_sol.apply(s * (rep + 1.5), penalized=True)
+            _ = float(junk.sum())
+            torch.cuda.synchronize()
+        # the solve path (which replays its own graph) agrees with the eager solve bitwise
+        b = g_sol.pack(forcing_rhs(dom.active, dims, h, 3))
+        xg, ig = g_sol.solve(b)
+        xe, ie = e_sol.solve(b)
+        assert ig["iters"] == ie["iters"] and torch.equal(xg, xe)
