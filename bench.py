@@ -70,7 +70,9 @@ def counter_traffic(kernel, n):
     k = d.get("kernels", {}).get(kernel)
     if not k:
         return None
-    return (k["fetch_kib"] + k["write_kib"]) * 1024.0 * d.get("copy_scale", 1.0)
+    if not d.get("fetch_scale") or not d.get("write_scale"):
+        return None
+    return round((k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0)
 
 
 def cpu_baseline(iters, n_full, seed):

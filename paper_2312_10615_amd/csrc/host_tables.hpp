@@ -22,7 +22,7 @@ inline Geom make_geom(int nx, int ny, int nz, double h, double eta, double gamma
   g.sy = round_up(g.nx + 2, 8);
   g.sz = g.sy * (g.ny + 2);
   g.rows = (g.ny + 2) * (g.nz + 2);
-  g.field = round_up(g.sz * (g.nz + 2), 64);
+  g.field = g.sz * (g.nz + 2);  // a multiple of 8 elements (64 B), since sy is
   g.h = h * std::ldexp(1.0, level);
   g.inv_h = 1.0 / g.h;
   g.c = eta / (g.h * g.h);

@@ -23,6 +23,34 @@ __device__ __forceinline__ int logical_block() {
   return (b % NXCD) * per + b / NXCD;
 }
 
+// Slab mapping of the slot kernels: XCD x (physical block b runs on XCD
+// b % 8) owns the rows J in [x*R, (x+1)*R), R = ceil((ny+2)/8), for every
+// plane, and walks them plane by plane.  The planes K-1, K, K+1 of a slab
+// are a few hundred kB per field, so the z-neighbours a stencil reads are
+// still in that XCD's L2 when it reaches them.
+__device__ __forceinline__ int slab_rows(const Geom& g) { return (g.ny + 2 + NXCD - 1) / NXCD; }
+
+// Blocks for `per_row` items per row (slots, or pairs of slots) in slab mapping.
+__host__ __device__ inline int slab_blocks(const Geom& g, int per_row) {
+  const int R = (g.ny + 2 + NXCD - 1) / NXCD;
+  const long per_xcd = ((long)per_row * R * (g.nz + 2) + BS - 1) / BS;
+  return (int)(per_xcd * NXCD);
+}
+
+// Item (column index X within the row, row J, plane K) of this thread; false
+// when the thread is past the end of its slab.
+__device__ __forceinline__ bool slab_item(const Geom& g, int per_row, int& X, int& J, int& K) {
+  const int R = slab_rows(g);
+  const int xcd = blockIdx.x % NXCD;
+  const long l = (long)(blockIdx.x / NXCD) * BS + threadIdx.x;
+  X = (int)(l % per_row);
+  const long t = l / per_row;
+  const int jl = (int)(t % R);
+  K = (int)(t / R);
+  J = xcd * R + jl;
+  return K < g.nz + 2 && J < g.ny + 2;
+}
+
 __device__ __forceinline__ void slot_ijk(const Geom& g, int s, int& I, int& J, int& K) {
   K = s / g.sz;
   const int rem = s - K * g.sz;
@@ -77,11 +105,10 @@ enum ApplyMode { AP_APPLY = 0, AP_RESID = 1, AP_APPLY_DOT = 2, AP_RESNORM = 3, A
 template <int MODE, typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
                                               T* __restrict__ y, double gamma, double* __restrict__ partial) {
-  const int s = logical_block() * BS + threadIdx.x;
   double acc = 0.0;
-  if (s < g.field) {
-    int I, J, K;
-    slot_ijk(g, s, I, J, K);
+  int I, J, K;
+  if (slab_item(g, g.sy, I, J, K)) {
+    const int s = g.idx(I, J, K);
     const int F = g.field;
     const T* ux = x;
     const T* uy = x + F;
@@ -118,13 +145,9 @@ __global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, c
 // Distributive Gauss-Seidel on V2 (Alg. 2, Eq. dist, Eq. ldist, Appendix A).
 // Half-slot threads: thread t handles the slot of colour `colour` in its pair.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool half_slot(const Geom& g, int t, int colour, int& I, int& J, int& K) {
-  const int half = g.sy >> 1;
-  const int row = t / half;
-  if (row >= g.rows) return false;
-  const int m = t - row * half;
-  K = row / (g.ny + 2);
-  J = row - K * (g.ny + 2);
+__device__ __forceinline__ bool half_slot(const Geom& g, int colour, int& I, int& J, int& K) {
+  int m;
+  if (!slab_item(g, g.sy >> 1, m, J, K)) return false;
   I = 2 * m + ((colour + 1 + J + K) & 1);
   return true;
 }
@@ -135,7 +158,7 @@ __device__ __forceinline__ bool half_slot(const Geom& g, int t, int colour, int&
 template <typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_dgs_u(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
   int I, J, K;
-  if (!half_slot(g, logical_block() * BS + threadIdx.x, colour, I, J, K)) return;
+  if (!half_slot(g, colour, I, J, K)) return;
   const int s = g.idx(I, J, K);
   const int F = g.field;
   T* ux = x;
@@ -158,7 +181,7 @@ template <typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_dgs_pf_own(Geom g, T* __restrict__ x, const TB* __restrict__ b,
                                                    T* __restrict__ dscr, int colour) {
   int I, J, K;
-  if (!half_slot(g, logical_block() * BS + threadIdx.x, colour, I, J, K)) return;
+  if (!half_slot(g, colour, I, J, K)) return;
   if (!g.p_v2(I, J, K)) return;
   const int s = g.idx(I, J, K);
   const int F = g.field;
@@ -187,7 +210,7 @@ template <typename T>
 __global__ __launch_bounds__(BS) void k_dgs_pf_nbr(Geom g, T* __restrict__ x, const T* __restrict__ dscr,
                                                    int colour) {
   int I, J, K;
-  if (!half_slot(g, logical_block() * BS + threadIdx.x, colour ^ 1, I, J, K)) return;
+  if (!half_slot(g, colour ^ 1, I, J, K)) return;
   if (!g.p_active(I, J, K)) return;
   const int s = g.idx(I, J, K);
   T* p = x + 3 * g.field;
@@ -209,7 +232,7 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_nbr(Geom g, T* __restrict__ x, co
 template <typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
   int I, J, K;
-  if (!half_slot(g, logical_block() * BS + threadIdx.x, colour, I, J, K)) return;
+  if (!half_slot(g, colour, I, J, K)) return;
   if (!g.p_v2(I, J, K)) return;
   const int s = g.idx(I, J, K);
   const int F = g.field;
@@ -245,58 +268,75 @@ __global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const 
 // applies the corrections (part 2).  K^-1 of the local saddle problem comes
 // from a per-level table indexed by the 6-bit face-activity type.
 // ---------------------------------------------------------------------------
+// Eight lanes per subdomain: lane r < 7 evaluates local residual row r
+// (0: u_x minus face, 1: u_x plus face, 2/3: u_y, 4/5: u_z, 6: p), then
+// forms delta_r = sum_j (K^-1)_rj r_j with the group's residuals gathered
+// by shuffles.  delta is stored as 8 doubles per subdomain.
 template <typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
                                                     const int* __restrict__ cells, int ncells,
                                                     const double* __restrict__ kinv, double* __restrict__ delta) {
-  const int c = blockIdx.x * BS + threadIdx.x;
-  if (c >= ncells) return;
-  const int s = cells[c];
-  int I, J, K;
-  slot_ijk(g, s, I, J, K);
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int c = t >> 3;
+  const int r = t & 7;
+  const bool valid = c < ncells;
+  const int s = valid ? cells[c] : 0;
+  int I = 1, J = 1, K = 1;
+  if (valid) slot_ijk(g, s, I, J, K);
   const int F = g.field;
   const T* ux = x;
   const T* uy = x + F;
   const T* uz = x + 2 * F;
   const T* p = x + 3 * F;
-  double r[7];
-  int type = 0;
   const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
-  r[0] = a0 ? (double)b[s] - row_u(g, ux, p, s, 1) : 0.0;
-  r[1] = a1 ? (double)b[s + 1] - row_u(g, ux, p, s + 1, 1) : 0.0;
-  r[2] = a2 ? (double)b[F + s] - row_u(g, uy, p, s, g.sy) : 0.0;
-  r[3] = a3 ? (double)b[F + s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy) : 0.0;
-  r[4] = a4 ? (double)b[2 * F + s] - row_u(g, uz, p, s, g.sz) : 0.0;
-  r[5] = a5 ? (double)b[2 * F + s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz) : 0.0;
-  r[6] = (double)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma);
-  type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
-  const double* km = kinv + type * 64;
-#pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < 7; ++j) acc += km[i * 8 + j] * r[j];
-    delta[c * 8 + i] = acc;
+  double res = 0.0;
+  if (valid) {
+    switch (r) {
+      case 0: if (a0) res = (double)b[s] - row_u(g, ux, p, s, 1); break;
+      case 1: if (a1) res = (double)b[s + 1] - row_u(g, ux, p, s + 1, 1); break;
+      case 2: if (a2) res = (double)b[F + s] - row_u(g, uy, p, s, g.sy); break;
+      case 3: if (a3) res = (double)b[F + s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy); break;
+      case 4: if (a4) res = (double)b[2 * F + s] - row_u(g, uz, p, s, g.sz); break;
+      case 5: if (a5) res = (double)b[2 * F + s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz); break;
+      case 6: res = (double)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
+      default: break;
+    }
   }
+  const int type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
+  const double* km = kinv + type * 64 + (r & 7) * 8;
+  const int base = (int)(threadIdx.x & 63) & ~7;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    const double rj = __shfl(res, base + j, 64);
+    acc += km[j] * rj;
+  }
+  if (valid && r < 7) delta[c * 8 + r] = acc;
 }
 
+// x[local DOF r of subdomain c] += delta_r, eight lanes per subdomain.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
                                                     int ncells, const double* __restrict__ delta) {
-  const int c = blockIdx.x * BS + threadIdx.x;
-  if (c >= ncells) return;
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int c = t >> 3;
+  const int r = t & 7;
+  if (c >= ncells || r == 7) return;
   const int s = cells[c];
   int I, J, K;
   slot_ijk(g, s, I, J, K);
   const int F = g.field;
-  const double* d = delta + c * 8;
-  if (I >= 2) x[s] = (T)((double)x[s] + d[0]);
-  if (I + 1 <= g.nx) x[s + 1] = (T)((double)x[s + 1] + d[1]);
-  if (J >= 2) x[F + s] = (T)((double)x[F + s] + d[2]);
-  if (J + 1 <= g.ny) x[F + s + g.sy] = (T)((double)x[F + s + g.sy] + d[3]);
-  if (K >= 2) x[2 * F + s] = (T)((double)x[2 * F + s] + d[4]);
-  if (K + 1 <= g.nz) x[2 * F + s + g.sz] = (T)((double)x[2 * F + s + g.sz] + d[5]);
-  x[3 * F + s] = (T)((double)x[3 * F + s] + d[6]);
+  int e = -1;
+  switch (r) {
+    case 0: if (I >= 2) e = s; break;
+    case 1: if (I + 1 <= g.nx) e = s + 1; break;
+    case 2: if (J >= 2) e = F + s; break;
+    case 3: if (J + 1 <= g.ny) e = F + s + g.sy; break;
+    case 4: if (K >= 2) e = 2 * F + s; break;
+    case 5: if (K + 1 <= g.nz) e = 2 * F + s + g.sz; break;
+    default: e = 3 * F + s; break;
+  }
+  if (e >= 0) x[e] = (T)((double)x[e] + delta[c * 8 + r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -307,10 +347,9 @@ __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, c
 // every fine slot that is not an unknown).
 template <typename T>
 __global__ __launch_bounds__(BS) void k_restrict(Geom f, Geom c, const T* __restrict__ r, T* __restrict__ bc) {
-  const int s = logical_block() * BS + threadIdx.x;
-  if (s >= c.field) return;
   int I, J, K;
-  slot_ijk(c, s, I, J, K);
+  if (!slab_item(c, c.sy, I, J, K)) return;
+  const int s = c.idx(I, J, K);
   const int Ff = f.field, Fc = c.field;
   const double wf[3] = {0.5, 1.0, 0.5};          // face axis: fine 2I-2, 2I-1, 2I
   const double wc[4] = {0.25, 0.75, 0.75, 0.25};  // cell axis: fine 2J-2 .. 2J+1
@@ -389,10 +428,9 @@ __device__ __forceinline__ void face_w(int I, int& n0, int& n1, double& w0, doub
 // x_fine += P e_coarse, one thread per fine slot.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __restrict__ e, T* __restrict__ x) {
-  const int s = logical_block() * BS + threadIdx.x;
-  if (s >= f.field) return;
   int I, J, K;
-  slot_ijk(f, s, I, J, K);
+  if (!slab_item(f, f.sy, I, J, K)) return;
+  const int s = f.idx(I, J, K);
   const int Ff = f.field, Fc = c.field;
   if (f.ux_active(I, J, K)) {
     int a0, a1, b0, b1, c0, c1;

@@ -166,8 +166,8 @@ int grid_for(long slots) {
   return (int)nb;
 }
 
-int half_grid(const Geom& g) { return grid_for((long)g.rows * (g.sy / 2)); }
-int slot_grid(const Geom& g) { return grid_for(g.field); }
+int half_grid(const Geom& g) { return slab_blocks(g, g.sy / 2); }
+int slot_grid(const Geom& g) { return slab_blocks(g, g.sy); }
 
 #define HIPCHK(call)                                  \
   do {                                                \
@@ -215,7 +215,7 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
   c->q = cv.take<double>(c->total);
   c->d = cv.take<double>(c->total);
   long maxblk = RED_BLOCKS;
-  for (int l = 0; l < L; ++l) maxblk = std::max<long>(maxblk, grid_for(c->lev[l].g.field));
+  for (int l = 0; l < L; ++l) maxblk = std::max<long>(maxblk, std::max(grid_for(c->lev[l].g.field), slot_grid(c->lev[l].g)));
   c->npartial = (int)maxblk;
   c->partial = cv.take<double>(2 * maxblk);
   c->dscal = cv.take<double>(16);
@@ -285,7 +285,7 @@ void vanka_symmetric(stokes_ctx* c, int l, double* x, const double* b) {
     const int k = pass < 8 ? pass : 15 - pass;
     const int n = lv.nv[k];
     if (n == 0) continue;
-    const int nb = (n + BS - 1) / BS;
+    const int nb = (8 * n + BS - 1) / BS;  // eight lanes per subdomain
     const Geom g = lv.g;
     const int* cells = lv.vcells[k];
     const double* kinv = lv.kinv;
