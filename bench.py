@@ -113,6 +113,7 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--kernel", default="dgs_pr", help="dominant kernel class timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-V-cycle (mixed precision) leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
@@ -174,6 +175,37 @@ def main():
     torch.cuda.synchronize()
     vcycle_ms = ev0.elapsed_time(ev1) / nvc
 
+    mixed = None
+    if not args.no_mixed:
+        # Mixed precision: FP32 V-cycle inside FP64 SQMR, same input and tolerance.
+        s32 = StokesSolver(n, n, n, h=h, precision=32)
+        b32 = b  # same layout (the layout does not depend on the V-cycle precision)
+        x32, i32 = s32.solve(b32, rtol=args.rtol, maxit=500)
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        for _ in range(args.steps):
+            x32, i32 = s32.solve(b32, rtol=args.rtol, maxit=500)
+        torch.cuda.synchronize()
+        t32 = (time.perf_counter() - tm0) / args.steps
+        err = float(torch.linalg.vector_norm(x32 - x) / torch.linalg.vector_norm(x))
+        xa = s32.pack(tuple(np.random.default_rng(1).standard_normal(a.shape) for a in sol.unpack(b)))
+        ya = s32.pack(tuple(np.random.default_rng(2).standard_normal(a.shape) for a in sol.unpack(b)))
+        wa, wb = float(torch.dot(xa, s32.vcycle(ya))), float(torch.dot(s32.vcycle(xa), ya))
+        ev0.record()
+        for _ in range(nvc):
+            s32.vcycle(s, out=t)
+        ev1.record()
+        torch.cuda.synchronize()
+        mixed = {"value": round(t32, 6), "unit": "s", "iterations": i32["iters"], "final_relres": i32["relres"],
+                 "status": i32["status"], "speedup_vs_fp64": round(ms_per_step / 1000.0 / t32, 3),
+                 "rel_err_vs_fp64_solution": err, "vcycle_asymmetry": abs(wa - wb) / abs(wa),
+                 "vcycle_ms": round(ev0.elapsed_time(ev1) / nvc, 3),
+                 "form": "FP32 V-cycle (level vectors, smoothers, transfers, stencils), FP64 SQMR, dots, "
+                         "true residual and coarsest solve"}
+        del s32, x32, xa, ya
+        print(f"[bench] mixed: {t32 * 1e3:.1f} ms, iters={i32['iters']}, err={err:.2e}", file=sys.stderr,
+              flush=True)
+
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -211,6 +243,8 @@ def main():
                      "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": klaunch,
                      "algorithmic_bytes_per_launch": abytes},
     }
+    if mixed is not None:
+        line["mixed_precision"] = mixed
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(info["iters"], n, args.seed)

@@ -86,7 +86,10 @@ typedef struct stokes_params {
   int32_t nu;                 /* DGS sweeps per smoothing phase (pre and post), >= 1;
                                  even for STOKES_SMOOTHER_SYMMETRIC */
   int32_t n_boundary;         /* symmetric Vanka applications per Vanka slot of Alg. 3, >= 1 */
-  int32_t vcycle_precision;   /* 64 (FP64 V-cycle) */
+  int32_t vcycle_precision;   /* 64: FP64 V-cycle.  32: the V-cycle's level vectors, smoother,
+                                 transfer and stencil arithmetic in FP32 (s converted on entry,
+                                 t converted back on exit, coarsest solve accumulated in FP64);
+                                 SQMR recurrences, inner products and the true residual stay FP64 */
   int32_t smoother;           /* STOKES_SMOOTHER_* */
   int32_t flags;              /* STOKES_FLAG_* */
 } stokes_params;

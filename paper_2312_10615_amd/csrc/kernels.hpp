@@ -74,24 +74,23 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// Rows of the operator (Eq. 2 / Section 4).  s = slot of the row, T = storage.
+// Rows of the operator (Eq. 2 / Section 4).  s = slot of the row; T is both
+// the storage and the arithmetic type (FP64, or FP32 inside an FP32 V-cycle).
 //   u_x row: (eta/h^2)(6u - 6 lattice neighbours) + (p(I,J,K) - p(I-1,J,K))/h
 //   p row  : -(1/h) sum_a (u_a(plus face) - u_a(minus face)) - gamma p
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ double row_u(const Geom& g, const T* __restrict__ u, const T* __restrict__ p, int s,
+__device__ __forceinline__ T row_u(const Geom& g, const T* __restrict__ u, const T* __restrict__ p, int s,
                                         int pstride) {
-  const double lap = 6.0 * (double)u[s] - (double)u[s - 1] - (double)u[s + 1] - (double)u[s - g.sy] -
-                     (double)u[s + g.sy] - (double)u[s - g.sz] - (double)u[s + g.sz];
-  return g.c * lap + ((double)p[s] - (double)p[s - pstride]) * g.inv_h;
+  const T lap = T(6) * u[s] - u[s - 1] - u[s + 1] - u[s - g.sy] - u[s + g.sy] - u[s - g.sz] - u[s + g.sz];
+  return (T)g.c * lap + (p[s] - p[s - pstride]) * (T)g.inv_h;
 }
 
 template <typename T>
-__device__ __forceinline__ double row_p(const Geom& g, const T* __restrict__ ux, const T* __restrict__ uy,
+__device__ __forceinline__ T row_p(const Geom& g, const T* __restrict__ ux, const T* __restrict__ uy,
                                         const T* __restrict__ uz, const T* __restrict__ p, int s, double gamma) {
-  const double div = ((double)ux[s + 1] - (double)ux[s]) + ((double)uy[s + g.sy] - (double)uy[s]) +
-                     ((double)uz[s + g.sz] - (double)uz[s]);
-  return -div * g.inv_h - gamma * (double)p[s];
+  const T div = (ux[s + 1] - ux[s]) + (uy[s + g.sy] - uy[s]) + (uz[s + g.sz] - uz[s]);
+  return -div * (T)g.inv_h - (T)gamma * p[s];
 }
 
 enum ApplyMode { AP_APPLY = 0, AP_RESID = 1, AP_APPLY_DOT = 2, AP_RESNORM = 3, AP_BNORM = 4 };
@@ -114,7 +113,7 @@ __global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, c
     const T* uy = x + F;
     const T* uz = x + 2 * F;
     const T* p = x + 3 * F;
-    double o[4] = {0.0, 0.0, 0.0, 0.0};
+    T o[4] = {T(0), T(0), T(0), T(0)};
     bool act[4];
     act[0] = g.ux_active(I, J, K);
     act[1] = g.uy_active(I, J, K);
@@ -128,10 +127,10 @@ __global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, c
     }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      double v = o[f];
-      if (MODE == AP_RESID || MODE == AP_RESNORM || MODE == AP_BNORM) v = act[f] ? (double)b[f * F + s] - v : 0.0;
-      if (MODE == AP_APPLY || MODE == AP_RESID || MODE == AP_APPLY_DOT) y[f * F + s] = (T)v;
-      if (MODE == AP_APPLY_DOT) acc += (double)x[f * F + s] * (double)(T)v;
+      T v = o[f];
+      if (MODE == AP_RESID || MODE == AP_RESNORM || MODE == AP_BNORM) v = act[f] ? (T)b[f * F + s] - v : T(0);
+      if (MODE == AP_APPLY || MODE == AP_RESID || MODE == AP_APPLY_DOT) y[f * F + s] = v;
+      if (MODE == AP_APPLY_DOT) acc += (double)x[f * F + s] * (double)v;
       if (MODE == AP_RESNORM || MODE == AP_BNORM) acc += v * v;
     }
   }
@@ -165,10 +164,10 @@ __global__ __launch_bounds__(BS) void k_dgs_u(Geom g, T* __restrict__ x, const T
   T* uy = x + F;
   T* uz = x + 2 * F;
   const T* p = x + 3 * F;
-  const double dinv = 1.0 / (6.0 * g.c);
-  if (g.ux_v2(I, J, K)) ux[s] = (T)((double)ux[s] + ((double)b[s] - row_u(g, ux, p, s, 1)) * dinv);
-  if (g.uy_v2(I, J, K)) uy[s] = (T)((double)uy[s] + ((double)b[F + s] - row_u(g, uy, p, s, g.sy)) * dinv);
-  if (g.uz_v2(I, J, K)) uz[s] = (T)((double)uz[s] + ((double)b[2 * F + s] - row_u(g, uz, p, s, g.sz)) * dinv);
+  const T dinv = (T)(1.0 / (6.0 * g.c));
+  if (g.ux_v2(I, J, K)) ux[s] = ux[s] + ((T)b[s] - row_u(g, ux, p, s, 1)) * dinv;
+  if (g.uy_v2(I, J, K)) uy[s] = uy[s] + ((T)b[F + s] - row_u(g, uy, p, s, g.sy)) * dinv;
+  if (g.uz_v2(I, J, K)) uz[s] = uz[s] + ((T)b[2 * F + s] - row_u(g, uz, p, s, g.sz)) * dinv;
 }
 
 // Pressure step of the forward sweep, part 1, on the V2 cells of one colour:
@@ -190,17 +189,17 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_own(Geom g, T* __restrict__ x, co
   T* uz = x + 2 * F;
   T* p = x + 3 * F;
   const double ih2 = g.inv_h * g.inv_h;
-  const double r = (double)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma);
-  const double delta = r / (-6.0 * (1.0 + g.gamma * g.eta) * ih2);
-  dscr[s] = (T)delta;
-  const double dh = delta * g.inv_h;
-  ux[s] = (T)((double)ux[s] - dh);
-  ux[s + 1] = (T)((double)ux[s + 1] + dh);
-  uy[s] = (T)((double)uy[s] - dh);
-  uy[s + g.sy] = (T)((double)uy[s + g.sy] + dh);
-  uz[s] = (T)((double)uz[s] - dh);
-  uz[s + g.sz] = (T)((double)uz[s + g.sz] + dh);
-  p[s] = (T)((double)p[s] + 6.0 * g.eta * delta * ih2);
+  const T r = (T)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma);
+  const T delta = r / (T)(-6.0 * (1.0 + g.gamma * g.eta) * ih2);
+  dscr[s] = delta;
+  const T dh = delta * (T)g.inv_h;
+  ux[s] = ux[s] - dh;
+  ux[s + 1] = ux[s + 1] + dh;
+  uy[s] = uy[s] - dh;
+  uy[s + g.sy] = uy[s + g.sy] + dh;
+  uz[s] = uz[s] - dh;
+  uz[s + g.sz] = uz[s + g.sz] + dh;
+  p[s] = p[s] + (T)(6.0 * g.eta * ih2) * delta;
 }
 
 // Part 2 on every cell of the other colour (V1 ring cells included): p_k -=
@@ -214,14 +213,14 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_nbr(Geom g, T* __restrict__ x, co
   if (!g.p_active(I, J, K)) return;
   const int s = g.idx(I, J, K);
   T* p = x + 3 * g.field;
-  double sum = 0.0;
-  if (g.p_v2(I - 1, J, K)) sum += (double)dscr[s - 1];
-  if (g.p_v2(I + 1, J, K)) sum += (double)dscr[s + 1];
-  if (g.p_v2(I, J - 1, K)) sum += (double)dscr[s - g.sy];
-  if (g.p_v2(I, J + 1, K)) sum += (double)dscr[s + g.sy];
-  if (g.p_v2(I, J, K - 1)) sum += (double)dscr[s - g.sz];
-  if (g.p_v2(I, J, K + 1)) sum += (double)dscr[s + g.sz];
-  if (sum != 0.0) p[s] = (T)((double)p[s] - g.eta * g.inv_h * g.inv_h * sum);
+  T sum = T(0);
+  if (g.p_v2(I - 1, J, K)) sum += dscr[s - 1];
+  if (g.p_v2(I + 1, J, K)) sum += dscr[s + 1];
+  if (g.p_v2(I, J - 1, K)) sum += dscr[s - g.sy];
+  if (g.p_v2(I, J + 1, K)) sum += dscr[s + g.sy];
+  if (g.p_v2(I, J, K - 1)) sum += dscr[s - g.sz];
+  if (g.p_v2(I, J, K + 1)) sum += dscr[s + g.sz];
+  if (sum != T(0)) p[s] = p[s] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
 }
 
 // Pressure step of the reverse sweep (Gauss-Seidel on M^T L~, Eq. ldist) on
@@ -245,20 +244,20 @@ __global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const 
   const TB* buz = b + 2 * F;
   const TB* bp = b + 3 * F;
   // sum_a (r(plus face) - r(minus face))
-  double fsum = ((double)bux[s + 1] - row_u(g, ux, p, s + 1, 1)) - ((double)bux[s] - row_u(g, ux, p, s, 1));
-  fsum += ((double)buy[s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy)) - ((double)buy[s] - row_u(g, uy, p, s, g.sy));
-  fsum += ((double)buz[s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz)) - ((double)buz[s] - row_u(g, uz, p, s, g.sz));
+  T fsum = ((T)bux[s + 1] - row_u(g, ux, p, s + 1, 1)) - ((T)bux[s] - row_u(g, ux, p, s, 1));
+  fsum += ((T)buy[s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy)) - ((T)buy[s] - row_u(g, uy, p, s, g.sy));
+  fsum += ((T)buz[s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz)) - ((T)buz[s] - row_u(g, uz, p, s, g.sz));
   const double gam = g.gamma;
-  const double rj = (double)bp[s] - row_p(g, ux, uy, uz, p, s, gam);
-  double nsum = (double)bp[s - 1] - row_p(g, ux, uy, uz, p, s - 1, gam);
-  nsum += (double)bp[s + 1] - row_p(g, ux, uy, uz, p, s + 1, gam);
-  nsum += (double)bp[s - g.sy] - row_p(g, ux, uy, uz, p, s - g.sy, gam);
-  nsum += (double)bp[s + g.sy] - row_p(g, ux, uy, uz, p, s + g.sy, gam);
-  nsum += (double)bp[s - g.sz] - row_p(g, ux, uy, uz, p, s - g.sz, gam);
-  nsum += (double)bp[s + g.sz] - row_p(g, ux, uy, uz, p, s + g.sz, gam);
+  const T rj = (T)bp[s] - row_p(g, ux, uy, uz, p, s, gam);
+  T nsum = (T)bp[s - 1] - row_p(g, ux, uy, uz, p, s - 1, gam);
+  nsum += (T)bp[s + 1] - row_p(g, ux, uy, uz, p, s + 1, gam);
+  nsum += (T)bp[s - g.sy] - row_p(g, ux, uy, uz, p, s - g.sy, gam);
+  nsum += (T)bp[s + g.sy] - row_p(g, ux, uy, uz, p, s + g.sy, gam);
+  nsum += (T)bp[s - g.sz] - row_p(g, ux, uy, uz, p, s - g.sz, gam);
+  nsum += (T)bp[s + g.sz] - row_p(g, ux, uy, uz, p, s + g.sz, gam);
   const double ih2 = g.inv_h * g.inv_h;
-  const double rt = fsum * g.inv_h + g.eta * ih2 * (6.0 * rj - nsum);
-  p[s] = (T)((double)p[s] + rt / (-6.0 * (1.0 + gam * g.eta) * ih2));
+  const T rt = fsum * (T)g.inv_h + (T)(g.eta * ih2) * (T(6) * rj - nsum);
+  p[s] = p[s] + rt / (T)(-6.0 * (1.0 + gam * g.eta) * ih2);
 }
 
 // ---------------------------------------------------------------------------
@@ -271,11 +270,11 @@ __global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const 
 // Eight lanes per subdomain: lane r < 7 evaluates local residual row r
 // (0: u_x minus face, 1: u_x plus face, 2/3: u_y, 4/5: u_z, 6: p), then
 // forms delta_r = sum_j (K^-1)_rj r_j with the group's residuals gathered
-// by shuffles.  delta is stored as 8 doubles per subdomain.
+// by shuffles.  delta is stored as 8 values per subdomain.
 template <typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
                                                     const int* __restrict__ cells, int ncells,
-                                                    const double* __restrict__ kinv, double* __restrict__ delta) {
+                                                    const T* __restrict__ kinv, T* __restrict__ delta) {
   const int t = blockIdx.x * BS + threadIdx.x;
   const int c = t >> 3;
   const int r = t & 7;
@@ -289,26 +288,26 @@ __global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict_
   const T* uz = x + 2 * F;
   const T* p = x + 3 * F;
   const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
-  double res = 0.0;
+  T res = T(0);
   if (valid) {
     switch (r) {
-      case 0: if (a0) res = (double)b[s] - row_u(g, ux, p, s, 1); break;
-      case 1: if (a1) res = (double)b[s + 1] - row_u(g, ux, p, s + 1, 1); break;
-      case 2: if (a2) res = (double)b[F + s] - row_u(g, uy, p, s, g.sy); break;
-      case 3: if (a3) res = (double)b[F + s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy); break;
-      case 4: if (a4) res = (double)b[2 * F + s] - row_u(g, uz, p, s, g.sz); break;
-      case 5: if (a5) res = (double)b[2 * F + s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz); break;
-      case 6: res = (double)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
+      case 0: if (a0) res = (T)b[s] - row_u(g, ux, p, s, 1); break;
+      case 1: if (a1) res = (T)b[s + 1] - row_u(g, ux, p, s + 1, 1); break;
+      case 2: if (a2) res = (T)b[F + s] - row_u(g, uy, p, s, g.sy); break;
+      case 3: if (a3) res = (T)b[F + s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy); break;
+      case 4: if (a4) res = (T)b[2 * F + s] - row_u(g, uz, p, s, g.sz); break;
+      case 5: if (a5) res = (T)b[2 * F + s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz); break;
+      case 6: res = (T)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
       default: break;
     }
   }
   const int type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
-  const double* km = kinv + type * 64 + (r & 7) * 8;
+  const T* km = kinv + type * 64 + (r & 7) * 8;
   const int base = (int)(threadIdx.x & 63) & ~7;
-  double acc = 0.0;
+  T acc = T(0);
 #pragma unroll
   for (int j = 0; j < 7; ++j) {
-    const double rj = __shfl(res, base + j, 64);
+    const T rj = __shfl(res, base + j, 64);
     acc += km[j] * rj;
   }
   if (valid && r < 7) delta[c * 8 + r] = acc;
@@ -317,7 +316,7 @@ __global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict_
 // x[local DOF r of subdomain c] += delta_r, eight lanes per subdomain.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
-                                                    int ncells, const double* __restrict__ delta) {
+                                                    int ncells, const T* __restrict__ delta) {
   const int t = blockIdx.x * BS + threadIdx.x;
   const int c = t >> 3;
   const int r = t & 7;
@@ -336,7 +335,7 @@ __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, c
     case 5: if (K + 1 <= g.nz) e = 2 * F + s + g.sz; break;
     default: e = 3 * F + s; break;
   }
-  if (e >= 0) x[e] = (T)((double)x[e] + delta[c * 8 + r]);
+  if (e >= 0) x[e] = x[e] + delta[c * 8 + r];
 }
 
 // ---------------------------------------------------------------------------
@@ -351,52 +350,52 @@ __global__ __launch_bounds__(BS) void k_restrict(Geom f, Geom c, const T* __rest
   if (!slab_item(c, c.sy, I, J, K)) return;
   const int s = c.idx(I, J, K);
   const int Ff = f.field, Fc = c.field;
-  const double wf[3] = {0.5, 1.0, 0.5};          // face axis: fine 2I-2, 2I-1, 2I
-  const double wc[4] = {0.25, 0.75, 0.75, 0.25};  // cell axis: fine 2J-2 .. 2J+1
+  const T wf[3] = {0.5, 1.0, 0.5};          // face axis: fine 2I-2, 2I-1, 2I
+  const T wc[4] = {0.25, 0.75, 0.75, 0.25};  // cell axis: fine 2J-2 .. 2J+1
   // u_x
   {
-    double acc = 0.0;
+    T acc = T(0);
     if (c.ux_active(I, J, K)) {
       for (int kk = 0; kk < 4; ++kk)
         for (int jj = 0; jj < 4; ++jj) {
-          const double w = wc[jj] * wc[kk];
+          const T w = wc[jj] * wc[kk];
           const int base = f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk);
-          acc += w * (wf[0] * (double)r[base] + wf[1] * (double)r[base + 1] + wf[2] * (double)r[base + 2]);
+          acc += w * (wf[0] * (T)r[base] + wf[1] * (T)r[base + 1] + wf[2] * (T)r[base + 2]);
         }
     }
-    bc[s] = (T)(acc * 0.125);
+    bc[s] = (T)(acc * T(0.125));
   }
   // u_y
   {
-    double acc = 0.0;
+    T acc = T(0);
     if (c.uy_active(I, J, K)) {
       for (int kk = 0; kk < 4; ++kk)
         for (int jj = 0; jj < 3; ++jj)
           for (int ii = 0; ii < 4; ++ii)
-            acc += wc[ii] * wf[jj] * wc[kk] * (double)r[Ff + f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk)];
+            acc += wc[ii] * wf[jj] * wc[kk] * (T)r[Ff + f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk)];
     }
-    bc[Fc + s] = (T)(acc * 0.125);
+    bc[Fc + s] = (T)(acc * T(0.125));
   }
   // u_z
   {
-    double acc = 0.0;
+    T acc = T(0);
     if (c.uz_active(I, J, K)) {
       for (int kk = 0; kk < 3; ++kk)
         for (int jj = 0; jj < 4; ++jj)
           for (int ii = 0; ii < 4; ++ii)
-            acc += wc[ii] * wc[jj] * wf[kk] * (double)r[2 * Ff + f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk)];
+            acc += wc[ii] * wc[jj] * wf[kk] * (T)r[2 * Ff + f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk)];
     }
-    bc[2 * Fc + s] = (T)(acc * 0.125);
+    bc[2 * Fc + s] = (T)(acc * T(0.125));
   }
   // p
   {
-    double acc = 0.0;
+    T acc = T(0);
     if (c.p_active(I, J, K)) {
       for (int kk = 0; kk < 2; ++kk)
         for (int jj = 0; jj < 2; ++jj)
-          for (int ii = 0; ii < 2; ++ii) acc += (double)r[3 * Ff + f.idx(2 * I - 1 + ii, 2 * J - 1 + jj, 2 * K - 1 + kk)];
+          for (int ii = 0; ii < 2; ++ii) acc += (T)r[3 * Ff + f.idx(2 * I - 1 + ii, 2 * J - 1 + jj, 2 * K - 1 + kk)];
     }
-    bc[3 * Fc + s] = (T)(acc * 0.125);
+    bc[3 * Fc + s] = (T)(acc * T(0.125));
   }
 }
 
@@ -438,12 +437,12 @@ __global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __r
     face_w(I, a0, a1, w0, w1);
     cell_w(J, b0, b1);
     cell_w(K, c0, c1);
-    auto at = [&](int i, int j, int k) { return (double)e[c.idx(i, j, k)]; };
-    const double v = w0 * (0.75 * (0.75 * at(a0, b0, c0) + 0.25 * at(a0, b1, c0)) +
-                           0.25 * (0.75 * at(a0, b0, c1) + 0.25 * at(a0, b1, c1))) +
-                     w1 * (0.75 * (0.75 * at(a1, b0, c0) + 0.25 * at(a1, b1, c0)) +
-                           0.25 * (0.75 * at(a1, b0, c1) + 0.25 * at(a1, b1, c1)));
-    x[s] = (T)((double)x[s] + v);
+    auto at = [&](int i, int j, int k) { return (T)e[c.idx(i, j, k)]; };
+    const T v = (T)w0 * (T(0.75) * (T(0.75) * at(a0, b0, c0) + T(0.25) * at(a0, b1, c0)) +
+                           T(0.25) * (T(0.75) * at(a0, b0, c1) + T(0.25) * at(a0, b1, c1))) +
+                     (T)w1 * (T(0.75) * (T(0.75) * at(a1, b0, c0) + T(0.25) * at(a1, b1, c0)) +
+                           T(0.25) * (T(0.75) * at(a1, b0, c1) + T(0.25) * at(a1, b1, c1)));
+    x[s] = x[s] + v;
   }
   if (f.uy_active(I, J, K)) {
     int a0, a1, b0, b1, c0, c1;
@@ -451,12 +450,12 @@ __global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __r
     face_w(J, b0, b1, w0, w1);
     cell_w(I, a0, a1);
     cell_w(K, c0, c1);
-    auto at = [&](int i, int j, int k) { return (double)e[Fc + c.idx(i, j, k)]; };
-    const double v = w0 * (0.75 * (0.75 * at(a0, b0, c0) + 0.25 * at(a1, b0, c0)) +
-                           0.25 * (0.75 * at(a0, b0, c1) + 0.25 * at(a1, b0, c1))) +
-                     w1 * (0.75 * (0.75 * at(a0, b1, c0) + 0.25 * at(a1, b1, c0)) +
-                           0.25 * (0.75 * at(a0, b1, c1) + 0.25 * at(a1, b1, c1)));
-    x[Ff + s] = (T)((double)x[Ff + s] + v);
+    auto at = [&](int i, int j, int k) { return (T)e[Fc + c.idx(i, j, k)]; };
+    const T v = (T)w0 * (T(0.75) * (T(0.75) * at(a0, b0, c0) + T(0.25) * at(a1, b0, c0)) +
+                           T(0.25) * (T(0.75) * at(a0, b0, c1) + T(0.25) * at(a1, b0, c1))) +
+                     (T)w1 * (T(0.75) * (T(0.75) * at(a0, b1, c0) + T(0.25) * at(a1, b1, c0)) +
+                           T(0.25) * (T(0.75) * at(a0, b1, c1) + T(0.25) * at(a1, b1, c1)));
+    x[Ff + s] = x[Ff + s] + v;
   }
   if (f.uz_active(I, J, K)) {
     int a0, a1, b0, b1, c0, c1;
@@ -464,16 +463,16 @@ __global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __r
     face_w(K, c0, c1, w0, w1);
     cell_w(I, a0, a1);
     cell_w(J, b0, b1);
-    auto at = [&](int i, int j, int k) { return (double)e[2 * Fc + c.idx(i, j, k)]; };
-    const double v = w0 * (0.75 * (0.75 * at(a0, b0, c0) + 0.25 * at(a1, b0, c0)) +
-                           0.25 * (0.75 * at(a0, b1, c0) + 0.25 * at(a1, b1, c0))) +
-                     w1 * (0.75 * (0.75 * at(a0, b0, c1) + 0.25 * at(a1, b0, c1)) +
-                           0.25 * (0.75 * at(a0, b1, c1) + 0.25 * at(a1, b1, c1)));
-    x[2 * Ff + s] = (T)((double)x[2 * Ff + s] + v);
+    auto at = [&](int i, int j, int k) { return (T)e[2 * Fc + c.idx(i, j, k)]; };
+    const T v = (T)w0 * (T(0.75) * (T(0.75) * at(a0, b0, c0) + T(0.25) * at(a1, b0, c0)) +
+                           T(0.25) * (T(0.75) * at(a0, b1, c0) + T(0.25) * at(a1, b1, c0))) +
+                     (T)w1 * (T(0.75) * (T(0.75) * at(a0, b0, c1) + T(0.25) * at(a1, b0, c1)) +
+                           T(0.25) * (T(0.75) * at(a0, b1, c1) + T(0.25) * at(a1, b1, c1)));
+    x[2 * Ff + s] = x[2 * Ff + s] + v;
   }
   if (f.p_active(I, J, K)) {
     const int ci = ((I - 1) >> 1) + 1, cj = ((J - 1) >> 1) + 1, ck = ((K - 1) >> 1) + 1;
-    x[3 * Ff + s] = (T)((double)x[3 * Ff + s] + (double)e[3 * Fc + c.idx(ci, cj, ck)]);
+    x[3 * Ff + s] = x[3 * Ff + s] + e[3 * Fc + c.idx(ci, cj, ck)];
   }
 }
 
@@ -500,6 +499,12 @@ __global__ __launch_bounds__(BS) void k_coarse_solve(const double* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(BS) void k_fill(T* __restrict__ x, long n, T v) {
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) x[i] = v;
+}
+
+// out = (To) in, elementwise (FP64 <-> FP32 at the V-cycle's entry and exit)
+template <typename Ti, typename To>
+__global__ __launch_bounds__(BS) void k_convert(const Ti* __restrict__ in, To* __restrict__ out, long n) {
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) out[i] = (To)in[i];
 }
 
 // partial[2*blk] = sum a.a, partial[2*blk+1] = sum a.c

@@ -22,15 +22,17 @@ using namespace sg;
 
 namespace {
 
+// Level buffers hold the V-cycle's storage type (double, or float for an
+// FP32 V-cycle).
 struct Level {
   Geom g;
-  double* b = nullptr;   // right-hand side (levels >= 1; level 0 uses the caller's)
-  double* x = nullptr;   // iterate (levels >= 1)
-  double* r = nullptr;   // residual scratch (all but the coarsest)
-  double* dscr = nullptr;  // DGS pressure-step deltas (p field)
+  void* b = nullptr;     // right-hand side (levels >= 1; level 0 only for an FP32 V-cycle)
+  void* x = nullptr;     // iterate (same)
+  void* r = nullptr;     // residual scratch (all but the coarsest)
+  void* dscr = nullptr;  // DGS pressure-step deltas (p field)
   int* vcells[8] = {};
   int nv[8] = {};
-  double* kinv = nullptr;  // 64 x 8 x 8 Vanka local inverses
+  void* kinv = nullptr;  // 64 x 8 x 8 Vanka local inverses
 };
 
 struct Carver {
@@ -69,7 +71,8 @@ struct stokes_ctx {
   int* cdof = nullptr;
   int nc = 0;
   // Vanka delta scratch (max colour count x 8)
-  double* vdelta = nullptr;
+  void* vdelta = nullptr;
+  int prec = 64;  // V-cycle precision
   // kernel timing (diagnostics)
   int prof_class = STOKES_KC_OFF, prof_level = -1;
   struct Pending { int k, l; hipEvent_t a, b; };
@@ -189,7 +192,7 @@ int validate(const stokes_params* p, int* levels_out) {
   if (p->nu < 1 || p->n_boundary < 1) return STOKES_EINVAL;
   if (p->smoother != STOKES_SMOOTHER_SPLIT && p->smoother != STOKES_SMOOTHER_SYMMETRIC) return STOKES_EINVAL;
   if (p->smoother == STOKES_SMOOTHER_SYMMETRIC && (p->nu % 2)) return STOKES_EINVAL;
-  if (p->vcycle_precision != 64) return STOKES_EINVAL;
+  if (p->vcycle_precision != 64 && p->vcycle_precision != 32) return STOKES_EINVAL;
   int L = p->levels;
   if (L == 0) L = count_levels(p->nx, p->ny, p->nz, 4);
   if (L < 1 || L > count_levels(p->nx, p->ny, p->nz, 2)) return STOKES_EINVAL;
@@ -206,6 +209,8 @@ int validate(const stokes_params* p, int* levels_out) {
 // Lay out (or size, when dry) everything the context keeps in the workspace.
 void carve(stokes_ctx* c, Carver& cv, int L) {
   const stokes_params& p = c->prm;
+  c->prec = p.vcycle_precision;
+  const size_t es = c->prec == 32 ? sizeof(float) : sizeof(double);
   c->lev.assign(L, Level{});
   for (int l = 0; l < L; ++l) c->lev[l].g = make_geom(p.nx, p.ny, p.nz, p.h, p.eta, p.gamma, l);
   const Geom& g0 = c->lev[0].g;
@@ -215,7 +220,8 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
   c->q = cv.take<double>(c->total);
   c->d = cv.take<double>(c->total);
   long maxblk = RED_BLOCKS;
-  for (int l = 0; l < L; ++l) maxblk = std::max<long>(maxblk, std::max(grid_for(c->lev[l].g.field), slot_grid(c->lev[l].g)));
+  for (int l = 0; l < L; ++l)
+    maxblk = std::max<long>(maxblk, std::max(grid_for(c->lev[l].g.field), slot_grid(c->lev[l].g)));
   c->npartial = (int)maxblk;
   c->partial = cv.take<double>(2 * maxblk);
   c->dscal = cv.take<double>(16);
@@ -223,14 +229,14 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
   for (int l = 0; l < L; ++l) {
     Level& lv = c->lev[l];
     const long tot = 4L * lv.g.field;
-    if (l > 0) {
-      lv.b = cv.take<double>(tot);
-      lv.x = cv.take<double>(tot);
+    if (l > 0 || c->prec == 32) {
+      lv.b = cv.take<char>(tot * es);
+      lv.x = cv.take<char>(tot * es);
     }
     if (l < L - 1) {
-      lv.r = cv.take<double>(tot);
-      lv.dscr = cv.take<double>(lv.g.field);
-      lv.kinv = cv.take<double>(64 * 64);
+      lv.r = cv.take<char>(tot * es);
+      lv.dscr = cv.take<char>(lv.g.field * es);
+      lv.kinv = cv.take<char>(64 * 64 * es);
       std::vector<int> cells[8];
       vanka_cells(lv.g, cells);
       for (int k = 0; k < 8; ++k) {
@@ -240,7 +246,7 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
       }
     }
   }
-  c->vdelta = cv.take<double>(8 * std::max<long>(vmax, 1));
+  c->vdelta = cv.take<char>(8 * std::max<long>(vmax, 1) * es);
   const Geom& gc = c->lev[L - 1].g;
   c->nc = (int)coarse_dofs(gc);
   c->cinv = cv.take<double>((size_t)c->nc * c->nc);
@@ -279,7 +285,8 @@ void launch(stokes_ctx* c, int cls, int level, F f) {
   f();
 }
 
-void vanka_symmetric(stokes_ctx* c, int l, double* x, const double* b) {
+template <typename T>
+void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
   const Level& lv = c->lev[l];
   for (int pass = 0; pass < 16; ++pass) {
     const int k = pass < 8 ? pass : 15 - pass;
@@ -288,45 +295,46 @@ void vanka_symmetric(stokes_ctx* c, int l, double* x, const double* b) {
     const int nb = (8 * n + BS - 1) / BS;  // eight lanes per subdomain
     const Geom g = lv.g;
     const int* cells = lv.vcells[k];
-    const double* kinv = lv.kinv;
-    double* vd = c->vdelta;
-    launch(c, STOKES_KC_VANKA_DELTA, l, [=] {
-      k_vanka_delta<double, double><<<nb, BS, 0, c->ks>>>(g, x, b, cells, n, kinv, vd);
-    });
-    launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_vanka_apply<double><<<nb, BS, 0, c->ks>>>(g, x, cells, n, vd); });
+    const T* kinv = (const T*)lv.kinv;
+    T* vd = (T*)c->vdelta;
+    launch(c, STOKES_KC_VANKA_DELTA, l,
+           [=] { k_vanka_delta<T, T><<<nb, BS, 0, c->ks>>>(g, x, b, cells, n, kinv, vd); });
+    launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_vanka_apply<T><<<nb, BS, 0, c->ks>>>(g, x, cells, n, vd); });
   }
 }
 
 // Forward DGS sweep on L~ M (Alg. 2, Eq. dist) over the V2 unknowns:
 // velocities red, black; pressures red, black.
-void dgs_forward(stokes_ctx* c, int l, double* x, const double* b) {
+template <typename T>
+void dgs_forward(stokes_ctx* c, int l, T* x, const T* b) {
   const Geom g = c->lev[l].g;
-  double* dscr = c->lev[l].dscr;
+  T* dscr = (T*)c->lev[l].dscr;
   const int hg = half_grid(g);
   for (int col = 0; col < 2; ++col)
-    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u<double, double><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
+    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u<T, T><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
   for (int col = 0; col < 2; ++col) {
-    launch(c, STOKES_KC_DGS_PF_OWN, l,
-           [=] { k_dgs_pf_own<double, double><<<hg, BS, 0, c->ks>>>(g, x, b, dscr, col); });
-    launch(c, STOKES_KC_DGS_PF_NBR, l, [=] { k_dgs_pf_nbr<double><<<hg, BS, 0, c->ks>>>(g, x, dscr, col); });
+    launch(c, STOKES_KC_DGS_PF_OWN, l, [=] { k_dgs_pf_own<T, T><<<hg, BS, 0, c->ks>>>(g, x, b, dscr, col); });
+    launch(c, STOKES_KC_DGS_PF_NBR, l, [=] { k_dgs_pf_nbr<T><<<hg, BS, 0, c->ks>>>(g, x, dscr, col); });
   }
 }
 
 // Reverse sweep: Gauss-Seidel on M^T L~ (Eq. ldist) in exactly the reverse
 // order: pressures black, red; velocities black, red.
-void dgs_reverse(stokes_ctx* c, int l, double* x, const double* b) {
+template <typename T>
+void dgs_reverse(stokes_ctx* c, int l, T* x, const T* b) {
   const Geom g = c->lev[l].g;
   const int hg = half_grid(g);
   for (int col = 1; col >= 0; --col)
-    launch(c, STOKES_KC_DGS_PR, l, [=] { k_dgs_pr<double, double><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
+    launch(c, STOKES_KC_DGS_PR, l, [=] { k_dgs_pr<T, T><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
   for (int col = 1; col >= 0; --col)
-    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u<double, double><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
+    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u<T, T><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
 }
 
 enum Interior { INT_SYMMETRIC, INT_REVERSE, INT_FORWARD };
 
 // Alg. 3: symmetric Vanka on V1, interior smoother on V2, symmetric Vanka on V1.
-void smooth(stokes_ctx* c, int l, double* x, const double* b, Interior kind, int sweeps) {
+template <typename T>
+void smooth(stokes_ctx* c, int l, T* x, const T* b, Interior kind, int sweeps) {
   for (int i = 0; i < c->prm.n_boundary; ++i) vanka_symmetric(c, l, x, b);
   for (int i = 0; i < sweeps; ++i) {
     if (kind != INT_FORWARD) {
@@ -339,7 +347,8 @@ void smooth(stokes_ctx* c, int l, double* x, const double* b, Interior kind, int
   for (int i = 0; i < c->prm.n_boundary; ++i) vanka_symmetric(c, l, x, b);
 }
 
-void presmooth(stokes_ctx* c, int l, double* x, const double* b) {
+template <typename T>
+void presmooth(stokes_ctx* c, int l, T* x, const T* b) {
   if (c->prm.smoother == STOKES_SMOOTHER_SYMMETRIC) {
     for (int i = 0; i < c->prm.nu / 2; ++i) smooth(c, l, x, b, INT_SYMMETRIC, 1);
   } else {
@@ -347,7 +356,8 @@ void presmooth(stokes_ctx* c, int l, double* x, const double* b) {
   }
 }
 
-void postsmooth(stokes_ctx* c, int l, double* x, const double* b) {
+template <typename T>
+void postsmooth(stokes_ctx* c, int l, T* x, const T* b) {
   if (c->prm.smoother == STOKES_SMOOTHER_SYMMETRIC) {
     for (int i = 0; i < c->prm.nu / 2; ++i) smooth(c, l, x, b, INT_SYMMETRIC, 1);
   } else {
@@ -355,12 +365,14 @@ void postsmooth(stokes_ctx* c, int l, double* x, const double* b) {
   }
 }
 
-void fill_zero(stokes_ctx* c, double* x, long n, int level = 0) {
-  launch(c, STOKES_KC_BLAS, level, [=] { k_fill<double><<<RED_BLOCKS, BS, 0, c->ks>>>(x, n, 0.0); });
+template <typename T>
+void fill_zero(stokes_ctx* c, T* x, long n, int level = 0) {
+  launch(c, STOKES_KC_BLAS, level, [=] { k_fill<T><<<RED_BLOCKS, BS, 0, c->ks>>>(x, n, T(0)); });
 }
 
 // x = V-CYCLE(L~, b, 0, L - l)
-void vcycle(stokes_ctx* c, int l, const double* b, double* x) {
+template <typename T>
+void vcycle(stokes_ctx* c, int l, const T* b, T* x) {
   const Geom g = c->lev[l].g;
   fill_zero(c, x, 4L * g.field, l);
   if (l == c->L - 1) {
@@ -368,24 +380,38 @@ void vcycle(stokes_ctx* c, int l, const double* b, double* x) {
     const double* cinv = c->cinv;
     const int* cdof = c->cdof;
     const int nc = c->nc;
-    launch(c, STOKES_KC_COARSE, l,
-           [=] { k_coarse_solve<double><<<nb, BS, 0, c->ks>>>(cinv, cdof, nc, b, x); });
+    launch(c, STOKES_KC_COARSE, l, [=] { k_coarse_solve<T><<<nb, BS, 0, c->ks>>>(cinv, cdof, nc, b, x); });
     return;
   }
   presmooth(c, l, x, b);
-  double* r = c->lev[l].r;
+  T* r = (T*)c->lev[l].r;
   const Geom gc = c->lev[l + 1].g;
-  double* bc = c->lev[l + 1].b;
-  double* xc = c->lev[l + 1].x;
+  T* bc = (T*)c->lev[l + 1].b;
+  T* xc = (T*)c->lev[l + 1].x;
   launch(c, STOKES_KC_APPLY, l, [=] {
-    k_apply<AP_RESID, double, double><<<slot_grid(g), BS, 0, c->ks>>>(g, x, b, r, g.gamma, nullptr);
+    k_apply<AP_RESID, T, T><<<slot_grid(g), BS, 0, c->ks>>>(g, x, b, r, g.gamma, nullptr);
   });
-  launch(c, STOKES_KC_RESTRICT, l,
-         [=] { k_restrict<double><<<slot_grid(gc), BS, 0, c->ks>>>(g, gc, r, bc); });
-  vcycle(c, l + 1, bc, xc);
-  launch(c, STOKES_KC_PROLONG, l,
-         [=] { k_prolong_add<double><<<slot_grid(g), BS, 0, c->ks>>>(g, gc, xc, x); });
+  launch(c, STOKES_KC_RESTRICT, l, [=] { k_restrict<T><<<slot_grid(gc), BS, 0, c->ks>>>(g, gc, r, bc); });
+  vcycle(c, l + 1, (const T*)bc, xc);
+  launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_add<T><<<slot_grid(g), BS, 0, c->ks>>>(g, gc, xc, x); });
   postsmooth(c, l, x, b);
+}
+
+// The whole preconditioner application t = W s: FP64 runs the V-cycle on the
+// caller's vectors; FP32 converts s once, runs the V-cycle on float level
+// buffers (all smoother, transfer and stencil arithmetic in FP32; the
+// coarsest solve accumulates in FP64) and converts the result back.
+void precondition(stokes_ctx* c, const double* s, double* t) {
+  if (c->prec == 64) {
+    vcycle<double>(c, 0, s, t);
+    return;
+  }
+  float* b0 = (float*)c->lev[0].b;
+  float* x0 = (float*)c->lev[0].x;
+  const long n = c->total;
+  launch(c, STOKES_KC_BLAS, 0, [=] { k_convert<double, float><<<RED_BLOCKS, BS, 0, c->ks>>>(s, b0, n); });
+  vcycle<float>(c, 0, b0, x0);
+  launch(c, STOKES_KC_BLAS, 0, [=] { k_convert<float, double><<<RED_BLOCKS, BS, 0, c->ks>>>(x0, t, n); });
 }
 
 void seg_open(stokes_ctx* c) {
@@ -416,7 +442,7 @@ void seg_close(stokes_ctx* c) {
 int run_vcycle(stokes_ctx* c, const double* s, double* t) {
   if (c->prm.flags & STOKES_FLAG_NO_GRAPH) {
     c->ks = c->stream;
-    vcycle(c, 0, s, t);
+    precondition(c, s, t);
     return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
   }
   stokes_ctx::GraphEntry* hit = nullptr;
@@ -432,7 +458,7 @@ int run_vcycle(stokes_ctx* c, const double* s, double* t) {
     c->capturing = true;
     c->ks = c->cap;
     seg_open(c);
-    vcycle(c, 0, s, t);
+    precondition(c, s, t);
     seg_close(c);
     c->capturing = false;
     c->ks = c->stream;
@@ -542,8 +568,11 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
     Level& lv = c->lev[l];
     std::vector<double> kinv;
     if (!vanka_inverses(lv.g, kinv)) return fail(STOKES_EINVAL);
-    if (hipMemcpyAsync(lv.kinv, kinv.data(), kinv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
-        hipSuccess)
+    std::vector<float> kinv_f(kinv.begin(), kinv.end());
+    const void* src = c->prec == 32 ? (const void*)kinv_f.data() : (const void*)kinv.data();
+    const size_t nbytes = kinv.size() * (c->prec == 32 ? sizeof(float) : sizeof(double));
+    if (hipMemcpyAsync(lv.kinv, src, nbytes, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
       return fail(STOKES_EDEVICE);
     std::vector<int> cells[8];
     vanka_cells(lv.g, cells);
@@ -566,9 +595,16 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
       return fail(STOKES_EDEVICE);
   }
   // workspace vectors start from zero (their ghost slots are never written otherwise)
-  for (int l = 1; l < L; ++l) {
-    fill_zero(c, c->lev[l].b, 4L * c->lev[l].g.field);
-    fill_zero(c, c->lev[l].x, 4L * c->lev[l].g.field);
+  for (int l = 0; l < L; ++l) {
+    if (!c->lev[l].b) continue;
+    const long n = 4L * c->lev[l].g.field;
+    if (c->prec == 32) {
+      fill_zero(c, (float*)c->lev[l].b, n);
+      fill_zero(c, (float*)c->lev[l].x, n);
+    } else {
+      fill_zero(c, (double*)c->lev[l].b, n);
+      fill_zero(c, (double*)c->lev[l].x, n);
+    }
   }
   fill_zero(c, c->s, c->total);
   fill_zero(c, c->t, c->total);

@@ -167,13 +167,14 @@ class StokesSolver:
     torch tensors of `layout.total` elements on the context's device."""
 
     def __init__(self, nx, ny, nz, h=None, *, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1,
-                 schedule="split", remove_mean=True, graphs=True, device=None, stream=None):
+                 schedule="split", precision=64, remove_mean=True, graphs=True, device=None, stream=None):
         import torch
         self.torch = torch
         h = 1.0 / max(nx, ny, nz) if h is None else h
         p = stokes_default_params(nx, ny, nz, h)
         p.eta, p.gamma, p.levels, p.nu, p.n_boundary = eta, gamma, levels, nu, n_boundary
         p.smoother = SMOOTHERS[schedule]
+        p.vcycle_precision = precision
         p.flags = (STOKES_FLAG_REMOVE_MEAN if remove_mean else 0) | (0 if graphs else STOKES_FLAG_NO_GRAPH)
         self.params = p
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())

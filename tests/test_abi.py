@@ -38,10 +38,14 @@ def test_defaults_and_workspace_sizes():
     assert 0 < small < big
     # four SQMR vectors of (N+2)^3-ish float64 slots at least
     assert small >= 4 * 4 * 34 ** 3 * 8
+    p.vcycle_precision = 32
+    mixed = S.stokes_workspace_bytes(p)
+    # FP32 level buffers (plus the level-0 copies) are smaller than FP64 ones
+    assert 0 < mixed < small * 1.1
 
 
 @pytest.mark.parametrize("field,value", [("nx", 1), ("h", 0.0), ("eta", -1.0), ("nu", 0), ("n_boundary", 0),
-                                         ("vcycle_precision", 16), ("levels", 6), ("levels", -1), ("smoother", 7),
+                                         ("vcycle_precision", 16), ("vcycle_precision", 33), ("levels", 6), ("levels", -1), ("smoother", 7),
                                          ("symmetric-odd-nu", 3)])
 def test_invalid_parameters_are_rejected_on_the_host(field, value):
     p = S.stokes_default_params(32, 32, 32, 1 / 32)
