@@ -1,4 +1,5 @@
-"""Build the gfx950 shared library of the solver (hipcc, in-tree).
+"""Build the gfx950 shared libraries in-tree with hipcc: the MG-SQMR solver
+(libstokes_mgsqmr.so) and the warm-start network kernels (libstokes_unet.so).
 
 Usage: python -m paper_2312_10615_amd.build
 """
@@ -12,8 +13,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libstokes_mgsqmr.so")
 SOURCES = [os.path.join(PKG, "csrc", "stokes_mgsqmr.hip")]
-HEADERS = [os.path.join(PKG, "csrc", f) for f in ("geom.hpp", "kernels.hpp", "host_tables.hpp")] + [
-    os.path.join(ROOT, "include", "stokes_mgsqmr.h")]
+UNET_LIB = os.path.join(PKG, "libstokes_unet.so")
+UNET_SOURCES = [os.path.join(PKG, "csrc", "unet.hip")]
+TARGETS = ((LIB, SOURCES), (UNET_LIB, UNET_SOURCES))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -24,17 +26,22 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), *SOURCES, "-o", tmp]
+def _build_one(lib: str, sources, verbose: bool) -> str:
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), *sources, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed to build " + LIB)
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError("hipcc failed to build " + lib)
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False):
+    """Compile every library (always, even when one is already there); returns their paths."""
+    return [_build_one(lib, src, verbose) for lib, src in TARGETS]
 
 
 if __name__ == "__main__":
