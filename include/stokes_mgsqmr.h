@@ -143,6 +143,21 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
 /* Layout of state vectors for this context. */
 int stokes_layout(const stokes_ctx* ctx, stokes_layout_t* out);
 
+/* Layout of the state vectors of multigrid level `level` (0 = finest, up to
+ * levels - 1): the same padded layout for the level's box of cells; `levels`
+ * reports the number of levels from this one down. */
+int stokes_level_layout(const stokes_ctx* ctx, int32_t level, stokes_layout_t* out);
+
+/* Grid transfers between the finest level and the next (Section 2): coarse =
+ * R fine with R = P^T / 8, and fine = P coarse (fine is overwritten), P the
+ * prolongation of the V-cycle (trilinear per staggered lattice, constant for
+ * p).  fine uses the level-0 layout, coarse the level-1 layout; inputs must be
+ * zero at slots that are not unknowns, outputs are.  FP64, async on the
+ * context's stream.  EINVAL for a one-level context or aliased vectors.
+ * Used to carry a warm start computed on the coarser grid to the finest one. */
+int stokes_restrict(stokes_ctx* ctx, const double* fine, double* coarse);
+int stokes_prolong(stokes_ctx* ctx, const double* coarse, double* fine);
+
 /* y = L x (penalized = 0) or y = L~ x (penalized = 1) on the finest level
  * (Eq. 2 / Section 4).  x and y are distinct device state vectors.  Async. */
 int stokes_apply(stokes_ctx* ctx, const double* x, double* y, int32_t penalized);

@@ -631,6 +631,39 @@ int stokes_layout(const stokes_ctx* c, stokes_layout_t* out) {
   return STOKES_OK;
 }
 
+int stokes_level_layout(const stokes_ctx* c, int32_t level, stokes_layout_t* out) {
+  if (!c || !out || level < 0 || level >= c->L) return STOKES_EINVAL;
+  const Geom& g = c->lev[level].g;
+  out->nx = g.nx;
+  out->ny = g.ny;
+  out->nz = g.nz;
+  out->sy = g.sy;
+  out->sz = g.sz;
+  for (int f = 0; f < 4; ++f) out->off[f] = (int64_t)f * g.field;
+  out->field = g.field;
+  out->total = 4L * g.field;
+  out->n_dofs = coarse_dofs(g);
+  out->levels = c->L - level;
+  return STOKES_OK;
+}
+
+int stokes_restrict(stokes_ctx* c, const double* fine, double* coarse) {
+  if (!c || !fine || !coarse || fine == coarse || c->L < 2) return STOKES_EINVAL;
+  const Geom& g = c->lev[0].g;
+  const Geom& gc = c->lev[1].g;
+  k_restrict<double><<<slot_grid(gc), BS, 0, c->stream>>>(g, gc, fine, coarse);
+  return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
+}
+
+int stokes_prolong(stokes_ctx* c, const double* coarse, double* fine) {
+  if (!c || !fine || !coarse || fine == coarse || c->L < 2) return STOKES_EINVAL;
+  const Geom& g = c->lev[0].g;
+  const Geom& gc = c->lev[1].g;
+  k_fill<double><<<RED_BLOCKS, BS, 0, c->stream>>>(fine, 4L * g.field, 0.0);
+  k_prolong_add<double><<<slot_grid(g), BS, 0, c->stream>>>(g, gc, coarse, fine);
+  return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
+}
+
 int stokes_apply(stokes_ctx* c, const double* x, double* y, int32_t penalized) {
   if (!c || !x || !y || x == y) return STOKES_EINVAL;
   const Geom& g = c->lev[0].g;

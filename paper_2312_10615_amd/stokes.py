@@ -42,9 +42,9 @@ class StokesInfo(ctypes.Structure):
                 ("bnorm", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double))]
 
 
-EXPORTS = ("stokes_default_params", "stokes_workspace_bytes", "stokes_setup", "stokes_layout", "stokes_apply",
-           "stokes_vcycle", "stokes_solve", "stokes_profile", "stokes_profile_read", "stokes_destroy",
-           "stokes_strerror")
+EXPORTS = ("stokes_default_params", "stokes_workspace_bytes", "stokes_setup", "stokes_layout", "stokes_level_layout",
+           "stokes_restrict", "stokes_prolong", "stokes_apply", "stokes_vcycle", "stokes_solve", "stokes_profile",
+           "stokes_profile_read", "stokes_destroy", "stokes_strerror")
 
 # kernel classes of stokes_profile()
 KC = {"apply": 0, "dgs_u": 1, "dgs_pf_own": 2, "dgs_pf_nbr": 3, "dgs_pr": 4, "vanka_delta": 5, "vanka_apply": 6,
@@ -67,6 +67,9 @@ def load_library(path: str = LIB_PATH):
     lib.stokes_workspace_bytes.argtypes = [P(StokesParams), P(ctypes.c_size_t)]
     lib.stokes_setup.argtypes = [P(StokesParams), vp, ctypes.c_size_t, vp, P(vp)]
     lib.stokes_layout.argtypes = [vp, P(StokesLayout)]
+    lib.stokes_level_layout.argtypes = [vp, i32, P(StokesLayout)]
+    lib.stokes_restrict.argtypes = [vp, vp, vp]
+    lib.stokes_prolong.argtypes = [vp, vp, vp]
     lib.stokes_apply.argtypes = [vp, vp, vp, i32]
     lib.stokes_vcycle.argtypes = [vp, vp, vp]
     lib.stokes_solve.argtypes = [vp, vp, vp, f64, i32, P(StokesInfo)]
@@ -119,6 +122,20 @@ def stokes_layout(ctx) -> StokesLayout:
     lay = StokesLayout()
     _check(load_library().stokes_layout(ctx, ctypes.byref(lay)), "stokes_layout")
     return lay
+
+
+def stokes_level_layout(ctx, level: int) -> StokesLayout:
+    lay = StokesLayout()
+    _check(load_library().stokes_level_layout(ctx, level, ctypes.byref(lay)), "stokes_level_layout")
+    return lay
+
+
+def stokes_restrict(ctx, fine_ptr: int, coarse_ptr: int) -> int:
+    return load_library().stokes_restrict(ctx, ctypes.c_void_p(fine_ptr), ctypes.c_void_p(coarse_ptr))
+
+
+def stokes_prolong(ctx, coarse_ptr: int, fine_ptr: int) -> int:
+    return load_library().stokes_prolong(ctx, ctypes.c_void_p(coarse_ptr), ctypes.c_void_p(fine_ptr))
 
 
 def stokes_apply(ctx, x_ptr: int, y_ptr: int, penalized: int = 0) -> int:
@@ -247,6 +264,22 @@ class StokesSolver:
         y = self.new_state() if out is None else out
         _check(stokes_apply(self.ctx, x.data_ptr(), y.data_ptr(), int(penalized)), "stokes_apply")
         return y
+
+    def level_layout(self, level):
+        return stokes_level_layout(self.ctx, level)
+
+    def restrict(self, fine, out=None):
+        """coarse = R fine (level 0 -> level 1 layout)."""
+        lay = self.level_layout(1)
+        c = out if out is not None else self.torch.zeros(lay.total, dtype=self.torch.float64, device=self.device)
+        _check(stokes_restrict(self.ctx, fine.data_ptr(), c.data_ptr()), "stokes_restrict")
+        return c
+
+    def prolong(self, coarse, out=None):
+        """fine = P coarse (level 1 -> level 0 layout)."""
+        f = out if out is not None else self.new_state()
+        _check(stokes_prolong(self.ctx, coarse.data_ptr(), f.data_ptr()), "stokes_prolong")
+        return f
 
     def vcycle(self, s, out=None):
         t = self.new_state() if out is None else out

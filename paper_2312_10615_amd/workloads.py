@@ -25,6 +25,7 @@ __all__ = [
     "face_centres",
     "cell_centres",
     "sinusoid_forcing",
+    "sinusoid_forcing_device",
     "mms_fields",
     "random_state",
 ]
@@ -138,6 +139,36 @@ def mms_force(axis: int, X, Y, Z, eta: float):
     sx, sy, sz = (np.sin(math.pi * X), np.sin(math.pi * Y), np.sin(math.pi * Z))
     grad_p = (-math.pi * sx * cy * cz, -math.pi * cx * sy * cz, -math.pi * cx * cy * sz)[axis]
     return -eta * lap_u + grad_p
+
+
+def sinusoid_forcing_device(nx: int, ny: int, nz: int, h: float, seed: int, device, n_modes: int = 8):
+    """`sinusoid_forcing` evaluated with torch on `device` (float64): the same
+    draws from the same PCG64 stream in the same order, so the two agree to the
+    rounding of the sine.  For generating many large right-hand sides quickly.
+    Returns torch tensors (fx, fy, fz) indexed [i, j, k]."""
+    import torch
+    rng = np.random.default_rng(seed)
+    dims = (nx, ny, nz)
+    out = []
+    for axis in range(3):
+        coords = []
+        for a in range(3):
+            n = dims[a] + 1 if a == axis else dims[a]
+            c = torch.arange(n, dtype=torch.float64, device=device) * h
+            if a != axis:
+                c = c + 0.5 * h
+            shape = [1, 1, 1]
+            shape[a] = n
+            coords.append(c.reshape(shape))
+        X, Y, Z = coords
+        f = torch.zeros((X.shape[0], Y.shape[1], Z.shape[2]), dtype=torch.float64, device=device)
+        for _ in range(n_modes):
+            k = rng.integers(1, 5, size=3)
+            amp = rng.standard_normal()
+            phase = rng.uniform(0.0, 2.0 * math.pi)
+            f += amp * torch.sin(2.0 * math.pi * (int(k[0]) * X + int(k[1]) * Y + int(k[2]) * Z) + phase)
+        out.append(f)
+    return tuple(out)
 
 
 def mms_fields(n: int, eta: float = 1.0):

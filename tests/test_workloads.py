@@ -37,3 +37,13 @@ def test_forcing_is_seeded_and_sized():
     assert [a.shape for a in f1] == [(9, 6, 4), (8, 7, 4), (8, 6, 5)]
     assert all(np.array_equal(a, b) for a, b in zip(f1, f2))
     assert not np.array_equal(f1[0], f3[0])
+
+
+def test_device_forcing_generator_agrees_with_numpy():
+    import torch
+    from paper_2312_10615_amd.workloads import sinusoid_forcing, sinusoid_forcing_device
+    a = sinusoid_forcing(12, 8, 10, 1 / 12, seed=5)
+    b = sinusoid_forcing_device(12, 8, 10, 1 / 12, seed=5, device="cpu")
+    for x, y in zip(a, b):
+        assert isinstance(y, torch.Tensor) and tuple(y.shape) == x.shape
+        assert np.allclose(y.numpy(), x, rtol=0, atol=1e-12)
