@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense bf16 matrix-core peak of MI355X
+WEIGHTS = os.path.join(ROOT, "paper_2312_10615_amd", "weights", "warmstart_128.npz")
 S = 8  # bytes per FP64 value
 
 
@@ -103,6 +105,123 @@ def cpu_baseline(iters, n_full, seed):
                       f"V-cycles of the GPU solve", "host_cpus": os.cpu_count()}
 
 
+def batched_leg(steps, rtol, seed):
+    """48 boxes with sizes drawn from {32,48,64,96,128} per axis, each with its
+    own seeded forcing, solved together (FP32 V-cycle, FP64 SQMR); also the
+    same boxes one after another with the single-box solver."""
+    import torch
+
+    from paper_2312_10615_amd.stokes import StokesBatch, StokesSolver
+    from paper_2312_10615_amd.workloads import batch_dims, sinusoid_forcing_device
+
+    dims = batch_dims(48, seed=seed)
+    h = 1.0 / 128
+    t0 = time.perf_counter()
+    bt = StokesBatch(dims, h=h, precision=32)
+    setup = time.perf_counter() - t0
+    fields = []
+    for d, (nx, ny, nz) in enumerate(dims):
+        f = sinusoid_forcing_device(nx, ny, nz, h, 1000 + d, bt.device)
+        fields.append(f + (torch.zeros((nx, ny, nz), dtype=torch.float64, device=bt.device),))
+    b = bt.pack(fields)
+    del fields
+    t0 = time.perf_counter()
+    tiles = bt.autotune()
+    tune_s = time.perf_counter() - t0
+    x, infos = bt.solve(b, rtol=rtol, maxit=200)  # warm-up (captures the graphs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x, infos = bt.solve(b, rtol=rtol, maxit=200)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    assert all(i["status"] == "ok" for i in infos), infos
+    # the same boxes one by one (single-box solver, graph V-cycle, FP32 form)
+    t_seq = 0.0
+    seq_iters = []
+    for d, dm in enumerate(dims):
+        sol = StokesSolver(*dm, h=h, precision=32, levels=bt.layouts[d].levels)
+        bd = bt.part(b, d).clone()
+        sol.solve(bd, rtol=rtol, maxit=200)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, inf = sol.solve(bd, rtol=rtol, maxit=200)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - ts
+        seq_iters.append(inf["iters"])
+        del sol
+    unknowns = int(sum(l.n_dofs for l in bt.layouts))
+    print(f"[bench] batched: {t_batch * 1e3:.1f} ms per batch, sequential {t_seq * 1e3:.1f} ms", file=sys.stderr,
+          flush=True)
+    return {"value": round(len(dims) / t_batch, 3), "unit": "solves/s", "boxes": len(dims),
+            "ms_per_batch": round(t_batch * 1e3, 3), "unknowns": unknowns,
+            "iterations": [i["iters"] for i in infos], "levels": [l.levels for l in bt.layouts],
+            "dims": [list(dm) for dm in dims], "final_relres_max": max(i["relres"] for i in infos),
+            "sequential_ms": round(t_seq * 1e3, 3), "sequential_iterations": seq_iters,
+            "speedup_vs_sequential": round(t_seq / t_batch, 3), "setup_s": round(setup, 3),
+            "autotune_s": round(tune_s, 3), "tile_x_extent": {k: v[:max(bt.layouts[i].levels for i in range(len(dims)))]
+                                                              for k, v in tiles.items()},
+            "form": "FP32 V-cycle, FP64 SQMR; h = 1/128; one graph replay for the set-up and first 10 iterations, "
+                    "then 2 iterations per replay"}
+
+
+def warm_start_leg(sol, b, steps, rtol, zero_ms, zero_iters):
+    """The learned warm start at 256^3: the network runs on the 128^3 level
+    (R b there), its guess is prolonged with P and SQMR starts from it.  Time
+    includes the guess.  Also the network forward's matrix-core throughput."""
+    import torch
+
+    from paper_2312_10615_amd import unet as U
+    from paper_2312_10615_amd.warmstart import load_weights
+
+    params, sigma, record = load_weights(WEIGHTS)
+    lay1 = sol.level_layout(1)
+    net = U.WarmStartNet(lay1.nx, lay1.ny, lay1.nz, params=params, sigma=sigma)
+    xc = torch.zeros(lay1.total, dtype=torch.float64, device=sol.device)
+    x0 = sol.new_state()
+
+    def guess():
+        net.initial_guess(sol.restrict(b), lay1, xc)
+        sol.prolong(xc, out=x0)
+
+    guess()
+    x, info = sol.solve(b, x0=x0, rtol=rtol, maxit=500)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        guess()
+        x, info = sol.solve(b, x0=x0, rtol=rtol, maxit=500)
+    torch.cuda.synchronize()
+    t_warm = (time.perf_counter() - t0) / steps
+    r0 = info["history"][0]
+    # network forward alone, HIP events around the 10 convolutions and the head
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nf = 10
+    ev0.record()
+    for _ in range(nf):
+        net.forward()
+    ev1.record()
+    torch.cuda.synchronize()
+    fwd_ms = ev0.elapsed_time(ev1) / nf
+    flops = 0
+    for name, spec, cin, cout in U.LAYERS:
+        dz, dy, dx = net.dims[U.LEVEL[name]]
+        flops += 2 * 27 * cin * cout * dz * dy * dx
+    tf = flops / (fwd_ms * 1e-3) / 1e12
+    print(f"[bench] warm start: {t_warm * 1e3:.1f} ms, iters {info['iters']} (zero guess {zero_iters})",
+          file=sys.stderr, flush=True)
+    return {"value": round(t_warm, 6), "unit": "s", "iterations": info["iters"], "zero_guess_iterations": zero_iters,
+            "final_relres": info["relres"], "status": info["status"],
+            "speedup_vs_fp64": round(zero_ms / 1000.0 / t_warm, 3), "guess_relres": r0,
+            "network": f"3-level U-Net 16/32/64 channels on the {lay1.nx}^3 level, bf16 on matrix cores",
+            "training": {k: record.get(k) for k in ("n", "pairs", "epochs", "lr", "train_seconds", "sigma")}
+            | {"final_loss": record.get("loss_history", [[0, None]])[-1][1]},
+            "roofline": {"bound": "mfma", "kernel": "k_conv3 (10 layers) + head, 128^3 forward",
+                         "achieved": round(tf, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / BF16_PEAK_TFLOPS, 4), "traffic": None, "forward_ms": round(fwd_ms, 4),
+                         "algorithmic_flops_per_forward": flops}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +233,8 @@ def main():
     ap.add_argument("--kernel", default="dgs_pr", help="dominant kernel class timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-V-cycle (mixed precision) leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 48-box batched leg")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
@@ -175,6 +296,10 @@ def main():
     torch.cuda.synchronize()
     vcycle_ms = ev0.elapsed_time(ev1) / nvc
 
+    warm = None
+    if not args.no_warm_start and os.path.exists(WEIGHTS):
+        warm = warm_start_leg(sol, b, args.steps, args.rtol, ms_per_step, info["iters"])
+
     mixed = None
     if not args.no_mixed:
         # Mixed precision: FP32 V-cycle inside FP64 SQMR, same input and tolerance.
@@ -205,6 +330,10 @@ def main():
         del s32, x32, xa, ya
         print(f"[bench] mixed: {t32 * 1e3:.1f} ms, iters={i32['iters']}, err={err:.2e}", file=sys.stderr,
               flush=True)
+
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(args.steps, args.rtol, args.seed)
 
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -245,6 +374,10 @@ def main():
     }
     if mixed is not None:
         line["mixed_precision"] = mixed
+    if batched is not None:
+        line["batched"] = batched
+    if warm is not None:
+        line["warm_start"] = warm
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(info["iters"], n, args.seed)

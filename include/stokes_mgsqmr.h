@@ -204,6 +204,49 @@ int stokes_profile_read(stokes_ctx* ctx, int32_t kernel_class, int32_t level, do
 /* Release the host context (never touches the caller's device memory). */
 void stokes_destroy(stokes_ctx* ctx);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent boxes solved together with MG-SQMR (the same method and
+ * schedule per box as stokes_solve).  Every kernel launch covers one step of
+ * the method for all boxes that take part in it, the SQMR scalars of every
+ * box stay on the device, a box that has finished drops out of later
+ * launches, and the iterations run as replays of captured HIP graphs (the
+ * first one holds the set-up phase and the first `first` iterations, each
+ * later one `later` iterations; defaults 10 and 2).
+ *
+ * p[0..n) gives each box its own size, spacing and levels (levels = 0: the
+ * single-box automatic rule, deepened while the coarsest system would exceed
+ * 2500 unknowns); nu, n_boundary, smoother and vcycle_precision must be equal
+ * for all boxes.  Box d's state vector is the slice [offset_d, offset_d +
+ * total_d) of one batch vector of stokes_batch_size() doubles
+ * (stokes_batch_layout); slots between slices are ignored.
+ * Ownership, streams and statuses as for a single box; the library allocates
+ * only its host context and two small pinned host buffers. */
+typedef struct stokes_batch stokes_batch;
+
+int stokes_batch_workspace_bytes(int32_t n, const stokes_params* p, size_t* bytes);
+int stokes_batch_setup(int32_t n, const stokes_params* p, void* workspace, size_t bytes, void* hip_stream,
+                       stokes_batch** out);
+int stokes_batch_layout(const stokes_batch* batch, int32_t box, int64_t* offset, stokes_layout_t* out);
+int stokes_batch_size(const stokes_batch* batch, int64_t* total);
+
+/* Tile shapes of the stencil kernels (x-extent of a block's 2-D tile: 32, 64,
+ * 128 or 256 items): times every shape of every kernel class on every level
+ * of this batch and keeps the fastest.  Synchronises.  choices (optional,
+ * host int[8 * 16]) receives the x-extent per [class][level] (0 = unused). */
+int stokes_batch_autotune(stokes_batch* batch, int32_t* choices);
+
+/* Iterations per graph replay (first >= 0, later >= 1). */
+int stokes_batch_set_chunks(stokes_batch* batch, int32_t first, int32_t later);
+
+/* Solve every box: b, x batch vectors (x in: initial guesses, out: iterates),
+ * rtol and maxit as for stokes_solve; info: host array of n entries (history
+ * is not recorded).  Synchronises.  Returns STOKES_OK when every box
+ * converged, else the status of the first box that did not. */
+int stokes_batch_solve(stokes_batch* batch, const double* b, double* x, double rtol, int32_t maxit,
+                       stokes_info* info);
+
+void stokes_batch_destroy(stokes_batch* batch);
+
 const char* stokes_strerror(int status);
 
 #ifdef __cplusplus

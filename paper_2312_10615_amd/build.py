@@ -12,7 +12,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libstokes_mgsqmr.so")
-SOURCES = [os.path.join(PKG, "csrc", "stokes_mgsqmr.hip")]
+SOURCES = [os.path.join(PKG, "csrc", "stokes_mgsqmr.hip"), os.path.join(PKG, "csrc", "batched.hip")]
 UNET_LIB = os.path.join(PKG, "libstokes_unet.so")
 UNET_SOURCES = [os.path.join(PKG, "csrc", "unet.hip")]
 TARGETS = ((LIB, SOURCES), (UNET_LIB, UNET_SOURCES))

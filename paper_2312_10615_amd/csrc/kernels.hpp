@@ -101,12 +101,12 @@ enum ApplyMode { AP_APPLY = 0, AP_RESID = 1, AP_APPLY_DOT = 2, AP_RESNORM = 3, A
 // AP_RESNORM:   partial[blk] = sum (b - L~ x)^2 over unknowns (no y)
 // AP_BNORM:     partial[blk] = sum b^2 over unknowns (x unused)
 // Every slot of y is written; slots that are not unknowns get 0.
+// One slot (I, J, K) of an apply pass; returns this slot's share of the reduction.
 template <int MODE, typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
-                                              T* __restrict__ y, double gamma, double* __restrict__ partial) {
+__device__ __forceinline__ double apply_item(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                             T* __restrict__ y, double gamma, int I, int J, int K) {
   double acc = 0.0;
-  int I, J, K;
-  if (slab_item(g, g.sy, I, J, K)) {
+  {
     const int s = g.idx(I, J, K);
     const int F = g.field;
     const T* ux = x;
@@ -134,6 +134,15 @@ __global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, c
       if (MODE == AP_RESNORM || MODE == AP_BNORM) acc += v * v;
     }
   }
+  return acc;
+}
+
+template <int MODE, typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
+                                              T* __restrict__ y, double gamma, double* __restrict__ partial) {
+  double acc = 0.0;
+  int I, J, K;
+  if (slab_item(g, g.sy, I, J, K)) acc = apply_item<MODE, T, TB>(g, x, b, y, gamma, I, J, K);
   if (MODE == AP_APPLY_DOT || MODE == AP_RESNORM || MODE == AP_BNORM) {
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -155,9 +164,8 @@ __device__ __forceinline__ bool half_slot(const Geom& g, int colour, int& I, int
 // Same-colour faces are not lattice neighbours and p is fixed, so the class
 // updates at once.
 template <typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_dgs_u(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
-  int I, J, K;
-  if (!half_slot(g, colour, I, J, K)) return;
+__device__ __forceinline__ void dgs_u_item(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, int I, int J,
+                                           int K) {
   const int s = g.idx(I, J, K);
   const int F = g.field;
   T* ux = x;
@@ -170,6 +178,13 @@ __global__ __launch_bounds__(BS) void k_dgs_u(Geom g, T* __restrict__ x, const T
   if (g.uz_v2(I, J, K)) uz[s] = uz[s] + ((T)b[2 * F + s] - row_u(g, uz, p, s, g.sz)) * dinv;
 }
 
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_dgs_u(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
+  int I, J, K;
+  if (!half_slot(g, colour, I, J, K)) return;
+  dgs_u_item<T, TB>(g, x, b, I, J, K);
+}
+
 // Pressure step of the forward sweep, part 1, on the V2 cells of one colour:
 // delta = r_j / d_j with d_j = (L~ M)_jj = -6 (1 + gamma eta) / h^2, then move
 // x along the column m_j of M = [[I, -B^T], [0, eta B B^T]] (Eq. dist) as far
@@ -177,10 +192,8 @@ __global__ __launch_bounds__(BS) void k_dgs_u(Geom g, T* __restrict__ x, const T
 // 6 eta delta / h^2.  A V2 cell's six faces and six neighbours are all
 // unknowns, so m_j is the full interior column.  delta is kept for part 2.
 template <typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_dgs_pf_own(Geom g, T* __restrict__ x, const TB* __restrict__ b,
-                                                   T* __restrict__ dscr, int colour) {
-  int I, J, K;
-  if (!half_slot(g, colour, I, J, K)) return;
+__device__ __forceinline__ void dgs_pf_own_item(const Geom& g, T* __restrict__ x, const TB* __restrict__ b,
+                                                T* __restrict__ dscr, int I, int J, int K) {
   if (!g.p_v2(I, J, K)) return;
   const int s = g.idx(I, J, K);
   const int F = g.field;
@@ -202,14 +215,20 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_own(Geom g, T* __restrict__ x, co
   p[s] = p[s] + (T)(6.0 * g.eta * ih2) * delta;
 }
 
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_dgs_pf_own(Geom g, T* __restrict__ x, const TB* __restrict__ b,
+                                                   T* __restrict__ dscr, int colour) {
+  int I, J, K;
+  if (!half_slot(g, colour, I, J, K)) return;
+  dgs_pf_own_item<T, TB>(g, x, b, dscr, I, J, K);
+}
+
 // Part 2 on every cell of the other colour (V1 ring cells included): p_k -=
 // (eta/h^2) * sum of the deltas of its V2 neighbours (the off-diagonal
 // entries of eta B B^T in the columns m_j).
 template <typename T>
-__global__ __launch_bounds__(BS) void k_dgs_pf_nbr(Geom g, T* __restrict__ x, const T* __restrict__ dscr,
-                                                   int colour) {
-  int I, J, K;
-  if (!half_slot(g, colour ^ 1, I, J, K)) return;
+__device__ __forceinline__ void dgs_pf_nbr_item(const Geom& g, T* __restrict__ x, const T* __restrict__ dscr, int I,
+                                                int J, int K) {
   if (!g.p_active(I, J, K)) return;
   const int s = g.idx(I, J, K);
   T* p = x + 3 * g.field;
@@ -223,15 +242,22 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_nbr(Geom g, T* __restrict__ x, co
   if (sum != T(0)) p[s] = p[s] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
 }
 
+template <typename T>
+__global__ __launch_bounds__(BS) void k_dgs_pf_nbr(Geom g, T* __restrict__ x, const T* __restrict__ dscr,
+                                                   int colour) {
+  int I, J, K;
+  if (!half_slot(g, colour ^ 1, I, J, K)) return;
+  dgs_pf_nbr_item<T>(g, x, dscr, I, J, K);
+}
+
 // Pressure step of the reverse sweep (Gauss-Seidel on M^T L~, Eq. ldist) on
 // the V2 cells of one colour: p_j += (m_j . r) / d_j with
 //   m_j . r = (1/h) sum_a (r(plus face) - r(minus face)) + (eta/h^2)(6 r_j - sum_k r_k)
 // over the six faces and six neighbours, r = b - L~ x.  Only p_j changes, and
 // no residual read here depends on another same-colour pressure.
 template <typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
-  int I, J, K;
-  if (!half_slot(g, colour, I, J, K)) return;
+__device__ __forceinline__ void dgs_pr_item(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, int I, int J,
+                                            int K) {
   if (!g.p_v2(I, J, K)) return;
   const int s = g.idx(I, J, K);
   const int F = g.field;
@@ -260,6 +286,13 @@ __global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const 
   p[s] = p[s] + rt / (T)(-6.0 * (1.0 + gam * g.eta) * ih2);
 }
 
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
+  int I, J, K;
+  if (!half_slot(g, colour, I, J, K)) return;
+  dgs_pr_item<T, TB>(g, x, b, I, J, K);
+}
+
 // ---------------------------------------------------------------------------
 // Multiplicative Vanka on V1 (Eq. mv), one colour class.  Each subdomain is
 // one V1 cell with its pressure and active faces; the class takes all its
@@ -271,11 +304,12 @@ __global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const 
 // (0: u_x minus face, 1: u_x plus face, 2/3: u_y, 4/5: u_z, 6: p), then
 // forms delta_r = sum_j (K^-1)_rj r_j with the group's residuals gathered
 // by shuffles.  delta is stored as 8 values per subdomain.
+// Lane t of the class (t & 7 must equal threadIdx.x & 7, and the eight lanes of
+// a subdomain share a wave); every lane of the wave must call it (shuffles).
 template <typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
-                                                    const int* __restrict__ cells, int ncells,
-                                                    const T* __restrict__ kinv, T* __restrict__ delta) {
-  const int t = blockIdx.x * BS + threadIdx.x;
+__device__ __forceinline__ void vanka_delta_item(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                                 const int* __restrict__ cells, int ncells, const T* __restrict__ kinv,
+                                                 T* __restrict__ delta, int t) {
   const int c = t >> 3;
   const int r = t & 7;
   const bool valid = c < ncells;
@@ -313,11 +347,17 @@ __global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict_
   if (valid && r < 7) delta[c * 8 + r] = acc;
 }
 
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
+                                                    const int* __restrict__ cells, int ncells,
+                                                    const T* __restrict__ kinv, T* __restrict__ delta) {
+  vanka_delta_item<T, TB>(g, x, b, cells, ncells, kinv, delta, blockIdx.x * BS + threadIdx.x);
+}
+
 // x[local DOF r of subdomain c] += delta_r, eight lanes per subdomain.
 template <typename T>
-__global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
-                                                    int ncells, const T* __restrict__ delta) {
-  const int t = blockIdx.x * BS + threadIdx.x;
+__device__ __forceinline__ void vanka_apply_item(const Geom& g, T* __restrict__ x, const int* __restrict__ cells,
+                                                 int ncells, const T* __restrict__ delta, int t) {
   const int c = t >> 3;
   const int r = t & 7;
   if (c >= ncells || r == 7) return;
@@ -338,6 +378,12 @@ __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, c
   if (e >= 0) x[e] = x[e] + delta[c * 8 + r];
 }
 
+template <typename T>
+__global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
+                                                    int ncells, const T* __restrict__ delta) {
+  vanka_apply_item<T>(g, x, cells, ncells, delta, blockIdx.x * BS + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Grid transfer (Section 2): R = P^T / 8 with P bilinear per velocity lattice
 // (weights 1, 1/2 along the face axis; 3/4, 1/4 across) and constant for p.
@@ -345,9 +391,8 @@ __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, c
 // Restriction: one thread per coarse slot; reads the fine residual r (zero at
 // every fine slot that is not an unknown).
 template <typename T>
-__global__ __launch_bounds__(BS) void k_restrict(Geom f, Geom c, const T* __restrict__ r, T* __restrict__ bc) {
-  int I, J, K;
-  if (!slab_item(c, c.sy, I, J, K)) return;
+__device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, const T* __restrict__ r,
+                                              T* __restrict__ bc, int I, int J, int K) {
   const int s = c.idx(I, J, K);
   const int Ff = f.field, Fc = c.field;
   const T wf[3] = {0.5, 1.0, 0.5};          // face axis: fine 2I-2, 2I-1, 2I
@@ -399,6 +444,13 @@ __global__ __launch_bounds__(BS) void k_restrict(Geom f, Geom c, const T* __rest
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(BS) void k_restrict(Geom f, Geom c, const T* __restrict__ r, T* __restrict__ bc) {
+  int I, J, K;
+  if (!slab_item(c, c.sy, I, J, K)) return;
+  restrict_item<T>(f, c, r, bc, I, J, K);
+}
+
 // 1D prolongation weights on the cell-centre lattice: fine padded index J
 // (1-based cell) takes 3/4 from coarse (j>>1)+1 and 1/4 from the coarse row on
 // its side (j = J-1).
@@ -426,9 +478,8 @@ __device__ __forceinline__ void face_w(int I, int& n0, int& n1, double& w0, doub
 
 // x_fine += P e_coarse, one thread per fine slot.
 template <typename T>
-__global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __restrict__ e, T* __restrict__ x) {
-  int I, J, K;
-  if (!slab_item(f, f.sy, I, J, K)) return;
+__device__ __forceinline__ void prolong_item(const Geom& f, const Geom& c, const T* __restrict__ e,
+                                             T* __restrict__ x, int I, int J, int K) {
   const int s = f.idx(I, J, K);
   const int Ff = f.field, Fc = c.field;
   if (f.ux_active(I, J, K)) {
@@ -476,21 +527,33 @@ __global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __r
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __restrict__ e, T* __restrict__ x) {
+  int I, J, K;
+  if (!slab_item(f, f.sy, I, J, K)) return;
+  prolong_item<T>(f, c, e, x, I, J, K);
+}
+
 // ---------------------------------------------------------------------------
 // Coarsest level: x = L~c^{-1} b with the dense inverse; one wave per row.
 // x must be zero beforehand (its ghost slots stay zero).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(BS) void k_coarse_solve(const double* __restrict__ kinv, const int* __restrict__ dof,
-                                                     int n, const T* __restrict__ b, T* __restrict__ x) {
-  const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
+__device__ __forceinline__ void coarse_row(const double* __restrict__ kinv, const int* __restrict__ dof, int n,
+                                           const T* __restrict__ b, T* __restrict__ x, int row, int lane) {
   double acc = 0.0;
   const double* kr = kinv + (size_t)row * n;
   for (int j = lane; j < n; j += 64) acc += kr[j] * (double)b[dof[j]];
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
   if (lane == 0) x[dof[row]] = (T)acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_coarse_solve(const double* __restrict__ kinv, const int* __restrict__ dof,
+                                                     int n, const T* __restrict__ b, T* __restrict__ x) {
+  const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  coarse_row<T>(kinv, dof, n, b, x, row, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,7 +571,7 @@ __global__ __launch_bounds__(BS) void k_convert(const Ti* __restrict__ in, To* _
 }
 
 // partial[2*blk] = sum a.a, partial[2*blk+1] = sum a.c
-__global__ __launch_bounds__(BS) void k_dot_aa_ac(const double* __restrict__ a, const double* __restrict__ c, long n,
+static __global__ __launch_bounds__(BS) void k_dot_aa_ac(const double* __restrict__ a, const double* __restrict__ c, long n,
                                                   double* __restrict__ partial) {
   double s0 = 0.0, s1 = 0.0;
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
@@ -525,7 +588,7 @@ __global__ __launch_bounds__(BS) void k_dot_aa_ac(const double* __restrict__ a, 
 }
 
 // sum of p over the cells (for the mean-pressure removal)
-__global__ __launch_bounds__(BS) void k_sum_p(Geom g, const double* __restrict__ x, double* __restrict__ partial) {
+static __global__ __launch_bounds__(BS) void k_sum_p(Geom g, const double* __restrict__ x, double* __restrict__ partial) {
   const int s = logical_block() * BS + threadIdx.x;
   double v = 0.0;
   if (s < g.field) {
@@ -537,7 +600,7 @@ __global__ __launch_bounds__(BS) void k_sum_p(Geom g, const double* __restrict__
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(BS) void k_shift_p(Geom g, double* __restrict__ x, double amount) {
+static __global__ __launch_bounds__(BS) void k_shift_p(Geom g, double* __restrict__ x, double amount) {
   const int s = logical_block() * BS + threadIdx.x;
   if (s >= g.field) return;
   int I, J, K;
@@ -546,7 +609,7 @@ __global__ __launch_bounds__(BS) void k_shift_p(Geom g, double* __restrict__ x, 
 }
 
 // Zero the ghost slots of a state vector (the caller's initial guess).
-__global__ __launch_bounds__(BS) void k_clear_ghosts(Geom g, double* __restrict__ x) {
+static __global__ __launch_bounds__(BS) void k_clear_ghosts(Geom g, double* __restrict__ x) {
   const int s = logical_block() * BS + threadIdx.x;
   if (s >= g.field) return;
   int I, J, K;
@@ -559,13 +622,13 @@ __global__ __launch_bounds__(BS) void k_clear_ghosts(Geom g, double* __restrict_
 }
 
 // s -= a * t
-__global__ __launch_bounds__(BS) void k_axpy_neg(double* __restrict__ s, const double* __restrict__ t, long n,
+static __global__ __launch_bounds__(BS) void k_axpy_neg(double* __restrict__ s, const double* __restrict__ t, long n,
                                                  double a) {
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) s[i] -= a * t[i];
 }
 
 // d = cd * d + cq * q;  x += d
-__global__ __launch_bounds__(BS) void k_update_dx(double* __restrict__ d, const double* __restrict__ q,
+static __global__ __launch_bounds__(BS) void k_update_dx(double* __restrict__ d, const double* __restrict__ q,
                                                   double* __restrict__ x, long n, double cd, double cq) {
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
     const double dv = cd * d[i] + cq * q[i];
@@ -575,13 +638,13 @@ __global__ __launch_bounds__(BS) void k_update_dx(double* __restrict__ d, const 
 }
 
 // q = t + beta * q
-__global__ __launch_bounds__(BS) void k_xpby(double* __restrict__ q, const double* __restrict__ t, long n,
+static __global__ __launch_bounds__(BS) void k_xpby(double* __restrict__ q, const double* __restrict__ t, long n,
                                              double bt) {
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) q[i] = t[i] + bt * q[i];
 }
 
 // out[k] = sum_b partial[b*stride + k], fixed order, single block.
-__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int nblk, int stride,
+static __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int nblk, int stride,
                                                  double* __restrict__ out) {
   __shared__ double sm[16];
   for (int k = 0; k < stride; ++k) {

@@ -44,7 +44,9 @@ class StokesInfo(ctypes.Structure):
 
 EXPORTS = ("stokes_default_params", "stokes_workspace_bytes", "stokes_setup", "stokes_layout", "stokes_level_layout",
            "stokes_restrict", "stokes_prolong", "stokes_apply", "stokes_vcycle", "stokes_solve", "stokes_profile",
-           "stokes_profile_read", "stokes_destroy", "stokes_strerror")
+           "stokes_profile_read", "stokes_destroy", "stokes_strerror", "stokes_batch_workspace_bytes",
+           "stokes_batch_setup", "stokes_batch_layout", "stokes_batch_size", "stokes_batch_autotune",
+           "stokes_batch_set_chunks", "stokes_batch_solve", "stokes_batch_destroy")
 
 # kernel classes of stokes_profile()
 KC = {"apply": 0, "dgs_u": 1, "dgs_pf_own": 2, "dgs_pf_nbr": 3, "dgs_pr": 4, "vanka_delta": 5, "vanka_apply": 6,
@@ -77,10 +79,19 @@ def load_library(path: str = LIB_PATH):
     lib.stokes_profile_read.argtypes = [vp, i32, i32, P(ctypes.c_double), P(ctypes.c_int64)]
     lib.stokes_destroy.argtypes = [vp]
     lib.stokes_destroy.restype = None
+    lib.stokes_batch_workspace_bytes.argtypes = [i32, P(StokesParams), P(ctypes.c_size_t)]
+    lib.stokes_batch_setup.argtypes = [i32, P(StokesParams), vp, ctypes.c_size_t, vp, P(vp)]
+    lib.stokes_batch_layout.argtypes = [vp, i32, P(ctypes.c_int64), P(StokesLayout)]
+    lib.stokes_batch_size.argtypes = [vp, P(ctypes.c_int64)]
+    lib.stokes_batch_autotune.argtypes = [vp, P(i32)]
+    lib.stokes_batch_set_chunks.argtypes = [vp, i32, i32]
+    lib.stokes_batch_solve.argtypes = [vp, vp, vp, f64, i32, P(StokesInfo)]
+    lib.stokes_batch_destroy.argtypes = [vp]
+    lib.stokes_batch_destroy.restype = None
     lib.stokes_strerror.argtypes = [ctypes.c_int]
     lib.stokes_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("stokes_destroy", "stokes_strerror"):
+        if name not in ("stokes_destroy", "stokes_strerror", "stokes_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -179,6 +190,46 @@ def stokes_strerror(code: int) -> str:
 
 # --- torch plumbing -------------------------------------------------------------
 
+def state_views(layout, state):
+    """The four fields of a padded state vector as [K, J, I] views."""
+    L = layout
+    nz2, ny2 = L.nz + 2, L.ny + 2
+    return [state[L.off[f]:L.off[f] + L.sz * nz2].view(nz2, ny2, L.sy) for f in range(4)]
+
+
+def pack_fields(layout, fields, out, device):
+    """Natural arrays (ux (nx+1,ny,nz), uy, uz, p), numpy or torch, indexed
+    [i,j,k] -> the padded state `out`; only unknowns are copied, every other
+    slot is 0."""
+    import torch
+    L = layout
+    nx, ny, nz = L.nx, L.ny, L.nz
+    st = out.zero_()
+    v = state_views(L, st)
+    t = [torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
+                         dtype=torch.float64).to(device) for a in fields]
+    v[0][1:nz + 1, 1:ny + 1, 2:nx + 1] = t[0][1:nx].permute(2, 1, 0)
+    v[1][1:nz + 1, 2:ny + 1, 1:nx + 1] = t[1][:, 1:ny].permute(2, 1, 0)
+    v[2][2:nz + 1, 1:ny + 1, 1:nx + 1] = t[2][:, :, 1:nz].permute(2, 1, 0)
+    v[3][1:nz + 1, 1:ny + 1, 1:nx + 1] = t[3].permute(2, 1, 0)
+    return st
+
+
+def unpack_fields(layout, state):
+    """Padded state -> natural numpy arrays (walls included, zero)."""
+    L = layout
+    nx, ny, nz = L.nx, L.ny, L.nz
+    v = state_views(L, state)
+    ux = v[0][1:nz + 1, 1:ny + 1, 1:nx + 2].permute(2, 1, 0).cpu().numpy().copy()
+    uy = v[1][1:nz + 1, 1:ny + 2, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
+    uz = v[2][1:nz + 2, 1:ny + 1, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
+    p = v[3][1:nz + 1, 1:ny + 1, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
+    ux[0] = ux[-1] = 0.0
+    uy[:, 0] = uy[:, -1] = 0.0
+    uz[:, :, 0] = uz[:, :, -1] = 0.0
+    return ux, uy, uz, p
+
+
 class StokesSolver:
     """Device workspace + context for one box.  State vectors are float64
     torch tensors of `layout.total` elements on the context's device."""
@@ -220,44 +271,14 @@ class StokesSolver:
     def new_state(self):
         return self.torch.zeros(self.layout.total, dtype=self.torch.float64, device=self.device)
 
-    def _views(self, state):
-        L = self.layout
-        nz2, ny2 = L.nz + 2, L.ny + 2
-        out = []
-        for f in range(4):
-            v = state[L.off[f]:L.off[f] + L.sz * nz2].view(nz2, ny2, L.sy)
-            out.append(v)
-        return out
-
     def pack(self, fields, out=None):
         """Natural arrays (ux (nx+1,ny,nz), uy, uz, p), numpy or torch, indexed
         [i,j,k] -> padded state; only unknowns are copied, every other slot is 0."""
-        torch = self.torch
-        L = self.layout
-        nx, ny, nz = L.nx, L.ny, L.nz
-        st = self.new_state() if out is None else out.zero_()
-        v = self._views(st)
-        t = [torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
-                             dtype=torch.float64).to(self.device) for a in fields]
-        v[0][1:nz + 1, 1:ny + 1, 2:nx + 1] = t[0][1:nx].permute(2, 1, 0)
-        v[1][1:nz + 1, 2:ny + 1, 1:nx + 1] = t[1][:, 1:ny].permute(2, 1, 0)
-        v[2][2:nz + 1, 1:ny + 1, 1:nx + 1] = t[2][:, :, 1:nz].permute(2, 1, 0)
-        v[3][1:nz + 1, 1:ny + 1, 1:nx + 1] = t[3].permute(2, 1, 0)
-        return st
+        return pack_fields(self.layout, fields, self.new_state() if out is None else out, self.device)
 
     def unpack(self, state):
         """Padded state -> natural numpy arrays (walls included, zero)."""
-        L = self.layout
-        nx, ny, nz = L.nx, L.ny, L.nz
-        v = self._views(state)
-        ux = v[0][1:nz + 1, 1:ny + 1, 1:nx + 2].permute(2, 1, 0).cpu().numpy().copy()
-        uy = v[1][1:nz + 1, 1:ny + 2, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
-        uz = v[2][1:nz + 2, 1:ny + 1, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
-        p = v[3][1:nz + 1, 1:ny + 1, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
-        ux[0] = ux[-1] = 0.0
-        uy[:, 0] = uy[:, -1] = 0.0
-        uz[:, :, 0] = uz[:, :, -1] = 0.0
-        return ux, uy, uz, p
+        return unpack_fields(self.layout, state)
 
     # operations
     def apply(self, x, penalized=False, out=None):
@@ -302,3 +323,97 @@ class StokesSolver:
             _check(code, "stokes_solve")
         return x, {"iters": info.iters, "status": STATUS_NAMES.get(code, str(code)), "relres": info.relres,
                    "bnorm": info.bnorm, "history": hist}
+
+
+class StokesBatch:
+    """Many boxes solved together (stokes_batch_*).  `dims` is a list of
+    (nx, ny, nz); every box gets spacing h (default 1 / 128) and the same
+    schedule and V-cycle precision.  Batch vectors are float64 tensors of
+    `size` elements; box d's state is `vector[offset[d] : offset[d] + total]`."""
+
+    def __init__(self, dims, h=1.0 / 128, *, eta=1.0, gamma=1e-3, nu=2, n_boundary=1, schedule="split",
+                 precision=32, remove_mean=True, levels=None, device=None, stream=None):
+        import torch
+        self.torch = torch
+        n = len(dims)
+        arr = (StokesParams * n)()
+        for i, (nx, ny, nz) in enumerate(dims):
+            p = stokes_default_params(nx, ny, nz, h)
+            p.eta, p.gamma, p.nu, p.n_boundary = eta, gamma, nu, n_boundary
+            p.levels = 0 if levels is None else int(levels[i])
+            p.smoother = SMOOTHERS[schedule]
+            p.vcycle_precision = precision
+            p.flags = STOKES_FLAG_REMOVE_MEAN if remove_mean else 0
+            arr[i] = p
+        self.params, self.n = arr, n
+        lib = load_library()
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.stokes_batch_workspace_bytes(n, arr, ctypes.byref(nbytes)), "stokes_batch_workspace_bytes")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        ptr = base + (-base) % 256
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.stokes_batch_setup(n, arr, ctypes.c_void_p(ptr), nbytes.value,
+                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)),
+                   "stokes_batch_setup")
+        self.ctx = ctx
+        self.offset, self.layouts = [], []
+        for d in range(n):
+            off = ctypes.c_int64(0)
+            lay = StokesLayout()
+            _check(lib.stokes_batch_layout(ctx, d, ctypes.byref(off), ctypes.byref(lay)), "stokes_batch_layout")
+            self.offset.append(int(off.value))
+            self.layouts.append(lay)
+        tot = ctypes.c_int64(0)
+        _check(lib.stokes_batch_size(ctx, ctypes.byref(tot)), "stokes_batch_size")
+        self.size = int(tot.value)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            load_library().stokes_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_vector(self):
+        return self.torch.zeros(self.size, dtype=self.torch.float64, device=self.device)
+
+    def part(self, vec, d):
+        return vec[self.offset[d]:self.offset[d] + self.layouts[d].total]
+
+    def pack(self, fields_per_box, out=None):
+        v = self.new_vector() if out is None else out.zero_()
+        for d, f in enumerate(fields_per_box):
+            pack_fields(self.layouts[d], f, self.part(v, d), self.device)
+        return v
+
+    def unpack(self, vec, d):
+        return unpack_fields(self.layouts[d], self.part(vec, d))
+
+    def autotune(self):
+        """Pick the tile shape of every stencil kernel class on every level; returns
+        {class: [x-extent per level]}."""
+        ch = (ctypes.c_int32 * (8 * 16))()
+        _check(load_library().stokes_batch_autotune(self.ctx, ch), "stokes_batch_autotune")
+        names = ("apply", "resid", "dgs_u", "dgs_pf_own", "dgs_pf_nbr", "dgs_pr", "restrict", "prolong")
+        return {nm: [int(ch[k * 16 + l]) for l in range(16)] for k, nm in enumerate(names)}
+
+    def set_chunks(self, first, later):
+        _check(load_library().stokes_batch_set_chunks(self.ctx, int(first), int(later)), "stokes_batch_set_chunks")
+
+    def solve(self, b, x0=None, rtol=1e-8, maxit=200):
+        x = self.new_vector() if x0 is None else x0.clone()
+        infos = (StokesInfo * self.n)()
+        code = load_library().stokes_batch_solve(self.ctx, ctypes.c_void_p(b.data_ptr()),
+                                                 ctypes.c_void_p(x.data_ptr()), rtol, maxit, infos)
+        if code in (STOKES_EINVAL, STOKES_EDEVICE):
+            _check(code, "stokes_batch_solve")
+        return x, [{"iters": i.iters, "status": STATUS_NAMES.get(i.status, str(i.status)), "relres": i.relres,
+                    "bnorm": i.bnorm} for i in infos]

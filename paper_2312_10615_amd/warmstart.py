@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -28,6 +29,8 @@ import numpy as np
 
 TRAIN_SEED0 = 1000      # training seeds: TRAIN_SEED0 .. TRAIN_SEED0 + pairs - 1
 EVAL_SEED0 = 100000     # held-out seeds
+# weights trained by `train --n 128 --pairs 2000 --epochs 4` (record inside the file)
+WEIGHTS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_128.npz")
 
 
 def _forcing_state(sol, n, seed, device):

@@ -26,6 +26,7 @@ __all__ = [
     "cell_centres",
     "sinusoid_forcing",
     "sinusoid_forcing_device",
+    "batch_dims",
     "mms_fields",
     "random_state",
 ]
@@ -169,6 +170,14 @@ def sinusoid_forcing_device(nx: int, ny: int, nz: int, h: float, seed: int, devi
             f += amp * torch.sin(2.0 * math.pi * (int(k[0]) * X + int(k[1]) * Y + int(k[2]) * Z) + phase)
         out.append(f)
     return tuple(out)
+
+
+def batch_dims(n_domains: int = 48, choices=(32, 48, 64, 96, 128), seed: int = 0):
+    """Box sizes of a batched workload: each of nx, ny, nz drawn uniformly from
+    `choices` (PCG64 stream `numpy.random.default_rng(seed)`, domain by domain,
+    x then y then z).  Returns a list of (nx, ny, nz)."""
+    rng = np.random.default_rng(seed)
+    return [tuple(int(choices[i]) for i in rng.integers(0, len(choices), size=3)) for _ in range(n_domains)]
 
 
 def mms_fields(n: int, eta: float = 1.0):

@@ -1,0 +1,104 @@
+"""Batched MG-SQMR (stokes_batch_*): every box of a mixed batch against the
+single-box GPU solver and against the oracle's operator.
+
+The batch runs the same per-item arithmetic as the single-box kernels; its
+inner products are summed in a different (fixed) block order, so iterates
+agree to rounding and the iteration counts agree (the SQMR sensitivity
+envelope of the single-box parity tests allows +-1 where a residual sits at
+the tolerance)."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import announce, cuda, forcing_rhs, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(8, 8, 8), (16, 8, 12), (12, 16, 8), (16, 16, 16), (8, 12, 16), (24, 8, 16), (6, 10, 8)]
+H = 1.0 / 16
+
+
+def _batch_problem(precision, dims=DIMS, seed0=10):
+    from oracle.domain import Domain, box_labels
+    from paper_2312_10615_amd.stokes import StokesBatch
+    bt = StokesBatch(dims, h=H, precision=precision)
+    rhs, doms = [], []
+    for d, dm in enumerate(dims):
+        dom = Domain(box_labels(dm), H)
+        doms.append(dom)
+        rhs.append(forcing_rhs(dom.active, dm, H, seed=seed0 + d))
+    return bt, rhs, doms
+
+
+def _oracle_relres(dom, x, b):
+    from oracle.operator import apply_operator
+    r = [bb - a for bb, a in zip(b, apply_operator(dom, x, 0.0))]
+    r = [np.where(m, v, 0.0) for m, v in zip(dom.active, r)]
+    return np.sqrt(sum(float(np.sum(v ** 2)) for v in r)) / np.sqrt(sum(float(np.sum(v ** 2)) for v in b))
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_batch_matches_single_box_solves(precision):
+    cuda()
+    from paper_2312_10615_amd.stokes import StokesSolver
+    announce(f"batched solve, {len(DIMS)} boxes, V-cycle FP{precision}")
+    bt, rhs, doms = _batch_problem(precision)
+    b = bt.pack(rhs)
+    x, infos = bt.solve(b, rtol=1e-8, maxit=100)
+    for d, dm in enumerate(DIMS):
+        lay = bt.layouts[d]
+        single = StokesSolver(*dm, h=H, precision=precision, levels=lay.levels)
+        xs, info = single.solve(single.pack(rhs[d]), rtol=1e-8, maxit=100)
+        got, want = bt.unpack(x, d), single.unpack(xs)
+        e = rel_err(got, want)
+        rr = _oracle_relres(doms[d], got, rhs[d])
+        announce(f"  box {dm} levels {lay.levels}: iters {infos[d]['iters']} (single {info['iters']}), "
+                 f"|batch - single| {e:.1e}, oracle relres {rr:.2e}")
+        assert infos[d]["status"] == "ok" and info["status"] == "ok"
+        assert abs(infos[d]["iters"] - info["iters"]) <= 1
+        assert rr <= 1e-8 * (1 + 1e-6)
+        if infos[d]["iters"] == info["iters"]:
+            assert e <= (1e-9 if precision == 64 else 1e-6), e
+        # pressure mean removed, walls zero
+        assert abs(float(np.mean(got[3]))) <= 1e-12 * max(1.0, float(np.abs(got[3]).max()))
+
+
+def test_batch_edge_cases_and_replays():
+    torch = cuda()
+    from paper_2312_10615_amd.stokes import StokesBatch
+    announce("batched edge cases: zero forcing, one-level box, maxit, replay determinism")
+    dims = [(8, 8, 8), (6, 10, 8), (16, 8, 8)]
+    bt, rhs, doms = _batch_problem(32, dims=dims, seed0=40)
+    rhs[0] = tuple(np.zeros_like(a) for a in rhs[0])
+    b = bt.pack(rhs)
+    x1, i1 = bt.solve(b, rtol=1e-8, maxit=100)
+    assert i1[0]["status"] == "ok" and i1[0]["iters"] == 0 and i1[0]["relres"] == 0.0
+    assert float(bt.part(x1, 0).abs().max()) == 0.0
+    # a single-level box: the V-cycle is the exact solve with L~ (not L: the
+    # penalty gamma separates them), so SQMR needs only a few iterations
+    assert bt.layouts[1].levels == 1 and i1[1]["iters"] <= 4 and i1[1]["status"] == "ok"
+    # the same call again replays the cached graphs: identical bits
+    x2, i2 = bt.solve(b, rtol=1e-8, maxit=100)
+    assert torch.equal(x1, x2) and [a["iters"] for a in i1] == [a["iters"] for a in i2]
+    # an iteration limit stops the unfinished boxes with ENOCONV
+    x3, i3 = bt.solve(b, rtol=1e-14, maxit=3)
+    assert i3[2]["status"] == "enoconv" and i3[2]["iters"] == 3
+    # a nonzero initial guess is accepted (ghost slots cleared) and converges
+    x4, i4 = bt.solve(b, x0=x1 + 1e-3, rtol=1e-8, maxit=100)
+    assert all(a["status"] == "ok" for a in i4)
+
+
+def test_autotune_keeps_results():
+    cuda()
+    announce("batched autotune")
+    bt, rhs, doms = _batch_problem(32)
+    b = bt.pack(rhs)
+    x0, i0 = bt.solve(b, rtol=1e-8, maxit=100)
+    choice = bt.autotune()
+    announce(f"  tile x-extents: {choice}")
+    assert all(v in (0, 32, 64, 128, 256) for vals in choice.values() for v in vals)
+    x1, i1 = bt.solve(b, rtol=1e-8, maxit=100)
+    for d in range(len(DIMS)):
+        assert i1[d]["status"] == "ok"
+        assert abs(i1[d]["iters"] - i0[d]["iters"]) <= 1
+        if i1[d]["iters"] == i0[d]["iters"]:
+            assert rel_err(bt.unpack(x1, d), bt.unpack(x0, d)) <= 1e-6

@@ -1,0 +1,59 @@
+"""The trained warm-start network (paper_2312_10615_amd/weights) against the
+method without it: same solver, same tolerance, zero initial guess vs the
+network's guess, on held-out seeds (never used in training)."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import announce, cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n, coarse_net):
+    from paper_2312_10615_amd import unet as U
+    from paper_2312_10615_amd.stokes import StokesSolver
+    from paper_2312_10615_amd.warmstart import WEIGHTS_FILE, load_weights
+    params, sigma, record = load_weights(WEIGHTS_FILE)
+    sol = StokesSolver(n, n, n, h=1.0 / n)
+    lay = sol.level_layout(1) if coarse_net else sol.layout
+    net = U.WarmStartNet(lay.nx, lay.ny, lay.nz, params=params, sigma=sigma)
+    return sol, lay, net
+
+
+def test_guess_beats_the_zero_guess_in_error_at_128():
+    torch = cuda()
+    from paper_2312_10615_amd.warmstart import EVAL_SEED0, _forcing_state
+    announce("warm start 128^3: error of the network guess")
+    sol, lay, net = _setup(128, False)
+    for s in (EVAL_SEED0, EVAL_SEED0 + 1):
+        b = _forcing_state(sol, 128, s, "cuda")
+        xs, info = sol.solve(b, rtol=1e-10, maxit=200)
+        x0 = net.initial_guess(b, lay, sol.new_state())
+        xw, iw = sol.solve(b, x0=x0, rtol=1e-8, maxit=200)
+        torch.cuda.synchronize()
+        # velocity error (pressure is defined up to a constant): guess vs zero
+        nu = lay.off[3]
+        err = float(torch.linalg.vector_norm((x0 - xs)[:nu]) / torch.linalg.vector_norm(xs[:nu]))
+        announce(f"  seed {s}: |u0 - u| / |u| = {err:.3f}, warm solve iters {iw['iters']} status {iw['status']}")
+        assert iw["status"] == "ok" and iw["relres"] <= 1e-8
+        assert err < 0.6
+
+
+def test_fewer_iterations_at_256_with_the_guess_from_128():
+    torch = cuda()
+    from paper_2312_10615_amd.warmstart import EVAL_SEED0, _forcing_state
+    announce("warm start 256^3 (network on the 128^3 level): iterations vs zero guess")
+    sol, lay, net = _setup(256, True)
+    xc = torch.zeros(lay.total, dtype=torch.float64, device="cuda")
+    zero, warm = [], []
+    for s in range(EVAL_SEED0, EVAL_SEED0 + 4):
+        b = _forcing_state(sol, 256, s, "cuda")
+        _, i0 = sol.solve(b, rtol=1e-8, maxit=200)
+        net.initial_guess(sol.restrict(b), lay, xc)
+        x0 = sol.prolong(xc)
+        _, i1 = sol.solve(b, x0=x0, rtol=1e-8, maxit=200)
+        assert i0["status"] == "ok" and i1["status"] == "ok"
+        zero.append(i0["iters"])
+        warm.append(i1["iters"])
+    announce(f"  iterations zero guess {zero}, network guess {warm}")
+    assert sum(warm) < sum(zero)
