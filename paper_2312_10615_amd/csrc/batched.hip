@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <thread>
 #include <vector>
 
 #include "batched_kernels.hpp"
@@ -680,6 +681,23 @@ int stokes_batch_setup(int32_t n, const stokes_params* p, void* workspace, size_
   if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) return fail(STOKES_EDEVICE);
   if (hipHostMalloc((void**)&c->hcount, sizeof(int)) != hipSuccess) return fail(STOKES_EDEVICE);
   if (hipHostMalloc((void**)&c->hsc, sizeof(BScal) * n) != hipSuccess) return fail(STOKES_EDEVICE);
+  // dense inverses of the coarsest systems: independent per box, O(n^3) each,
+  // so they are formed on host threads
+  std::vector<std::vector<int>> cdofs(n);
+  std::vector<std::vector<double>> cinvs(n);
+  std::vector<char> cok(n, 0);
+  {
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned w = 0; w < hw; ++w)
+      pool.emplace_back([&, w] {
+        for (int d = (int)w; d < n; d += (int)hw) {
+          const BLev& b = c->hlev[c->L[d] - 1][d];
+          cok[d] = coarse_inverse(b.g, cdofs[d], cinvs[d]) ? 1 : 0;
+        }
+      });
+    for (auto& th : pool) th.join();
+  }
   // upload: Vanka inverses, cells, coarse inverses, level tables, batch offsets
   const int prec = c->prec;
   std::vector<double> kd;
@@ -705,12 +723,13 @@ int stokes_batch_setup(int32_t n, const stokes_params* p, void* workspace, size_
                   hipSuccess)
             return fail(STOKES_EDEVICE);
       } else {
-        std::vector<int> dof;
-        std::vector<double> inv;
-        if (!coarse_inverse(b.g, dof, inv)) return fail(STOKES_EINVAL);
-        if (hipMemcpy((void*)b.cinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy((void*)b.cdof, dof.data(), dof.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        if (!cok[d]) return fail(STOKES_EINVAL);
+        if (hipMemcpy((void*)b.cinv, cinvs[d].data(), cinvs[d].size() * sizeof(double), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy((void*)b.cdof, cdofs[d].data(), cdofs[d].size() * sizeof(int), hipMemcpyHostToDevice) !=
+                hipSuccess)
           return fail(STOKES_EDEVICE);
+        std::vector<double>().swap(cinvs[d]);
       }
     }
   for (int l = 0; l < c->Lmax; ++l)

@@ -46,43 +46,41 @@ inline int count_levels(int nx, int ny, int nz, int min_cells) {
 }
 
 // In-place Gauss-Jordan inversion with partial pivoting of a row-major n x n
-// matrix.  Returns false if a pivot is exactly zero.
+// matrix (n^3 multiply-adds: the inverse overwrites A column by column, no
+// augmented identity).  Returns false if a pivot is exactly zero.
 inline bool invert(std::vector<double>& a, int n) {
-  std::vector<double> inv((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
-  for (int col = 0; col < n; ++col) {
-    int piv = col;
-    double best = std::fabs(a[(size_t)col * n + col]);
-    for (int r = col + 1; r < n; ++r) {
-      const double v = std::fabs(a[(size_t)r * n + col]);
+  std::vector<int> swapped(n);
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    double best = std::fabs(a[(size_t)k * n + k]);
+    for (int r = k + 1; r < n; ++r) {
+      const double v = std::fabs(a[(size_t)r * n + k]);
       if (v > best) {
         best = v;
         piv = r;
       }
     }
     if (best == 0.0) return false;
-    if (piv != col) {
-      for (int k = 0; k < n; ++k) {
-        std::swap(a[(size_t)piv * n + k], a[(size_t)col * n + k]);
-        std::swap(inv[(size_t)piv * n + k], inv[(size_t)col * n + k]);
-      }
-    }
-    const double d = 1.0 / a[(size_t)col * n + col];
-    for (int k = 0; k < n; ++k) {
-      a[(size_t)col * n + k] *= d;
-      inv[(size_t)col * n + k] *= d;
-    }
+    swapped[k] = piv;
+    if (piv != k)
+      for (int j = 0; j < n; ++j) std::swap(a[(size_t)piv * n + j], a[(size_t)k * n + j]);
+    double* rk = &a[(size_t)k * n];
+    const double d = 1.0 / rk[k];
+    rk[k] = 1.0;
+    for (int j = 0; j < n; ++j) rk[j] *= d;
     for (int r = 0; r < n; ++r) {
-      if (r == col) continue;
-      const double f = a[(size_t)r * n + col];
+      if (r == k) continue;
+      double* rr = &a[(size_t)r * n];
+      const double f = rr[k];
       if (f == 0.0) continue;
-      for (int k = 0; k < n; ++k) {
-        a[(size_t)r * n + k] -= f * a[(size_t)col * n + k];
-        inv[(size_t)r * n + k] -= f * inv[(size_t)col * n + k];
-      }
+      rr[k] = 0.0;
+      for (int j = 0; j < n; ++j) rr[j] -= f * rk[j];
     }
   }
-  a.swap(inv);
+  // the row swaps of A become column swaps of the inverse, in reverse order
+  for (int k = n - 1; k >= 0; --k)
+    if (swapped[k] != k)
+      for (int r = 0; r < n; ++r) std::swap(a[(size_t)r * n + k], a[(size_t)r * n + swapped[k]]);
   return true;
 }
 
