@@ -17,6 +17,7 @@
 #include "../../include/stokes_mgsqmr.h"
 #include "host_tables.hpp"
 #include "kernels.hpp"
+#include "tail_kernels.hpp"
 
 using namespace sg;
 
@@ -72,6 +73,10 @@ struct stokes_ctx {
   int nc = 0;
   // Vanka delta scratch (max colour count x 8)
   void* vdelta = nullptr;
+  // the small levels, run by one workgroup (tail < 0: none)
+  int tail = -1;
+  TailLev* tlev = nullptr;
+  TailArgs targs{};
   int prec = 64;  // V-cycle precision
   // kernel timing (diagnostics)
   int prof_class = STOKES_KC_OFF, prof_level = -1;
@@ -247,6 +252,7 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
     }
   }
   c->vdelta = cv.take<char>(8 * std::max<long>(vmax, 1) * es);
+  c->tlev = cv.take<TailLev>(TAIL_MAX);
   const Geom& gc = c->lev[L - 1].g;
   c->nc = (int)coarse_dofs(gc);
   c->cinv = cv.take<double>((size_t)c->nc * c->nc);
@@ -373,6 +379,12 @@ void fill_zero(stokes_ctx* c, T* x, long n, int level = 0) {
 // x = V-CYCLE(L~, b, 0, L - l)
 template <typename T>
 void vcycle(stokes_ctx* c, int l, const T* b, T* x) {
+  if (l == c->tail) {
+    const TailArgs a = c->targs;
+    const TailLev* tl = c->tlev;
+    launch(c, STOKES_KC_TAIL, l, [=] { k_tail<T><<<1, TAIL_BS, 0, c->ks>>>(a, tl, x, b); });
+    return;
+  }
   const Geom g = c->lev[l].g;
   fill_zero(c, x, 4L * g.field, l);
   if (l == c->L - 1) {
@@ -591,6 +603,46 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
     if (hipMemcpyAsync(c->cinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
             hipSuccess ||
         hipMemcpyAsync(c->cdof, dof.data(), dof.size() * sizeof(int), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return fail(STOKES_EDEVICE);
+  }
+  // the tail: the first level with at most TAIL_CELLS cells, down to the coarsest
+  if (p->flags & STOKES_FLAG_TAIL) {
+    for (int l = 0; l < L; ++l) {
+      const Geom& g = c->lev[l].g;
+      if ((long)g.nx * g.ny * g.nz <= TAIL_CELLS && L - l <= TAIL_MAX) {
+        c->tail = l;
+        break;
+      }
+    }
+  }
+  if (c->tail >= 0) {
+    std::vector<TailLev> tl(L - c->tail);
+    for (int l = c->tail; l < L; ++l) {
+      TailLev& t = tl[l - c->tail];
+      const Level& lv = c->lev[l];
+      t = TailLev{};
+      t.g = lv.g;
+      if (l + 1 < L) t.gc = c->lev[l + 1].g;
+      t.x = lv.x;
+      t.b = lv.b;
+      t.r = lv.r;
+      t.dscr = lv.dscr;
+      t.kinv = lv.kinv;
+      for (int k = 0; k < 8; ++k) {
+        t.vc[k] = lv.vcells[k];
+        t.nv[k] = lv.nv[k];
+      }
+      if (l == L - 1) {
+        t.cinv = c->cinv;
+        t.cdof = c->cdof;
+        t.nc = c->nc;
+      }
+    }
+    c->targs = TailArgs{L - c->tail, p->nu, p->n_boundary, p->smoother == STOKES_SMOOTHER_SYMMETRIC ? 1 : 0,
+                        c->vdelta};
+    if (hipMemcpyAsync(c->tlev, tl.data(), sizeof(TailLev) * tl.size(), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
       return fail(STOKES_EDEVICE);
   }

@@ -237,3 +237,24 @@ def test_vcycle_graph_replays_match_eager_launches():
         xg, ig = g_sol.solve(b)
         xe, ie = e_sol.solve(b)
         assert ig["iters"] == ie["iters"] and torch.equal(xg, xe)
+
+
+@pytest.mark.parametrize("dims,precision,sched", [((16, 16, 16), 64, "split"), ((32, 32, 32), 64, "split"),
+                                                  ((64, 48, 32), 64, "symmetric"), ((32, 32, 32), 32, "split"),
+                                                  ((64, 64, 64), 32, "split")])
+def test_one_workgroup_tail_matches_per_level_launches(dims, precision, sched):
+    """The levels of <= 16^3 cells run as one workgroup; the V-cycle and the
+    whole solve are bit for bit those of one launch per level and phase."""
+    torch = cuda()
+    from paper_2312_10615_amd.stokes import StokesSolver
+    from oracle.domain import Domain, box_labels
+    announce(f"tail vs per-level launches {dims} FP{precision} {sched}")
+    h = 1.0 / max(dims)
+    a = StokesSolver(*dims, h=h, precision=precision, schedule=sched, tail=True)
+    b_ = StokesSolver(*dims, h=h, precision=precision, schedule=sched)
+    dom = Domain(box_labels(dims), h)
+    rhs = a.pack(forcing_rhs(dom.active, dims, h, seed=3))
+    assert torch.equal(a.vcycle(rhs), b_.vcycle(rhs))
+    xa, ia = a.solve(rhs, rtol=1e-8, maxit=200)
+    xb, ib = b_.solve(rhs, rtol=1e-8, maxit=200)
+    assert ia["iters"] == ib["iters"] and torch.equal(xa, xb)
