@@ -71,10 +71,22 @@ enum {
  *    phases, nu/2 times (nu even). */
 enum { STOKES_SMOOTHER_SPLIT = 0, STOKES_SMOOTHER_SYMMETRIC = 1 };
 
+/* The V1 (boundary) smoother of Alg. 3 (Section 3.2):
+ *  STOKES_VANKA_MULT8: symmetric multiplicative Vanka, the paper's 8 colour
+ *    classes (i&1) + 2(j&1) + 4(k&1), classes 0..7 then 7..0, each class
+ *    updated at once from the state at its start.  Default.
+ *  STOKES_VANKA_MULT27: the same with 27 classes (i%3) + 3(j%3) + 9(k%3);
+ *    same-class cells are three apart and share no stencil entry, so a class
+ *    step equals solving its subdomains one after another (Eq. mv).
+ *  STOKES_VANKA_ADDITIVE: additive Vanka (Eq. av), every V1 subdomain from
+ *    the same residual, corrections summed (applied class by class so that
+ *    shared faces are summed in a fixed order); symmetric by itself. */
+enum { STOKES_VANKA_MULT8 = 0, STOKES_VANKA_MULT27 = 1, STOKES_VANKA_ADDITIVE = 2 };
+
 /* Solver parameters.  Defaults (stokes_default_params): eta = 1, gamma = 1e-3
  * (the penalty of Section 4; Section 6 uses 1e-3), levels = 0 (auto), nu = 2,
  * n_boundary = 1, vcycle_precision = 64, smoother = STOKES_SMOOTHER_SPLIT,
- * flags = STOKES_FLAG_REMOVE_MEAN. */
+ * flags = STOKES_FLAG_REMOVE_MEAN, vanka = STOKES_VANKA_MULT8, cycle = 1. */
 typedef struct stokes_params {
   int32_t nx, ny, nz;         /* interior cells per axis, each >= 2 */
   double h;                   /* cell edge; > 0 */
@@ -92,6 +104,10 @@ typedef struct stokes_params {
                                  SQMR recurrences, inner products and the true residual stay FP64 */
   int32_t smoother;           /* STOKES_SMOOTHER_* */
   int32_t flags;              /* STOKES_FLAG_* */
+  int32_t vanka;              /* STOKES_VANKA_* */
+  int32_t cycle;              /* 1: V-cycle (Alg. 1).  2: W-cycle - the coarse correction of every
+                                 level above the coarsest is two cycles of the next level, the
+                                 second starting from the first's result (Section 2) */
 } stokes_params;
 
 /* After convergence subtract the mean pressure over the cells (the closed box
@@ -163,6 +179,15 @@ int stokes_level_layout(const stokes_ctx* ctx, int32_t level, stokes_layout_t* o
 int stokes_restrict(stokes_ctx* ctx, const double* fine, double* coarse);
 int stokes_prolong(stokes_ctx* ctx, const double* coarse, double* fine);
 
+/* Dirichlet data moved to the right-hand side (Section 5): out = b - L g at
+ * the unknowns and 0 elsewhere, where g is a state vector that holds the
+ * boundary values in its slots that are not unknowns (tangential velocities
+ * in the ghost slots of the Dirichlet cells, wall-normal velocities on the
+ * wall faces) and 0 at the unknowns.  The solution of L x = out plus g is the
+ * discrete solution with those boundary values (e.g. the lid of the driven
+ * cavity of Section 6).  Async; out must differ from g and b. */
+int stokes_lift(stokes_ctx* ctx, const double* g, const double* b, double* out);
+
 /* y = L x (penalized = 0) or y = L~ x (penalized = 1) on the finest level
  * (Eq. 2 / Section 4).  x and y are distinct device state vectors.  Async. */
 int stokes_apply(stokes_ctx* ctx, const double* x, double* y, int32_t penalized);
@@ -222,7 +247,7 @@ void stokes_destroy(stokes_ctx* ctx);
  * p[0..n) gives each box its own size, spacing and levels (levels = 0: the
  * single-box automatic rule, deepened while the coarsest system would exceed
  * 2500 unknowns); nu, n_boundary, smoother and vcycle_precision must be equal
- * for all boxes.  Box d's state vector is the slice [offset_d, offset_d +
+ * for all boxes, vanka must be STOKES_VANKA_MULT8 and cycle 1.  Box d's state vector is the slice [offset_d, offset_d +
  * total_d) of one batch vector of stokes_batch_size() doubles
  * (stokes_batch_layout); slots between slices are ignored.
  * Ownership, streams and statuses as for a single box; the library allocates

@@ -148,8 +148,11 @@ class Domain:
         i, j, k = np.ogrid[0:shp[0], 0:shp[1], 0:shp[2]]
         return ((i + j + k) & 1).astype(np.int8)
 
-    def vanka_colour(self) -> np.ndarray:
-        """8-colour class of every cell: (i&1) + 2(j&1) + 4(k&1)."""
+    def vanka_colour(self, period: int = 2) -> np.ndarray:
+        """Colour class of every cell: (i mod q) + q (j mod q) + q^2 (k mod q).
+        q = 2 is the paper's 8-colour scheme (Section 6); with q = 3 (27
+        classes) same-class cells are three apart and share no stencil entry."""
         nx, ny, nz = self.dims
         i, j, k = np.ogrid[0:nx, 0:ny, 0:nz]
-        return ((i & 1) + 2 * (j & 1) + 4 * (k & 1)).astype(np.int8)
+        q = period
+        return ((i % q) + q * (j % q) + q * q * (k % q)).astype(np.int16)

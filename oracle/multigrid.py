@@ -22,6 +22,13 @@ Smoothing schedules.  `nu` counts DGS sweeps per smoothing phase (a
 Reading (levels): with levels = 0 the hierarchy halves every axis while all
 axes are even and every halved axis keeps at least 4 cells; an explicit
 level count may go down to 2 cells per axis.
+
+Variants.  `vanka` picks the V1 smoother (smoother.vanka_apply: the paper's
+8-colour symmetric multiplicative Vanka, a 27-colour one, or additive Vanka,
+Eq. av).  `cycle` = 2 makes the W-cycle the paper mentions (Section 2,
+compared with the V-cycle in the appendix experiments): the coarse
+correction of every non-coarsest level is two cycles on the next level, the
+second starting from the first's result.
 """
 from __future__ import annotations
 
@@ -50,14 +57,18 @@ def max_levels(dims) -> int:
 class Hierarchy:
     """Levels 0 (finest) .. levels-1 (coarsest) of a box domain."""
 
-    def __init__(self, dims, h, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1, schedule="split"):
+    def __init__(self, dims, h, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1, schedule="split",
+                 vanka="mult8", cycle=1):
         if levels == 0:
             levels = auto_levels(dims)
         if levels < 1 or levels > max_levels(dims):
             raise ValueError("too many levels for these dimensions")
         if schedule not in ("split", "symmetric") or nu < 1 or (schedule == "symmetric" and nu % 2):
             raise ValueError("bad smoothing schedule")
+        if vanka not in ("mult8", "mult27", "additive") or cycle not in (1, 2):
+            raise ValueError("bad smoother variant or cycle")
         self.nu, self.n_boundary, self.schedule = nu, n_boundary, schedule
+        self.vanka, self.cycle = vanka, cycle
         self.doms = [Domain(box_labels(dims), h, eta, gamma)]
         for _ in range(levels - 1):
             self.doms.append(self.doms[-1].coarsen())
@@ -74,15 +85,19 @@ class Hierarchy:
         return from_vector(dom, np.linalg.solve(self.coarse_matrix, to_vector(dom, b)))
 
 
-def vcycle(H: Hierarchy, b, level: int = 0):
-    """t = V-CYCLE(L~, b, 0, levels - level) of Alg. 1."""
+def vcycle(H: Hierarchy, b, level: int = 0, x=None):
+    """t = V-CYCLE(L~, b, x, levels - level) of Alg. 1 (x = 0 unless given);
+    a W-cycle when H.cycle = 2."""
     if level == H.levels - 1:
         return H.coarse_solve(b)
     dom, coarse = H.doms[level], H.doms[level + 1]
-    x = zeros_like_state(dom)
+    x = zeros_like_state(dom) if x is None else x
     x = presmooth(H, level, x, b)
     r = residual(dom, x, b, dom.gamma)
-    e = vcycle(H, restrict(dom, coarse, r), level + 1)
+    bc = restrict(dom, coarse, r)
+    e = None
+    for _ in range(H.cycle):
+        e = vcycle(H, bc, level + 1, e)
     x = tuple(v + dv for v, dv in zip(x, prolong(dom, coarse, e)))
     return postsmooth(H, level, x, b)
 
@@ -99,18 +114,18 @@ def presmooth(H: Hierarchy, level: int, x, b):
     dom, diags = H.doms[level], H.diags[level]
     if H.schedule == "symmetric":
         for _ in range(H.nu // 2):
-            x = smooth(dom, x, b, H.n_boundary, diags)
+            x = smooth(dom, x, b, H.n_boundary, diags, vanka=H.vanka)
         return x
-    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_reverse, H.nu))
+    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_reverse, H.nu), vanka=H.vanka)
 
 
 def postsmooth(H: Hierarchy, level: int, x, b):
     dom, diags = H.doms[level], H.diags[level]
     if H.schedule == "symmetric":
         for _ in range(H.nu // 2):
-            x = smooth(dom, x, b, H.n_boundary, diags)
+            x = smooth(dom, x, b, H.n_boundary, diags, vanka=H.vanka)
         return x
-    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_forward, H.nu))
+    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_forward, H.nu), vanka=H.vanka)
 
 
 def apply_L(H: Hierarchy, x):

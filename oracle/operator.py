@@ -115,3 +115,18 @@ def assemble(dom: Domain, gamma: float = 0.0, dense: bool = False):
         e[j] = 0.0
     m = np.stack(cols, axis=1)
     return m if dense else sp.csr_matrix(m)
+
+
+def lid_lift(dom: Domain, velocity: float):
+    """Right-hand side of a lid: the top wall (the plus-z side) moves along x
+    with `velocity`, every other wall is at rest (the driven cavity of
+    Section 6).  The paper moves Dirichlet values to the right-hand side
+    (Section 5); with the tangential ghost value at the Dirichlet cell's face
+    centre (first order), the u_x faces of the top cell row have the lid's
+    u_x as their +z lattice neighbour, so each of their rows gains
+    (eta / h^2) * velocity.  Returns the state to add to b (zero elsewhere)."""
+    nx, ny, nz = dom.dims
+    bx = np.zeros(dom.shapes[0])
+    bx[:, :, nz - 1] = dom.eta / dom.h ** 2 * velocity
+    bx = np.where(dom.active[0], bx, 0.0)
+    return bx, np.zeros(dom.shapes[1]), np.zeros(dom.shapes[2]), np.zeros(dom.shapes[3])

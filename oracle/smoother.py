@@ -174,16 +174,10 @@ def vanka_local_matrix(eta: float, h: float, gamma: float, act: np.ndarray) -> n
     return K
 
 
-def vanka_color(dom: Domain, x, b, colour: int):
-    """One colour class of multiplicative Vanka on V1.
-
-    Reading (intra-colour semantics): all subdomains of one class take their
-    local residual from the state at the start of the class and then apply
-    their corrections, i.e. x <- x + sum_i C_i^T K_i^{-1} C_i (b - L~ x) over
-    the class.  Same-class subdomains share no unknown (cells two apart), so
-    the corrections never overlap.
-    """
-    cells = np.argwhere(dom.v1[3] & (dom.vanka_colour() == colour))
+def vanka_cells_step(dom: Domain, x, b, cells: np.ndarray):
+    """x <- x + sum_i C_i^T K_i^{-1} C_i (b - L~ x) over the given V1 cells, every
+    local residual taken from the same state; corrections of subdomains that
+    share an unknown add up (Eq. av when the cells are all of V1)."""
     if cells.shape[0] == 0:
         return x
     idx, act = vanka_slots(dom, cells)
@@ -198,16 +192,53 @@ def vanka_color(dom: Domain, x, b, colour: int):
     return tuple(x)
 
 
-def vanka_symmetric(dom: Domain, x, b):
-    """Symmetric multiplicative Vanka (Section 3.2): classes 0..7, then 7..0."""
-    for colour in range(8):
-        x = vanka_color(dom, x, b, colour)
-    for colour in reversed(range(8)):
-        x = vanka_color(dom, x, b, colour)
+def vanka_color(dom: Domain, x, b, colour: int, period: int = 2):
+    """One colour class of multiplicative Vanka on V1.
+
+    Reading (intra-colour semantics): all subdomains of one class take their
+    local residual from the state at the start of the class and then apply
+    their corrections, i.e. x <- x + sum_i C_i^T K_i^{-1} C_i (b - L~ x) over
+    the class.  Same-class subdomains share no unknown (cells two apart), so
+    the corrections never overlap.  With period 3 (27 classes) they do not
+    even share a stencil entry, so the class step equals the one-subdomain-
+    at-a-time sequence of Eq. mv in any order inside the class.
+    """
+    cells = np.argwhere(dom.v1[3] & (dom.vanka_colour(period) == colour))
+    return vanka_cells_step(dom, x, b, cells)
+
+
+def vanka_symmetric(dom: Domain, x, b, period: int = 2):
+    """Symmetric multiplicative Vanka (Section 3.2): classes 0..n-1, then n-1..0."""
+    n = period ** 3
+    for colour in range(n):
+        x = vanka_color(dom, x, b, colour, period)
+    for colour in reversed(range(n)):
+        x = vanka_color(dom, x, b, colour, period)
     return x
 
 
-def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None, interior=None):
+def vanka_additive(dom: Domain, x, b):
+    """Additive Vanka (Eq. av): every V1 subdomain solves from the same
+    residual and the corrections are summed, x <- x + S_AV (b - L~ x)."""
+    return vanka_cells_step(dom, x, b, np.argwhere(dom.v1[3]))
+
+
+VANKA_KINDS = ("mult8", "mult27", "additive")
+
+
+def vanka_apply(dom: Domain, x, b, kind: str = "mult8"):
+    """One application of the chosen V1 smoother: symmetric multiplicative with
+    8 or 27 colour classes, or additive (symmetric by itself, App. B)."""
+    if kind == "mult8":
+        return vanka_symmetric(dom, x, b, 2)
+    if kind == "mult27":
+        return vanka_symmetric(dom, x, b, 3)
+    if kind == "additive":
+        return vanka_additive(dom, x, b)
+    raise ValueError(kind)
+
+
+def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None, interior=None, vanka: str = "mult8"):
     """Alg. 3: symmetric Vanka on V1, an interior smoother on V2, symmetric
     Vanka on V1.  The interior smoother defaults to the symmetric DGS of
     Section 3.1; `interior(dom, x, b, diags)` replaces it.
@@ -217,8 +248,8 @@ def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None, interior=None):
     Vanka applications fill each Vanka slot.
     """
     for _ in range(n_boundary):
-        x = vanka_symmetric(dom, x, b)
+        x = vanka_apply(dom, x, b, vanka)
     x = (interior or dgs_symmetric)(dom, x, b, diags)
     for _ in range(n_boundary):
-        x = vanka_symmetric(dom, x, b)
+        x = vanka_apply(dom, x, b, vanka)
     return x

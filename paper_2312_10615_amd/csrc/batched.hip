@@ -77,6 +77,8 @@ int validate_batch(int n, const stokes_params* p) {
     if (q.smoother != STOKES_SMOOTHER_SPLIT && q.smoother != STOKES_SMOOTHER_SYMMETRIC) return STOKES_EINVAL;
     if (q.smoother == STOKES_SMOOTHER_SYMMETRIC && q.nu % 2) return STOKES_EINVAL;
     if (q.vcycle_precision != 64 && q.vcycle_precision != 32) return STOKES_EINVAL;
+    // batches run the paper's V-cycle with the 8-colour multiplicative Vanka
+    if (q.vanka != STOKES_VANKA_MULT8 || q.cycle != 1) return STOKES_EINVAL;
     // the smoothing schedule runs level-synchronously: one schedule for the batch
     if (q.nu != p[0].nu || q.n_boundary != p[0].n_boundary || q.smoother != p[0].smoother ||
         q.vcycle_precision != p[0].vcycle_precision)

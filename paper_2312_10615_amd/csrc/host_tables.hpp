@@ -170,14 +170,21 @@ inline bool coarse_inverse(const Geom& g, std::vector<int>& dof, std::vector<dou
 }
 
 // Slots of the V1 cells (cells with a face on the Dirichlet layer), split by
-// the 8-colour class.
-inline void vanka_cells(const Geom& g, std::vector<int> cells[8]) {
-  for (int c = 0; c < 8; ++c) cells[c].clear();
+// colour class (i mod q) + q (j mod q) + q^2 (k mod q), 0-based i, j, k;
+// q = 2 gives the 8 classes of Section 6, q = 3 27 classes.  `cells` has q^3
+// entries.
+inline void vanka_cells(const Geom& g, std::vector<int>* cells, int period = 2) {
+  const int nc = period * period * period;
+  for (int c = 0; c < nc; ++c) cells[c].clear();
   for (int K = 1; K <= g.nz; ++K)
     for (int J = 1; J <= g.ny; ++J)
       for (int I = 1; I <= g.nx; ++I) {
         const bool ring = I == 1 || I == g.nx || J == 1 || J == g.ny || K == 1 || K == g.nz;
-        if (ring) cells[Geom::vanka_colour(I, J, K)].push_back(g.idx(I, J, K));
+        if (!ring) continue;
+        const int colour = period == 2 ? Geom::vanka_colour(I, J, K)
+                                       : ((I - 1) % period) + period * ((J - 1) % period) +
+                                             period * period * ((K - 1) % period);
+        cells[colour].push_back(g.idx(I, J, K));
       }
 }
 

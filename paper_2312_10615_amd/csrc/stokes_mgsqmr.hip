@@ -31,8 +31,9 @@ struct Level {
   void* x = nullptr;     // iterate (same)
   void* r = nullptr;     // residual scratch (all but the coarsest)
   void* dscr = nullptr;  // DGS pressure-step deltas (p field)
-  int* vcells[8] = {};
-  int nv[8] = {};
+  int* vcells[27] = {};   // V1 cells per colour class (8 or 27 classes)
+  int nv[27] = {};
+  long doff[27] = {};     // class slice of the Vanka delta buffer (additive Vanka keeps all classes)
   void* kinv = nullptr;  // 64 x 8 x 8 Vanka local inverses
 };
 
@@ -183,6 +184,8 @@ int slot_grid(const Geom& g) { return slab_blocks(g, g.sy); }
     if (e_ != hipSuccess) return STOKES_EDEVICE;      \
   } while (0)
 
+int vanka_classes(const stokes_params& p) { return p.vanka == STOKES_VANKA_MULT27 ? 27 : 8; }
+
 long coarse_dofs(const Geom& g) {
   return (long)(g.nx - 1) * g.ny * g.nz + (long)g.nx * (g.ny - 1) * g.nz + (long)g.nx * g.ny * (g.nz - 1) +
          (long)g.nx * g.ny * g.nz;
@@ -198,6 +201,9 @@ int validate(const stokes_params* p, int* levels_out) {
   if (p->smoother != STOKES_SMOOTHER_SPLIT && p->smoother != STOKES_SMOOTHER_SYMMETRIC) return STOKES_EINVAL;
   if (p->smoother == STOKES_SMOOTHER_SYMMETRIC && (p->nu % 2)) return STOKES_EINVAL;
   if (p->vcycle_precision != 64 && p->vcycle_precision != 32) return STOKES_EINVAL;
+  if (p->vanka != STOKES_VANKA_MULT8 && p->vanka != STOKES_VANKA_MULT27 && p->vanka != STOKES_VANKA_ADDITIVE)
+    return STOKES_EINVAL;
+  if (p->cycle != 1 && p->cycle != 2) return STOKES_EINVAL;
   int L = p->levels;
   if (L == 0) L = count_levels(p->nx, p->ny, p->nz, 4);
   if (L < 1 || L > count_levels(p->nx, p->ny, p->nz, 2)) return STOKES_EINVAL;
@@ -242,12 +248,16 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
       lv.r = cv.take<char>(tot * es);
       lv.dscr = cv.take<char>(lv.g.field * es);
       lv.kinv = cv.take<char>(64 * 64 * es);
-      std::vector<int> cells[8];
-      vanka_cells(lv.g, cells);
-      for (int k = 0; k < 8; ++k) {
+      std::vector<int> cells[27];
+      const int nc = vanka_classes(p);
+      vanka_cells(lv.g, cells, nc == 27 ? 3 : 2);
+      long sum = 0;
+      for (int k = 0; k < nc; ++k) {
         lv.nv[k] = (int)cells[k].size();
         lv.vcells[k] = cv.take<int>(std::max<size_t>(cells[k].size(), 1));
-        vmax = std::max<long>(vmax, lv.nv[k]);
+        lv.doff[k] = p.vanka == STOKES_VANKA_ADDITIVE ? sum : 0;
+        sum += 8L * lv.nv[k];
+        vmax = std::max<long>(vmax, p.vanka == STOKES_VANKA_ADDITIVE ? sum / 8 : lv.nv[k]);
       }
     }
   }
@@ -292,20 +302,47 @@ void launch(stokes_ctx* c, int cls, int level, F f) {
 }
 
 template <typename T>
-void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
+void vanka_delta(stokes_ctx* c, int l, const T* x, const T* b, int k) {
   const Level& lv = c->lev[l];
-  for (int pass = 0; pass < 16; ++pass) {
-    const int k = pass < 8 ? pass : 15 - pass;
-    const int n = lv.nv[k];
-    if (n == 0) continue;
-    const int nb = (8 * n + BS - 1) / BS;  // eight lanes per subdomain
-    const Geom g = lv.g;
-    const int* cells = lv.vcells[k];
-    const T* kinv = (const T*)lv.kinv;
-    T* vd = (T*)c->vdelta;
-    launch(c, STOKES_KC_VANKA_DELTA, l,
-           [=] { k_vanka_delta<T, T><<<nb, BS, 0, c->ks>>>(g, x, b, cells, n, kinv, vd); });
-    launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_vanka_apply<T><<<nb, BS, 0, c->ks>>>(g, x, cells, n, vd); });
+  const int n = lv.nv[k];
+  if (n == 0) return;
+  const int nb = (8 * n + BS - 1) / BS;  // eight lanes per subdomain
+  const Geom g = lv.g;
+  const int* cells = lv.vcells[k];
+  const T* kinv = (const T*)lv.kinv;
+  T* vd = (T*)c->vdelta + lv.doff[k];
+  launch(c, STOKES_KC_VANKA_DELTA, l,
+         [=] { k_vanka_delta<T, T><<<nb, BS, 0, c->ks>>>(g, x, b, cells, n, kinv, vd); });
+}
+
+template <typename T>
+void vanka_correct(stokes_ctx* c, int l, T* x, int k) {
+  const Level& lv = c->lev[l];
+  const int n = lv.nv[k];
+  if (n == 0) return;
+  const int nb = (8 * n + BS - 1) / BS;
+  const Geom g = lv.g;
+  const int* cells = lv.vcells[k];
+  const T* vd = (const T*)c->vdelta + lv.doff[k];
+  launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_vanka_apply<T><<<nb, BS, 0, c->ks>>>(g, x, cells, n, vd); });
+}
+
+// One application of the V1 smoother in a Vanka slot of Alg. 3: symmetric
+// multiplicative Vanka (classes forward then backward; each class from the
+// state at its start), or additive Vanka (Eq. av: every class from the same
+// state, the corrections then added class by class in a fixed order).
+template <typename T>
+void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
+  const int nc = vanka_classes(c->prm);
+  if (c->prm.vanka == STOKES_VANKA_ADDITIVE) {
+    for (int k = 0; k < nc; ++k) vanka_delta<T>(c, l, x, b, k);
+    for (int k = 0; k < nc; ++k) vanka_correct<T>(c, l, x, k);
+    return;
+  }
+  for (int pass = 0; pass < 2 * nc; ++pass) {
+    const int k = pass < nc ? pass : 2 * nc - 1 - pass;
+    vanka_delta<T>(c, l, x, b, k);
+    vanka_correct<T>(c, l, x, k);
   }
 }
 
@@ -376,9 +413,10 @@ void fill_zero(stokes_ctx* c, T* x, long n, int level = 0) {
   launch(c, STOKES_KC_BLAS, level, [=] { k_fill<T><<<RED_BLOCKS, BS, 0, c->ks>>>(x, n, T(0)); });
 }
 
-// x = V-CYCLE(L~, b, 0, L - l)
+// x = V-CYCLE(L~, b, 0, L - l) (from the current x when zero_init is false);
+// with cycle = 2 the coarse correction is two cycles (a W-cycle)
 template <typename T>
-void vcycle(stokes_ctx* c, int l, const T* b, T* x) {
+void vcycle(stokes_ctx* c, int l, const T* b, T* x, bool zero_init = true) {
   if (l == c->tail) {
     const TailArgs a = c->targs;
     const TailLev* tl = c->tlev;
@@ -386,7 +424,7 @@ void vcycle(stokes_ctx* c, int l, const T* b, T* x) {
     return;
   }
   const Geom g = c->lev[l].g;
-  fill_zero(c, x, 4L * g.field, l);
+  if (zero_init) fill_zero(c, x, 4L * g.field, l);
   if (l == c->L - 1) {
     const int nb = (c->nc + (BS / 64) - 1) / (BS / 64);
     const double* cinv = c->cinv;
@@ -405,6 +443,7 @@ void vcycle(stokes_ctx* c, int l, const T* b, T* x) {
   });
   launch(c, STOKES_KC_RESTRICT, l, [=] { k_restrict<T><<<slot_grid(gc), BS, 0, c->ks>>>(g, gc, r, bc); });
   vcycle(c, l + 1, (const T*)bc, xc);
+  for (int i = 1; i < c->prm.cycle; ++i) vcycle(c, l + 1, (const T*)bc, xc, false);
   launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_add<T><<<slot_grid(g), BS, 0, c->ks>>>(g, gc, xc, x); });
   postsmooth(c, l, x, b);
 }
@@ -529,6 +568,8 @@ int stokes_default_params(int32_t nx, int32_t ny, int32_t nz, double h, stokes_p
   p->vcycle_precision = 64;
   p->smoother = STOKES_SMOOTHER_SPLIT;
   p->flags = STOKES_FLAG_REMOVE_MEAN;
+  p->vanka = STOKES_VANKA_MULT8;
+  p->cycle = 1;
   return STOKES_OK;
 }
 
@@ -586,9 +627,10 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
     if (hipMemcpyAsync(lv.kinv, src, nbytes, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
       return fail(STOKES_EDEVICE);
-    std::vector<int> cells[8];
-    vanka_cells(lv.g, cells);
-    for (int k = 0; k < 8; ++k) {
+    std::vector<int> cells[27];
+    const int nc = vanka_classes(c->prm);
+    vanka_cells(lv.g, cells, nc == 27 ? 3 : 2);
+    for (int k = 0; k < nc; ++k) {
       if (cells[k].empty()) continue;
       if (hipMemcpyAsync(lv.vcells[k], cells[k].data(), cells[k].size() * sizeof(int), hipMemcpyHostToDevice,
                          c->stream) != hipSuccess)
@@ -607,7 +649,7 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
       return fail(STOKES_EDEVICE);
   }
   // the tail: the first level with at most TAIL_CELLS cells, down to the coarsest
-  if (p->flags & STOKES_FLAG_TAIL) {
+  if ((p->flags & STOKES_FLAG_TAIL) && p->vanka == STOKES_VANKA_MULT8 && p->cycle == 1) {
     for (int l = 0; l < L; ++l) {
       const Geom& g = c->lev[l].g;
       if ((long)g.nx * g.ny * g.nz <= TAIL_CELLS && L - l <= TAIL_MAX) {
@@ -713,6 +755,14 @@ int stokes_prolong(stokes_ctx* c, const double* coarse, double* fine) {
   const Geom& gc = c->lev[1].g;
   k_fill<double><<<RED_BLOCKS, BS, 0, c->stream>>>(fine, 4L * g.field, 0.0);
   k_prolong_add<double><<<slot_grid(g), BS, 0, c->stream>>>(g, gc, coarse, fine);
+  return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
+}
+
+int stokes_lift(stokes_ctx* c, const double* g, const double* b, double* out) {
+  if (!c || !g || !b || !out || g == out || b == out) return STOKES_EINVAL;
+  const Geom& ge = c->lev[0].g;
+  // b - L g at the unknowns (g holds the boundary values outside them), 0 elsewhere
+  k_apply<AP_RESID, double, double><<<slot_grid(ge), BS, 0, c->stream>>>(ge, g, b, out, 0.0, nullptr);
   return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
 }
 

@@ -21,6 +21,7 @@ STOKES_FLAG_REMOVE_MEAN = 1
 STOKES_FLAG_NO_GRAPH = 2
 STOKES_FLAG_TAIL = 4
 SMOOTHERS = {"split": 0, "symmetric": 1}
+VANKA = {"mult8": 0, "mult27": 1, "additive": 2}
 STATUS_NAMES = {0: "ok", 1: "einval", 2: "enoconv", 3: "ebreakdown", 4: "enonfinite", 5: "edevice"}
 
 
@@ -28,7 +29,8 @@ class StokesParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("h", ctypes.c_double), ("eta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("levels", ctypes.c_int32), ("nu", ctypes.c_int32), ("n_boundary", ctypes.c_int32),
-                ("vcycle_precision", ctypes.c_int32), ("smoother", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("vcycle_precision", ctypes.c_int32), ("smoother", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("vanka", ctypes.c_int32), ("cycle", ctypes.c_int32)]
 
 
 class StokesLayout(ctypes.Structure):
@@ -44,7 +46,7 @@ class StokesInfo(ctypes.Structure):
 
 
 EXPORTS = ("stokes_default_params", "stokes_workspace_bytes", "stokes_setup", "stokes_layout", "stokes_level_layout",
-           "stokes_restrict", "stokes_prolong", "stokes_apply", "stokes_vcycle", "stokes_solve", "stokes_profile",
+           "stokes_restrict", "stokes_prolong", "stokes_lift", "stokes_apply", "stokes_vcycle", "stokes_solve", "stokes_profile",
            "stokes_profile_read", "stokes_destroy", "stokes_strerror", "stokes_batch_workspace_bytes",
            "stokes_batch_setup", "stokes_batch_layout", "stokes_batch_size", "stokes_batch_autotune",
            "stokes_batch_set_chunks", "stokes_batch_solve", "stokes_batch_destroy")
@@ -72,6 +74,7 @@ def load_library(path: str = LIB_PATH):
     lib.stokes_layout.argtypes = [vp, P(StokesLayout)]
     lib.stokes_level_layout.argtypes = [vp, i32, P(StokesLayout)]
     lib.stokes_restrict.argtypes = [vp, vp, vp]
+    lib.stokes_lift.argtypes = [vp, vp, vp, vp]
     lib.stokes_prolong.argtypes = [vp, vp, vp]
     lib.stokes_apply.argtypes = [vp, vp, vp, i32]
     lib.stokes_vcycle.argtypes = [vp, vp, vp]
@@ -236,8 +239,8 @@ class StokesSolver:
     torch tensors of `layout.total` elements on the context's device."""
 
     def __init__(self, nx, ny, nz, h=None, *, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1,
-                 schedule="split", precision=64, remove_mean=True, graphs=True, tail=False, device=None,
-                 stream=None):
+                 schedule="split", precision=64, remove_mean=True, graphs=True, tail=False, vanka="mult8",
+                 cycle=1, device=None, stream=None):
         import torch
         self.torch = torch
         h = 1.0 / max(nx, ny, nz) if h is None else h
@@ -245,6 +248,7 @@ class StokesSolver:
         p.eta, p.gamma, p.levels, p.nu, p.n_boundary = eta, gamma, levels, nu, n_boundary
         p.smoother = SMOOTHERS[schedule]
         p.vcycle_precision = precision
+        p.vanka, p.cycle = VANKA[vanka], int(cycle)
         p.flags = (STOKES_FLAG_REMOVE_MEAN if remove_mean else 0) | (0 if graphs else STOKES_FLAG_NO_GRAPH) | \
             (STOKES_FLAG_TAIL if tail else 0)
         self.params = p
@@ -304,6 +308,23 @@ class StokesSolver:
         f = out if out is not None else self.new_state()
         _check(stokes_prolong(self.ctx, coarse.data_ptr(), f.data_ptr()), "stokes_prolong")
         return f
+
+    def lift(self, g, b, out=None):
+        """out = b - L g at the unknowns: boundary values held in g's non-unknown slots
+        moved to the right-hand side."""
+        o = out if out is not None else self.new_state()
+        _check(load_library().stokes_lift(self.ctx, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                          ctypes.c_void_p(o.data_ptr())), "stokes_lift")
+        return o
+
+    def lid_boundary(self, velocity):
+        """State vector holding a lid on the plus-z wall moving along x with
+        `velocity`: the u_x ghost slots above the top cell row, zero elsewhere."""
+        L = self.layout
+        g = self.new_state()
+        v = state_views(L, g)
+        v[0][L.nz + 1, 1:L.ny + 1, 2:L.nx + 1] = velocity
+        return g
 
     def vcycle(self, s, out=None):
         t = self.new_state() if out is None else out

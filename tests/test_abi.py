@@ -46,6 +46,7 @@ def test_defaults_and_workspace_sizes():
 
 @pytest.mark.parametrize("field,value", [("nx", 1), ("h", 0.0), ("eta", -1.0), ("nu", 0), ("n_boundary", 0),
                                          ("vcycle_precision", 16), ("vcycle_precision", 33), ("levels", 6), ("levels", -1), ("smoother", 7),
+                                         ("vanka", 3), ("cycle", 3), ("cycle", 0),
                                          ("symmetric-odd-nu", 3)])
 def test_invalid_parameters_are_rejected_on_the_host(field, value):
     p = S.stokes_default_params(32, 32, 32, 1 / 32)
