@@ -124,11 +124,18 @@ typedef struct stokes_params {
  * per V-cycle at 256^3). */
 #define STOKES_FLAG_TAIL 4
 
+/* A state vector holds u_x, u_y, u_z, p, each over the padded slots
+ * s = I + sy J + sz K (I in [0, nx+1], ... ; cell (I,J,K) owns p(I,J,K) and
+ * its minus faces u_x(I,J,K), u_y(I,J,K), u_z(I,J,K)).  sy and sz are odd, so
+ * s & 1 is the red/black colour of the slot, and each field stores its two
+ * colours apart: field f's slot s is element
+ *     off[f] + (s & 1) * (field / 2) + (s >> 1).
+ * Elements that are not unknowns hold 0. */
 typedef struct stokes_layout_t {
   int32_t nx, ny, nz;         /* interior cells */
-  int64_t sy, sz;             /* element strides of J and K (stride of I is 1) */
+  int64_t sy, sz;             /* slot pitches of J and K (odd; the pitch of I is 1) */
   int64_t off[4];             /* element offset of u_x, u_y, u_z, p */
-  int64_t field;              /* elements per field (off[f+1] - off[f]) */
+  int64_t field;              /* elements per field (off[f+1] - off[f]), even */
   int64_t total;              /* elements in one state vector */
   int64_t n_dofs;             /* number of unknowns */
   int32_t levels;             /* resolved level count */

@@ -54,13 +54,14 @@ typedef struct {
   const uint16_t* src1; /* CAT_UP / MASKED only, 16-byte aligned */
 } unet_source;
 
-/* Layout of a Stokes state vector (see stokes_layout in stokes_mgsqmr.h):
- * field f (u_x, u_y, u_z, p) of padded cell (I, J, K) is at
- * off[f] + I + sy*J + sz*K, I in [0, nx+1], and so on. */
+/* Layout of a Stokes state vector (stokes_layout_t in stokes_mgsqmr.h): field
+ * f (u_x, u_y, u_z, p) of padded cell (I, J, K), slot s = I + sy J + sz K, is
+ * element off[f] + (s & 1) * half + (s >> 1); half = field / 2. */
 typedef struct {
   int32_t nx, ny, nz;
   int64_t sy, sz;
   int64_t off[4];
+  int64_t half;
 } unet_state_layout;
 
 /* ---------------------------------------------------------------- weights */

@@ -336,10 +336,11 @@ __global__ __launch_bounds__(BS) void kb_clear_ghosts(const BEnt* __restrict__ t
   slot_ijk(g, s, I, J, K);
   double* xv = x + voff[d];
   const int F = g.field;
-  if (!g.ux_active(I, J, K)) xv[s] = 0.0;
-  if (!g.uy_active(I, J, K)) xv[F + s] = 0.0;
-  if (!g.uz_active(I, J, K)) xv[2 * F + s] = 0.0;
-  if (!g.p_active(I, J, K)) xv[3 * F + s] = 0.0;
+  const int e = g.at(s);
+  if (!g.ux_active(I, J, K)) xv[e] = 0.0;
+  if (!g.uy_active(I, J, K)) xv[F + e] = 0.0;
+  if (!g.uz_active(I, J, K)) xv[2 * F + e] = 0.0;
+  if (!g.p_active(I, J, K)) xv[3 * F + e] = 0.0;
 }
 
 // partial[blk] = sum of active p over the block's slots (pressure mean)
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(BS) void kb_sum_p(const BEnt* __restrict__ tab, int
   if (s < g.field) {
     int I, J, K;
     slot_ijk(g, s, I, J, K);
-    if (g.p_active(I, J, K)) v = x[voff[d] + 3L * g.field + s];
+    if (g.p_active(I, J, K)) v = x[voff[d] + 3L * g.field + g.at(s)];
   }
   const double t = block_sum(v);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(BS) void kb_shift_p(const BEnt* __restrict__ tab, i
   int I, J, K;
   slot_ijk(g, s, I, J, K);
   const double mean = sc[d].red[RED0] / ((double)g.nx * g.ny * g.nz);
-  if (g.p_active(I, J, K)) x[voff[d] + 3L * g.field + s] -= mean;
+  if (g.p_active(I, J, K)) x[voff[d] + 3L * g.field + g.at(s)] -= mean;
 }
 
 // sc[d].red[slot + k] = sum of partial[blk * stride + k] over the domain's blocks, in order

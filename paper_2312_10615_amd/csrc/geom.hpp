@@ -3,8 +3,12 @@
 //
 // A level is a box of nx*ny*nz cells of edge h surrounded by one layer of
 // Dirichlet cells (Section 5 of the paper; label coarsening keeps a box a
-// box).  Every field (u_x, u_y, u_z, p) is stored in the same padded array of
-// (nx+2) x (ny+2) x (nz+2) slots, x fastest, rows padded to a pitch `sy`.
+// box).  Every field (u_x, u_y, u_z, p) uses the same padded grid of
+// (nx+2) x (ny+2) x (nz+2) slots: slot s = I + sy J + sz K, x fastest, with an
+// odd row pitch sy and an odd plane pitch sz, so that s & 1 is the parity of
+// I + J + K, the red/black colour of the slot.  A field stores its two colours
+// apart: slot s lives at element at(s) = (s & 1) half + (s >> 1), so a colour
+// pass of the smoothers reads and writes contiguous half-fields.
 // Cell (I,J,K) (padded, 1-based for interior cells) owns p at (I,J,K), its
 // minus-x face u_x at (I,J,K) and its plus-x face u_x at (I+1,J,K); y and z
 // likewise.  Slots that are not unknowns hold zero.
@@ -20,15 +24,18 @@
 
 struct Geom {
   int nx, ny, nz;   // interior cells
-  int sy;           // row pitch (elements), even
-  int sz;           // plane stride = sy * (ny + 2)
-  int field;        // elements per field (multiple of 64)
+  int sy;           // row pitch (slots), odd
+  int sz;           // plane pitch (slots), odd, >= sy * (ny + 2)
+  int field;        // elements per field: slots rounded up to even
+  int half;         // field / 2: the colour-1 slots start here
   int rows;         // (ny + 2) * (nz + 2)
   double h, inv_h;  // cell edge and its inverse
   double c;         // eta / h^2 (the viscous stencil weight)
   double eta, gamma;
 
   SG_HD int idx(int I, int J, int K) const { return I + sy * J + sz * K; }
+  // element of slot s inside a field (red/black split)
+  SG_HD int at(int s) const { return (s & 1) * half + (s >> 1); }
 
   // --- unknowns (Section 5: faces between two interior cells, interior cells) ---
   SG_HD bool ux_active(int I, int J, int K) const {

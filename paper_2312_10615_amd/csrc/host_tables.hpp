@@ -19,10 +19,12 @@ inline Geom make_geom(int nx, int ny, int nz, double h, double eta, double gamma
   g.nx = nx >> level;
   g.ny = ny >> level;
   g.nz = nz >> level;
-  g.sy = round_up(g.nx + 2, 8);
-  g.sz = g.sy * (g.ny + 2);
+  g.sy = (g.nx + 2) | 1;            // odd pitches: slot parity = colour
+  g.sz = (g.sy * (g.ny + 2)) | 1;
   g.rows = (g.ny + 2) * (g.nz + 2);
-  g.field = g.sz * (g.nz + 2);  // a multiple of 8 elements (64 B), since sy is
+  const long slots = (long)g.sz * (g.nz + 2);
+  g.field = (int)(slots + (slots & 1));
+  g.half = g.field / 2;
   g.h = h * std::ldexp(1.0, level);
   g.inv_h = 1.0 / g.h;
   g.c = eta / (g.h * g.h);
@@ -121,10 +123,13 @@ inline bool vanka_inverses(const Geom& g, std::vector<double>& out) {
 
 // Dense L~ at a (small) level, in the order of `dof` (element offsets inside a
 // state vector: all u_x, then u_y, u_z, p, each x-fastest), then inverted.
+// The matrix is assembled on slot codes f * F + s (slot arithmetic for the
+// neighbours); `dof` holds the matching element offsets f * F + at(s).
 inline bool coarse_inverse(const Geom& g, std::vector<int>& dof, std::vector<double>& inv) {
   dof.clear();
   const int F = g.field;
-  std::vector<int> pos((size_t)4 * F, -1);
+  std::vector<int> pos((size_t)4 * F, -1);   // slot code -> row
+  std::vector<int> code;                     // row -> slot code
   for (int f = 0; f < 4; ++f)
     for (int K = 0; K < g.nz + 2; ++K)
       for (int J = 0; J < g.ny + 2; ++J)
@@ -134,19 +139,21 @@ inline bool coarse_inverse(const Geom& g, std::vector<int>& dof, std::vector<dou
                            : f == 2 ? g.uz_active(I, J, K)
                                     : g.p_active(I, J, K);
           if (act) {
-            pos[(size_t)f * F + g.idx(I, J, K)] = (int)dof.size();
-            dof.push_back(f * F + g.idx(I, J, K));
+            const int slot = g.idx(I, J, K);
+            pos[(size_t)f * F + slot] = (int)code.size();
+            code.push_back(f * F + slot);
+            dof.push_back(f * F + g.at(slot));
           }
         }
-  const int n = (int)dof.size();
+  const int n = (int)code.size();
   std::vector<double> a((size_t)n * n, 0.0);
-  auto add = [&](int row, long col_elem, double v) {
-    const int c = pos[(size_t)col_elem];
+  auto add = [&](int row, long col_code, double v) {
+    const int c = pos[(size_t)col_code];
     if (c >= 0) a[(size_t)row * n + c] += v;
   };
   const int strides[3] = {1, g.sy, g.sz};
   for (int r = 0; r < n; ++r) {
-    const int e = dof[r];
+    const int e = code[r];
     const int f = e / F, s = e % F;
     if (f < 3) {
       add(r, e, 6.0 * g.c);

@@ -82,15 +82,17 @@ __device__ __forceinline__ double block_sum(double v) {
 template <typename T>
 __device__ __forceinline__ T row_u(const Geom& g, const T* __restrict__ u, const T* __restrict__ p, int s,
                                         int pstride) {
-  const T lap = T(6) * u[s] - u[s - 1] - u[s + 1] - u[s - g.sy] - u[s + g.sy] - u[s - g.sz] - u[s + g.sz];
-  return (T)g.c * lap + (p[s] - p[s - pstride]) * (T)g.inv_h;
+  const T lap = T(6) * u[g.at(s)] - u[g.at(s - 1)] - u[g.at(s + 1)] - u[g.at(s - g.sy)] - u[g.at(s + g.sy)] -
+                u[g.at(s - g.sz)] - u[g.at(s + g.sz)];
+  return (T)g.c * lap + (p[g.at(s)] - p[g.at(s - pstride)]) * (T)g.inv_h;
 }
 
 template <typename T>
 __device__ __forceinline__ T row_p(const Geom& g, const T* __restrict__ ux, const T* __restrict__ uy,
                                         const T* __restrict__ uz, const T* __restrict__ p, int s, double gamma) {
-  const T div = (ux[s + 1] - ux[s]) + (uy[s + g.sy] - uy[s]) + (uz[s + g.sz] - uz[s]);
-  return -div * (T)g.inv_h - (T)gamma * p[s];
+  const T div = (ux[g.at(s + 1)] - ux[g.at(s)]) + (uy[g.at(s + g.sy)] - uy[g.at(s)]) +
+                (uz[g.at(s + g.sz)] - uz[g.at(s)]);
+  return -div * (T)g.inv_h - (T)gamma * p[g.at(s)];
 }
 
 enum ApplyMode { AP_APPLY = 0, AP_RESID = 1, AP_APPLY_DOT = 2, AP_RESNORM = 3, AP_BNORM = 4 };
@@ -128,9 +130,10 @@ __device__ __forceinline__ double apply_item(const Geom& g, const T* __restrict_
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       T v = o[f];
-      if (MODE == AP_RESID || MODE == AP_RESNORM || MODE == AP_BNORM) v = act[f] ? (T)b[f * F + s] - v : T(0);
-      if (MODE == AP_APPLY || MODE == AP_RESID || MODE == AP_APPLY_DOT) y[f * F + s] = v;
-      if (MODE == AP_APPLY_DOT) acc += (double)x[f * F + s] * (double)v;
+      const int e = f * F + g.at(s);
+      if (MODE == AP_RESID || MODE == AP_RESNORM || MODE == AP_BNORM) v = act[f] ? (T)b[e] - v : T(0);
+      if (MODE == AP_APPLY || MODE == AP_RESID || MODE == AP_APPLY_DOT) y[e] = v;
+      if (MODE == AP_APPLY_DOT) acc += (double)x[e] * (double)v;
       if (MODE == AP_RESNORM || MODE == AP_BNORM) acc += v * v;
     }
   }
@@ -173,9 +176,10 @@ __device__ __forceinline__ void dgs_u_item(const Geom& g, T* __restrict__ x, con
   T* uz = x + 2 * F;
   const T* p = x + 3 * F;
   const T dinv = (T)(1.0 / (6.0 * g.c));
-  if (g.ux_v2(I, J, K)) ux[s] = ux[s] + ((T)b[s] - row_u(g, ux, p, s, 1)) * dinv;
-  if (g.uy_v2(I, J, K)) uy[s] = uy[s] + ((T)b[F + s] - row_u(g, uy, p, s, g.sy)) * dinv;
-  if (g.uz_v2(I, J, K)) uz[s] = uz[s] + ((T)b[2 * F + s] - row_u(g, uz, p, s, g.sz)) * dinv;
+  const int e = g.at(s);
+  if (g.ux_v2(I, J, K)) ux[e] = ux[e] + ((T)b[e] - row_u(g, ux, p, s, 1)) * dinv;
+  if (g.uy_v2(I, J, K)) uy[e] = uy[e] + ((T)b[F + e] - row_u(g, uy, p, s, g.sy)) * dinv;
+  if (g.uz_v2(I, J, K)) uz[e] = uz[e] + ((T)b[2 * F + e] - row_u(g, uz, p, s, g.sz)) * dinv;
 }
 
 template <typename T, typename TB>
@@ -202,17 +206,19 @@ __device__ __forceinline__ void dgs_pf_own_item(const Geom& g, T* __restrict__ x
   T* uz = x + 2 * F;
   T* p = x + 3 * F;
   const double ih2 = g.inv_h * g.inv_h;
-  const T r = (T)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma);
+  const int e = g.at(s);
+  const T r = (T)b[3 * F + e] - row_p(g, ux, uy, uz, p, s, g.gamma);
   const T delta = r / (T)(-6.0 * (1.0 + g.gamma * g.eta) * ih2);
-  dscr[s] = delta;
+  dscr[e] = delta;
   const T dh = delta * (T)g.inv_h;
-  ux[s] = ux[s] - dh;
-  ux[s + 1] = ux[s + 1] + dh;
-  uy[s] = uy[s] - dh;
-  uy[s + g.sy] = uy[s + g.sy] + dh;
-  uz[s] = uz[s] - dh;
-  uz[s + g.sz] = uz[s + g.sz] + dh;
-  p[s] = p[s] + (T)(6.0 * g.eta * ih2) * delta;
+  const int ex = g.at(s + 1), ey = g.at(s + g.sy), ez = g.at(s + g.sz);
+  ux[e] = ux[e] - dh;
+  ux[ex] = ux[ex] + dh;
+  uy[e] = uy[e] - dh;
+  uy[ey] = uy[ey] + dh;
+  uz[e] = uz[e] - dh;
+  uz[ez] = uz[ez] + dh;
+  p[e] = p[e] + (T)(6.0 * g.eta * ih2) * delta;
 }
 
 template <typename T, typename TB>
@@ -233,13 +239,14 @@ __device__ __forceinline__ void dgs_pf_nbr_item(const Geom& g, T* __restrict__ x
   const int s = g.idx(I, J, K);
   T* p = x + 3 * g.field;
   T sum = T(0);
-  if (g.p_v2(I - 1, J, K)) sum += dscr[s - 1];
-  if (g.p_v2(I + 1, J, K)) sum += dscr[s + 1];
-  if (g.p_v2(I, J - 1, K)) sum += dscr[s - g.sy];
-  if (g.p_v2(I, J + 1, K)) sum += dscr[s + g.sy];
-  if (g.p_v2(I, J, K - 1)) sum += dscr[s - g.sz];
-  if (g.p_v2(I, J, K + 1)) sum += dscr[s + g.sz];
-  if (sum != T(0)) p[s] = p[s] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
+  if (g.p_v2(I - 1, J, K)) sum += dscr[g.at(s - 1)];
+  if (g.p_v2(I + 1, J, K)) sum += dscr[g.at(s + 1)];
+  if (g.p_v2(I, J - 1, K)) sum += dscr[g.at(s - g.sy)];
+  if (g.p_v2(I, J + 1, K)) sum += dscr[g.at(s + g.sy)];
+  if (g.p_v2(I, J, K - 1)) sum += dscr[g.at(s - g.sz)];
+  if (g.p_v2(I, J, K + 1)) sum += dscr[g.at(s + g.sz)];
+  const int e = g.at(s);
+  if (sum != T(0)) p[e] = p[e] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
 }
 
 template <typename T>
@@ -270,20 +277,21 @@ __device__ __forceinline__ void dgs_pr_item(const Geom& g, T* __restrict__ x, co
   const TB* buz = b + 2 * F;
   const TB* bp = b + 3 * F;
   // sum_a (r(plus face) - r(minus face))
-  T fsum = ((T)bux[s + 1] - row_u(g, ux, p, s + 1, 1)) - ((T)bux[s] - row_u(g, ux, p, s, 1));
-  fsum += ((T)buy[s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy)) - ((T)buy[s] - row_u(g, uy, p, s, g.sy));
-  fsum += ((T)buz[s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz)) - ((T)buz[s] - row_u(g, uz, p, s, g.sz));
+  const int e = g.at(s);
+  T fsum = ((T)bux[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1)) - ((T)bux[e] - row_u(g, ux, p, s, 1));
+  fsum += ((T)buy[g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy)) - ((T)buy[e] - row_u(g, uy, p, s, g.sy));
+  fsum += ((T)buz[g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz)) - ((T)buz[e] - row_u(g, uz, p, s, g.sz));
   const double gam = g.gamma;
-  const T rj = (T)bp[s] - row_p(g, ux, uy, uz, p, s, gam);
-  T nsum = (T)bp[s - 1] - row_p(g, ux, uy, uz, p, s - 1, gam);
-  nsum += (T)bp[s + 1] - row_p(g, ux, uy, uz, p, s + 1, gam);
-  nsum += (T)bp[s - g.sy] - row_p(g, ux, uy, uz, p, s - g.sy, gam);
-  nsum += (T)bp[s + g.sy] - row_p(g, ux, uy, uz, p, s + g.sy, gam);
-  nsum += (T)bp[s - g.sz] - row_p(g, ux, uy, uz, p, s - g.sz, gam);
-  nsum += (T)bp[s + g.sz] - row_p(g, ux, uy, uz, p, s + g.sz, gam);
+  const T rj = (T)bp[e] - row_p(g, ux, uy, uz, p, s, gam);
+  T nsum = (T)bp[g.at(s - 1)] - row_p(g, ux, uy, uz, p, s - 1, gam);
+  nsum += (T)bp[g.at(s + 1)] - row_p(g, ux, uy, uz, p, s + 1, gam);
+  nsum += (T)bp[g.at(s - g.sy)] - row_p(g, ux, uy, uz, p, s - g.sy, gam);
+  nsum += (T)bp[g.at(s + g.sy)] - row_p(g, ux, uy, uz, p, s + g.sy, gam);
+  nsum += (T)bp[g.at(s - g.sz)] - row_p(g, ux, uy, uz, p, s - g.sz, gam);
+  nsum += (T)bp[g.at(s + g.sz)] - row_p(g, ux, uy, uz, p, s + g.sz, gam);
   const double ih2 = g.inv_h * g.inv_h;
   const T rt = fsum * (T)g.inv_h + (T)(g.eta * ih2) * (T(6) * rj - nsum);
-  p[s] = p[s] + rt / (T)(-6.0 * (1.0 + gam * g.eta) * ih2);
+  p[e] = p[e] + rt / (T)(-6.0 * (1.0 + gam * g.eta) * ih2);
 }
 
 template <typename T, typename TB>
@@ -325,13 +333,13 @@ __device__ __forceinline__ void vanka_delta_item(const Geom& g, const T* __restr
   T res = T(0);
   if (valid) {
     switch (r) {
-      case 0: if (a0) res = (T)b[s] - row_u(g, ux, p, s, 1); break;
-      case 1: if (a1) res = (T)b[s + 1] - row_u(g, ux, p, s + 1, 1); break;
-      case 2: if (a2) res = (T)b[F + s] - row_u(g, uy, p, s, g.sy); break;
-      case 3: if (a3) res = (T)b[F + s + g.sy] - row_u(g, uy, p, s + g.sy, g.sy); break;
-      case 4: if (a4) res = (T)b[2 * F + s] - row_u(g, uz, p, s, g.sz); break;
-      case 5: if (a5) res = (T)b[2 * F + s + g.sz] - row_u(g, uz, p, s + g.sz, g.sz); break;
-      case 6: res = (T)b[3 * F + s] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
+      case 0: if (a0) res = (T)b[g.at(s)] - row_u(g, ux, p, s, 1); break;
+      case 1: if (a1) res = (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1); break;
+      case 2: if (a2) res = (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy); break;
+      case 3: if (a3) res = (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy); break;
+      case 4: if (a4) res = (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz); break;
+      case 5: if (a5) res = (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz); break;
+      case 6: res = (T)b[3 * F + g.at(s)] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
       default: break;
     }
   }
@@ -367,13 +375,13 @@ __device__ __forceinline__ void vanka_apply_item(const Geom& g, T* __restrict__ 
   const int F = g.field;
   int e = -1;
   switch (r) {
-    case 0: if (I >= 2) e = s; break;
-    case 1: if (I + 1 <= g.nx) e = s + 1; break;
-    case 2: if (J >= 2) e = F + s; break;
-    case 3: if (J + 1 <= g.ny) e = F + s + g.sy; break;
-    case 4: if (K >= 2) e = 2 * F + s; break;
-    case 5: if (K + 1 <= g.nz) e = 2 * F + s + g.sz; break;
-    default: e = 3 * F + s; break;
+    case 0: if (I >= 2) e = g.at(s); break;
+    case 1: if (I + 1 <= g.nx) e = g.at(s + 1); break;
+    case 2: if (J >= 2) e = F + g.at(s); break;
+    case 3: if (J + 1 <= g.ny) e = F + g.at(s + g.sy); break;
+    case 4: if (K >= 2) e = 2 * F + g.at(s); break;
+    case 5: if (K + 1 <= g.nz) e = 2 * F + g.at(s + g.sz); break;
+    default: e = 3 * F + g.at(s); break;
   }
   if (e >= 0) x[e] = x[e] + delta[c * 8 + r];
 }
@@ -393,7 +401,7 @@ __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, c
 template <typename T>
 __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, const T* __restrict__ r,
                                               T* __restrict__ bc, int I, int J, int K) {
-  const int s = c.idx(I, J, K);
+  const int s = c.at(c.idx(I, J, K));
   const int Ff = f.field, Fc = c.field;
   const T wf[3] = {0.5, 1.0, 0.5};          // face axis: fine 2I-2, 2I-1, 2I
   const T wc[4] = {0.25, 0.75, 0.75, 0.25};  // cell axis: fine 2J-2 .. 2J+1
@@ -405,7 +413,7 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
         for (int jj = 0; jj < 4; ++jj) {
           const T w = wc[jj] * wc[kk];
           const int base = f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk);
-          acc += w * (wf[0] * (T)r[base] + wf[1] * (T)r[base + 1] + wf[2] * (T)r[base + 2]);
+          acc += w * (wf[0] * (T)r[f.at(base)] + wf[1] * (T)r[f.at(base + 1)] + wf[2] * (T)r[f.at(base + 2)]);
         }
     }
     bc[s] = (T)(acc * T(0.125));
@@ -417,7 +425,7 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
       for (int kk = 0; kk < 4; ++kk)
         for (int jj = 0; jj < 3; ++jj)
           for (int ii = 0; ii < 4; ++ii)
-            acc += wc[ii] * wf[jj] * wc[kk] * (T)r[Ff + f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk)];
+            acc += wc[ii] * wf[jj] * wc[kk] * (T)r[Ff + f.at(f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk))];
     }
     bc[Fc + s] = (T)(acc * T(0.125));
   }
@@ -428,7 +436,7 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
       for (int kk = 0; kk < 3; ++kk)
         for (int jj = 0; jj < 4; ++jj)
           for (int ii = 0; ii < 4; ++ii)
-            acc += wc[ii] * wc[jj] * wf[kk] * (T)r[2 * Ff + f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk)];
+            acc += wc[ii] * wc[jj] * wf[kk] * (T)r[2 * Ff + f.at(f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk))];
     }
     bc[2 * Fc + s] = (T)(acc * T(0.125));
   }
@@ -438,7 +446,7 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
     if (c.p_active(I, J, K)) {
       for (int kk = 0; kk < 2; ++kk)
         for (int jj = 0; jj < 2; ++jj)
-          for (int ii = 0; ii < 2; ++ii) acc += (T)r[3 * Ff + f.idx(2 * I - 1 + ii, 2 * J - 1 + jj, 2 * K - 1 + kk)];
+          for (int ii = 0; ii < 2; ++ii) acc += (T)r[3 * Ff + f.at(f.idx(2 * I - 1 + ii, 2 * J - 1 + jj, 2 * K - 1 + kk))];
     }
     bc[3 * Fc + s] = (T)(acc * T(0.125));
   }
@@ -480,7 +488,7 @@ __device__ __forceinline__ void face_w(int I, int& n0, int& n1, double& w0, doub
 template <typename T>
 __device__ __forceinline__ void prolong_item(const Geom& f, const Geom& c, const T* __restrict__ e,
                                              T* __restrict__ x, int I, int J, int K) {
-  const int s = f.idx(I, J, K);
+  const int s = f.at(f.idx(I, J, K));
   const int Ff = f.field, Fc = c.field;
   if (f.ux_active(I, J, K)) {
     int a0, a1, b0, b1, c0, c1;
@@ -488,11 +496,11 @@ __device__ __forceinline__ void prolong_item(const Geom& f, const Geom& c, const
     face_w(I, a0, a1, w0, w1);
     cell_w(J, b0, b1);
     cell_w(K, c0, c1);
-    auto at = [&](int i, int j, int k) { return (T)e[c.idx(i, j, k)]; };
-    const T v = (T)w0 * (T(0.75) * (T(0.75) * at(a0, b0, c0) + T(0.25) * at(a0, b1, c0)) +
-                           T(0.25) * (T(0.75) * at(a0, b0, c1) + T(0.25) * at(a0, b1, c1))) +
-                     (T)w1 * (T(0.75) * (T(0.75) * at(a1, b0, c0) + T(0.25) * at(a1, b1, c0)) +
-                           T(0.25) * (T(0.75) * at(a1, b0, c1) + T(0.25) * at(a1, b1, c1)));
+    auto ev = [&](int i, int j, int k) { return (T)e[c.at(c.idx(i, j, k))]; };
+    const T v = (T)w0 * (T(0.75) * (T(0.75) * ev(a0, b0, c0) + T(0.25) * ev(a0, b1, c0)) +
+                           T(0.25) * (T(0.75) * ev(a0, b0, c1) + T(0.25) * ev(a0, b1, c1))) +
+                     (T)w1 * (T(0.75) * (T(0.75) * ev(a1, b0, c0) + T(0.25) * ev(a1, b1, c0)) +
+                           T(0.25) * (T(0.75) * ev(a1, b0, c1) + T(0.25) * ev(a1, b1, c1)));
     x[s] = x[s] + v;
   }
   if (f.uy_active(I, J, K)) {
@@ -501,11 +509,11 @@ __device__ __forceinline__ void prolong_item(const Geom& f, const Geom& c, const
     face_w(J, b0, b1, w0, w1);
     cell_w(I, a0, a1);
     cell_w(K, c0, c1);
-    auto at = [&](int i, int j, int k) { return (T)e[Fc + c.idx(i, j, k)]; };
-    const T v = (T)w0 * (T(0.75) * (T(0.75) * at(a0, b0, c0) + T(0.25) * at(a1, b0, c0)) +
-                           T(0.25) * (T(0.75) * at(a0, b0, c1) + T(0.25) * at(a1, b0, c1))) +
-                     (T)w1 * (T(0.75) * (T(0.75) * at(a0, b1, c0) + T(0.25) * at(a1, b1, c0)) +
-                           T(0.25) * (T(0.75) * at(a0, b1, c1) + T(0.25) * at(a1, b1, c1)));
+    auto ev = [&](int i, int j, int k) { return (T)e[Fc + c.at(c.idx(i, j, k))]; };
+    const T v = (T)w0 * (T(0.75) * (T(0.75) * ev(a0, b0, c0) + T(0.25) * ev(a1, b0, c0)) +
+                           T(0.25) * (T(0.75) * ev(a0, b0, c1) + T(0.25) * ev(a1, b0, c1))) +
+                     (T)w1 * (T(0.75) * (T(0.75) * ev(a0, b1, c0) + T(0.25) * ev(a1, b1, c0)) +
+                           T(0.25) * (T(0.75) * ev(a0, b1, c1) + T(0.25) * ev(a1, b1, c1)));
     x[Ff + s] = x[Ff + s] + v;
   }
   if (f.uz_active(I, J, K)) {
@@ -514,16 +522,16 @@ __device__ __forceinline__ void prolong_item(const Geom& f, const Geom& c, const
     face_w(K, c0, c1, w0, w1);
     cell_w(I, a0, a1);
     cell_w(J, b0, b1);
-    auto at = [&](int i, int j, int k) { return (T)e[2 * Fc + c.idx(i, j, k)]; };
-    const T v = (T)w0 * (T(0.75) * (T(0.75) * at(a0, b0, c0) + T(0.25) * at(a1, b0, c0)) +
-                           T(0.25) * (T(0.75) * at(a0, b1, c0) + T(0.25) * at(a1, b1, c0))) +
-                     (T)w1 * (T(0.75) * (T(0.75) * at(a0, b0, c1) + T(0.25) * at(a1, b0, c1)) +
-                           T(0.25) * (T(0.75) * at(a0, b1, c1) + T(0.25) * at(a1, b1, c1)));
+    auto ev = [&](int i, int j, int k) { return (T)e[2 * Fc + c.at(c.idx(i, j, k))]; };
+    const T v = (T)w0 * (T(0.75) * (T(0.75) * ev(a0, b0, c0) + T(0.25) * ev(a1, b0, c0)) +
+                           T(0.25) * (T(0.75) * ev(a0, b1, c0) + T(0.25) * ev(a1, b1, c0))) +
+                     (T)w1 * (T(0.75) * (T(0.75) * ev(a0, b0, c1) + T(0.25) * ev(a1, b0, c1)) +
+                           T(0.25) * (T(0.75) * ev(a0, b1, c1) + T(0.25) * ev(a1, b1, c1)));
     x[2 * Ff + s] = x[2 * Ff + s] + v;
   }
   if (f.p_active(I, J, K)) {
     const int ci = ((I - 1) >> 1) + 1, cj = ((J - 1) >> 1) + 1, ck = ((K - 1) >> 1) + 1;
-    x[3 * Ff + s] = x[3 * Ff + s] + e[3 * Fc + c.idx(ci, cj, ck)];
+    x[3 * Ff + s] = x[3 * Ff + s] + e[3 * Fc + c.at(c.idx(ci, cj, ck))];
   }
 }
 
@@ -594,7 +602,7 @@ static __global__ __launch_bounds__(BS) void k_sum_p(Geom g, const double* __res
   if (s < g.field) {
     int I, J, K;
     slot_ijk(g, s, I, J, K);
-    if (g.p_active(I, J, K)) v = x[3 * g.field + s];
+    if (g.p_active(I, J, K)) v = x[3 * g.field + g.at(s)];
   }
   const double t = block_sum(v);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -605,7 +613,7 @@ static __global__ __launch_bounds__(BS) void k_shift_p(Geom g, double* __restric
   if (s >= g.field) return;
   int I, J, K;
   slot_ijk(g, s, I, J, K);
-  if (g.p_active(I, J, K)) x[3 * g.field + s] -= amount;
+  if (g.p_active(I, J, K)) x[3 * g.field + g.at(s)] -= amount;
 }
 
 // Zero the ghost slots of a state vector (the caller's initial guess).
@@ -615,10 +623,11 @@ static __global__ __launch_bounds__(BS) void k_clear_ghosts(Geom g, double* __re
   int I, J, K;
   slot_ijk(g, s, I, J, K);
   const int F = g.field;
-  if (!g.ux_active(I, J, K)) x[s] = 0.0;
-  if (!g.uy_active(I, J, K)) x[F + s] = 0.0;
-  if (!g.uz_active(I, J, K)) x[2 * F + s] = 0.0;
-  if (!g.p_active(I, J, K)) x[3 * F + s] = 0.0;
+  const int e = g.at(s);
+  if (!g.ux_active(I, J, K)) x[e] = 0.0;
+  if (!g.uy_active(I, J, K)) x[F + e] = 0.0;
+  if (!g.uz_active(I, J, K)) x[2 * F + e] = 0.0;
+  if (!g.p_active(I, J, K)) x[3 * F + e] = 0.0;
 }
 
 // s -= a * t

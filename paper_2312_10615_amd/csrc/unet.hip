@@ -565,11 +565,13 @@ __global__ __launch_bounds__(BS) void k_adam(float* __restrict__ p, const float*
 
 struct Lay {
   int nx, ny, nz;
-  long sy, sz, off[4];
+  long sy, sz, off[4], half;
 };
 
+// element (inside a field) of the slot of voxel (i, j, k): padded cell (i+1, j+1, k+1)
 __device__ __forceinline__ long slot(const Lay& L, int i, int j, int k) {
-  return (long)(i + 1) + L.sy * (j + 1) + L.sz * (k + 1);
+  const long s = (long)(i + 1) + L.sy * (j + 1) + L.sz * (k + 1);
+  return (s & 1) * L.half + (s >> 1);
 }
 
 __global__ __launch_bounds__(BS) void k_vel_sumsq(const double* __restrict__ b, Lay L, double* __restrict__ partial) {
@@ -627,7 +629,8 @@ __global__ __launch_bounds__(BS) void k_output_to_state(const float* __restrict_
   if (e >= 4 * field) return;
   const int f = (int)(e / field);
   const long r = e - f * field;
-  const int K = (int)(r / L.sz), J = (int)((r % L.sz) / L.sy), I = (int)(r % L.sy);
+  const long rp = r % L.sz;  // slot within its plane
+  const int K = (int)(r / L.sz), J = (int)(rp / L.sy), I = (int)(rp % L.sy);
   bool un = I >= 1 && I <= L.nx && J >= 1 && J <= L.ny && K >= 1 && K <= L.nz;
   if (f == 0) un = un && I >= 2;
   if (f == 1) un = un && J >= 2;
@@ -637,7 +640,7 @@ __global__ __launch_bounds__(BS) void k_output_to_state(const float* __restrict_
     const long v = ((long)(K - 1) * L.ny + (J - 1)) * L.nx + (I - 1);
     val = (double)out[v * 4 + f] * scale[0] * (double)sigma[f];
   }
-  x[L.off[f] + r] = val;
+  x[L.off[f] + (r & 1) * L.half + (r >> 1)] = val;
 }
 
 __global__ __launch_bounds__(BS) void k_channel_sumsq(const float* __restrict__ t, long nvox,
@@ -739,11 +742,13 @@ bool wgrad_shape(const unet_source* x, int cout, WgradShape& w) {
 }
 
 Lay to_lay(const unet_state_layout* L) {
-  return Lay{L->nx, L->ny, L->nz, (long)L->sy, (long)L->sz, {(long)L->off[0], (long)L->off[1], (long)L->off[2], (long)L->off[3]}};
+  return Lay{L->nx, L->ny, L->nz, (long)L->sy, (long)L->sz,
+             {(long)L->off[0], (long)L->off[1], (long)L->off[2], (long)L->off[3]}, (long)L->half};
 }
 
 bool lay_ok(const unet_state_layout* L) {
-  return L && L->nx > 0 && L->ny > 0 && L->nz > 0 && L->sy >= L->nx + 2 && L->sz >= L->sy * (L->ny + 2);
+  return L && L->nx > 0 && L->ny > 0 && L->nz > 0 && L->sy >= L->nx + 2 && L->sz >= L->sy * (L->ny + 2) &&
+         2 * L->half >= L->sz * (L->nz + 2);
 }
 
 }  // namespace
@@ -917,7 +922,7 @@ int unet_state_to_target(const double* x, const unet_state_layout* L, const doub
 int unet_output_to_state(const float* out, const unet_state_layout* L, const double* scale, const float* sigma,
                          double* x, void* stream) {
   if (!out || !lay_ok(L) || !scale || !sigma || !x) return UNET_EINVAL;
-  const long field = (long)L->sz * (L->nz + 2);
+  const long field = 2 * L->half;
   for (int f = 1; f < 4; ++f)
     if (L->off[f] - L->off[f - 1] < field) return UNET_EINVAL;
   k_output_to_state<<<grid1(4 * field), BS, 0, S(stream)>>>(out, to_lay(L), scale, sigma, x, field);

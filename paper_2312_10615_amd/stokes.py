@@ -194,11 +194,17 @@ def stokes_strerror(code: int) -> str:
 
 # --- torch plumbing -------------------------------------------------------------
 
-def state_views(layout, state):
-    """The four fields of a padded state vector as [K, J, I] views."""
+def field_index(layout, device):
+    """[K, J, I] -> element of padded cell (I, J, K) inside a field: its slot
+    s = I + sy J + sz K is stored at (s & 1) * field/2 + (s >> 1) (red and
+    black slots apart)."""
+    import torch
     L = layout
-    nz2, ny2 = L.nz + 2, L.ny + 2
-    return [state[L.off[f]:L.off[f] + L.sz * nz2].view(nz2, ny2, L.sy) for f in range(4)]
+    K = torch.arange(L.nz + 2, dtype=torch.int64, device=device).view(-1, 1, 1)
+    J = torch.arange(L.ny + 2, dtype=torch.int64, device=device).view(1, -1, 1)
+    I = torch.arange(L.sy, dtype=torch.int64, device=device).view(1, 1, -1)
+    s = I + L.sy * J + L.sz * K
+    return (s & 1) * (L.field // 2) + (s >> 1)
 
 
 def pack_fields(layout, fields, out, device):
@@ -209,13 +215,13 @@ def pack_fields(layout, fields, out, device):
     L = layout
     nx, ny, nz = L.nx, L.ny, L.nz
     st = out.zero_()
-    v = state_views(L, st)
+    e = field_index(L, st.device)
     t = [torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
                          dtype=torch.float64).to(device) for a in fields]
-    v[0][1:nz + 1, 1:ny + 1, 2:nx + 1] = t[0][1:nx].permute(2, 1, 0)
-    v[1][1:nz + 1, 2:ny + 1, 1:nx + 1] = t[1][:, 1:ny].permute(2, 1, 0)
-    v[2][2:nz + 1, 1:ny + 1, 1:nx + 1] = t[2][:, :, 1:nz].permute(2, 1, 0)
-    v[3][1:nz + 1, 1:ny + 1, 1:nx + 1] = t[3].permute(2, 1, 0)
+    st[L.off[0] + e[1:nz + 1, 1:ny + 1, 2:nx + 1]] = t[0][1:nx].permute(2, 1, 0)
+    st[L.off[1] + e[1:nz + 1, 2:ny + 1, 1:nx + 1]] = t[1][:, 1:ny].permute(2, 1, 0)
+    st[L.off[2] + e[2:nz + 1, 1:ny + 1, 1:nx + 1]] = t[2][:, :, 1:nz].permute(2, 1, 0)
+    st[L.off[3] + e[1:nz + 1, 1:ny + 1, 1:nx + 1]] = t[3].permute(2, 1, 0)
     return st
 
 
@@ -223,11 +229,11 @@ def unpack_fields(layout, state):
     """Padded state -> natural numpy arrays (walls included, zero)."""
     L = layout
     nx, ny, nz = L.nx, L.ny, L.nz
-    v = state_views(L, state)
-    ux = v[0][1:nz + 1, 1:ny + 1, 1:nx + 2].permute(2, 1, 0).cpu().numpy().copy()
-    uy = v[1][1:nz + 1, 1:ny + 2, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
-    uz = v[2][1:nz + 2, 1:ny + 1, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
-    p = v[3][1:nz + 1, 1:ny + 1, 1:nx + 1].permute(2, 1, 0).cpu().numpy().copy()
+    e = field_index(L, state.device)
+    ux = state[L.off[0] + e[1:nz + 1, 1:ny + 1, 1:nx + 2]].permute(2, 1, 0).cpu().numpy().copy()
+    uy = state[L.off[1] + e[1:nz + 1, 1:ny + 2, 1:nx + 1]].permute(2, 1, 0).cpu().numpy().copy()
+    uz = state[L.off[2] + e[1:nz + 2, 1:ny + 1, 1:nx + 1]].permute(2, 1, 0).cpu().numpy().copy()
+    p = state[L.off[3] + e[1:nz + 1, 1:ny + 1, 1:nx + 1]].permute(2, 1, 0).cpu().numpy().copy()
     ux[0] = ux[-1] = 0.0
     uy[:, 0] = uy[:, -1] = 0.0
     uz[:, :, 0] = uz[:, :, -1] = 0.0
@@ -322,8 +328,8 @@ class StokesSolver:
         `velocity`: the u_x ghost slots above the top cell row, zero elsewhere."""
         L = self.layout
         g = self.new_state()
-        v = state_views(L, g)
-        v[0][L.nz + 1, 1:L.ny + 1, 2:L.nx + 1] = velocity
+        e = field_index(L, g.device)
+        g[L.off[0] + e[L.nz + 1, 1:L.ny + 1, 2:L.nx + 1]] = velocity
         return g
 
     def vcycle(self, s, out=None):

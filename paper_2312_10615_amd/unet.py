@@ -59,7 +59,7 @@ class Source(ctypes.Structure):
 
 class StateLayout(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("sy", ctypes.c_int64),
-                ("sz", ctypes.c_int64), ("off", ctypes.c_int64 * 4)]
+                ("sz", ctypes.c_int64), ("off", ctypes.c_int64 * 4), ("half", ctypes.c_int64)]
 
 
 def load_library():
@@ -198,6 +198,7 @@ def state_layout(lay):
     L.sy, L.sz = lay.sy, lay.sz
     for f in range(4):
         L.off[f] = lay.off[f]
+    L.half = lay.field // 2
     return L
 
 

@@ -81,3 +81,27 @@ def test_setup_rejects_null_workspace_without_touching_a_device():
 def test_strerror_names_every_status():
     for code in range(6):
         assert S.stokes_strerror(code) != "unknown status"
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4), (5, 6, 7), (16, 9, 3)])
+def test_red_black_field_index_is_a_bijection_split_by_colour(dims):
+    """Host view of the state layout: odd pitches make the slot parity the
+    cell colour (I + J + K) & 1, and each field stores colour 0 in its first
+    half and colour 1 in its second, every slot at its own element."""
+    import types
+
+    import torch
+    nx, ny, nz = dims
+    sy = (nx + 2) | 1
+    sz = (sy * (ny + 2)) | 1
+    slots = sz * (nz + 2)
+    lay = types.SimpleNamespace(nx=nx, ny=ny, nz=nz, sy=sy, sz=sz, field=slots + (slots & 1))
+    e = S.field_index(lay, "cpu")
+    assert e.shape == (nz + 2, ny + 2, sy)
+    flat = e.flatten()
+    assert flat.unique().numel() == flat.numel() and int(flat.min()) >= 0 and int(flat.max()) < lay.field
+    K, J, I = torch.meshgrid(torch.arange(nz + 2), torch.arange(ny + 2), torch.arange(sy), indexing="ij")
+    colour = (I + J + K) & 1
+    assert bool(((e >= lay.field // 2) == (colour == 1)).all())
+    # along a row, same-colour cells are neighbours in memory
+    assert bool((e[1, 1, 3::2][:-1] + 1 == e[1, 1, 3::2][1:]).all())

@@ -15,7 +15,7 @@ from oracle.domain import Domain, box_labels
 from oracle.multigrid import Hierarchy, vcycle
 from oracle.operator import apply_operator, assemble, from_vector, to_vector
 from oracle.sqmr import mg_sqmr, remove_pressure_mean, sqmr
-from paper_2312_10615_amd.stokes import StokesSolver
+from paper_2312_10615_amd.stokes import StokesSolver, field_index
 from tests.gpu_helpers import announce, cuda, forcing_rhs, max_rel, random_fields, rel_err
 
 pytestmark = pytest.mark.gpu
@@ -192,7 +192,7 @@ def test_edge_cases():
     assert info3["iters"] == 0 and float(x[lay.off[0]]) == 0.0
     # non-finite right-hand side
     bad = b.clone()
-    bad[lay.off[3] + lay.sz + lay.sy + 1] = float("nan")
+    bad[lay.off[3] + int(field_index(lay, "cpu")[1, 1, 1])] = float("nan")   # p of cell (1,1,1)
     x, info = sol.solve(bad)
     assert info["status"] == "enonfinite"
     # smallest box, single level (the V-cycle is the exact inverse of L~):
