@@ -135,7 +135,7 @@ typedef struct stokes_layout_t {
   int32_t nx, ny, nz;         /* interior cells */
   int64_t sy, sz;             /* slot pitches of J and K (odd; the pitch of I is 1) */
   int64_t off[4];             /* element offset of u_x, u_y, u_z, p */
-  int64_t field;              /* elements per field (off[f+1] - off[f]), even */
+  int64_t field;              /* elements per field (off[f+1] - off[f]), a multiple of 8 */
   int64_t total;              /* elements in one state vector */
   int64_t n_dofs;             /* number of unknowns */
   int32_t levels;             /* resolved level count */

@@ -303,7 +303,7 @@ void carve(stokes_batch* c, Carve& cv) {
     });
     c->tcoarse[l] = add_table(c, c->coarse[l], [&](int d) { return (c->hlev[l][d].nc + 3) / 4; });
     for (int k = 0; k < 8; ++k)
-      c->tvanka[l][k] = add_table(c, c->smooth[l], [&](int d) { return (8 * c->hlev[l][d].nv[k] + BS - 1) / BS; });
+      c->tvanka[l][k] = add_table(c, c->smooth[l], [&](int d) { return (c->hlev[l][d].nv[k] + BS - 1) / BS; });
   }
   c->partial = cv.take<double>(2 * maxblk);
   c->arena = cv.take<BEnt>(c->harena.size());

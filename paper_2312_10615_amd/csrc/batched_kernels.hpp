@@ -156,7 +156,7 @@ __global__ __launch_bounds__(BS) void kb_prolong(const BEnt* __restrict__ tab, i
   prolong_item<T>(g, lev[d].gc, (const T*)lev[d].xc, (T*)lev[d].x, I, J, K);
 }
 
-// Vanka, one colour class: eight lanes per V1 cell of each domain
+// Vanka, one colour class: one thread per V1 cell of each domain
 template <typename T>
 __global__ __launch_bounds__(BS) void kb_vanka_delta(const BEnt* __restrict__ tab, int nent,
                                                      const BLev* __restrict__ lev, const int* __restrict__ done,

@@ -1,0 +1,368 @@
+// Distributive Gauss-Seidel (Alg. 2, Eq. dist, Eq. ldist) with V cells per
+// thread for the single-box solver.  The kernels compute exactly what the
+// one-cell items in kernels.hpp compute, cell by cell and in the same order
+// of operations; only the memory access is different.
+//
+// With the red/black split every stencil neighbour of a slot of parity par
+// sits in the other half, at an element shifted by a constant: slot s + o of
+// the cell whose own element is e is element
+//     ((par + o) & 1) * half + e + ((par + o) >> 1).
+// So the V consecutive own elements of a thread have V consecutive
+// neighbours for every offset o, and each operand of the stencil is one wide
+// load (16 bytes: two doubles or four floats) instead of V narrow ones.  The
+// stencil kernels are bound by the rate at which the texture-address units
+// take load instructions, which this divides by V.
+//
+// A thread takes V consecutive cells of one colour inside one row; the last
+// pack of a row may be short (n < V cells).  Loads may run past the row into
+// the next row's elements (always inside the field, whose ghost planes and
+// rows are wider than a pack); stores of a short pack go cell by cell, so no
+// element another thread owns is written.  Every element a full pack stores
+// belongs to its cells alone (own element, or a plus face whose minus-side
+// cell is in the pack), so unchanged values written back race with nothing.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace sg {
+
+typedef double wd2 __attribute__((ext_vector_type(2), aligned(8)));
+typedef float wf2 __attribute__((ext_vector_type(2), aligned(4)));
+typedef float wf4 __attribute__((ext_vector_type(4), aligned(4)));
+
+template <typename T, int V>
+struct Pack {
+  T v[V];
+};
+
+// V consecutive elements in one load (the hardware accepts dword alignment).
+template <typename T, int V>
+__device__ __forceinline__ Pack<T, V> ldp(const T* p) {
+  Pack<T, V> r;
+  if constexpr (V == 1) {
+    r.v[0] = p[0];
+  } else if constexpr (sizeof(T) == 8 && V == 2) {
+    const wd2 w = *(const wd2*)p;
+    r.v[0] = w.x;
+    r.v[1] = w.y;
+  } else if constexpr (sizeof(T) == 4 && V == 2) {
+    const wf2 w = *(const wf2*)p;
+    r.v[0] = w.x;
+    r.v[1] = w.y;
+  } else {
+    static_assert(sizeof(T) == 4 && V == 4, "pack of 16 bytes at most");
+    const wf4 w = *(const wf4*)p;
+    r.v[0] = w.x;
+    r.v[1] = w.y;
+    r.v[2] = w.z;
+    r.v[3] = w.w;
+  }
+  return r;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void stp(T* p, const Pack<T, V>& r) {
+  if constexpr (V == 1) {
+    p[0] = r.v[0];
+  } else if constexpr (sizeof(T) == 8 && V == 2) {
+    wd2 w;
+    w.x = r.v[0];
+    w.y = r.v[1];
+    *(wd2*)p = w;
+  } else if constexpr (sizeof(T) == 4 && V == 2) {
+    wf2 w;
+    w.x = r.v[0];
+    w.y = r.v[1];
+    *(wf2*)p = w;
+  } else {
+    wf4 w;
+    w.x = r.v[0];
+    w.y = r.v[1];
+    w.z = r.v[2];
+    w.w = r.v[3];
+    *(wf4*)p = w;
+  }
+}
+
+// Store the cells of a pack that are flagged; a full pack in one store.
+template <typename T, int V>
+__device__ __forceinline__ void stp_cells(T* p, const Pack<T, V>& r, int n, const bool* act) {
+  if (n == V) {
+    stp<T, V>(p, r);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (i < n && act[i]) p[i] = r.v[i];
+  }
+}
+
+// The pack of this thread: cells I0, I0+2, ... of row (J, K), colour parity par.
+template <int V>
+struct RowPack {
+  int e0;   // element (inside the half) of the first cell
+  int n;    // cells of the row in the pack, 1..V
+  int I0, J, K;
+  int par;
+  int half;
+  // element of slot s_i + o (cell i of the pack is element el(o) + i)
+  __device__ __forceinline__ int el(int o) const {
+    const int q = par + o;
+    return (q & 1) * half + e0 + (q >> 1);
+  }
+};
+
+// Packs of a row of one parity; only interior rows hold cells that change.
+template <int V>
+__host__ __device__ inline int pack_per_row(const Geom& g) {
+  return (((g.sy + 1) >> 1) + V - 1) / V;
+}
+
+template <int V>
+__device__ __forceinline__ bool row_pack(const Geom& g, int par, RowPack<V>& rp) {
+  int m;
+  if (!slab_item(g, pack_per_row<V>(g), m, rp.J, rp.K)) return false;
+  if (rp.J < 1 || rp.J > g.ny || rp.K < 1 || rp.K > g.nz) return false;
+  const int q = (par + rp.J + rp.K) & 1;  // I parity of the row's slots of parity par
+  const int nrow = (g.sy - q + 1) >> 1;
+  const int first = m * V;
+  if (first >= nrow) return false;
+  rp.n = nrow - first < V ? nrow - first : V;
+  rp.I0 = q + 2 * first;
+  rp.e0 = ((g.sy * rp.J + g.sz * rp.K + q) >> 1) + first;
+  rp.par = par;
+  rp.half = g.half;
+  return true;
+}
+
+// Velocity step on the V2 faces of one colour (dgs_u_item, V cells).
+template <typename T, typename TB, int V>
+__global__ __launch_bounds__(BS) void k_dgs_u_v(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
+  RowPack<V> rp;
+  if (!row_pack<V>(g, colour ^ 1, rp)) return;
+  const int F = g.field;
+  const T* p = x + 3 * F;
+  const T dinv = (T)(1.0 / (6.0 * g.c));
+  const int eo = rp.el(0);
+  const Pack<T, V> P = ldp<T, V>(p + eo);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    bool act[V];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int I = rp.I0 + 2 * i;
+      act[i] = i < rp.n && (f == 0 ? g.ux_v2(I, rp.J, rp.K) : f == 1 ? g.uy_v2(I, rp.J, rp.K) : g.uz_v2(I, rp.J, rp.K));
+      any = any || act[i];
+    }
+    if (!any) continue;
+    T* u = x + f * F;
+    const int ps = f == 0 ? 1 : f == 1 ? g.sy : g.sz;
+    Pack<T, V> U = ldp<T, V>(u + eo);
+    const Pack<TB, V> Bv = ldp<TB, V>(b + f * F + eo);
+    const Pack<T, V> xm = ldp<T, V>(u + rp.el(-1)), xp = ldp<T, V>(u + rp.el(1));
+    const Pack<T, V> ym = ldp<T, V>(u + rp.el(-g.sy)), yp = ldp<T, V>(u + rp.el(g.sy));
+    const Pack<T, V> zm = ldp<T, V>(u + rp.el(-g.sz)), zp = ldp<T, V>(u + rp.el(g.sz));
+    const Pack<T, V> Pm = ldp<T, V>(p + rp.el(-ps));
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      if (!act[i]) continue;
+      const T lap = T(6) * U.v[i] - xm.v[i] - xp.v[i] - ym.v[i] - yp.v[i] - zm.v[i] - zp.v[i];
+      const T row = (T)g.c * lap + (P.v[i] - Pm.v[i]) * (T)g.inv_h;
+      U.v[i] = U.v[i] + ((T)Bv.v[i] - row) * dinv;
+    }
+    stp_cells<T, V>(u + eo, U, rp.n, act);
+  }
+}
+
+// Forward-sweep pressure step, part 1 (dgs_pf_own_item, V cells).
+template <typename T, typename TB, int V>
+__global__ __launch_bounds__(BS) void k_dgs_pf_own_v(Geom g, T* __restrict__ x, const TB* __restrict__ b,
+                                                     T* __restrict__ dscr, int colour) {
+  RowPack<V> rp;
+  if (!row_pack<V>(g, colour ^ 1, rp)) return;
+  bool act[V];
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    act[i] = i < rp.n && g.p_v2(rp.I0 + 2 * i, rp.J, rp.K);
+    any = any || act[i];
+  }
+  if (!any) return;
+  const int F = g.field;
+  T* ux = x;
+  T* uy = x + F;
+  T* uz = x + 2 * F;
+  T* p = x + 3 * F;
+  const double ih2 = g.inv_h * g.inv_h;
+  const int eo = rp.el(0), ex = rp.el(1), ey = rp.el(g.sy), ez = rp.el(g.sz);
+  Pack<T, V> X0 = ldp<T, V>(ux + eo), X1 = ldp<T, V>(ux + ex);
+  Pack<T, V> Y0 = ldp<T, V>(uy + eo), Y1 = ldp<T, V>(uy + ey);
+  Pack<T, V> Z0 = ldp<T, V>(uz + eo), Z1 = ldp<T, V>(uz + ez);
+  Pack<T, V> P0 = ldp<T, V>(p + eo);
+  const Pack<TB, V> Bp = ldp<TB, V>(b + 3 * F + eo);
+  Pack<T, V> D;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    D.v[i] = T(0);
+    if (!act[i]) continue;
+    const T div = (X1.v[i] - X0.v[i]) + (Y1.v[i] - Y0.v[i]) + (Z1.v[i] - Z0.v[i]);
+    const T r = (T)Bp.v[i] - (-div * (T)g.inv_h - (T)g.gamma * P0.v[i]);
+    const T delta = r / (T)(-6.0 * (1.0 + g.gamma * g.eta) * ih2);
+    D.v[i] = delta;
+    const T dh = delta * (T)g.inv_h;
+    X0.v[i] = X0.v[i] - dh;
+    X1.v[i] = X1.v[i] + dh;
+    Y0.v[i] = Y0.v[i] - dh;
+    Y1.v[i] = Y1.v[i] + dh;
+    Z0.v[i] = Z0.v[i] - dh;
+    Z1.v[i] = Z1.v[i] + dh;
+    P0.v[i] = P0.v[i] + (T)(6.0 * g.eta * ih2) * delta;
+  }
+  stp_cells<T, V>(dscr + eo, D, rp.n, act);
+  stp_cells<T, V>(ux + eo, X0, rp.n, act);
+  stp_cells<T, V>(ux + ex, X1, rp.n, act);
+  stp_cells<T, V>(uy + eo, Y0, rp.n, act);
+  stp_cells<T, V>(uy + ey, Y1, rp.n, act);
+  stp_cells<T, V>(uz + eo, Z0, rp.n, act);
+  stp_cells<T, V>(uz + ez, Z1, rp.n, act);
+  stp_cells<T, V>(p + eo, P0, rp.n, act);
+}
+
+// Forward-sweep pressure step, part 2 (dgs_pf_nbr_item, V cells of the other colour).
+template <typename T, int V>
+__global__ __launch_bounds__(BS) void k_dgs_pf_nbr_v(Geom g, T* __restrict__ x, const T* __restrict__ dscr,
+                                                     int colour) {
+  RowPack<V> rp;
+  if (!row_pack<V>(g, colour, rp)) return;
+  bool act[V];
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    act[i] = i < rp.n && g.p_active(rp.I0 + 2 * i, rp.J, rp.K);
+    any = any || act[i];
+  }
+  if (!any) return;
+  T* p = x + 3 * g.field;
+  const int eo = rp.el(0);
+  const Pack<T, V> dxm = ldp<T, V>(dscr + rp.el(-1)), dxp = ldp<T, V>(dscr + rp.el(1));
+  const Pack<T, V> dym = ldp<T, V>(dscr + rp.el(-g.sy)), dyp = ldp<T, V>(dscr + rp.el(g.sy));
+  const Pack<T, V> dzm = ldp<T, V>(dscr + rp.el(-g.sz)), dzp = ldp<T, V>(dscr + rp.el(g.sz));
+  Pack<T, V> P = ldp<T, V>(p + eo);
+  const int J = rp.J, K = rp.K;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    if (!act[i]) continue;
+    const int I = rp.I0 + 2 * i;
+    T sum = T(0);
+    if (g.p_v2(I - 1, J, K)) sum += dxm.v[i];
+    if (g.p_v2(I + 1, J, K)) sum += dxp.v[i];
+    if (g.p_v2(I, J - 1, K)) sum += dym.v[i];
+    if (g.p_v2(I, J + 1, K)) sum += dyp.v[i];
+    if (g.p_v2(I, J, K - 1)) sum += dzm.v[i];
+    if (g.p_v2(I, J, K + 1)) sum += dzp.v[i];
+    if (sum != T(0)) P.v[i] = P.v[i] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
+  }
+  stp_cells<T, V>(p + eo, P, rp.n, act);
+}
+
+// Reverse-sweep pressure step (dgs_pr_item, V cells).  Its thirteen local
+// residuals read about 56 distinct operands per cell; held all at once, the
+// packs of V cells would not fit the register file.  So the residuals are
+// taken in stages of G: at the end of a stage the base element (and the
+// uniform sizes) pass through an empty asm statement that also takes the
+// stage's accumulated results, so the next stage's loads can neither be
+// merged with earlier ones nor issued before the stage's arithmetic, and
+// each stage holds only its own operands in registers.  Operands shared by
+// residuals of different stages are loaded again (from the cache).
+template <typename T, typename TB, int V, int G>
+__global__ __launch_bounds__(BS) void k_dgs_pr_v(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
+  RowPack<V> rp;
+  if (!row_pack<V>(g, colour ^ 1, rp)) return;
+  bool act[V];
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    act[i] = i < rp.n && g.p_v2(rp.I0 + 2 * i, rp.J, rp.K);
+    any = any || act[i];
+  }
+  if (!any) return;
+  int F = g.field;
+  int sy = g.sy, sz = g.sz, hf = g.half;
+  int eb = rp.e0;
+  int done = 0;  // residuals evaluated so far
+  auto stage = [&](const T* acc) {
+    if (++done % G != 0) return;
+#pragma unroll
+    for (int i = 0; i < V; ++i) asm volatile("" : "+v"(eb) : "v"(acc[i]));
+    asm volatile("" : "+v"(eb), "+s"(F), "+s"(sy), "+s"(sz), "+s"(hf));
+  };
+  auto L = [&](int f, int o) {
+    const int q = rp.par + o;
+    return ldp<T, V>(x + (f * F + (q & 1) * hf + eb + (q >> 1)));
+  };
+  auto LB = [&](int f, int o) {
+    const int q = rp.par + o;
+    return ldp<TB, V>(b + (f * F + (q & 1) * hf + eb + (q >> 1)));
+  };
+  // local residual of the row of u field f (pitch ps) at slot s_i + o
+  auto res_u = [&](int f, int o, int ps, T* out) {
+    const Pack<T, V> c0 = L(f, o), xm = L(f, o - 1), xp = L(f, o + 1), ym = L(f, o - sy), yp = L(f, o + sy),
+                     zm = L(f, o - sz), zp = L(f, o + sz), pc = L(3, o), pm = L(3, o - ps);
+    const Pack<TB, V> bb = LB(f, o);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const T lap = T(6) * c0.v[i] - xm.v[i] - xp.v[i] - ym.v[i] - yp.v[i] - zm.v[i] - zp.v[i];
+      out[i] = (T)bb.v[i] - ((T)g.c * lap + (pc.v[i] - pm.v[i]) * (T)g.inv_h);
+    }
+  };
+  // local residual of the p row at slot s_i + o
+  const double gam = g.gamma;
+  auto res_p = [&](int o, T* out) {
+    const Pack<T, V> x0 = L(0, o), x1 = L(0, o + 1), y0 = L(1, o), y1 = L(1, o + sy), z0 = L(2, o),
+                     z1 = L(2, o + sz), pc = L(3, o);
+    const Pack<TB, V> bb = LB(3, o);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const T div = (x1.v[i] - x0.v[i]) + (y1.v[i] - y0.v[i]) + (z1.v[i] - z0.v[i]);
+      out[i] = (T)bb.v[i] - (-div * (T)g.inv_h - (T)gam * pc.v[i]);
+    }
+  };
+  // the plus- and minus-face residuals of each axis, in the order of the
+  // one-cell kernel: fsum = (r+x - r-x) + (r+y - r-y) + (r+z - r-z)
+  T fsum[V], a[V], c[V], rj[V], nsum[V];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int ps = f == 0 ? 1 : f == 1 ? sy : sz;
+    res_u(f, ps, ps, a);
+    stage(a);
+    res_u(f, 0, ps, c);
+#pragma unroll
+    for (int i = 0; i < V; ++i) fsum[i] = f == 0 ? a[i] - c[i] : fsum[i] + (a[i] - c[i]);
+    stage(fsum);
+  }
+  res_p(0, rj);
+  stage(rj);
+  res_p(-1, nsum);
+  stage(nsum);
+  const int offs[5] = {1, -sy, sy, -sz, sz};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    res_p(offs[k], a);
+#pragma unroll
+    for (int i = 0; i < V; ++i) nsum[i] += a[i];
+    stage(nsum);
+  }
+  const double ih2 = g.inv_h * g.inv_h;
+  T* p = x + 3 * g.field;
+  const int eo = rp.el(0);
+  Pack<T, V> P = ldp<T, V>(p + eo);
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    if (!act[i]) continue;
+    const T rt = fsum[i] * (T)g.inv_h + (T)(g.eta * ih2) * (T(6) * rj[i] - nsum[i]);
+    P.v[i] = P.v[i] + rt / (T)(-6.0 * (1.0 + gam * g.eta) * ih2);
+  }
+  stp_cells<T, V>(p + eo, P, rp.n, act);
+}
+
+}  // namespace sg

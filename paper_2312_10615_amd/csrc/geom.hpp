@@ -26,7 +26,7 @@ struct Geom {
   int nx, ny, nz;   // interior cells
   int sy;           // row pitch (slots), odd
   int sz;           // plane pitch (slots), odd, >= sy * (ny + 2)
-  int field;        // elements per field: slots rounded up to even
+  int field;        // elements per field: slots + 8 spare, rounded up to a multiple of 8
   int half;         // field / 2: the colour-1 slots start here
   int rows;         // (ny + 2) * (nz + 2)
   double h, inv_h;  // cell edge and its inverse

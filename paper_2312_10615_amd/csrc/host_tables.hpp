@@ -23,7 +23,9 @@ inline Geom make_geom(int nx, int ny, int nz, double h, double eta, double gamma
   g.sz = (g.sy * (g.ny + 2)) | 1;
   g.rows = (g.ny + 2) * (g.nz + 2);
   const long slots = (long)g.sz * (g.nz + 2);
-  g.field = (int)(slots + (slots & 1));
+  // at least 8 spare slots past the last plane (packs of the DGS kernels may
+  // read up to 6 slots past a ghost plane), and a multiple of 8 (halves of 4)
+  g.field = (int)((slots + 8 + 7) / 8 * 8);
   g.half = g.field / 2;
   g.h = h * std::ldexp(1.0, level);
   g.inv_h = 1.0 / g.h;

@@ -51,6 +51,19 @@ __device__ __forceinline__ bool slab_item(const Geom& g, int per_row, int& X, in
   return K < g.nz + 2 && J < g.ny + 2;
 }
 
+// Slot kernels walk each row parity by parity: the first (sy+1)/2 items of a
+// row take its slots of one parity, the rest the other, so the 64 lanes of a
+// wave read one run of consecutive elements of a half field (and the
+// stencil's neighbours, all of the other parity, one run of the other half).
+__device__ __forceinline__ bool split_slot(const Geom& g, int& I, int& J, int& K) {
+  const int hr = (g.sy + 1) >> 1;
+  int X;
+  if (!slab_item(g, 2 * hr, X, J, K)) return false;
+  const int c = X >= hr;
+  I = 2 * (X - c * hr) + ((c + J + K) & 1);
+  return I < g.sy;
+}
+
 __device__ __forceinline__ void slot_ijk(const Geom& g, int s, int& I, int& J, int& K) {
   K = s / g.sz;
   const int rem = s - K * g.sz;
@@ -145,7 +158,7 @@ __global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, c
                                               T* __restrict__ y, double gamma, double* __restrict__ partial) {
   double acc = 0.0;
   int I, J, K;
-  if (slab_item(g, g.sy, I, J, K)) acc = apply_item<MODE, T, TB>(g, x, b, y, gamma, I, J, K);
+  if (split_slot(g, I, J, K)) acc = apply_item<MODE, T, TB>(g, x, b, y, gamma, I, J, K);
   if (MODE == AP_APPLY_DOT || MODE == AP_RESNORM || MODE == AP_BNORM) {
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -308,51 +321,73 @@ __global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const 
 // applies the corrections (part 2).  K^-1 of the local saddle problem comes
 // from a per-level table indexed by the 6-bit face-activity type.
 // ---------------------------------------------------------------------------
-// Eight lanes per subdomain: lane r < 7 evaluates local residual row r
-// (0: u_x minus face, 1: u_x plus face, 2/3: u_y, 4/5: u_z, 6: p), then
-// forms delta_r = sum_j (K^-1)_rj r_j with the group's residuals gathered
-// by shuffles.  delta is stored as 8 values per subdomain.
-// Lane t of the class (t & 7 must equal threadIdx.x & 7, and the eight lanes of
-// a subdomain share a wave); every lane of the wave must call it (shuffles).
+// One thread per subdomain: thread c evaluates the cell's seven local
+// residual rows (0: u_x minus face, 1: u_x plus face, 2/3: u_y, 4/5: u_z,
+// 6: p) and forms delta_r = sum_j (K^-1)_rj r_j.  delta is stored by row:
+// delta[r * ncells + c].  The class lists hold cells in slot order, and with
+// the red/black split consecutive cells of a class along a row are adjacent
+// elements of a half field, so neighbouring threads read neighbouring
+// elements on the planes normal to y and z.
 template <typename T, typename TB>
-__device__ __forceinline__ void vanka_delta_item(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
-                                                 const int* __restrict__ cells, int ncells, const T* __restrict__ kinv,
-                                                 T* __restrict__ delta, int t) {
-  const int c = t >> 3;
-  const int r = t & 7;
-  const bool valid = c < ncells;
-  const int s = valid ? cells[c] : 0;
-  int I = 1, J = 1, K = 1;
-  if (valid) slot_ijk(g, s, I, J, K);
+__device__ __forceinline__ void vanka_delta_at(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                               int s, const T* __restrict__ kinv, T* __restrict__ delta, int c,
+                                               int ncells) {
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
   const int F = g.field;
   const T* ux = x;
   const T* uy = x + F;
   const T* uz = x + 2 * F;
   const T* p = x + 3 * F;
   const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
-  T res = T(0);
-  if (valid) {
-    switch (r) {
-      case 0: if (a0) res = (T)b[g.at(s)] - row_u(g, ux, p, s, 1); break;
-      case 1: if (a1) res = (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1); break;
-      case 2: if (a2) res = (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy); break;
-      case 3: if (a3) res = (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy); break;
-      case 4: if (a4) res = (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz); break;
-      case 5: if (a5) res = (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz); break;
-      case 6: res = (T)b[3 * F + g.at(s)] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
-      default: break;
-    }
-  }
+  T res[7];
+  res[0] = a0 ? (T)b[g.at(s)] - row_u(g, ux, p, s, 1) : T(0);
+  res[1] = a1 ? (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1) : T(0);
+  res[2] = a2 ? (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy) : T(0);
+  res[3] = a3 ? (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy) : T(0);
+  res[4] = a4 ? (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz) : T(0);
+  res[5] = a5 ? (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz) : T(0);
+  res[6] = (T)b[3 * F + g.at(s)] - row_p(g, ux, uy, uz, p, s, g.gamma);
   const int type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
-  const T* km = kinv + type * 64 + (r & 7) * 8;
-  const int base = (int)(threadIdx.x & 63) & ~7;
-  T acc = T(0);
+  const T* km = kinv + type * 64;
 #pragma unroll
-  for (int j = 0; j < 7; ++j) {
-    const T rj = __shfl(res, base + j, 64);
-    acc += km[j] * rj;
+  for (int r = 0; r < 7; ++r) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) acc += km[r * 8 + j] * res[j];
+    delta[(long)r * ncells + c] = acc;
   }
-  if (valid && r < 7) delta[c * 8 + r] = acc;
+}
+
+// x[local DOF r of subdomain c] += delta_r, one thread per subdomain.
+template <typename T>
+__device__ __forceinline__ void vanka_apply_at(const Geom& g, T* __restrict__ x, int s, const T* __restrict__ delta,
+                                               int c, int ncells) {
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
+  const int F = g.field;
+  const T* d = delta + c;
+  const long n = ncells;
+  if (I >= 2) x[g.at(s)] += d[0];
+  if (I + 1 <= g.nx) x[g.at(s + 1)] += d[n];
+  if (J >= 2) x[F + g.at(s)] += d[2 * n];
+  if (J + 1 <= g.ny) x[F + g.at(s + g.sy)] += d[3 * n];
+  if (K >= 2) x[2 * F + g.at(s)] += d[4 * n];
+  if (K + 1 <= g.nz) x[2 * F + g.at(s + g.sz)] += d[5 * n];
+  x[3 * F + g.at(s)] += d[6 * n];
+}
+
+template <typename T, typename TB>
+__device__ __forceinline__ void vanka_delta_item(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                                 const int* __restrict__ cells, int ncells, const T* __restrict__ kinv,
+                                                 T* __restrict__ delta, int c) {
+  if (c < ncells) vanka_delta_at<T, TB>(g, x, b, cells[c], kinv, delta, c, ncells);
+}
+
+template <typename T>
+__device__ __forceinline__ void vanka_apply_item(const Geom& g, T* __restrict__ x, const int* __restrict__ cells,
+                                                 int ncells, const T* __restrict__ delta, int c) {
+  if (c < ncells) vanka_apply_at<T>(g, x, cells[c], delta, c, ncells);
 }
 
 template <typename T, typename TB>
@@ -362,34 +397,56 @@ __global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict_
   vanka_delta_item<T, TB>(g, x, b, cells, ncells, kinv, delta, blockIdx.x * BS + threadIdx.x);
 }
 
-// x[local DOF r of subdomain c] += delta_r, eight lanes per subdomain.
-template <typename T>
-__device__ __forceinline__ void vanka_apply_item(const Geom& g, T* __restrict__ x, const int* __restrict__ cells,
-                                                 int ncells, const T* __restrict__ delta, int t) {
-  const int c = t >> 3;
-  const int r = t & 7;
-  if (c >= ncells || r == 7) return;
-  const int s = cells[c];
-  int I, J, K;
-  slot_ijk(g, s, I, J, K);
-  const int F = g.field;
-  int e = -1;
-  switch (r) {
-    case 0: if (I >= 2) e = g.at(s); break;
-    case 1: if (I + 1 <= g.nx) e = g.at(s + 1); break;
-    case 2: if (J >= 2) e = F + g.at(s); break;
-    case 3: if (J + 1 <= g.ny) e = F + g.at(s + g.sy); break;
-    case 4: if (K >= 2) e = 2 * F + g.at(s); break;
-    case 5: if (K + 1 <= g.nz) e = 2 * F + g.at(s + g.sz); break;
-    default: e = 3 * F + g.at(s); break;
-  }
-  if (e >= 0) x[e] = x[e] + delta[c * 8 + r];
-}
-
 template <typename T>
 __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
                                                     int ncells, const T* __restrict__ delta) {
   vanka_apply_item<T>(g, x, cells, ncells, delta, blockIdx.x * BS + threadIdx.x);
+}
+
+// A whole Vanka smoothing step on a small level in one workgroup: the class
+// passes of vanka_symmetric (delta, then apply, class by class) with a
+// workgroup barrier in place of each kernel boundary.  Within a pass the
+// items are independent, so the result is that of the per-class launches,
+// bit for bit.  On a level whose classes hold a few thousand cells, a pass
+// costs the workgroup one or two memory round trips, where two graph-replayed
+// launches cost several microseconds each.
+constexpr int VSWEEP_BS = 1024;
+constexpr int VSWEEP_MAX_CLASS = 512;  // largest class a level may have to use it (one CU streams it)
+
+struct VSweep {
+  Geom g;
+  int nc;        // colour classes (8 or 27)
+  int additive;  // Eq. av: every class from the same state, then the corrections class by class
+  const int* vc[27];
+  int nv[27];
+  long doff[27];
+  const void* kinv;
+};
+
+template <typename T>
+__global__ __launch_bounds__(VSWEEP_BS) void k_vanka_sweep(VSweep a, T* __restrict__ x, const T* __restrict__ b,
+                                                          T* __restrict__ vd) {
+  const int t = threadIdx.x;
+  const T* kinv = (const T*)a.kinv;
+  if (a.additive) {
+    for (int k = 0; k < a.nc; ++k)
+      for (int c = t; c < a.nv[k]; c += VSWEEP_BS)
+        vanka_delta_item<T, T>(a.g, x, b, a.vc[k], a.nv[k], kinv, vd + a.doff[k], c);
+    __syncthreads();
+    for (int k = 0; k < a.nc; ++k) {
+      for (int c = t; c < a.nv[k]; c += VSWEEP_BS) vanka_apply_item<T>(a.g, x, a.vc[k], a.nv[k], vd + a.doff[k], c);
+      __syncthreads();
+    }
+    return;
+  }
+  for (int pass = 0; pass < 2 * a.nc; ++pass) {
+    const int k = pass < a.nc ? pass : 2 * a.nc - 1 - pass;
+    const int n = a.nv[k];
+    for (int c = t; c < n; c += VSWEEP_BS) vanka_delta_item<T, T>(a.g, x, b, a.vc[k], n, kinv, vd, c);
+    __syncthreads();
+    for (int c = t; c < n; c += VSWEEP_BS) vanka_apply_item<T>(a.g, x, a.vc[k], n, vd, c);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -455,7 +512,7 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
 template <typename T>
 __global__ __launch_bounds__(BS) void k_restrict(Geom f, Geom c, const T* __restrict__ r, T* __restrict__ bc) {
   int I, J, K;
-  if (!slab_item(c, c.sy, I, J, K)) return;
+  if (!slab_item(c, c.sy, I, J, K)) return;  // consecutive coarse slots: dense fine reads
   restrict_item<T>(f, c, r, bc, I, J, K);
 }
 
@@ -538,7 +595,7 @@ __device__ __forceinline__ void prolong_item(const Geom& f, const Geom& c, const
 template <typename T>
 __global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __restrict__ e, T* __restrict__ x) {
   int I, J, K;
-  if (!slab_item(f, f.sy, I, J, K)) return;
+  if (!split_slot(f, I, J, K)) return;
   prolong_item<T>(f, c, e, x, I, J, K);
 }
 

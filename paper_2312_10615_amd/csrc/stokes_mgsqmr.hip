@@ -16,6 +16,7 @@
 
 #include "../../include/stokes_mgsqmr.h"
 #include "host_tables.hpp"
+#include "dgs_vec.hpp"
 #include "kernels.hpp"
 #include "tail_kernels.hpp"
 
@@ -175,8 +176,8 @@ int grid_for(long slots) {
   return (int)nb;
 }
 
-int half_grid(const Geom& g) { return slab_blocks(g, g.sy / 2); }
-int slot_grid(const Geom& g) { return slab_blocks(g, g.sy); }
+int slot_grid(const Geom& g) { return slab_blocks(g, g.sy + 1); }  // split_slot: sy + 1 items per row
+int restrict_grid(const Geom& gc) { return slab_blocks(gc, gc.sy); }  // k_restrict: one item per coarse slot
 
 #define HIPCHK(call)                                  \
   do {                                                \
@@ -185,6 +186,13 @@ int slot_grid(const Geom& g) { return slab_blocks(g, g.sy); }
   } while (0)
 
 int vanka_classes(const stokes_params& p) { return p.vanka == STOKES_VANKA_MULT27 ? 27 : 8; }
+
+// Levels whose Vanka step runs in one workgroup (k_vanka_sweep).
+bool vsweep_level(const Level& lv, int nc) {
+  for (int k = 0; k < nc; ++k)
+    if (lv.nv[k] > VSWEEP_MAX_CLASS) return false;
+  return true;
+}
 
 long coarse_dofs(const Geom& g) {
   return (long)(g.nx - 1) * g.ny * g.nz + (long)g.nx * (g.ny - 1) * g.nz + (long)g.nx * g.ny * (g.nz - 1) +
@@ -306,7 +314,7 @@ void vanka_delta(stokes_ctx* c, int l, const T* x, const T* b, int k) {
   const Level& lv = c->lev[l];
   const int n = lv.nv[k];
   if (n == 0) return;
-  const int nb = (8 * n + BS - 1) / BS;  // eight lanes per subdomain
+  const int nb = (n + BS - 1) / BS;  // one thread per subdomain
   const Geom g = lv.g;
   const int* cells = lv.vcells[k];
   const T* kinv = (const T*)lv.kinv;
@@ -320,7 +328,7 @@ void vanka_correct(stokes_ctx* c, int l, T* x, int k) {
   const Level& lv = c->lev[l];
   const int n = lv.nv[k];
   if (n == 0) return;
-  const int nb = (8 * n + BS - 1) / BS;
+  const int nb = (n + BS - 1) / BS;
   const Geom g = lv.g;
   const int* cells = lv.vcells[k];
   const T* vd = (const T*)c->vdelta + lv.doff[k];
@@ -334,6 +342,22 @@ void vanka_correct(stokes_ctx* c, int l, T* x, int k) {
 template <typename T>
 void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
   const int nc = vanka_classes(c->prm);
+  const Level& lv = c->lev[l];
+  if (vsweep_level(lv, nc)) {  // small level: the whole step in one workgroup
+    VSweep a{};
+    a.g = lv.g;
+    a.nc = nc;
+    a.additive = c->prm.vanka == STOKES_VANKA_ADDITIVE;
+    for (int k = 0; k < nc; ++k) {
+      a.vc[k] = lv.vcells[k];
+      a.nv[k] = lv.nv[k];
+      a.doff[k] = lv.doff[k];
+    }
+    a.kinv = lv.kinv;
+    T* vd = (T*)c->vdelta;
+    launch(c, STOKES_KC_VANKA_DELTA, l, [=] { k_vanka_sweep<T><<<1, VSWEEP_BS, 0, c->ks>>>(a, x, b, vd); });
+    return;
+  }
   if (c->prm.vanka == STOKES_VANKA_ADDITIVE) {
     for (int k = 0; k < nc; ++k) vanka_delta<T>(c, l, x, b, k);
     for (int k = 0; k < nc; ++k) vanka_correct<T>(c, l, x, k);
@@ -348,16 +372,29 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
 
 // Forward DGS sweep on L~ M (Alg. 2, Eq. dist) over the V2 unknowns:
 // velocities red, black; pressures red, black.
+// Cells per thread of the DGS kernels: one 16-byte load per operand.
+template <typename T>
+constexpr int dgs_pack() {
+  return 16 / (int)sizeof(T);
+}
+
+template <typename T>
+int dgs_grid(const Geom& g) {
+  return slab_blocks(g, pack_per_row<dgs_pack<T>()>(g));
+}
+
 template <typename T>
 void dgs_forward(stokes_ctx* c, int l, T* x, const T* b) {
+  constexpr int V = dgs_pack<T>();
   const Geom g = c->lev[l].g;
   T* dscr = (T*)c->lev[l].dscr;
-  const int hg = half_grid(g);
+  const int hg = dgs_grid<T>(g);
   for (int col = 0; col < 2; ++col)
-    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u<T, T><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
+    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
   for (int col = 0; col < 2; ++col) {
-    launch(c, STOKES_KC_DGS_PF_OWN, l, [=] { k_dgs_pf_own<T, T><<<hg, BS, 0, c->ks>>>(g, x, b, dscr, col); });
-    launch(c, STOKES_KC_DGS_PF_NBR, l, [=] { k_dgs_pf_nbr<T><<<hg, BS, 0, c->ks>>>(g, x, dscr, col); });
+    launch(c, STOKES_KC_DGS_PF_OWN, l,
+           [=] { k_dgs_pf_own_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, dscr, col); });
+    launch(c, STOKES_KC_DGS_PF_NBR, l, [=] { k_dgs_pf_nbr_v<T, V><<<hg, BS, 0, c->ks>>>(g, x, dscr, col); });
   }
 }
 
@@ -365,12 +402,19 @@ void dgs_forward(stokes_ctx* c, int l, T* x, const T* b) {
 // order: pressures black, red; velocities black, red.
 template <typename T>
 void dgs_reverse(stokes_ctx* c, int l, T* x, const T* b) {
+  constexpr int V = dgs_pack<T>();
   const Geom g = c->lev[l].g;
-  const int hg = half_grid(g);
+  const int hg = dgs_grid<T>(g);
+  const int pg = slab_blocks(g, g.sy / 2);  // one cell per thread (half_slot)
   for (int col = 1; col >= 0; --col)
-    launch(c, STOKES_KC_DGS_PR, l, [=] { k_dgs_pr<T, T><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
+    launch(c, STOKES_KC_DGS_PR, l, [=] {
+      if constexpr (sizeof(T) == 8)  // FP64: the one-cell kernel (its 56 operands in flight) is faster
+        k_dgs_pr<T, T><<<pg, BS, 0, c->ks>>>(g, x, b, col);
+      else
+        k_dgs_pr_v<T, T, V, 1><<<hg, BS, 0, c->ks>>>(g, x, b, col);
+    });
   for (int col = 1; col >= 0; --col)
-    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u<T, T><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
+    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
 }
 
 enum Interior { INT_SYMMETRIC, INT_REVERSE, INT_FORWARD };
@@ -441,7 +485,7 @@ void vcycle(stokes_ctx* c, int l, const T* b, T* x, bool zero_init = true) {
   launch(c, STOKES_KC_APPLY, l, [=] {
     k_apply<AP_RESID, T, T><<<slot_grid(g), BS, 0, c->ks>>>(g, x, b, r, g.gamma, nullptr);
   });
-  launch(c, STOKES_KC_RESTRICT, l, [=] { k_restrict<T><<<slot_grid(gc), BS, 0, c->ks>>>(g, gc, r, bc); });
+  launch(c, STOKES_KC_RESTRICT, l, [=] { k_restrict<T><<<restrict_grid(gc), BS, 0, c->ks>>>(g, gc, r, bc); });
   vcycle(c, l + 1, (const T*)bc, xc);
   for (int i = 1; i < c->prm.cycle; ++i) vcycle(c, l + 1, (const T*)bc, xc, false);
   launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_add<T><<<slot_grid(g), BS, 0, c->ks>>>(g, gc, xc, x); });
@@ -745,7 +789,7 @@ int stokes_restrict(stokes_ctx* c, const double* fine, double* coarse) {
   if (!c || !fine || !coarse || fine == coarse || c->L < 2) return STOKES_EINVAL;
   const Geom& g = c->lev[0].g;
   const Geom& gc = c->lev[1].g;
-  k_restrict<double><<<slot_grid(gc), BS, 0, c->stream>>>(g, gc, fine, coarse);
+  k_restrict<double><<<restrict_grid(gc), BS, 0, c->stream>>>(g, gc, fine, coarse);
   return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
 }
 

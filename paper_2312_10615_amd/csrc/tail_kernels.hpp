@@ -102,14 +102,11 @@ template <typename T>
 __device__ void tl_vanka_symmetric(const TailLev& L, T* x, const T* b, T* vd) {
   for (int pass = 0; pass < 16; ++pass) {
     const int k = pass < 8 ? pass : 15 - pass;
-    const int n8 = 8 * L.nv[k];
-    if (n8 == 0) continue;
-    // every thread runs every round (the eight lanes of a cell shuffle together)
-    for (int base = 0; base < n8; base += TAIL_BS)
-      vanka_delta_item<T, T>(L.g, x, b, L.vc[k], L.nv[k], (const T*)L.kinv, vd, base + (int)threadIdx.x);
+    const int n = L.nv[k];
+    if (n == 0) continue;
+    for (int c = threadIdx.x; c < n; c += TAIL_BS) vanka_delta_item<T, T>(L.g, x, b, L.vc[k], n, (const T*)L.kinv, vd, c);
     __syncthreads();
-    for (int base = 0; base < n8; base += TAIL_BS)
-      vanka_apply_item<T>(L.g, x, L.vc[k], L.nv[k], vd, base + (int)threadIdx.x);
+    for (int c = threadIdx.x; c < n; c += TAIL_BS) vanka_apply_item<T>(L.g, x, L.vc[k], n, vd, c);
     __syncthreads();
   }
 }

@@ -95,7 +95,7 @@ def test_red_black_field_index_is_a_bijection_split_by_colour(dims):
     sy = (nx + 2) | 1
     sz = (sy * (ny + 2)) | 1
     slots = sz * (nz + 2)
-    lay = types.SimpleNamespace(nx=nx, ny=ny, nz=nz, sy=sy, sz=sz, field=slots + (slots & 1))
+    lay = types.SimpleNamespace(nx=nx, ny=ny, nz=nz, sy=sy, sz=sz, field=(slots + 15) // 8 * 8)
     e = S.field_index(lay, "cpu")
     assert e.shape == (nz + 2, ny + 2, sy)
     flat = e.flatten()
