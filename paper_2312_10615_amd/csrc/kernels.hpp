@@ -599,6 +599,75 @@ __global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __r
   prolong_item<T>(f, c, e, x, I, J, K);
 }
 
+// The same update, one thread per coarse cell for its eight fine children
+// (padded fine I = 2Ic-1+di, and so on, di, dj, dk in {0, 1}).  The
+// children's interpolation stencils overlap: the 55 coarse values they use
+// are loaded once (about 200 loads for eight one-child threads).  Each
+// value is formed by the expression prolong_item uses, with the same
+// operands in the same order (the face_w / cell_w indices, fixed for each
+// child), so the result is the same bit for bit.  Every fine unknown lies in
+// a child of an interior coarse cell, and each child belongs to one thread.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_prolong_children(Geom f, Geom c, const T* __restrict__ e,
+                                                         T* __restrict__ x) {
+  int X, Jc, Kc;
+  if (!slab_item(c, c.nx, X, Jc, Kc)) return;
+  if (Jc < 1 || Jc > c.ny || Kc < 1 || Kc > c.nz) return;
+  const int Ic = X + 1;
+  const int Fc = c.field, Ff = f.field;
+  // u_x at coarse faces Ic..Ic+1, rows Jc-1..Jc+1, planes Kc-1..Kc+1 (and so on)
+  T U[2][3][3], Vy[3][2][3], W[3][3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int bj = 0; bj < 3; ++bj)
+#pragma unroll
+      for (int ck = 0; ck < 3; ++ck) {
+        if (a < 2) U[a][bj][ck] = e[c.at(c.idx(Ic + a, Jc - 1 + bj, Kc - 1 + ck))];
+        if (bj < 2) Vy[a][bj][ck] = e[Fc + c.at(c.idx(Ic - 1 + a, Jc + bj, Kc - 1 + ck))];
+        if (ck < 2) W[a][bj][ck] = e[2 * Fc + c.at(c.idx(Ic - 1 + a, Jc - 1 + bj, Kc + ck))];
+      }
+  const T pc = e[3 * Fc + c.at(c.idx(Ic, Jc, Kc))];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const int di = d & 1, dj = (d >> 1) & 1, dk = d >> 2;
+    const int I = 2 * Ic - 1 + di, J = 2 * Jc - 1 + dj, K = 2 * Kc - 1 + dk;
+    const int s = f.at(f.idx(I, J, K));
+    // face axis: weight 1 on the coarse face below an even fine face, 1/2 on
+    // both neighbours of an odd one; cell axes: 3/4 own coarse cell, 1/4 the
+    // one on the fine cell's side
+    const T w0 = di ? T(0.5) : T(1), w1 = di ? T(0.5) : T(0);
+    const int n1 = dj ? 2 : 0, m1 = dk ? 2 : 0, l1 = di ? 2 : 0;
+    if (f.ux_active(I, J, K)) {
+      const int a1 = di;
+      const T v = w0 * (T(0.75) * (T(0.75) * U[0][1][1] + T(0.25) * U[0][n1][1]) +
+                        T(0.25) * (T(0.75) * U[0][1][m1] + T(0.25) * U[0][n1][m1])) +
+                  w1 * (T(0.75) * (T(0.75) * U[a1][1][1] + T(0.25) * U[a1][n1][1]) +
+                        T(0.25) * (T(0.75) * U[a1][1][m1] + T(0.25) * U[a1][n1][m1]));
+      x[s] = x[s] + v;
+    }
+    if (f.uy_active(I, J, K)) {
+      const T v0 = dj ? T(0.5) : T(1), v1 = dj ? T(0.5) : T(0);
+      const int b1 = dj;
+      const T v = v0 * (T(0.75) * (T(0.75) * Vy[1][0][1] + T(0.25) * Vy[l1][0][1]) +
+                        T(0.25) * (T(0.75) * Vy[1][0][m1] + T(0.25) * Vy[l1][0][m1])) +
+                  v1 * (T(0.75) * (T(0.75) * Vy[1][b1][1] + T(0.25) * Vy[l1][b1][1]) +
+                        T(0.25) * (T(0.75) * Vy[1][b1][m1] + T(0.25) * Vy[l1][b1][m1]));
+      x[Ff + s] = x[Ff + s] + v;
+    }
+    if (f.uz_active(I, J, K)) {
+      const T z0 = dk ? T(0.5) : T(1), z1 = dk ? T(0.5) : T(0);
+      const int c1 = dk;
+      const T v = z0 * (T(0.75) * (T(0.75) * W[1][1][0] + T(0.25) * W[l1][1][0]) +
+                        T(0.25) * (T(0.75) * W[1][n1][0] + T(0.25) * W[l1][n1][0])) +
+                  z1 * (T(0.75) * (T(0.75) * W[1][1][c1] + T(0.25) * W[l1][1][c1]) +
+                        T(0.25) * (T(0.75) * W[1][n1][c1] + T(0.25) * W[l1][n1][c1]));
+      x[2 * Ff + s] = x[2 * Ff + s] + v;
+    }
+    if (f.p_active(I, J, K)) x[3 * Ff + s] = x[3 * Ff + s] + pc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Coarsest level: x = L~c^{-1} b with the dense inverse; one wave per row.
 // x must be zero beforehand (its ghost slots stay zero).

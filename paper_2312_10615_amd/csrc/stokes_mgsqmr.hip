@@ -16,7 +16,7 @@
 
 #include "../../include/stokes_mgsqmr.h"
 #include "host_tables.hpp"
-#include "dgs_vec.hpp"
+#include "packed_kernels.hpp"
 #include "kernels.hpp"
 #include "tail_kernels.hpp"
 
@@ -178,6 +178,7 @@ int grid_for(long slots) {
 
 int slot_grid(const Geom& g) { return slab_blocks(g, g.sy + 1); }  // split_slot: sy + 1 items per row
 int restrict_grid(const Geom& gc) { return slab_blocks(gc, gc.sy); }  // k_restrict: one item per coarse slot
+int prolong_grid(const Geom& gc) { return slab_blocks(gc, gc.nx); }  // k_prolong_children: one per coarse cell
 
 #define HIPCHK(call)                                  \
   do {                                                \
@@ -379,6 +380,11 @@ constexpr int dgs_pack() {
 }
 
 template <typename T>
+int apply_grid(const Geom& g) {
+  return slab_blocks(g, slot_packs_per_row<dgs_pack<T>()>(g));
+}
+
+template <typename T>
 int dgs_grid(const Geom& g) {
   return slab_blocks(g, pack_per_row<dgs_pack<T>()>(g));
 }
@@ -483,12 +489,12 @@ void vcycle(stokes_ctx* c, int l, const T* b, T* x, bool zero_init = true) {
   T* bc = (T*)c->lev[l + 1].b;
   T* xc = (T*)c->lev[l + 1].x;
   launch(c, STOKES_KC_APPLY, l, [=] {
-    k_apply<AP_RESID, T, T><<<slot_grid(g), BS, 0, c->ks>>>(g, x, b, r, g.gamma, nullptr);
+    k_apply_v<AP_RESID, T, T, dgs_pack<T>()><<<apply_grid<T>(g), BS, 0, c->ks>>>(g, x, b, r, g.gamma, nullptr);
   });
   launch(c, STOKES_KC_RESTRICT, l, [=] { k_restrict<T><<<restrict_grid(gc), BS, 0, c->ks>>>(g, gc, r, bc); });
   vcycle(c, l + 1, (const T*)bc, xc);
   for (int i = 1; i < c->prm.cycle; ++i) vcycle(c, l + 1, (const T*)bc, xc, false);
-  launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_add<T><<<slot_grid(g), BS, 0, c->ks>>>(g, gc, xc, x); });
+  launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_children<T><<<prolong_grid(gc), BS, 0, c->ks>>>(g, gc, xc, x); });
   postsmooth(c, l, x, b);
 }
 
@@ -798,7 +804,7 @@ int stokes_prolong(stokes_ctx* c, const double* coarse, double* fine) {
   const Geom& g = c->lev[0].g;
   const Geom& gc = c->lev[1].g;
   k_fill<double><<<RED_BLOCKS, BS, 0, c->stream>>>(fine, 4L * g.field, 0.0);
-  k_prolong_add<double><<<slot_grid(g), BS, 0, c->stream>>>(g, gc, coarse, fine);
+  k_prolong_children<double><<<prolong_grid(gc), BS, 0, c->stream>>>(g, gc, coarse, fine);
   return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
 }
 
@@ -806,7 +812,7 @@ int stokes_lift(stokes_ctx* c, const double* g, const double* b, double* out) {
   if (!c || !g || !b || !out || g == out || b == out) return STOKES_EINVAL;
   const Geom& ge = c->lev[0].g;
   // b - L g at the unknowns (g holds the boundary values outside them), 0 elsewhere
-  k_apply<AP_RESID, double, double><<<slot_grid(ge), BS, 0, c->stream>>>(ge, g, b, out, 0.0, nullptr);
+  k_apply_v<AP_RESID, double, double, 2><<<apply_grid<double>(ge), BS, 0, c->stream>>>(ge, g, b, out, 0.0, nullptr);
   return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
 }
 
@@ -815,7 +821,7 @@ int stokes_apply(stokes_ctx* c, const double* x, double* y, int32_t penalized) {
   const Geom& g = c->lev[0].g;
   {
     Prof pf(c, STOKES_KC_APPLY, 0);
-    k_apply<AP_APPLY, double, double><<<slot_grid(g), BS, 0, c->stream>>>(g, x, (const double*)nullptr, y,
+    k_apply_v<AP_APPLY, double, double, 2><<<apply_grid<double>(g), BS, 0, c->stream>>>(g, x, (const double*)nullptr, y,
                                                                                penalized ? g.gamma : 0.0, nullptr);
   }
   return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
@@ -831,7 +837,7 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
   const Geom& g = c->lev[0].g;
   const long n = c->total;
   const int gf = grid_for(g.field);  // flat kernels (ghost clearing, pressure mean)
-  const int ga = slot_grid(g);        // tiled operator kernels
+  const int ga = apply_grid<double>(g);  // packed operator kernels
   auto fill_info = [&](int iters, int status, double relres, double bn) {
     if (info) {
       info->iters = iters;
@@ -848,7 +854,7 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
   // ||b|| over the unknowns
   {
     Prof pf(c, STOKES_KC_APPLY, 0);
-    k_apply<AP_BNORM, double, double><<<ga, BS, 0, c->stream>>>(g, (const double*)nullptr, b, (double*)nullptr, 0.0,
+    k_apply_v<AP_BNORM, double, double, 2><<<ga, BS, 0, c->stream>>>(g, (const double*)nullptr, b, (double*)nullptr, 0.0,
                                                                 c->partial);
   }
   if (reduce_to_host(c, ga, 1) != STOKES_OK) return fill_info(0, STOKES_EDEVICE, NAN, NAN);
@@ -863,11 +869,11 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
   // s0 = b - L x0, with ||s0||^2
   {
     Prof pf(c, STOKES_KC_APPLY, 0);
-    k_apply<AP_RESID, double, double><<<ga, BS, 0, c->stream>>>(g, x, b, c->s, 0.0, nullptr);
+    k_apply_v<AP_RESID, double, double, 2><<<ga, BS, 0, c->stream>>>(g, x, b, c->s, 0.0, nullptr);
   }
   {
     Prof pf(c, STOKES_KC_APPLY, 0);
-    k_apply<AP_RESNORM, double, double><<<ga, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
+    k_apply_v<AP_RESNORM, double, double, 2><<<ga, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
   }
   if (reduce_to_host(c, ga, 1) != STOKES_OK) return fill_info(0, STOKES_EDEVICE, NAN, bnorm);
   double relres = std::sqrt(c->hscal[0]) / bnorm;
@@ -915,7 +921,7 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
     // t = L q, sigma = q . t
     {
       Prof pf(c, STOKES_KC_APPLY, 0);
-      k_apply<AP_APPLY_DOT, double, double><<<ga, BS, 0, c->stream>>>(g, c->q, (const double*)nullptr, c->t, 0.0,
+      k_apply_v<AP_APPLY_DOT, double, double, 2><<<ga, BS, 0, c->stream>>>(g, c->q, (const double*)nullptr, c->t, 0.0,
                                                                       c->partial);
     }
     if (reduce_to_host(c, ga, 1) != STOKES_OK) return finish(j - 1, STOKES_EDEVICE);
@@ -947,7 +953,7 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
     // true residual
     {
       Prof pf(c, STOKES_KC_APPLY, 0);
-      k_apply<AP_RESNORM, double, double><<<ga, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
+      k_apply_v<AP_RESNORM, double, double, 2><<<ga, BS, 0, c->stream>>>(g, x, b, (double*)nullptr, 0.0, c->partial);
     }
     if (reduce_to_host(c, ga, 1) != STOKES_OK) return finish(j, STOKES_EDEVICE);
     relres = std::sqrt(c->hscal[0]) / bnorm;

