@@ -16,7 +16,6 @@ current kernel source, else null.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -51,10 +50,8 @@ def algorithmic_bytes(kernel, n):
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("geom.hpp", "kernels.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2312_10615_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
+    from paper_2312_10615_amd.profiling import kernel_source_hash as h
+    return h()
 
 
 def counter_traffic(kernel, n):

@@ -121,7 +121,7 @@ struct stokes_batch {
   std::vector<BEnt> harena;
   BEnt* arena = nullptr;
   Tab tcls[NCLS][MAXL][NBX];
-  Tab tvec, tfield, tzero[MAXL], tcoarse[MAXL], tvanka[MAXL][8];
+  Tab tvec, tfield, tzero[MAXL], tcoarse[MAXL], tvanka[MAXL][8], tvapply[MAXL][8];
   int bx[NCLS][MAXL];
   int chunk_first = 10, chunk = 2;
   // graphs, keyed by (b, x)
@@ -302,8 +302,10 @@ void carve(stokes_batch* c, Carve& cv) {
       return (int)((4L * c->hlev[l][d].g.field + 4 * BS - 1) / (4 * BS));
     });
     c->tcoarse[l] = add_table(c, c->coarse[l], [&](int d) { return (c->hlev[l][d].nc + 3) / 4; });
-    for (int k = 0; k < 8; ++k)
-      c->tvanka[l][k] = add_table(c, c->smooth[l], [&](int d) { return (c->hlev[l][d].nv[k] + BS - 1) / BS; });
+    for (int k = 0; k < 8; ++k) {
+      c->tvanka[l][k] = add_table(c, c->smooth[l], [&](int d) { return (8 * c->hlev[l][d].nv[k] + BS - 1) / BS; });
+      c->tvapply[l][k] = add_table(c, c->smooth[l], [&](int d) { return (c->hlev[l][d].nv[k] + BS - 1) / BS; });
+    }
   }
   c->partial = cv.take<double>(2 * maxblk);
   c->arena = cv.take<BEnt>(c->harena.size());
@@ -358,9 +360,10 @@ void b_vanka_symmetric(stokes_batch* c, int l) {
   for (int pass = 0; pass < 16; ++pass) {
     const int k = pass < 8 ? pass : 15 - pass;
     const Tab& t = c->tvanka[l][k];
+    const Tab& ta = c->tvapply[l][k];
     if (!t.n) continue;
     kb_vanka_delta<T><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done, k, (T*)c->vdelta);
-    kb_vanka_apply<T><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done, k, (const T*)c->vdelta);
+    kb_vanka_apply<T><<<ta.blocks, BS, 0, c->ks>>>(c->tab(ta), ta.n, c->dlev[l], c->done, k, (const T*)c->vdelta);
   }
 }
 

@@ -156,14 +156,15 @@ __global__ __launch_bounds__(BS) void kb_prolong(const BEnt* __restrict__ tab, i
   prolong_item<T>(g, lev[d].gc, (const T*)lev[d].xc, (T*)lev[d].x, I, J, K);
 }
 
-// Vanka, one colour class: one thread per V1 cell of each domain
+// Vanka, one colour class of each domain: eight lanes per V1 cell for the
+// residuals, one thread per cell for the corrections
 template <typename T>
 __global__ __launch_bounds__(BS) void kb_vanka_delta(const BEnt* __restrict__ tab, int nent,
                                                      const BLev* __restrict__ lev, const int* __restrict__ done,
                                                      int colour, T* __restrict__ delta) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
-  vanka_delta_item<T, T>(g, (const T*)lev[d].x, (const T*)lev[d].b, lev[d].vc[colour], lev[d].nv[colour],
+  vanka_delta8_item<T, T>(g, (const T*)lev[d].x, (const T*)lev[d].b, lev[d].vc[colour], lev[d].nv[colour],
                          (const T*)lev[d].kinv, delta + lev[d].voff[colour], lb * BS + (int)threadIdx.x);
 }
 

@@ -390,10 +390,71 @@ __device__ __forceinline__ void vanka_apply_item(const Geom& g, T* __restrict__ 
   if (c < ncells) vanka_apply_at<T>(g, x, cells[c], delta, c, ncells);
 }
 
+// The same residuals and products with eight lanes per subdomain: lane r < 7
+// evaluates local residual row r and forms delta_r from the group's
+// residuals, gathered by shuffles.  Each lane makes about 9 loads where the
+// one-thread form makes about 60 in a row, so on levels where a pass is a
+// latency chain this form finishes sooner.  Output as above.  Lane t of the
+// class (t & 7 must equal threadIdx.x & 7, and the eight lanes of a subdomain
+// share a wave); every lane of the wave must call it (shuffles).
+template <typename T, typename TB>
+__device__ __forceinline__ void vanka_delta8_item(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                                  const int* __restrict__ cells, int ncells, const T* __restrict__ kinv,
+                                                  T* __restrict__ delta, int t) {
+  const int c = t >> 3;
+  const int r = t & 7;
+  const bool valid = c < ncells;
+  const int s = valid ? cells[c] : 0;
+  int I = 1, J = 1, K = 1;
+  if (valid) slot_ijk(g, s, I, J, K);
+  const int F = g.field;
+  const T* ux = x;
+  const T* uy = x + F;
+  const T* uz = x + 2 * F;
+  const T* p = x + 3 * F;
+  const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
+  T res = T(0);
+  if (valid) {
+    switch (r) {
+      case 0: if (a0) res = (T)b[g.at(s)] - row_u(g, ux, p, s, 1); break;
+      case 1: if (a1) res = (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1); break;
+      case 2: if (a2) res = (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy); break;
+      case 3: if (a3) res = (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy); break;
+      case 4: if (a4) res = (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz); break;
+      case 5: if (a5) res = (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz); break;
+      case 6: res = (T)b[3 * F + g.at(s)] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
+      default: break;
+    }
+  }
+  const int type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
+  const T* km = kinv + type * 64 + r * 8;
+  const int base = (int)(threadIdx.x & 63) & ~7;
+  T acc = T(0);
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    const T rj = __shfl(res, base + j, 64);
+    acc += km[j] * rj;
+  }
+  if (valid && r < 7) delta[(long)r * ncells + c] = acc;
+}
+
+// Residual pass of one class: eight lanes per subdomain, or one thread per
+// subdomain for classes of more than VANKA_LANES_MAX cells (there the pass is
+// bound by bandwidth, not by its latency chain, and one thread per cell
+// issues fewer instructions).
+constexpr int VANKA_LANES_MAX = 16384;
+
 template <typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_vanka_delta(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
                                                     const int* __restrict__ cells, int ncells,
                                                     const T* __restrict__ kinv, T* __restrict__ delta) {
+  vanka_delta8_item<T, TB>(g, x, b, cells, ncells, kinv, delta, blockIdx.x * BS + threadIdx.x);
+}
+
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_vanka_delta1(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
+                                                     const int* __restrict__ cells, int ncells,
+                                                     const T* __restrict__ kinv, T* __restrict__ delta) {
   vanka_delta_item<T, TB>(g, x, b, cells, ncells, kinv, delta, blockIdx.x * BS + threadIdx.x);
 }
 

@@ -315,13 +315,19 @@ void vanka_delta(stokes_ctx* c, int l, const T* x, const T* b, int k) {
   const Level& lv = c->lev[l];
   const int n = lv.nv[k];
   if (n == 0) return;
-  const int nb = (n + BS - 1) / BS;  // one thread per subdomain
   const Geom g = lv.g;
   const int* cells = lv.vcells[k];
   const T* kinv = (const T*)lv.kinv;
   T* vd = (T*)c->vdelta + lv.doff[k];
-  launch(c, STOKES_KC_VANKA_DELTA, l,
-         [=] { k_vanka_delta<T, T><<<nb, BS, 0, c->ks>>>(g, x, b, cells, n, kinv, vd); });
+  if (n > VANKA_LANES_MAX) {  // one thread per subdomain
+    const int nb = (n + BS - 1) / BS;
+    launch(c, STOKES_KC_VANKA_DELTA, l,
+           [=] { k_vanka_delta1<T, T><<<nb, BS, 0, c->ks>>>(g, x, b, cells, n, kinv, vd); });
+  } else {  // eight lanes per subdomain
+    const int nb = (8 * n + BS - 1) / BS;
+    launch(c, STOKES_KC_VANKA_DELTA, l,
+           [=] { k_vanka_delta<T, T><<<nb, BS, 0, c->ks>>>(g, x, b, cells, n, kinv, vd); });
+  }
 }
 
 template <typename T>

@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("geom.hpp", "kernels.hpp"):
+    for f in ("geom.hpp", "kernels.hpp", "packed_kernels.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2312_10615_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -44,8 +44,8 @@ def _largest_dispatches(path, counter):
     return best
 
 
-SHORT = {"k_dgs_u<": "dgs_u", "k_dgs_pr<": "dgs_pr", "k_dgs_pf_own<": "dgs_pf_own", "k_dgs_pf_nbr<": "dgs_pf_nbr",
-         "k_apply<1,": "apply", "k_restrict<": "restrict", "k_prolong_add<": "prolong"}
+SHORT = {"k_dgs_u_v<": "dgs_u", "k_dgs_pr<": "dgs_pr", "k_dgs_pf_own_v<": "dgs_pf_own", "k_dgs_pf_nbr_v<": "dgs_pf_nbr",
+         "k_apply_v<1,": "apply", "k_restrict<": "restrict", "k_prolong_children<": "prolong"}
 
 
 def summarize_counters(fetch_csv, write_csv, n, copy_bytes=1 << 30):
