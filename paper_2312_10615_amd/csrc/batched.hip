@@ -277,6 +277,18 @@ void carve(stokes_batch* c, Carve& cv) {
         default: return tile_blocks<256>(g, g.sy / per_row_div);
       }
     };
+    auto dslot = [&](int l, int d, int k) -> int {
+      const Geom& g = c->hlev[l][d].g;
+      const int V = c->prec == 32 ? 4 : 2;
+      if (!(k == CL_PR && c->prec != 32)) return flat_blocks(g, (((g.sy + 1) >> 1) + V - 1) / V);  // packed: flat
+      const int per_row = g.sy / 2;
+      switch (v) {
+        case 0: return tile_blocks<32>(g, per_row);
+        case 1: return tile_blocks<64>(g, per_row);
+        case 2: return tile_blocks<128>(g, per_row);
+        default: return tile_blocks<256>(g, per_row);
+      }
+    };
     auto cslot = [&](int l, int d) -> int {
       const Geom& g = c->hlev[l][d].gc;
       switch (v) {
@@ -293,8 +305,9 @@ void carve(stokes_batch* c, Carve& cv) {
       c->tcls[CL_RESID][l][v] = add_table(c, S, [&](int d) { return slot(l, d, 1); });
       c->tcls[CL_PROLONG][l][v] = add_table(c, S, [&](int d) { return slot(l, d, 1); });
       c->tcls[CL_RESTRICT][l][v] = add_table(c, S, [&](int d) { return cslot(l, d); });
+      // DGS classes: row packs of 16 bytes (V cells), one cell per thread for the FP64 reverse pressure step
       for (int k : {CL_DGSU, CL_PFOWN, CL_PFNBR, CL_PR})
-        c->tcls[k][l][v] = add_table(c, S, [&](int d) { return slot(l, d, 2); });
+        c->tcls[k][l][v] = add_table(c, S, [&](int d) { return dslot(l, d, k); });
     }
   }
   for (int l = 0; l < c->Lmax; ++l) {

@@ -7,6 +7,7 @@
 #pragma once
 
 #include "kernels.hpp"
+#include "packed_kernels.hpp"
 
 namespace sg {
 
@@ -89,15 +90,45 @@ __global__ __launch_bounds__(BS) void kb_resid(const BEnt* __restrict__ tab, int
   apply_item<AP_RESID, T, T>(g, (const T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].r, g.gamma, I, J, K);
 }
 
+// DGS passes: packs of V cells of one colour in a row (the single-box packed
+// items; V = 16 bytes / element size).  A row holds few packs (5 to 33 on
+// the batch's boxes), so the packs of consecutive rows are laid out flat
+// rather than in BX-wide tiles (which would leave most lanes idle); the
+// tile width does not matter for these classes.  The FP64 reverse pressure
+// step keeps one cell per thread in tiles, as on a single box.
+__host__ __device__ inline int flat_blocks(const Geom& g, int per_row) {
+  return (int)(((long)per_row * (g.ny + 2) * (g.nz + 2) + BS - 1) / BS);
+}
+
+__device__ __forceinline__ bool flat_item(const Geom& g, int per_row, int lb, int& X, int& J, int& K) {
+  const long l = (long)lb * BS + threadIdx.x;
+  X = (int)(l % per_row);
+  const long r = l / per_row;
+  J = (int)(r % (g.ny + 2));
+  K = (int)(r / (g.ny + 2));
+  return K < g.nz + 2;
+}
+
+template <typename T>
+__host__ __device__ constexpr int bpack() {
+  return 16 / (int)sizeof(T);
+}
+
+template <typename T>
+__host__ __device__ constexpr bool bpack_pr() {
+  return sizeof(T) == 4;
+}
+
 template <typename T, int BX>
 __global__ __launch_bounds__(BS) void kb_dgs_u(const BEnt* __restrict__ tab, int nent, const BLev* __restrict__ lev,
                                                const int* __restrict__ done, int colour) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
+  constexpr int V = bpack<T>();
   int m, J, K;
-  if (!tile_item<BX>(g, g.sy >> 1, lb, m, J, K)) return;
-  const int I = 2 * m + ((colour + 1 + J + K) & 1);
-  dgs_u_item<T, T>(g, (T*)lev[d].x, (const T*)lev[d].b, I, J, K);
+  if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
+  RowPack<V> rp;
+  if (row_pack_at<V>(g, colour ^ 1, m, J, K, rp)) dgs_u_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, rp);
 }
 
 template <typename T, int BX>
@@ -106,10 +137,12 @@ __global__ __launch_bounds__(BS) void kb_dgs_pf_own(const BEnt* __restrict__ tab
                                                     int colour) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
+  constexpr int V = bpack<T>();
   int m, J, K;
-  if (!tile_item<BX>(g, g.sy >> 1, lb, m, J, K)) return;
-  const int I = 2 * m + ((colour + 1 + J + K) & 1);
-  dgs_pf_own_item<T, T>(g, (T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].dscr, I, J, K);
+  if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
+  RowPack<V> rp;
+  if (row_pack_at<V>(g, colour ^ 1, m, J, K, rp))
+    dgs_pf_own_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].dscr, rp);
 }
 
 template <typename T, int BX>
@@ -118,10 +151,11 @@ __global__ __launch_bounds__(BS) void kb_dgs_pf_nbr(const BEnt* __restrict__ tab
                                                     int colour) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
+  constexpr int V = bpack<T>();
   int m, J, K;
-  if (!tile_item<BX>(g, g.sy >> 1, lb, m, J, K)) return;
-  const int I = 2 * m + (((colour ^ 1) + 1 + J + K) & 1);
-  dgs_pf_nbr_item<T>(g, (T*)lev[d].x, (const T*)lev[d].dscr, I, J, K);
+  if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
+  RowPack<V> rp;
+  if (row_pack_at<V>(g, colour, m, J, K, rp)) dgs_pf_nbr_pack<T, V>(g, (T*)lev[d].x, (const T*)lev[d].dscr, rp);
 }
 
 template <typename T, int BX>
@@ -129,10 +163,18 @@ __global__ __launch_bounds__(BS) void kb_dgs_pr(const BEnt* __restrict__ tab, in
                                                 const int* __restrict__ done, int colour) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
-  int m, J, K;
-  if (!tile_item<BX>(g, g.sy >> 1, lb, m, J, K)) return;
-  const int I = 2 * m + ((colour + 1 + J + K) & 1);
-  dgs_pr_item<T, T>(g, (T*)lev[d].x, (const T*)lev[d].b, I, J, K);
+  if constexpr (bpack_pr<T>()) {
+    constexpr int V = bpack<T>();
+    int m, J, K;
+    if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
+    RowPack<V> rp;
+    if (row_pack_at<V>(g, colour ^ 1, m, J, K, rp)) dgs_pr_pack<T, T, V, 1>(g, (T*)lev[d].x, (const T*)lev[d].b, rp);
+  } else {
+    int m, J, K;
+    if (!tile_item<BX>(g, g.sy >> 1, lb, m, J, K)) return;
+    const int I = 2 * m + ((colour + 1 + J + K) & 1);
+    dgs_pr_item<T, T>(g, (T*)lev[d].x, (const T*)lev[d].b, I, J, K);
+  }
 }
 
 // restriction into the next level: one item per coarse slot

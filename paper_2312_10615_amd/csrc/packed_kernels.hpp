@@ -117,11 +117,12 @@ __host__ __device__ inline int pack_per_row(const Geom& g) {
   return (((g.sy + 1) >> 1) + V - 1) / V;
 }
 
+// Pack m of row (J, K); false when the row or the pack holds no cell.
 template <int V>
-__device__ __forceinline__ bool row_pack(const Geom& g, int par, RowPack<V>& rp) {
-  int m;
-  if (!slab_item(g, pack_per_row<V>(g), m, rp.J, rp.K)) return false;
-  if (rp.J < 1 || rp.J > g.ny || rp.K < 1 || rp.K > g.nz) return false;
+__device__ __forceinline__ bool row_pack_at(const Geom& g, int par, int m, int J, int K, RowPack<V>& rp) {
+  rp.J = J;
+  rp.K = K;
+  if (J < 1 || J > g.ny || K < 1 || K > g.nz) return false;
   const int q = (par + rp.J + rp.K) & 1;  // I parity of the row's slots of parity par
   const int nrow = (g.sy - q + 1) >> 1;
   const int first = m * V;
@@ -134,11 +135,17 @@ __device__ __forceinline__ bool row_pack(const Geom& g, int par, RowPack<V>& rp)
   return true;
 }
 
+// The pack of this thread in the slab mapping of the single-box kernels.
+template <int V>
+__device__ __forceinline__ bool row_pack(const Geom& g, int par, RowPack<V>& rp) {
+  int m, J, K;
+  if (!slab_item(g, pack_per_row<V>(g), m, J, K)) return false;
+  return row_pack_at<V>(g, par, m, J, K, rp);
+}
+
 // Velocity step on the V2 faces of one colour (dgs_u_item, V cells).
 template <typename T, typename TB, int V>
-__global__ __launch_bounds__(BS) void k_dgs_u_v(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
-  RowPack<V> rp;
-  if (!row_pack<V>(g, colour ^ 1, rp)) return;
+__device__ __forceinline__ void dgs_u_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, const RowPack<V>& rp) {
   const int F = g.field;
   const T* p = x + 3 * F;
   const T dinv = (T)(1.0 / (6.0 * g.c));
@@ -174,12 +181,15 @@ __global__ __launch_bounds__(BS) void k_dgs_u_v(Geom g, T* __restrict__ x, const
   }
 }
 
+template <typename T, typename TB, int V>
+__global__ __launch_bounds__(BS) void k_dgs_u_v(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
+  RowPack<V> rp;
+  if (row_pack<V>(g, colour ^ 1, rp)) dgs_u_pack<T, TB, V>(g, x, b, rp);
+}
+
 // Forward-sweep pressure step, part 1 (dgs_pf_own_item, V cells).
 template <typename T, typename TB, int V>
-__global__ __launch_bounds__(BS) void k_dgs_pf_own_v(Geom g, T* __restrict__ x, const TB* __restrict__ b,
-                                                     T* __restrict__ dscr, int colour) {
-  RowPack<V> rp;
-  if (!row_pack<V>(g, colour ^ 1, rp)) return;
+__device__ __forceinline__ void dgs_pf_own_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, T* __restrict__ dscr, const RowPack<V>& rp) {
   bool act[V];
   bool any = false;
 #pragma unroll
@@ -228,12 +238,16 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_own_v(Geom g, T* __restrict__ x, 
   stp_cells<T, V>(p + eo, P0, rp.n, act);
 }
 
+template <typename T, typename TB, int V>
+__global__ __launch_bounds__(BS) void k_dgs_pf_own_v(Geom g, T* __restrict__ x, const TB* __restrict__ b,
+                                                     T* __restrict__ dscr, int colour) {
+  RowPack<V> rp;
+  if (row_pack<V>(g, colour ^ 1, rp)) dgs_pf_own_pack<T, TB, V>(g, x, b, dscr, rp);
+}
+
 // Forward-sweep pressure step, part 2 (dgs_pf_nbr_item, V cells of the other colour).
 template <typename T, int V>
-__global__ __launch_bounds__(BS) void k_dgs_pf_nbr_v(Geom g, T* __restrict__ x, const T* __restrict__ dscr,
-                                                     int colour) {
-  RowPack<V> rp;
-  if (!row_pack<V>(g, colour, rp)) return;
+__device__ __forceinline__ void dgs_pf_nbr_pack(const Geom& g, T* __restrict__ x, const T* __restrict__ dscr, const RowPack<V>& rp) {
   bool act[V];
   bool any = false;
 #pragma unroll
@@ -265,6 +279,13 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_nbr_v(Geom g, T* __restrict__ x, 
   stp_cells<T, V>(p + eo, P, rp.n, act);
 }
 
+template <typename T, int V>
+__global__ __launch_bounds__(BS) void k_dgs_pf_nbr_v(Geom g, T* __restrict__ x, const T* __restrict__ dscr,
+                                                     int colour) {
+  RowPack<V> rp;
+  if (row_pack<V>(g, colour, rp)) dgs_pf_nbr_pack<T, V>(g, x, dscr, rp);
+}
+
 // Reverse-sweep pressure step (dgs_pr_item, V cells).  Its thirteen local
 // residuals read about 56 distinct operands per cell; held all at once, the
 // packs of V cells would not fit the register file.  So the residuals are
@@ -275,9 +296,7 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_nbr_v(Geom g, T* __restrict__ x, 
 // each stage holds only its own operands in registers.  Operands shared by
 // residuals of different stages are loaded again (from the cache).
 template <typename T, typename TB, int V, int G>
-__global__ __launch_bounds__(BS) void k_dgs_pr_v(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
-  RowPack<V> rp;
-  if (!row_pack<V>(g, colour ^ 1, rp)) return;
+__device__ __forceinline__ void dgs_pr_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, const RowPack<V>& rp) {
   bool act[V];
   bool any = false;
 #pragma unroll
@@ -363,6 +382,12 @@ __global__ __launch_bounds__(BS) void k_dgs_pr_v(Geom g, T* __restrict__ x, cons
     P.v[i] = P.v[i] + rt / (T)(-6.0 * (1.0 + gam * g.eta) * ih2);
   }
   stp_cells<T, V>(p + eo, P, rp.n, act);
+}
+
+template <typename T, typename TB, int V, int G>
+__global__ __launch_bounds__(BS) void k_dgs_pr_v(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
+  RowPack<V> rp;
+  if (row_pack<V>(g, colour ^ 1, rp)) dgs_pr_pack<T, TB, V, G>(g, x, b, rp);
 }
 
 // ---------------------------------------------------------------------------
