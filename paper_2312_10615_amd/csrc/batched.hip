@@ -268,15 +268,6 @@ void carve(stokes_batch* c, Carve& cv) {
   c->tfield = add_table(c, doms, [&](int d) { return (c->hlev[0][d].g.field + BS - 1) / BS; });
   note(c->tfield);
   for (int v = 0; v < NBX; ++v) {
-    auto slot = [&](int l, int d, int per_row_div) -> int {
-      const Geom& g = c->hlev[l][d].g;
-      switch (v) {
-        case 0: return tile_blocks<32>(g, g.sy / per_row_div);
-        case 1: return tile_blocks<64>(g, g.sy / per_row_div);
-        case 2: return tile_blocks<128>(g, g.sy / per_row_div);
-        default: return tile_blocks<256>(g, g.sy / per_row_div);
-      }
-    };
     auto dslot = [&](int l, int d, int k) -> int {
       const Geom& g = c->hlev[l][d].g;
       const int V = c->prec == 32 ? 4 : 2;
@@ -298,12 +289,21 @@ void carve(stokes_batch* c, Carve& cv) {
         default: return tile_blocks<256>(g, g.sy);
       }
     };
-    c->tcls[CL_APPLY0][0][v] = add_table(c, doms, [&](int d) { return slot(0, d, 1); });
+    // operator passes: slot packs laid out flat (FP64 packs of 2 at level 0; V-cycle precision below)
+    auto apack = [&](int l, int d, int V) -> int {
+      const Geom& g = c->hlev[l][d].g;
+      return flat_blocks(g, 2 * ((((g.sy + 1) >> 1) + V - 1) / V));
+    };
+    c->tcls[CL_APPLY0][0][v] = add_table(c, doms, [&](int d) { return apack(0, d, 2); });
     note(c->tcls[CL_APPLY0][0][v]);
     for (int l = 0; l < c->Lmax; ++l) {
       const std::vector<int>& S = c->smooth[l];
-      c->tcls[CL_RESID][l][v] = add_table(c, S, [&](int d) { return slot(l, d, 1); });
-      c->tcls[CL_PROLONG][l][v] = add_table(c, S, [&](int d) { return slot(l, d, 1); });
+      c->tcls[CL_RESID][l][v] = add_table(c, S, [&](int d) { return apack(l, d, c->prec == 32 ? 4 : 2); });
+      // prolongation: one thread per coarse cell, flat
+      c->tcls[CL_PROLONG][l][v] = add_table(c, S, [&](int d) {
+        const Geom& gc = c->hlev[l][d].gc;
+        return flat_blocks(gc, gc.nx);
+      });
       c->tcls[CL_RESTRICT][l][v] = add_table(c, S, [&](int d) { return cslot(l, d); });
       // DGS classes: row packs of 16 bytes (V cells), one cell per thread for the FP64 reverse pressure step
       for (int k : {CL_DGSU, CL_PFOWN, CL_PFNBR, CL_PR})

@@ -72,6 +72,20 @@ __device__ __forceinline__ bool tile_item(const Geom& g, int per_row, int lb, in
   return X < per_row && J < g.ny + 2 && K < g.nz + 2;
 }
 
+// Items laid out flat: item l = (row-major row, x) with per_row items a row.
+__host__ __device__ inline int flat_blocks(const Geom& g, int per_row) {
+  return (int)(((long)per_row * (g.ny + 2) * (g.nz + 2) + BS - 1) / BS);
+}
+
+__device__ __forceinline__ bool flat_item(const Geom& g, int per_row, int lb, int& X, int& J, int& K) {
+  const long l = (long)lb * BS + threadIdx.x;
+  X = (int)(l % per_row);
+  const long r = l / per_row;
+  J = (int)(r % (g.ny + 2));
+  K = (int)(r / (g.ny + 2));
+  return K < g.nz + 2;
+}
+
 #define SG_BATCH_ENTRY()                   \
   const int e_ = bent_find(tab, nent);     \
   const int d = tab[e_].dom;               \
@@ -85,9 +99,12 @@ __global__ __launch_bounds__(BS) void kb_resid(const BEnt* __restrict__ tab, int
                                                const int* __restrict__ done) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
-  int I, J, K;
-  if (!tile_item<BX>(g, g.sy, lb, I, J, K)) return;
-  apply_item<AP_RESID, T, T>(g, (const T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].r, g.gamma, I, J, K);
+  constexpr int V = 16 / (int)sizeof(T);
+  int X, J, K;
+  if (!flat_item(g, slot_packs_per_row<V>(g), lb, X, J, K)) return;
+  RowPack<V> rp;
+  if (slot_pack_at<V>(g, X, J, K, rp))
+    apply_pack<AP_RESID, T, T, V>(g, (const T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].r, g.gamma, rp);
 }
 
 // DGS passes: packs of V cells of one colour in a row (the single-box packed
@@ -96,18 +113,6 @@ __global__ __launch_bounds__(BS) void kb_resid(const BEnt* __restrict__ tab, int
 // rather than in BX-wide tiles (which would leave most lanes idle); the
 // tile width does not matter for these classes.  The FP64 reverse pressure
 // step keeps one cell per thread in tiles, as on a single box.
-__host__ __device__ inline int flat_blocks(const Geom& g, int per_row) {
-  return (int)(((long)per_row * (g.ny + 2) * (g.nz + 2) + BS - 1) / BS);
-}
-
-__device__ __forceinline__ bool flat_item(const Geom& g, int per_row, int lb, int& X, int& J, int& K) {
-  const long l = (long)lb * BS + threadIdx.x;
-  X = (int)(l % per_row);
-  const long r = l / per_row;
-  J = (int)(r % (g.ny + 2));
-  K = (int)(r / (g.ny + 2));
-  return K < g.nz + 2;
-}
 
 template <typename T>
 __host__ __device__ constexpr int bpack() {
@@ -192,10 +197,11 @@ template <typename T, int BX>
 __global__ __launch_bounds__(BS) void kb_prolong(const BEnt* __restrict__ tab, int nent, const BLev* __restrict__ lev,
                                                  const int* __restrict__ done) {
   SG_BATCH_ENTRY();
-  const Geom g = lev[d].g;
-  int I, J, K;
-  if (!tile_item<BX>(g, g.sy, lb, I, J, K)) return;
-  prolong_item<T>(g, lev[d].gc, (const T*)lev[d].xc, (T*)lev[d].x, I, J, K);
+  const Geom gc = lev[d].gc;
+  int X, Jc, Kc;  // one thread per coarse cell for its eight fine children, laid out flat
+  if (!flat_item(gc, gc.nx, lb, X, Jc, Kc)) return;
+  if (Jc < 1 || Jc > gc.ny || Kc < 1 || Kc > gc.nz) return;
+  prolong_children_item<T>(lev[d].g, gc, (const T*)lev[d].xc, (T*)lev[d].x, X + 1, Jc, Kc);
 }
 
 // Vanka, one colour class of each domain: eight lanes per V1 cell for the
@@ -259,9 +265,10 @@ __global__ __launch_bounds__(BS) void kb_apply_vec(const BEnt* __restrict__ tab,
   const Geom g = lev[d].g;
   const long o = voff[d];
   double acc = 0.0;
-  int I, J, K;
-  if (tile_item<BX>(g, g.sy, lb, I, J, K))
-    acc = apply_item<MODE, double, double>(g, x + o, b ? b + o : nullptr, y ? y + o : nullptr, 0.0, I, J, K);
+  int X, J, K;
+  RowPack<2> rp;
+  if (flat_item(g, slot_packs_per_row<2>(g), lb, X, J, K) && slot_pack_at<2>(g, X, J, K, rp))
+    acc = apply_pack<MODE, double, double, 2>(g, x + o, b ? b + o : nullptr, y ? y + o : nullptr, 0.0, rp);
   if (MODE == AP_APPLY_DOT || MODE == AP_RESNORM || MODE == AP_BNORM) {
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;

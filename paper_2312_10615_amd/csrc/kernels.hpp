@@ -669,12 +669,8 @@ __global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __r
 // child), so the result is the same bit for bit.  Every fine unknown lies in
 // a child of an interior coarse cell, and each child belongs to one thread.
 template <typename T>
-__global__ __launch_bounds__(BS) void k_prolong_children(Geom f, Geom c, const T* __restrict__ e,
-                                                         T* __restrict__ x) {
-  int X, Jc, Kc;
-  if (!slab_item(c, c.nx, X, Jc, Kc)) return;
-  if (Jc < 1 || Jc > c.ny || Kc < 1 || Kc > c.nz) return;
-  const int Ic = X + 1;
+__device__ __forceinline__ void prolong_children_item(const Geom& f, const Geom& c, const T* __restrict__ e,
+                                                      T* __restrict__ x, int Ic, int Jc, int Kc) {
   const int Fc = c.field, Ff = f.field;
   // u_x at coarse faces Ic..Ic+1, rows Jc-1..Jc+1, planes Kc-1..Kc+1 (and so on)
   T U[2][3][3], Vy[3][2][3], W[3][3][2];
@@ -727,6 +723,15 @@ __global__ __launch_bounds__(BS) void k_prolong_children(Geom f, Geom c, const T
     }
     if (f.p_active(I, J, K)) x[3 * Ff + s] = x[3 * Ff + s] + pc;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_prolong_children(Geom f, Geom c, const T* __restrict__ e,
+                                                         T* __restrict__ x) {
+  int X, Jc, Kc;
+  if (!slab_item(c, c.nx, X, Jc, Kc)) return;
+  if (Jc < 1 || Jc > c.ny || Kc < 1 || Kc > c.nz) return;
+  prolong_children_item<T>(f, c, e, x, X + 1, Jc, Kc);
 }
 
 // ---------------------------------------------------------------------------

@@ -401,11 +401,12 @@ __host__ __device__ inline int slot_packs_per_row(const Geom& g) {
   return 2 * ((((g.sy + 1) >> 1) + V - 1) / V);
 }
 
+// Pack X (0 <= X < slot_packs_per_row) of row (J, K).
 template <int V>
-__device__ __forceinline__ bool slot_pack(const Geom& g, RowPack<V>& rp) {
+__device__ __forceinline__ bool slot_pack_at(const Geom& g, int X, int J, int K, RowPack<V>& rp) {
   const int ppr = slot_packs_per_row<V>(g) >> 1;
-  int X;
-  if (!slab_item(g, 2 * ppr, X, rp.J, rp.K)) return false;
+  rp.J = J;
+  rp.K = K;
   const int q = X >= ppr;  // I parity of the pack's slots
   const int m = X - q * ppr;
   const int nrow = (g.sy - q + 1) >> 1;
@@ -419,98 +420,112 @@ __device__ __forceinline__ bool slot_pack(const Geom& g, RowPack<V>& rp) {
   return true;
 }
 
+template <int V>
+__device__ __forceinline__ bool slot_pack(const Geom& g, RowPack<V>& rp) {
+  int X, J, K;
+  if (!slab_item(g, slot_packs_per_row<V>(g), X, J, K)) return false;
+  return slot_pack_at<V>(g, X, J, K, rp);
+}
+
+// One pack of an operator pass; returns the pack's share of the reduction.
+template <int MODE, typename T, typename TB, int V>
+__device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                             T* __restrict__ y, double gamma, const RowPack<V>& rp) {
+  double acc = 0.0;
+  int F = g.field;
+  int sy = g.sy, sz = g.sz, hf = g.half;
+  int eb = rp.e0;
+  auto stage = [&](const T* dep) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) asm volatile("" : "+v"(eb) : "v"(dep[i]));
+    asm volatile("" : "+v"(eb), "+s"(F), "+s"(sy), "+s"(sz), "+s"(hf));
+  };
+  auto L = [&](int f, int o) {
+    const int q = rp.par + o;
+    return ldp<T, V>(x + (f * F + (q & 1) * hf + eb + (q >> 1)));
+  };
+  const int J = rp.J, K = rp.K;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    bool act[V];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int I = rp.I0 + 2 * i;
+      act[i] = i < rp.n && (f == 0   ? g.ux_active(I, J, K)
+                            : f == 1 ? g.uy_active(I, J, K)
+                            : f == 2 ? g.uz_active(I, J, K)
+                                     : g.p_active(I, J, K));
+      any = any || act[i];
+    }
+    T o[V];
+    T own[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) o[i] = own[i] = T(0);
+    if (MODE != AP_BNORM && any) {
+      if (f < 3) {
+        const int ps = f == 0 ? 1 : f == 1 ? sy : sz;
+        const Pack<T, V> c0 = L(f, 0), xm = L(f, -1), xp = L(f, 1), ym = L(f, -sy), yp = L(f, sy), zm = L(f, -sz),
+                         zp = L(f, sz), pc = L(3, 0), pm = L(3, -ps);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const T lap = T(6) * c0.v[i] - xm.v[i] - xp.v[i] - ym.v[i] - yp.v[i] - zm.v[i] - zp.v[i];
+          o[i] = (T)g.c * lap + (pc.v[i] - pm.v[i]) * (T)g.inv_h;
+          own[i] = c0.v[i];
+        }
+      } else {
+        const Pack<T, V> x0 = L(0, 0), x1 = L(0, 1), y0 = L(1, 0), y1 = L(1, sy), z0 = L(2, 0), z1 = L(2, sz),
+                         pc = L(3, 0);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const T div = (x1.v[i] - x0.v[i]) + (y1.v[i] - y0.v[i]) + (z1.v[i] - z0.v[i]);
+          o[i] = -div * (T)g.inv_h - (T)gamma * pc.v[i];
+          own[i] = pc.v[i];
+        }
+      }
+    }
+    T v[V];
+    if (MODE == AP_RESID || MODE == AP_RESNORM || MODE == AP_BNORM) {
+      Pack<TB, V> bb;
+#pragma unroll
+      for (int i = 0; i < V; ++i) bb.v[i] = TB(0);
+      if (any) bb = ldp<TB, V>(b + (f * F + (rp.par & 1) * hf + eb));
+#pragma unroll
+      for (int i = 0; i < V; ++i) v[i] = act[i] ? (T)bb.v[i] - o[i] : T(0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < V; ++i) v[i] = act[i] ? o[i] : T(0);
+    }
+    if (MODE == AP_APPLY || MODE == AP_RESID || MODE == AP_APPLY_DOT) {
+      T* yo = y + f * F + rp.el(0);
+      if (rp.n == V) {
+        Pack<T, V> w;
+#pragma unroll
+        for (int i = 0; i < V; ++i) w.v[i] = v[i];
+        stp<T, V>(yo, w);
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+          if (i < rp.n) yo[i] = v[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      if (i >= rp.n) continue;
+      if (MODE == AP_APPLY_DOT) acc += (double)own[i] * (double)v[i];
+      if (MODE == AP_RESNORM || MODE == AP_BNORM) acc += (double)v[i] * (double)v[i];
+    }
+    stage(v);
+  }
+  return acc;
+}
+
 template <int MODE, typename T, typename TB, int V>
 __global__ __launch_bounds__(BS) void k_apply_v(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
                                                 T* __restrict__ y, double gamma, double* __restrict__ partial) {
   double acc = 0.0;
   RowPack<V> rp;
-  if (slot_pack<V>(g, rp)) {
-    int F = g.field;
-    int sy = g.sy, sz = g.sz, hf = g.half;
-    int eb = rp.e0;
-    auto stage = [&](const T* dep) {
-#pragma unroll
-      for (int i = 0; i < V; ++i) asm volatile("" : "+v"(eb) : "v"(dep[i]));
-      asm volatile("" : "+v"(eb), "+s"(F), "+s"(sy), "+s"(sz), "+s"(hf));
-    };
-    auto L = [&](int f, int o) {
-      const int q = rp.par + o;
-      return ldp<T, V>(x + (f * F + (q & 1) * hf + eb + (q >> 1)));
-    };
-    const int J = rp.J, K = rp.K;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      bool act[V];
-      bool any = false;
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        const int I = rp.I0 + 2 * i;
-        act[i] = i < rp.n && (f == 0   ? g.ux_active(I, J, K)
-                              : f == 1 ? g.uy_active(I, J, K)
-                              : f == 2 ? g.uz_active(I, J, K)
-                                       : g.p_active(I, J, K));
-        any = any || act[i];
-      }
-      T o[V];
-      T own[V];
-#pragma unroll
-      for (int i = 0; i < V; ++i) o[i] = own[i] = T(0);
-      if (MODE != AP_BNORM && any) {
-        if (f < 3) {
-          const int ps = f == 0 ? 1 : f == 1 ? sy : sz;
-          const Pack<T, V> c0 = L(f, 0), xm = L(f, -1), xp = L(f, 1), ym = L(f, -sy), yp = L(f, sy), zm = L(f, -sz),
-                           zp = L(f, sz), pc = L(3, 0), pm = L(3, -ps);
-#pragma unroll
-          for (int i = 0; i < V; ++i) {
-            const T lap = T(6) * c0.v[i] - xm.v[i] - xp.v[i] - ym.v[i] - yp.v[i] - zm.v[i] - zp.v[i];
-            o[i] = (T)g.c * lap + (pc.v[i] - pm.v[i]) * (T)g.inv_h;
-            own[i] = c0.v[i];
-          }
-        } else {
-          const Pack<T, V> x0 = L(0, 0), x1 = L(0, 1), y0 = L(1, 0), y1 = L(1, sy), z0 = L(2, 0), z1 = L(2, sz),
-                           pc = L(3, 0);
-#pragma unroll
-          for (int i = 0; i < V; ++i) {
-            const T div = (x1.v[i] - x0.v[i]) + (y1.v[i] - y0.v[i]) + (z1.v[i] - z0.v[i]);
-            o[i] = -div * (T)g.inv_h - (T)gamma * pc.v[i];
-            own[i] = pc.v[i];
-          }
-        }
-      }
-      T v[V];
-      if (MODE == AP_RESID || MODE == AP_RESNORM || MODE == AP_BNORM) {
-        Pack<TB, V> bb;
-#pragma unroll
-        for (int i = 0; i < V; ++i) bb.v[i] = TB(0);
-        if (any) bb = ldp<TB, V>(b + (f * F + (rp.par & 1) * hf + eb));
-#pragma unroll
-        for (int i = 0; i < V; ++i) v[i] = act[i] ? (T)bb.v[i] - o[i] : T(0);
-      } else {
-#pragma unroll
-        for (int i = 0; i < V; ++i) v[i] = act[i] ? o[i] : T(0);
-      }
-      if (MODE == AP_APPLY || MODE == AP_RESID || MODE == AP_APPLY_DOT) {
-        T* yo = y + f * F + rp.el(0);
-        if (rp.n == V) {
-          Pack<T, V> w;
-#pragma unroll
-          for (int i = 0; i < V; ++i) w.v[i] = v[i];
-          stp<T, V>(yo, w);
-        } else {
-#pragma unroll
-          for (int i = 0; i < V; ++i)
-            if (i < rp.n) yo[i] = v[i];
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        if (i >= rp.n) continue;
-        if (MODE == AP_APPLY_DOT) acc += (double)own[i] * (double)v[i];
-        if (MODE == AP_RESNORM || MODE == AP_BNORM) acc += (double)v[i] * (double)v[i];
-      }
-      stage(v);
-    }
-  }
+  if (slot_pack<V>(g, rp)) acc = apply_pack<MODE, T, TB, V>(g, x, b, y, gamma, rp);
   if (MODE == AP_APPLY_DOT || MODE == AP_RESNORM || MODE == AP_BNORM) {
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
