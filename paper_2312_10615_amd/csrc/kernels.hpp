@@ -828,20 +828,18 @@ static __global__ __launch_bounds__(BS) void k_axpy_neg(double* __restrict__ s, 
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) s[i] -= a * t[i];
 }
 
-// d = cd * d + cq * q;  x += d
-static __global__ __launch_bounds__(BS) void k_update_dx(double* __restrict__ d, const double* __restrict__ q,
-                                                  double* __restrict__ x, long n, double cd, double cq) {
+// d = cd * d + cq * q;  x += d;  q = t + beta * q (the next direction, from the
+// same q): the iterate update and the direction update in one pass over q
+static __global__ __launch_bounds__(BS) void k_update_dxq(double* __restrict__ d, double* __restrict__ q,
+                                                   double* __restrict__ x, const double* __restrict__ t, long n,
+                                                   double cd, double cq, double bt) {
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
-    const double dv = cd * d[i] + cq * q[i];
+    const double qv = q[i];
+    const double dv = cd * d[i] + cq * qv;
     d[i] = dv;
     x[i] += dv;
+    q[i] = t[i] + bt * qv;
   }
-}
-
-// q = t + beta * q
-static __global__ __launch_bounds__(BS) void k_xpby(double* __restrict__ q, const double* __restrict__ t, long n,
-                                             double bt) {
-  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) q[i] = t[i] + bt * q[i];
 }
 
 // out[k] = sum_b partial[b*stride + k], fixed order, single block.

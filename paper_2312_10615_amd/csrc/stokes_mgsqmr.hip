@@ -953,7 +953,9 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
     tau = tau * nu * cc;
     {
       Prof pf(c, STOKES_KC_BLAS, 0);
-      k_update_dx<<<RED_BLOCKS, BS, 0, c->stream>>>(c->d, c->q, x, n, cc * cc * nu_prev * nu_prev, cc * cc * alpha);
+      // with the next direction q = t + (rho_new / rho) q in the same pass (unused when the loop ends here)
+      k_update_dxq<<<RED_BLOCKS, BS, 0, c->stream>>>(c->d, c->q, x, c->t, n, cc * cc * nu_prev * nu_prev,
+                                                      cc * cc * alpha, rho_new / rho);
     }
     nu_prev = nu;
     // true residual
@@ -967,11 +969,6 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
     if (!std::isfinite(relres) || !std::isfinite(tnorm)) return finish(j, STOKES_ENONFINITE);
     if (relres <= rtol) return finish(j, STOKES_OK);
     if (rho == 0.0) return finish(j, STOKES_EBREAKDOWN);
-    const double beta = rho_new / rho;
-    {
-      Prof pf(c, STOKES_KC_BLAS, 0);
-      k_xpby<<<RED_BLOCKS, BS, 0, c->stream>>>(c->q, c->t, n, beta);
-    }
     rho = rho_new;
   }
   return finish(maxit, STOKES_ENOCONV);
