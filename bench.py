@@ -201,9 +201,22 @@ def warm_start_leg(sol, b, steps, rtol, zero_ms, zero_iters):
     torch.cuda.synchronize()
     fwd_ms = ev0.elapsed_time(ev1) / nf
     flops = 0
+    bound_s = 0.0  # per layer, the larger of its matrix-core time and its HBM time (bf16 in and out once)
+    chans = {name: cout for name, _, _, cout in U.LAYERS}
     for name, spec, cin, cout in U.LAYERS:
         dz, dy, dx = net.dims[U.LEVEL[name]]
-        flops += 2 * 27 * cin * cout * dz * dy * dx
+        vox = dz * dy * dx
+        f = 2 * 27 * cin * cout * vox
+        if isinstance(spec, tuple) and spec[0] == "pool":
+            elems_in = 8 * vox * cin
+        elif isinstance(spec, tuple) and spec[0] == "cat":
+            elems_in = vox // 8 * chans[spec[1]] + vox * (cin - chans[spec[1]])
+        else:
+            elems_in = vox * cin
+        flops += f
+        bound_s += max(f / (BF16_PEAK_TFLOPS * 1e12), 2 * (elems_in + vox * cout) / (HBM_PEAK_GBPS * 1e9))
+    vox0 = net.dims[0][0] * net.dims[0][1] * net.dims[0][2]
+    bound_s += (2 * U.HEAD_IN + 4 * U.HEAD_OUT) * vox0 / (HBM_PEAK_GBPS * 1e9)  # head: bf16 in, float out
     tf = flops / (fwd_ms * 1e-3) / 1e12
     print(f"[bench] warm start: {t_warm * 1e3:.1f} ms, iters {info['iters']} (zero guess {zero_iters})",
           file=sys.stderr, flush=True)
@@ -216,7 +229,9 @@ def warm_start_leg(sol, b, steps, rtol, zero_ms, zero_iters):
             "roofline": {"bound": "mfma", "kernel": "k_conv3 (10 layers) + head, 128^3 forward",
                          "achieved": round(tf, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(tf / BF16_PEAK_TFLOPS, 4), "traffic": None, "forward_ms": round(fwd_ms, 4),
-                         "algorithmic_flops_per_forward": flops}}
+                         "algorithmic_flops_per_forward": flops,
+                         "layer_bound_ms": round(bound_s * 1e3, 4),
+                         "frac_of_layer_bound": round(bound_s * 1e3 / fwd_ms, 4)}}
 
 
 def main():
