@@ -8,8 +8,12 @@ JSON that bench.py reads for `roofline.traffic`:
     (bytes copied / counter reading), which absorb the counters' request-size
     accounting on this GPU.
 
+`level_times` times one V-cycle per level and kernel class with the
+library's own event timing (diagnostics; needs a GPU).
+
 Usage:
-  python -m paper_2312_10615_amd.profiling FETCH.csv WRITE.csv out.json --n 256
+  python -m paper_2312_10615_amd.profiling counters FETCH.csv WRITE.csv out.json --n 256
+  python -m paper_2312_10615_amd.profiling levels --n 256 --precision 64
 """
 from __future__ import annotations
 
@@ -70,13 +74,64 @@ def summarize_counters(fetch_csv, write_csv, n, copy_bytes=1 << 30):
     return out
 
 
+def level_times(n, precision, vcycles=3):
+    """Per level and kernel class of one V-cycle at n^3 (sinusoid forcing, seed 0):
+    (milliseconds, launches), from the library's own event timing (which adds
+    about 2 us per launch), plus the graph-replayed V-cycle time in ms."""
+    import numpy as np
+    import torch
+
+    from paper_2312_10615_amd.stokes import KC, StokesSolver
+    from paper_2312_10615_amd.workloads import sinusoid_forcing
+    sol = StokesSolver(n, n, n, precision=precision)
+    f = sinusoid_forcing(n, n, n, 1.0 / n, seed=0)
+    b = sol.pack((f[0], f[1], f[2], np.zeros((n, n, n))))
+    t = sol.new_state()
+    rows = []
+    for lv in range(sol.layout.levels):
+        sol.profile("all", lv)
+        for _ in range(vcycles):
+            sol.vcycle(b, out=t)
+        parts = {}
+        for name in KC:
+            ms, cnt = sol.profile_read(name, lv)
+            if cnt:
+                parts[name] = (ms / vcycles, cnt // vcycles)
+        rows.append(parts)
+    sol.profile("off")
+    sol.vcycle(b, out=t)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        sol.vcycle(b, out=t)
+    e1.record()
+    torch.cuda.synchronize()
+    return rows, e0.elapsed_time(e1) / 5
+
+
 def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("fetch_csv")
-    ap.add_argument("write_csv")
-    ap.add_argument("out")
-    ap.add_argument("--n", type=int, default=256)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd")
+    c = sub.add_parser("counters", help="summarise FETCH_SIZE / WRITE_SIZE runs")
+    c.add_argument("fetch_csv")
+    c.add_argument("write_csv")
+    c.add_argument("out")
+    c.add_argument("--n", type=int, default=256)
+    lv = sub.add_parser("levels", help="time one V-cycle per level and kernel class (GPU)")
+    lv.add_argument("--n", type=int, default=256)
+    lv.add_argument("--precision", type=int, default=64, choices=(32, 64))
     a = ap.parse_args()
+    if a.cmd == "levels":
+        rows, vc_ms = level_times(a.n, a.precision)
+        for i, parts in enumerate(rows):
+            tot = sum(ms for ms, _ in parts.values())
+            print(f"FP{a.precision} level {i}: {tot:.3f} ms  " +
+                  " ".join(f"{k}={ms:.3f}ms/{cnt}" for k, (ms, cnt) in parts.items()), flush=True)
+        print(f"FP{a.precision} V-cycle replayed from its graph: {vc_ms:.3f} ms", flush=True)
+        return
+    if a.cmd != "counters":
+        ap.error("choose a subcommand: counters or levels")
     d = summarize_counters(a.fetch_csv, a.write_csv, a.n)
     json.dump(d, open(a.out, "w"), indent=1)
     print(json.dumps(d, indent=1))
