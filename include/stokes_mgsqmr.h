@@ -32,14 +32,19 @@
  *
  * State vectors ("x", "b", "s", "t", "y" below) are float64 device arrays of
  * stokes_layout_t.total elements holding u_x, u_y, u_z and p in the padded
- * layout described by stokes_layout(): element (I, J, K) of field f sits at
- * off[f] + I + sy*J + sz*K, padded indices I in [0, nx+2), J in [0, ny+2),
- * K in [0, nz+2).  Pressure of cell (i,j,k) (0-based) is at (i+1, j+1, k+1);
+ * layout described by stokes_layout(): padded cell (I, J, K), I in [0, nx+2),
+ * J in [0, ny+2), K in [0, nz+2), is slot s = I + sy*J + sz*K, and field f of
+ * slot s is element off[f] + (s & 1) * (field / 2) + (s >> 1) (the red/black
+ * split, see stokes_layout_t).  Pressure of cell (i,j,k) (0-based) is at (i+1, j+1, k+1);
  * u_x on the face x = i*h of row (j,k) is at (i+1, j+1, k+1), i = 0..nx
  * (i = 0 and i = nx are walls); u_y, u_z alike.  Slots that are not unknowns
  * ("ghost slots": walls, Dirichlet ghosts, pitch padding) must hold zero in
  * every input that the library reads as x; the library writes zero there in
  * every vector it outputs.  Right-hand sides may hold anything in ghost slots.
+ * A field also has elements that are no slot (its spare tail, and the one
+ * element between two planes when sy*(ny+2) is even): they are zero in the x
+ * of stokes_solve and the t of stokes_vcycle, never read as input, and left
+ * as they are in the other outputs.
  */
 #ifndef STOKES_MGSQMR_H
 #define STOKES_MGSQMR_H
@@ -119,9 +124,9 @@ typedef struct stokes_params {
  * stream). */
 #define STOKES_FLAG_NO_GRAPH 2
 /* Run the levels of <= 16^3 cells as one launch of one 1024-thread workgroup
- * (same results bit for bit).  Off by default: replayed from a graph, the
- * per-level launches of those levels are faster (about 1.1 ms against 1.8 ms
- * per V-cycle at 256^3). */
+ * (the same arithmetic as the per-level launches; results agree to rounding).
+ * Off by default: replayed from a graph, the per-level launches of those
+ * levels are faster. */
 #define STOKES_FLAG_TAIL 4
 
 /* A state vector holds u_x, u_y, u_z, p, each over the padded slots
