@@ -549,6 +549,7 @@ __global__ void kb_sq_nu(BScal* sc, const int* done, int D) {
   s.cd = cc * cc * s.nu_prev * s.nu_prev;
   s.cq = cc * cc * s.alpha;
   s.nu_prev = nu;
+  s.beta = s.red[2] / s.rho;  // next direction, formed with the update (unused if the domain stops)
 }
 
 __global__ void kb_sq_check(BScal* sc, int* done, int D) {
@@ -569,7 +570,6 @@ __global__ void kb_sq_check(BScal* sc, int* done, int D) {
     s.status = STOKES_ENOCONV;
     done[d] = 1;
   } else {
-    s.beta = s.red[2] / s.rho;
     s.rho = s.red[2];
   }
 }
@@ -637,11 +637,11 @@ void phase_iteration(stokes_batch* c, const double* b, double* x) {
   kb_dot2<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->t, c->s, c->partial);
   seg(c, RED0, 2, tv, c->done);
   kb_sq_nu<<<dgrid(D), 64, 0, c->ks>>>(c->sc, c->done, D);
-  kb_update_dx<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->sc, c->dv, c->q, x);
+  kb_update_dxq<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->sc, c->dv, c->q, x,
+                                             c->t);
   apply0<AP_RESNORM>(c, x, b, nullptr);
   seg(c, RED0, 1, ta, c->done);
   kb_sq_check<<<dgrid(D), 64, 0, c->ks>>>(c->sc, c->done, D);
-  kb_xpby<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->sc, c->q, c->t);
 }
 
 // capture `iters` iterations (after the set-up phase when `with_init`) into one graph

@@ -205,7 +205,8 @@ __global__ __launch_bounds__(BS) void kb_prolong(const BEnt* __restrict__ tab, i
 }
 
 // Vanka, one colour class of each domain: eight lanes per V1 cell for the
-// residuals, one thread per cell for the corrections
+// residuals (one thread per cell measured no faster on the batch's boxes),
+// one thread per cell for the corrections
 template <typename T>
 __global__ __launch_bounds__(BS) void kb_vanka_delta(const BEnt* __restrict__ tab, int nent,
                                                      const BLev* __restrict__ lev, const int* __restrict__ done,
@@ -296,23 +297,16 @@ __global__ __launch_bounds__(BS) void kb_axpy_neg(const BEnt* __restrict__ tab, 
   SG_VEC_LOOP(s[i] -= a * t[i]);
 }
 
-__global__ __launch_bounds__(BS) void kb_update_dx(const BEnt* __restrict__ tab, int nent,
-                                                   const int* __restrict__ done, const long* __restrict__ voff,
-                                                   const long* __restrict__ vlen, const BScal* __restrict__ sc,
-                                                   double* __restrict__ dv, const double* __restrict__ q,
-                                                   double* __restrict__ x) {
+// d = cd d + cq q; x += d; q = t + beta q (the next direction from the same q)
+__global__ __launch_bounds__(BS) void kb_update_dxq(const BEnt* __restrict__ tab, int nent,
+                                                    const int* __restrict__ done, const long* __restrict__ voff,
+                                                    const long* __restrict__ vlen, const BScal* __restrict__ sc,
+                                                    double* __restrict__ dv, double* __restrict__ q,
+                                                    double* __restrict__ x, const double* __restrict__ t) {
   SG_BATCH_ENTRY();
-  const double cd = sc[d].cd, cq = sc[d].cq;
-  SG_VEC_LOOP(const double v = cd * dv[i] + cq * q[i]; dv[i] = v; x[i] += v);
-}
-
-__global__ __launch_bounds__(BS) void kb_xpby(const BEnt* __restrict__ tab, int nent, const int* __restrict__ done,
-                                              const long* __restrict__ voff, const long* __restrict__ vlen,
-                                              const BScal* __restrict__ sc, double* __restrict__ q,
-                                              const double* __restrict__ t) {
-  SG_BATCH_ENTRY();
-  const double bt = sc[d].beta;
-  SG_VEC_LOOP(q[i] = t[i] + bt * q[i]);
+  const double cd = sc[d].cd, cq = sc[d].cq, bt = sc[d].beta;
+  SG_VEC_LOOP(const double qv = q[i]; const double v = cd * dv[i] + cq * qv; dv[i] = v; x[i] += v;
+              q[i] = t[i] + bt * qv);
 }
 
 // q = t, d = 0 (start of SQMR)
