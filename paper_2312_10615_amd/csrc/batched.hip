@@ -122,6 +122,7 @@ struct stokes_batch {
   BEnt* arena = nullptr;
   Tab tcls[NCLS][MAXL][NBX];
   Tab tvec, tfield, tzero[MAXL], tcoarse[MAXL], tvanka[MAXL][8], tvapply[MAXL][8];
+  Tab tsweep[MAXL];  // boxes whose Vanka step on the level runs in one workgroup
   int bx[NCLS][MAXL];
   int chunk_first = 10, chunk = 2;
   // graphs, keyed by (b, x)
@@ -315,9 +316,21 @@ void carve(stokes_batch* c, Carve& cv) {
       return (int)((4L * c->hlev[l][d].g.field + 4 * BS - 1) / (4 * BS));
     });
     c->tcoarse[l] = add_table(c, c->coarse[l], [&](int d) { return (c->hlev[l][d].nc + 3) / 4; });
+    // small boxes of the level: the whole Vanka step in one workgroup each;
+    // the others one launch per class pass
+    auto small = [&](int d) {
+      for (int k = 0; k < 8; ++k)
+        if (c->hlev[l][d].nv[k] > VSWEEP_MAX_CLASS) return false;
+      return true;
+    };
+    c->tsweep[l] = add_table(c, c->smooth[l], [&](int d) { return small(d) ? 1 : 0; });
     for (int k = 0; k < 8; ++k) {
-      c->tvanka[l][k] = add_table(c, c->smooth[l], [&](int d) { return (8 * c->hlev[l][d].nv[k] + BS - 1) / BS; });
-      c->tvapply[l][k] = add_table(c, c->smooth[l], [&](int d) { return (c->hlev[l][d].nv[k] + BS - 1) / BS; });
+      c->tvanka[l][k] = add_table(c, c->smooth[l], [&](int d) {
+        return small(d) ? 0 : (8 * c->hlev[l][d].nv[k] + BS - 1) / BS;
+      });
+      c->tvapply[l][k] = add_table(c, c->smooth[l], [&](int d) {
+        return small(d) ? 0 : (c->hlev[l][d].nv[k] + BS - 1) / BS;
+      });
     }
   }
   c->partial = cv.take<double>(2 * maxblk);
@@ -370,6 +383,8 @@ void l_prolong(stokes_batch* c, int l, int v) {
 
 template <typename T>
 void b_vanka_symmetric(stokes_batch* c, int l) {
+  const Tab& ts = c->tsweep[l];
+  if (ts.n) kb_vanka_sweep<T><<<ts.blocks, VSWEEP_BS, 0, c->ks>>>(c->tab(ts), ts.n, c->dlev[l], c->done, (T*)c->vdelta);
   for (int pass = 0; pass < 16; ++pass) {
     const int k = pass < 8 ? pass : 15 - pass;
     const Tab& t = c->tvanka[l][k];
