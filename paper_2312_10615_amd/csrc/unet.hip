@@ -73,18 +73,22 @@ __device__ __forceinline__ uint32_t gate2(uint32_t d, uint32_t m) {
   return lo | hi;
 }
 
-// 8 channels [c, c+8) of the layer input at voxel (z, y, x), inside the grid
+// 8 channels [c, c+8) of the layer input at voxel (z, y, x), inside the grid.
+// MODE >= 0 fixes the source mode at compile time (the kernel then carries
+// no registers for the other modes' paths); MODE = -1 reads it from s.
+template <int MODE = -1>
 __device__ __forceinline__ uint4 load8(const Src& s, int z, int y, int x, int c) {
-  if (s.mode == UNET_SRC_DIRECT) {
+  const int mode = MODE >= 0 ? MODE : s.mode;
+  if (mode == UNET_SRC_DIRECT) {
     return *(const uint4*)(s.s0 + (((size_t)z * s.ny + y) * s.nx + x) * s.ch + c);
   }
-  if (s.mode == UNET_SRC_MASKED) {
+  if (mode == UNET_SRC_MASKED) {
     const size_t o = (((size_t)z * s.ny + y) * s.nx + x) * s.ch + c;
     const uint4 d = *(const uint4*)(s.s0 + o);
     const uint4 m = *(const uint4*)(s.s1 + o);
     return uint4{gate2(d.x, m.x), gate2(d.y, m.y), gate2(d.z, m.z), gate2(d.w, m.w)};
   }
-  if (s.mode == UNET_SRC_POOL) {
+  if (mode == UNET_SRC_POOL) {
     const int fy = 2 * s.ny, fx = 2 * s.nx;
     float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -126,7 +130,7 @@ __device__ __forceinline__ void tile_origin(const Src& s, int tile, int& x0, int
 
 // Stage channels [cbase, cbase + CC) of the halo tile around (x0, y0, z0) into
 // lds[hv * STR + c]; voxels outside the grid read as zero.
-template <int CC, int STR>
+template <int CC, int STR, int MODE = -1>
 __device__ __forceinline__ void stage_halo(const Src& s, int x0, int y0, int z0, int cbase, uint16_t* lds) {
   constexpr int OCT = CC / 8;
   for (int i = threadIdx.x; i < HV * OCT; i += BS) {
@@ -134,7 +138,8 @@ __device__ __forceinline__ void stage_halo(const Src& s, int x0, int y0, int z0,
     const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
     const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
     uint4 v = uint4{0u, 0u, 0u, 0u};
-    if (gx >= 0 && gx < s.nx && gy >= 0 && gy < s.ny && gz >= 0 && gz < s.nz) v = load8(s, gz, gy, gx, cbase + c8 * 8);
+    if (gx >= 0 && gx < s.nx && gy >= 0 && gy < s.ny && gz >= 0 && gz < s.nz)
+      v = load8<MODE>(s, gz, gy, gx, cbase + c8 * 8);
     *(uint4*)(lds + hv * STR + c8 * 8) = v;
   }
 }
@@ -149,7 +154,7 @@ struct Chunk {
   static constexpr int KS = (KOCT + 3) / 4;
 };
 
-template <int CC, int NS>
+template <int CC, int NS, int MODE>
 __global__ __launch_bounds__(BS) void k_conv3(Src src, int cout, const uint4* __restrict__ frag,
                                               const float* __restrict__ bias, void* __restrict__ out, int relu,
                                               int out_f32) {
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(BS) void k_conv3(Src src, int cout, const uint4* __
   const int nchunks = src.ch / CC;
   for (int q = 0; q < nchunks; ++q) {
     __syncthreads();
-    stage_halo<CC, STR>(src, x0, y0, z0, q * CC, lds);
+    stage_halo<CC, STR, MODE>(src, x0, y0, z0, q * CC, lds);
     __syncthreads();
     const uint4* wq = frag + (size_t)q * KS * NS * 64;
     for (int ks = 0; ks < KS; ++ks) {
@@ -704,18 +709,31 @@ long tiles_of(const unet_source* s) {
   return (long)((s->nx + TX - 1) / TX) * ((s->ny + TY - 1) / TY) * ((s->nz + TZ - 1) / TZ);
 }
 
-template <int CC>
+template <int CC, int MODE>
 int conv_ns(const Src& s, int ns, int cout, const uint4* frag, const float* bias, void* out, int relu, int f32,
             hipStream_t st, long tiles) {
   switch (ns) {
-    case 1: k_conv3<CC, 1><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
-    case 2: k_conv3<CC, 2><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
-    case 3: k_conv3<CC, 3><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
-    case 4: k_conv3<CC, 4><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
-    case 6: k_conv3<CC, 6><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
+    case 1: k_conv3<CC, 1, MODE><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
+    case 2: k_conv3<CC, 2, MODE><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
+    case 3: k_conv3<CC, 3, MODE><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
+    case 4: k_conv3<CC, 4, MODE><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
+    case 6: k_conv3<CC, 6, MODE><<<tiles, BS, 0, st>>>(s, cout, frag, bias, out, relu, f32); break;
     default: return UNET_EINVAL;
   }
   return ret();
+}
+
+// one kernel per source mode: the staging then holds no registers for the others
+template <int CC>
+int conv_ns(const Src& s, int ns, int cout, const uint4* frag, const float* bias, void* out, int relu, int f32,
+            hipStream_t st, long tiles) {
+  switch (s.mode) {
+    case UNET_SRC_DIRECT: return conv_ns<CC, UNET_SRC_DIRECT>(s, ns, cout, frag, bias, out, relu, f32, st, tiles);
+    case UNET_SRC_POOL: return conv_ns<CC, UNET_SRC_POOL>(s, ns, cout, frag, bias, out, relu, f32, st, tiles);
+    case UNET_SRC_CAT_UP: return conv_ns<CC, UNET_SRC_CAT_UP>(s, ns, cout, frag, bias, out, relu, f32, st, tiles);
+    case UNET_SRC_MASKED: return conv_ns<CC, UNET_SRC_MASKED>(s, ns, cout, frag, bias, out, relu, f32, st, tiles);
+    default: return UNET_EINVAL;
+  }
 }
 
 // wgrad launch shape: grid.y = chunks x pair groups, grid.x = tile groups
