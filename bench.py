@@ -40,7 +40,7 @@ def algorithmic_bytes(kernel, n):
     nu, npr = dof_counts(n)
     return {
         "dgs_u": (2 * nu + npr) * S,            # read u, p, b_u(colour); write u(colour)
-        "dgs_pr": (2 * nu + 2.5 * npr) * S,     # read u, p, b_u, b_p; write p(colour)
+        "dgs_pr": (nu + 2.5 * npr) * S,         # read b_u, b_p, p; write p(colour)
         "dgs_pf_own": (2 * nu + 2 * npr) * S,   # read u, p/2, b_p/2; write u, p/2, delta/2
         "dgs_pf_nbr": 1.5 * npr * S,            # read delta/2, p/2; write p/2
         "apply": 3 * (nu + npr) * S,            # residual: read x, b; write r

@@ -269,17 +269,10 @@ void carve(stokes_batch* c, Carve& cv) {
   c->tfield = add_table(c, doms, [&](int d) { return (c->hlev[0][d].g.field + BS - 1) / BS; });
   note(c->tfield);
   for (int v = 0; v < NBX; ++v) {
-    auto dslot = [&](int l, int d, int k) -> int {
+    auto dslot = [&](int l, int d) -> int {  // DGS classes: row packs, flat
       const Geom& g = c->hlev[l][d].g;
       const int V = c->prec == 32 ? 4 : 2;
-      if (!(k == CL_PR && c->prec != 32)) return flat_blocks(g, (((g.sy + 1) >> 1) + V - 1) / V);  // packed: flat
-      const int per_row = g.sy / 2;
-      switch (v) {
-        case 0: return tile_blocks<32>(g, per_row);
-        case 1: return tile_blocks<64>(g, per_row);
-        case 2: return tile_blocks<128>(g, per_row);
-        default: return tile_blocks<256>(g, per_row);
-      }
+      return flat_blocks(g, (((g.sy + 1) >> 1) + V - 1) / V);
     };
     auto cslot = [&](int l, int d) -> int {
       const Geom& g = c->hlev[l][d].gc;
@@ -306,9 +299,9 @@ void carve(stokes_batch* c, Carve& cv) {
         return flat_blocks(gc, gc.nx);
       });
       c->tcls[CL_RESTRICT][l][v] = add_table(c, S, [&](int d) { return cslot(l, d); });
-      // DGS classes: row packs of 16 bytes (V cells), one cell per thread for the FP64 reverse pressure step
+      // DGS classes: row packs of 16 bytes (V cells)
       for (int k : {CL_DGSU, CL_PFOWN, CL_PFNBR, CL_PR})
-        c->tcls[k][l][v] = add_table(c, S, [&](int d) { return dslot(l, d, k); });
+        c->tcls[k][l][v] = add_table(c, S, [&](int d) { return dslot(l, d); });
     }
   }
   for (int l = 0; l < c->Lmax; ++l) {

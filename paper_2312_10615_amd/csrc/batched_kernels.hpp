@@ -111,17 +111,11 @@ __global__ __launch_bounds__(BS) void kb_resid(const BEnt* __restrict__ tab, int
 // items; V = 16 bytes / element size).  A row holds few packs (5 to 33 on
 // the batch's boxes), so the packs of consecutive rows are laid out flat
 // rather than in BX-wide tiles (which would leave most lanes idle); the
-// tile width does not matter for these classes.  The FP64 reverse pressure
-// step keeps one cell per thread in tiles, as on a single box.
+// tile width does not matter for these classes.
 
 template <typename T>
 __host__ __device__ constexpr int bpack() {
   return 16 / (int)sizeof(T);
-}
-
-template <typename T>
-__host__ __device__ constexpr bool bpack_pr() {
-  return sizeof(T) == 4;
 }
 
 template <typename T, int BX>
@@ -168,18 +162,11 @@ __global__ __launch_bounds__(BS) void kb_dgs_pr(const BEnt* __restrict__ tab, in
                                                 const int* __restrict__ done, int colour) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
-  if constexpr (bpack_pr<T>()) {
-    constexpr int V = bpack<T>();
-    int m, J, K;
-    if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
-    RowPack<V> rp;
-    if (row_pack_at<V>(g, colour ^ 1, m, J, K, rp)) dgs_pr_pack<T, T, V, 1>(g, (T*)lev[d].x, (const T*)lev[d].b, rp);
-  } else {
-    int m, J, K;
-    if (!tile_item<BX>(g, g.sy >> 1, lb, m, J, K)) return;
-    const int I = 2 * m + ((colour + 1 + J + K) & 1);
-    dgs_pr_item<T, T>(g, (T*)lev[d].x, (const T*)lev[d].b, I, J, K);
-  }
+  constexpr int V = bpack<T>();
+  int m, J, K;
+  if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
+  RowPack<V> rp;
+  if (row_pack_at<V>(g, colour ^ 1, m, J, K, rp)) dgs_pr_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, rp);
 }
 
 // restriction into the next level: one item per coarse slot

@@ -51,19 +51,6 @@ __device__ __forceinline__ bool slab_item(const Geom& g, int per_row, int& X, in
   return K < g.nz + 2 && J < g.ny + 2;
 }
 
-// Slot kernels walk each row parity by parity: the first (sy+1)/2 items of a
-// row take its slots of one parity, the rest the other, so the 64 lanes of a
-// wave read one run of consecutive elements of a half field (and the
-// stencil's neighbours, all of the other parity, one run of the other half).
-__device__ __forceinline__ bool split_slot(const Geom& g, int& I, int& J, int& K) {
-  const int hr = (g.sy + 1) >> 1;
-  int X;
-  if (!slab_item(g, 2 * hr, X, J, K)) return false;
-  const int c = X >= hr;
-  I = 2 * (X - c * hr) + ((c + J + K) & 1);
-  return I < g.sy;
-}
-
 __device__ __forceinline__ void slot_ijk(const Geom& g, int s, int& I, int& J, int& K) {
   K = s / g.sz;
   const int rem = s - K * g.sz;
@@ -153,29 +140,9 @@ __device__ __forceinline__ double apply_item(const Geom& g, const T* __restrict_
   return acc;
 }
 
-template <int MODE, typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_apply(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
-                                              T* __restrict__ y, double gamma, double* __restrict__ partial) {
-  double acc = 0.0;
-  int I, J, K;
-  if (split_slot(g, I, J, K)) acc = apply_item<MODE, T, TB>(g, x, b, y, gamma, I, J, K);
-  if (MODE == AP_APPLY_DOT || MODE == AP_RESNORM || MODE == AP_BNORM) {
-    const double t = block_sum(acc);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Distributive Gauss-Seidel on V2 (Alg. 2, Eq. dist, Eq. ldist, Appendix A).
-// Half-slot threads: thread t handles the slot of colour `colour` in its pair.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool half_slot(const Geom& g, int colour, int& I, int& J, int& K) {
-  int m;
-  if (!slab_item(g, g.sy >> 1, m, J, K)) return false;
-  I = 2 * m + ((colour + 1 + J + K) & 1);
-  return true;
-}
-
 // Velocity Gauss-Seidel step on the V2 faces of one colour: u += r / (6 eta/h^2).
 // Same-colour faces are not lattice neighbours and p is fixed, so the class
 // updates at once.
@@ -193,13 +160,6 @@ __device__ __forceinline__ void dgs_u_item(const Geom& g, T* __restrict__ x, con
   if (g.ux_v2(I, J, K)) ux[e] = ux[e] + ((T)b[e] - row_u(g, ux, p, s, 1)) * dinv;
   if (g.uy_v2(I, J, K)) uy[e] = uy[e] + ((T)b[F + e] - row_u(g, uy, p, s, g.sy)) * dinv;
   if (g.uz_v2(I, J, K)) uz[e] = uz[e] + ((T)b[2 * F + e] - row_u(g, uz, p, s, g.sz)) * dinv;
-}
-
-template <typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_dgs_u(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
-  int I, J, K;
-  if (!half_slot(g, colour, I, J, K)) return;
-  dgs_u_item<T, TB>(g, x, b, I, J, K);
 }
 
 // Pressure step of the forward sweep, part 1, on the V2 cells of one colour:
@@ -234,14 +194,6 @@ __device__ __forceinline__ void dgs_pf_own_item(const Geom& g, T* __restrict__ x
   p[e] = p[e] + (T)(6.0 * g.eta * ih2) * delta;
 }
 
-template <typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_dgs_pf_own(Geom g, T* __restrict__ x, const TB* __restrict__ b,
-                                                   T* __restrict__ dscr, int colour) {
-  int I, J, K;
-  if (!half_slot(g, colour, I, J, K)) return;
-  dgs_pf_own_item<T, TB>(g, x, b, dscr, I, J, K);
-}
-
 // Part 2 on every cell of the other colour (V1 ring cells included): p_k -=
 // (eta/h^2) * sum of the deltas of its V2 neighbours (the off-diagonal
 // entries of eta B B^T in the columns m_j).
@@ -262,56 +214,40 @@ __device__ __forceinline__ void dgs_pf_nbr_item(const Geom& g, T* __restrict__ x
   if (sum != T(0)) p[e] = p[e] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
 }
 
-template <typename T>
-__global__ __launch_bounds__(BS) void k_dgs_pf_nbr(Geom g, T* __restrict__ x, const T* __restrict__ dscr,
-                                                   int colour) {
-  int I, J, K;
-  if (!half_slot(g, colour ^ 1, I, J, K)) return;
-  dgs_pf_nbr_item<T>(g, x, dscr, I, J, K);
-}
-
 // Pressure step of the reverse sweep (Gauss-Seidel on M^T L~, Eq. ldist) on
-// the V2 cells of one colour: p_j += (m_j . r) / d_j with
-//   m_j . r = (1/h) sum_a (r(plus face) - r(minus face)) + (eta/h^2)(6 r_j - sum_k r_k)
-// over the six faces and six neighbours, r = b - L~ x.  Only p_j changes, and
-// no residual read here depends on another same-colour pressure.
+// the V2 cells of one colour: p_j += (m_j . r) / d_j, r = b - L~ x, where
+// m_j = (-B^T e_j, eta B B^T e_j) is column j of M.  The row m_j^T L~ is
+// column j of L~ M: velocity part (-A B^T + eta B^T B B^T) e_j, pressure part
+// -(1 + gamma eta) B B^T e_j.  When the six faces and six neighbours of j are
+// unknowns (every V2 cell), B B^T e_j is the lattice stencil
+// (6 e_j - neighbours)/h^2 and A acts on the faces of j as the lattice
+// Laplacian; the lattice gradient commutes with the lattice Laplacian, so the
+// velocity part vanishes (A = -eta Lap_u, B B^T = -Lap_p there).  Hence
+//   m_j . r = m_j . b + (1 + gamma eta)(6 p_j - sum_k p_k)/h^2,
+//   m_j . b = (1/h) sum_a (b(plus face) - b(minus face)) + (eta/h^2)(6 b_j - sum_k b_k):
+// 13 values of b and 7 of p, where the thirteen local residuals of m_j . r
+// read ~56 operands.  Same update up to rounding (and without the residual
+// form's cancellation of the velocity terms).  Only p_j changes, and no value
+// read here is another same-colour pressure.
 template <typename T, typename TB>
 __device__ __forceinline__ void dgs_pr_item(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, int I, int J,
                                             int K) {
   if (!g.p_v2(I, J, K)) return;
   const int s = g.idx(I, J, K);
   const int F = g.field;
-  const T* ux = x;
-  const T* uy = x + F;
-  const T* uz = x + 2 * F;
   T* p = x + 3 * F;
-  const TB* bux = b;
-  const TB* buy = b + F;
-  const TB* buz = b + 2 * F;
   const TB* bp = b + 3 * F;
-  // sum_a (r(plus face) - r(minus face))
   const int e = g.at(s);
-  T fsum = ((T)bux[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1)) - ((T)bux[e] - row_u(g, ux, p, s, 1));
-  fsum += ((T)buy[g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy)) - ((T)buy[e] - row_u(g, uy, p, s, g.sy));
-  fsum += ((T)buz[g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz)) - ((T)buz[e] - row_u(g, uz, p, s, g.sz));
-  const double gam = g.gamma;
-  const T rj = (T)bp[e] - row_p(g, ux, uy, uz, p, s, gam);
-  T nsum = (T)bp[g.at(s - 1)] - row_p(g, ux, uy, uz, p, s - 1, gam);
-  nsum += (T)bp[g.at(s + 1)] - row_p(g, ux, uy, uz, p, s + 1, gam);
-  nsum += (T)bp[g.at(s - g.sy)] - row_p(g, ux, uy, uz, p, s - g.sy, gam);
-  nsum += (T)bp[g.at(s + g.sy)] - row_p(g, ux, uy, uz, p, s + g.sy, gam);
-  nsum += (T)bp[g.at(s - g.sz)] - row_p(g, ux, uy, uz, p, s - g.sz, gam);
-  nsum += (T)bp[g.at(s + g.sz)] - row_p(g, ux, uy, uz, p, s + g.sz, gam);
+  const int exm = g.at(s - 1), exp_ = g.at(s + 1), eym = g.at(s - g.sy), eyp = g.at(s + g.sy), ezm = g.at(s - g.sz),
+            ezp = g.at(s + g.sz);
+  const T fsum = ((T)b[exp_] - (T)b[e]) + ((T)b[F + eyp] - (T)b[F + e]) + ((T)b[2 * F + ezp] - (T)b[2 * F + e]);
+  const T bsum = (T)bp[exm] + (T)bp[exp_] + (T)bp[eym] + (T)bp[eyp] + (T)bp[ezm] + (T)bp[ezp];
+  const T psum = p[exm] + p[exp_] + p[eym] + p[eyp] + p[ezm] + p[ezp];
+  const T pj = p[e];
   const double ih2 = g.inv_h * g.inv_h;
-  const T rt = fsum * (T)g.inv_h + (T)(g.eta * ih2) * (T(6) * rj - nsum);
-  p[e] = p[e] + rt / (T)(-6.0 * (1.0 + gam * g.eta) * ih2);
-}
-
-template <typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_dgs_pr(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
-  int I, J, K;
-  if (!half_slot(g, colour, I, J, K)) return;
-  dgs_pr_item<T, TB>(g, x, b, I, J, K);
+  const double kap = 1.0 + g.gamma * g.eta;
+  const T rt = (fsum * (T)g.inv_h + (T)(g.eta * ih2) * (T(6) * (T)bp[e] - bsum)) + (T)(kap * ih2) * (T(6) * pj - psum);
+  p[e] = pj + rt / (T)(-6.0 * kap * ih2);
 }
 
 // ---------------------------------------------------------------------------
@@ -602,7 +538,7 @@ __device__ __forceinline__ void face_w(int I, int& n0, int& n1, double& w0, doub
   }
 }
 
-// x_fine += P e_coarse, one thread per fine slot.
+// x_fine += P e_coarse at one fine slot (I, J, K).
 template <typename T>
 __device__ __forceinline__ void prolong_item(const Geom& f, const Geom& c, const T* __restrict__ e,
                                              T* __restrict__ x, int I, int J, int K) {
@@ -651,13 +587,6 @@ __device__ __forceinline__ void prolong_item(const Geom& f, const Geom& c, const
     const int ci = ((I - 1) >> 1) + 1, cj = ((J - 1) >> 1) + 1, ck = ((K - 1) >> 1) + 1;
     x[3 * Ff + s] = x[3 * Ff + s] + e[3 * Fc + c.at(c.idx(ci, cj, ck))];
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(BS) void k_prolong_add(Geom f, Geom c, const T* __restrict__ e, T* __restrict__ x) {
-  int I, J, K;
-  if (!split_slot(f, I, J, K)) return;
-  prolong_item<T>(f, c, e, x, I, J, K);
 }
 
 // The same update, one thread per coarse cell for its eight fine children

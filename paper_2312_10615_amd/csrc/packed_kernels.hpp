@@ -286,16 +286,9 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_nbr_v(Geom g, T* __restrict__ x, 
   if (row_pack<V>(g, colour, rp)) dgs_pf_nbr_pack<T, V>(g, x, dscr, rp);
 }
 
-// Reverse-sweep pressure step (dgs_pr_item, V cells).  Its thirteen local
-// residuals read about 56 distinct operands per cell; held all at once, the
-// packs of V cells would not fit the register file.  So the residuals are
-// taken in stages of G: at the end of a stage the base element (and the
-// uniform sizes) pass through an empty asm statement that also takes the
-// stage's accumulated results, so the next stage's loads can neither be
-// merged with earlier ones nor issued before the stage's arithmetic, and
-// each stage holds only its own operands in registers.  Operands shared by
-// residuals of different stages are loaded again (from the cache).
-template <typename T, typename TB, int V, int G>
+// Reverse-sweep pressure step (dgs_pr_item, V cells): 13 wide loads of b and
+// 7 of p per pack.
+template <typename T, typename TB, int V>
 __device__ __forceinline__ void dgs_pr_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, const RowPack<V>& rp) {
   bool act[V];
   bool any = false;
@@ -305,96 +298,50 @@ __device__ __forceinline__ void dgs_pr_pack(const Geom& g, T* __restrict__ x, co
     any = any || act[i];
   }
   if (!any) return;
-  int F = g.field;
-  int sy = g.sy, sz = g.sz, hf = g.half;
-  int eb = rp.e0;
-  int done = 0;  // residuals evaluated so far
-  auto stage = [&](const T* acc) {
-    if (++done % G != 0) return;
-#pragma unroll
-    for (int i = 0; i < V; ++i) asm volatile("" : "+v"(eb) : "v"(acc[i]));
-    asm volatile("" : "+v"(eb), "+s"(F), "+s"(sy), "+s"(sz), "+s"(hf));
-  };
-  auto L = [&](int f, int o) {
-    const int q = rp.par + o;
-    return ldp<T, V>(x + (f * F + (q & 1) * hf + eb + (q >> 1)));
-  };
-  auto LB = [&](int f, int o) {
-    const int q = rp.par + o;
-    return ldp<TB, V>(b + (f * F + (q & 1) * hf + eb + (q >> 1)));
-  };
-  // local residual of the row of u field f (pitch ps) at slot s_i + o
-  auto res_u = [&](int f, int o, int ps, T* out) {
-    const Pack<T, V> c0 = L(f, o), xm = L(f, o - 1), xp = L(f, o + 1), ym = L(f, o - sy), yp = L(f, o + sy),
-                     zm = L(f, o - sz), zp = L(f, o + sz), pc = L(3, o), pm = L(3, o - ps);
-    const Pack<TB, V> bb = LB(f, o);
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      const T lap = T(6) * c0.v[i] - xm.v[i] - xp.v[i] - ym.v[i] - yp.v[i] - zm.v[i] - zp.v[i];
-      out[i] = (T)bb.v[i] - ((T)g.c * lap + (pc.v[i] - pm.v[i]) * (T)g.inv_h);
-    }
-  };
-  // local residual of the p row at slot s_i + o
-  const double gam = g.gamma;
-  auto res_p = [&](int o, T* out) {
-    const Pack<T, V> x0 = L(0, o), x1 = L(0, o + 1), y0 = L(1, o), y1 = L(1, o + sy), z0 = L(2, o),
-                     z1 = L(2, o + sz), pc = L(3, o);
-    const Pack<TB, V> bb = LB(3, o);
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      const T div = (x1.v[i] - x0.v[i]) + (y1.v[i] - y0.v[i]) + (z1.v[i] - z0.v[i]);
-      out[i] = (T)bb.v[i] - (-div * (T)g.inv_h - (T)gam * pc.v[i]);
-    }
-  };
-  // the plus- and minus-face residuals of each axis, in the order of the
-  // one-cell kernel: fsum = (r+x - r-x) + (r+y - r-y) + (r+z - r-z)
-  T fsum[V], a[V], c[V], rj[V], nsum[V];
-#pragma unroll
-  for (int f = 0; f < 3; ++f) {
-    const int ps = f == 0 ? 1 : f == 1 ? sy : sz;
-    res_u(f, ps, ps, a);
-    stage(a);
-    res_u(f, 0, ps, c);
-#pragma unroll
-    for (int i = 0; i < V; ++i) fsum[i] = f == 0 ? a[i] - c[i] : fsum[i] + (a[i] - c[i]);
-    stage(fsum);
-  }
-  res_p(0, rj);
-  stage(rj);
-  res_p(-1, nsum);
-  stage(nsum);
-  const int offs[5] = {1, -sy, sy, -sz, sz};
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    res_p(offs[k], a);
-#pragma unroll
-    for (int i = 0; i < V; ++i) nsum[i] += a[i];
-    stage(nsum);
-  }
-  const double ih2 = g.inv_h * g.inv_h;
-  T* p = x + 3 * g.field;
-  const int eo = rp.el(0);
+  const int F = g.field;
+  T* p = x + 3 * F;
+  const TB* bp = b + 3 * F;
+  const int eo = rp.el(0), exm = rp.el(-1), exp_ = rp.el(1), eym = rp.el(-g.sy), eyp = rp.el(g.sy),
+            ezm = rp.el(-g.sz), ezp = rp.el(g.sz);
+  const Pack<TB, V> bx0 = ldp<TB, V>(b + eo), bx1 = ldp<TB, V>(b + exp_);
+  const Pack<TB, V> by0 = ldp<TB, V>(b + F + eo), by1 = ldp<TB, V>(b + F + eyp);
+  const Pack<TB, V> bz0 = ldp<TB, V>(b + 2 * F + eo), bz1 = ldp<TB, V>(b + 2 * F + ezp);
+  const Pack<TB, V> bj = ldp<TB, V>(bp + eo);
+  const Pack<TB, V> bxm = ldp<TB, V>(bp + exm), bxp = ldp<TB, V>(bp + exp_), bym = ldp<TB, V>(bp + eym),
+                    byp = ldp<TB, V>(bp + eyp), bzm = ldp<TB, V>(bp + ezm), bzp = ldp<TB, V>(bp + ezp);
+  const Pack<T, V> pxm = ldp<T, V>(p + exm), pxp = ldp<T, V>(p + exp_), pym = ldp<T, V>(p + eym),
+                   pyp = ldp<T, V>(p + eyp), pzm = ldp<T, V>(p + ezm), pzp = ldp<T, V>(p + ezp);
   Pack<T, V> P = ldp<T, V>(p + eo);
+  const double ih2 = g.inv_h * g.inv_h;
+  const double kap = 1.0 + g.gamma * g.eta;
 #pragma unroll
   for (int i = 0; i < V; ++i) {
     if (!act[i]) continue;
-    const T rt = fsum[i] * (T)g.inv_h + (T)(g.eta * ih2) * (T(6) * rj[i] - nsum[i]);
-    P.v[i] = P.v[i] + rt / (T)(-6.0 * (1.0 + gam * g.eta) * ih2);
+    const T fsum = ((T)bx1.v[i] - (T)bx0.v[i]) + ((T)by1.v[i] - (T)by0.v[i]) + ((T)bz1.v[i] - (T)bz0.v[i]);
+    const T bsum = (T)bxm.v[i] + (T)bxp.v[i] + (T)bym.v[i] + (T)byp.v[i] + (T)bzm.v[i] + (T)bzp.v[i];
+    const T psum = pxm.v[i] + pxp.v[i] + pym.v[i] + pyp.v[i] + pzm.v[i] + pzp.v[i];
+    const T rt = (fsum * (T)g.inv_h + (T)(g.eta * ih2) * (T(6) * (T)bj.v[i] - bsum)) +
+                 (T)(kap * ih2) * (T(6) * P.v[i] - psum);
+    P.v[i] = P.v[i] + rt / (T)(-6.0 * kap * ih2);
   }
   stp_cells<T, V>(p + eo, P, rp.n, act);
 }
 
-template <typename T, typename TB, int V, int G>
+template <typename T, typename TB, int V>
 __global__ __launch_bounds__(BS) void k_dgs_pr_v(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
   RowPack<V> rp;
-  if (row_pack<V>(g, colour ^ 1, rp)) dgs_pr_pack<T, TB, V, G>(g, x, b, rp);
+  if (row_pack<V>(g, colour ^ 1, rp)) dgs_pr_pack<T, TB, V>(g, x, b, rp);
 }
 
 // ---------------------------------------------------------------------------
-// The operator passes (k_apply's modes) with V slots per thread.  A thread
+// The operator passes (the ApplyMode modes) with V slots per thread.  A thread
 // takes V consecutive slots of one parity in one row, every row and both
 // parities (ghost slots included: y gets 0 there).  The four rows are four
-// stages (see k_dgs_pr_v): each holds only its own operands in registers.
+// stages: at the end of a stage the base element (and the uniform sizes) pass
+// through an empty asm statement that also takes the stage's results, so the
+// next stage's loads can neither be merged with earlier ones nor issued
+// before the stage's arithmetic, and each stage holds only its own operands
+// in registers (operands shared by two rows are loaded again, from the cache).
 // ---------------------------------------------------------------------------
 template <int V>
 __host__ __device__ inline int slot_packs_per_row(const Geom& g) {

@@ -176,7 +176,22 @@ int grid_for(long slots) {
   return (int)nb;
 }
 
-int slot_grid(const Geom& g) { return slab_blocks(g, g.sy + 1); }  // split_slot: sy + 1 items per row
+// Cells per thread of the packed kernels: one 16-byte load per operand.
+template <typename T>
+constexpr int dgs_pack() {
+  return 16 / (int)sizeof(T);
+}
+
+template <typename T>
+int apply_grid(const Geom& g) {  // k_apply_v: slot packs of each row
+  return slab_blocks(g, slot_packs_per_row<dgs_pack<T>()>(g));
+}
+
+template <typename T>
+int dgs_grid(const Geom& g) {  // packed DGS kernels: packs of one colour per row
+  return slab_blocks(g, pack_per_row<dgs_pack<T>()>(g));
+}
+
 int restrict_grid(const Geom& gc) { return slab_blocks(gc, gc.sy); }  // k_restrict: one item per coarse slot
 int prolong_grid(const Geom& gc) { return slab_blocks(gc, gc.nx); }  // k_prolong_children: one per coarse cell
 
@@ -241,7 +256,7 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
   c->d = cv.take<double>(c->total);
   long maxblk = RED_BLOCKS;
   for (int l = 0; l < L; ++l)
-    maxblk = std::max<long>(maxblk, std::max(grid_for(c->lev[l].g.field), slot_grid(c->lev[l].g)));
+    maxblk = std::max<long>(maxblk, std::max(grid_for(c->lev[l].g.field), apply_grid<double>(c->lev[l].g)));
   c->npartial = (int)maxblk;
   c->partial = cv.take<double>(2 * maxblk);
   c->dscal = cv.take<double>(16);
@@ -379,22 +394,6 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
 
 // Forward DGS sweep on L~ M (Alg. 2, Eq. dist) over the V2 unknowns:
 // velocities red, black; pressures red, black.
-// Cells per thread of the DGS kernels: one 16-byte load per operand.
-template <typename T>
-constexpr int dgs_pack() {
-  return 16 / (int)sizeof(T);
-}
-
-template <typename T>
-int apply_grid(const Geom& g) {
-  return slab_blocks(g, slot_packs_per_row<dgs_pack<T>()>(g));
-}
-
-template <typename T>
-int dgs_grid(const Geom& g) {
-  return slab_blocks(g, pack_per_row<dgs_pack<T>()>(g));
-}
-
 template <typename T>
 void dgs_forward(stokes_ctx* c, int l, T* x, const T* b) {
   constexpr int V = dgs_pack<T>();
@@ -417,14 +416,8 @@ void dgs_reverse(stokes_ctx* c, int l, T* x, const T* b) {
   constexpr int V = dgs_pack<T>();
   const Geom g = c->lev[l].g;
   const int hg = dgs_grid<T>(g);
-  const int pg = slab_blocks(g, g.sy / 2);  // one cell per thread (half_slot)
   for (int col = 1; col >= 0; --col)
-    launch(c, STOKES_KC_DGS_PR, l, [=] {
-      if constexpr (sizeof(T) == 8)  // FP64: the one-cell kernel (its 56 operands in flight) is faster
-        k_dgs_pr<T, T><<<pg, BS, 0, c->ks>>>(g, x, b, col);
-      else
-        k_dgs_pr_v<T, T, V, 1><<<hg, BS, 0, c->ks>>>(g, x, b, col);
-    });
+    launch(c, STOKES_KC_DGS_PR, l, [=] { k_dgs_pr_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
   for (int col = 1; col >= 0; --col)
     launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
 }

@@ -4,9 +4,12 @@ Bars: operator apply <= 1e-14 (max-abs relative), one V-cycle <= 1e-12,
 SQMR iterates x_j <= 1e-10 (relative 2-norm) while the recurrence is well
 conditioned, and within 10x the oracle's own sensitivity to 1e-15 noise after
 that (SQMR amplifies rounding differences as the iteration proceeds).  The
-floating-point differences come only from summation order and fused
-multiply-adds; every ordering decision (colours, sweep directions, Vanka
-classes) is the same on both sides.
+floating-point differences come from summation order, fused multiply-adds
+and the reverse DGS pressure step, which the kernels evaluate through an
+identity of the V2 rows of M^T L~ (checked on the assembled matrix by
+test_reverse_pressure_row_has_no_velocity_part) where the oracle forms the
+residual; every ordering decision (colours, sweep directions, Vanka classes)
+is the same on both sides.
 """
 import numpy as np
 import pytest

@@ -110,6 +110,59 @@ def test_distribute_and_collect_are_adjoint():
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+@pytest.mark.parametrize("dims,eta,gamma", [((6, 8, 6), 0.8, 1e-3), ((7, 6, 5), 1.3, 0.4)])
+def test_reverse_pressure_row_has_no_velocity_part(dims, eta, gamma):
+    """The row m_j^T L~ of the reverse sweep (Eq. ldist), for every V2 cell j,
+    on the assembled L~: its velocity entries vanish and its pressure entries
+    are -(1 + gamma eta)/h^2 (6 at j, -1 at the six neighbours).  The GPU
+    kernels evaluate m_j . (b - L~ x) through this identity."""
+    dom = dom_of(dims, eta=eta, gamma=gamma)
+    Lt = assemble(dom, gamma, dense=True)
+    fid, _, _ = dof_tags(dom)
+    pidx = from_vector(dom, np.arange(dom.n_dofs(), dtype=float))[3]
+    nx, ny, nz = dims
+    kap = (1 + gamma * eta) / dom.h ** 2
+    checked = 0
+    for i, j, k in zip(*np.nonzero(dom.v2[3])):
+        e = np.zeros(dom.shapes[3])
+        e[i, j, k] = 1.0
+        row = Lt @ to_vector(dom, distribute(dom, e))  # L~ symmetric: row j of M^T L~
+        scale = np.abs(row).max()
+        assert np.abs(row[fid < 3]).max() <= 1e-13 * scale
+        want = np.zeros(dom.shapes[3])
+        want[i, j, k] = -6.0 * kap
+        for di, dj, dk in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            want[i + di, j + dj, k + dk] = kap
+        got = np.zeros(dom.shapes[3])
+        got[dom.active[3]] = row[pidx[dom.active[3]].astype(int)]
+        assert np.allclose(got, want, rtol=0, atol=1e-13 * scale)
+        checked += 1
+    assert checked == (nx - 2) * (ny - 2) * (nz - 2)
+
+
+def test_reverse_pressure_update_from_b_and_p_alone():
+    """collect(b - L~ x) at the V2 cells equals
+    (1/h) sum_a (b(plus face) - b(minus face)) + (eta/h^2)(6 b_j - sum_k b_k)
+    + (1 + gamma eta)(6 p_j - sum_k p_k)/h^2, for random x and b."""
+    dom = dom_of((7, 6, 8), eta=0.7, gamma=0.2)
+    x, b = rand_state(dom, 11), rand_state(dom, 12)
+    got = collect(dom, residual(dom, x, b, dom.gamma))
+    h, eta, gam = dom.h, dom.eta, dom.gamma
+    bx, by, bz, bp = b
+    p = x[3]
+    c = (slice(1, -1),) * 3
+    fsum = ((bx[2:-1, 1:-1, 1:-1] - bx[1:-2, 1:-1, 1:-1]) + (by[1:-1, 2:-1, 1:-1] - by[1:-1, 1:-2, 1:-1]) +
+            (bz[1:-1, 1:-1, 2:-1] - bz[1:-1, 1:-1, 1:-2]))
+
+    def nsum(a):
+        return (a[:-2, 1:-1, 1:-1] + a[2:, 1:-1, 1:-1] + a[1:-1, :-2, 1:-1] + a[1:-1, 2:, 1:-1] +
+                a[1:-1, 1:-1, :-2] + a[1:-1, 1:-1, 2:])
+
+    want = (fsum / h + eta / h ** 2 * (6 * bp[c] - nsum(bp)) + (1 + gam * eta) / h ** 2 * (6 * p[c] - nsum(p)))
+    assert dom.v2[3][c].all() and dom.v2[3].sum() == want.size
+    assert np.allclose(got[c], want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+
+
 @pytest.mark.parametrize("dims", [(6, 6, 6), (6, 4, 8)])
 def test_dgs_sweeps_equal_literal_one_unknown_loop(dims):
     """Alg. 2 run literally, one unknown at a time in the traversal order with
