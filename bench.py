@@ -242,7 +242,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--kernel", default="dgs_pr", help="dominant kernel class timed for the roofline")
+    ap.add_argument("--kernel", default="dgs_u", help="dominant kernel class timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-V-cycle (mixed precision) leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-box batched leg")
