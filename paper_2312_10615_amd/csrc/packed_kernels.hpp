@@ -375,6 +375,11 @@ __device__ __forceinline__ bool slot_pack(const Geom& g, RowPack<V>& rp) {
 }
 
 // One pack of an operator pass; returns the pack's share of the reduction.
+// The p row's operands are the centres and plus neighbours of the three
+// velocity rows and the centre pressure, which the velocity stages load
+// anyway: the pressure centre and the divergence, summed in the order of
+// row_p, are carried from stage to stage (25 wide loads of x per pack
+// instead of 34).
 template <int MODE, typename T, typename TB, int V>
 __device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
                                              T* __restrict__ y, double gamma, const RowPack<V>& rp) {
@@ -392,6 +397,16 @@ __device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict_
     return ldp<T, V>(x + (f * F + (q & 1) * hf + eb + (q >> 1)));
   };
   const int J = rp.J, K = rp.K;
+  bool actp[V];
+  bool anyp = false;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    actp[i] = i < rp.n && g.p_active(rp.I0 + 2 * i, J, K);
+    anyp = anyp || actp[i];
+  }
+  T pcv[V], dv[V];  // carried: centre pressure, divergence so far
+#pragma unroll
+  for (int i = 0; i < V; ++i) pcv[i] = dv[i] = T(0);
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     bool act[V];
@@ -399,35 +414,55 @@ __device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict_
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       const int I = rp.I0 + 2 * i;
-      act[i] = i < rp.n && (f == 0   ? g.ux_active(I, J, K)
-                            : f == 1 ? g.uy_active(I, J, K)
-                            : f == 2 ? g.uz_active(I, J, K)
-                                     : g.p_active(I, J, K));
+      act[i] = f == 3 ? actp[i]
+                      : i < rp.n && (f == 0 ? g.ux_active(I, J, K) : f == 1 ? g.uy_active(I, J, K) : g.uz_active(I, J, K));
       any = any || act[i];
     }
     T o[V];
     T own[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) o[i] = own[i] = T(0);
-    if (MODE != AP_BNORM && any) {
+    if (MODE != AP_BNORM) {
+      if (f == 0 && (any || anyp)) {
+        const Pack<T, V> pc = L(3, 0);
+#pragma unroll
+        for (int i = 0; i < V; ++i) pcv[i] = pc.v[i];
+      }
       if (f < 3) {
         const int ps = f == 0 ? 1 : f == 1 ? sy : sz;
-        const Pack<T, V> c0 = L(f, 0), xm = L(f, -1), xp = L(f, 1), ym = L(f, -sy), yp = L(f, sy), zm = L(f, -sz),
-                         zp = L(f, sz), pc = L(3, 0), pm = L(3, -ps);
+        if (any || anyp) {
+          const Pack<T, V> c0 = L(f, 0), up = L(f, ps);
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-          const T lap = T(6) * c0.v[i] - xm.v[i] - xp.v[i] - ym.v[i] - yp.v[i] - zm.v[i] - zp.v[i];
-          o[i] = (T)g.c * lap + (pc.v[i] - pm.v[i]) * (T)g.inv_h;
-          own[i] = c0.v[i];
+          for (int i = 0; i < V; ++i) {
+            dv[i] = f == 0 ? up.v[i] - c0.v[i] : dv[i] + (up.v[i] - c0.v[i]);
+            own[i] = c0.v[i];
+          }
+          if (any) {
+            // the minus and the two transverse pairs of neighbours; the plus neighbour is `up`
+            const int oa = f == 0 ? sy : 1, ob = f == 2 ? sy : sz;
+            const Pack<T, V> um = L(f, -ps), am = L(f, -oa), ap = L(f, oa), bm = L(f, -ob), bp = L(f, ob),
+                             pm = L(3, -ps);
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+              // row_u's order: 6c - x- - x+ - y- - y+ - z- - z+
+              T xm, xp, ym, yp, zm, zp;
+              if (f == 0) {
+                xm = um.v[i]; xp = up.v[i]; ym = am.v[i]; yp = ap.v[i]; zm = bm.v[i]; zp = bp.v[i];
+              } else if (f == 1) {
+                xm = am.v[i]; xp = ap.v[i]; ym = um.v[i]; yp = up.v[i]; zm = bm.v[i]; zp = bp.v[i];
+              } else {
+                xm = am.v[i]; xp = ap.v[i]; ym = bm.v[i]; yp = bp.v[i]; zm = um.v[i]; zp = up.v[i];
+              }
+              const T lap = T(6) * c0.v[i] - xm - xp - ym - yp - zm - zp;
+              o[i] = (T)g.c * lap + (pcv[i] - pm.v[i]) * (T)g.inv_h;
+            }
+          }
         }
-      } else {
-        const Pack<T, V> x0 = L(0, 0), x1 = L(0, 1), y0 = L(1, 0), y1 = L(1, sy), z0 = L(2, 0), z1 = L(2, sz),
-                         pc = L(3, 0);
+      } else if (any) {
 #pragma unroll
         for (int i = 0; i < V; ++i) {
-          const T div = (x1.v[i] - x0.v[i]) + (y1.v[i] - y0.v[i]) + (z1.v[i] - z0.v[i]);
-          o[i] = -div * (T)g.inv_h - (T)gamma * pc.v[i];
-          own[i] = pc.v[i];
+          o[i] = -dv[i] * (T)g.inv_h - (T)gamma * pcv[i];
+          own[i] = pcv[i];
         }
       }
     }
