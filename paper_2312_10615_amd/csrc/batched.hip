@@ -293,10 +293,10 @@ void carve(stokes_batch* c, Carve& cv) {
     for (int l = 0; l < c->Lmax; ++l) {
       const std::vector<int>& S = c->smooth[l];
       c->tcls[CL_RESID][l][v] = add_table(c, S, [&](int d) { return apack(l, d, c->prec == 32 ? 4 : 2); });
-      // prolongation: one thread per coarse cell, flat
+      // prolongation: one thread per pair of coarse cells, flat
       c->tcls[CL_PROLONG][l][v] = add_table(c, S, [&](int d) {
         const Geom& gc = c->hlev[l][d].gc;
-        return flat_blocks(gc, gc.nx);
+        return flat_blocks(gc, (gc.nx + 1) >> 1);
       });
       c->tcls[CL_RESTRICT][l][v] = add_table(c, S, [&](int d) { return cslot(l, d); });
       // DGS classes: row packs of 16 bytes (V cells)

@@ -185,10 +185,10 @@ __global__ __launch_bounds__(BS) void kb_prolong(const BEnt* __restrict__ tab, i
                                                  const int* __restrict__ done) {
   SG_BATCH_ENTRY();
   const Geom gc = lev[d].gc;
-  int X, Jc, Kc;  // one thread per coarse cell for its eight fine children, laid out flat
-  if (!flat_item(gc, gc.nx, lb, X, Jc, Kc)) return;
+  int X, Jc, Kc;  // one thread per pair of coarse cells for their sixteen fine children, laid out flat
+  if (!flat_item(gc, (gc.nx + 1) >> 1, lb, X, Jc, Kc)) return;
   if (Jc < 1 || Jc > gc.ny || Kc < 1 || Kc > gc.nz) return;
-  prolong_children_item<T>(lev[d].g, gc, (const T*)lev[d].xc, (T*)lev[d].x, X + 1, Jc, Kc);
+  prolong_pair_item<T>(lev[d].g, gc, (const T*)lev[d].xc, (T*)lev[d].x, 2 * X + 1, Jc, Kc);
 }
 
 // Vanka, one colour class of each domain: eight lanes per V1 cell for the

@@ -451,7 +451,30 @@ __global__ __launch_bounds__(VSWEEP_BS) void k_vanka_sweep(VSweep a, T* __restri
 // (weights 1, 1/2 along the face axis; 3/4, 1/4 across) and constant for p.
 // ---------------------------------------------------------------------------
 // Restriction: one thread per coarse slot; reads the fine residual r (zero at
-// every fine slot that is not an unknown).
+// every fine slot that is not an unknown).  A coarse slot I reads the fine
+// slots 2I-2 .. 2I+1 of each fine row it touches: 2I-2 and 2I are adjacent
+// elements of one half field, 2I-1 and 2I+1 of the other, so a fine row is
+// two 16-byte loads (the weighted sums keep their order term by term).
+template <typename T>
+struct FineRow {
+  T r0, r1, r2, r3;  // fine slots 2I-2, 2I-1, 2I, 2I+1 of one row
+};
+
+template <typename T>
+__device__ __forceinline__ FineRow<T> fine_row(const Geom& f, const T* __restrict__ r, int s) {
+  FineRow<T> w;
+  if constexpr (sizeof(T) == 8) {
+    typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));
+    const d2 a = *(const d2*)(r + f.at(s)), b = *(const d2*)(r + f.at(s + 1));
+    w.r0 = a.x; w.r2 = a.y; w.r1 = b.x; w.r3 = b.y;
+  } else {
+    typedef float f2 __attribute__((ext_vector_type(2), aligned(4)));
+    const f2 a = *(const f2*)(r + f.at(s)), b = *(const f2*)(r + f.at(s + 1));
+    w.r0 = a.x; w.r2 = a.y; w.r1 = b.x; w.r3 = b.y;
+  }
+  return w;
+}
+
 template <typename T>
 __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, const T* __restrict__ r,
                                               T* __restrict__ bc, int I, int J, int K) {
@@ -466,8 +489,8 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
       for (int kk = 0; kk < 4; ++kk)
         for (int jj = 0; jj < 4; ++jj) {
           const T w = wc[jj] * wc[kk];
-          const int base = f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk);
-          acc += w * (wf[0] * (T)r[f.at(base)] + wf[1] * (T)r[f.at(base + 1)] + wf[2] * (T)r[f.at(base + 2)]);
+          const FineRow<T> q = fine_row(f, r, f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk));
+          acc += w * (wf[0] * q.r0 + wf[1] * q.r1 + wf[2] * q.r2);
         }
     }
     bc[s] = (T)(acc * T(0.125));
@@ -477,9 +500,11 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
     T acc = T(0);
     if (c.uy_active(I, J, K)) {
       for (int kk = 0; kk < 4; ++kk)
-        for (int jj = 0; jj < 3; ++jj)
-          for (int ii = 0; ii < 4; ++ii)
-            acc += wc[ii] * wf[jj] * wc[kk] * (T)r[Ff + f.at(f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk))];
+        for (int jj = 0; jj < 3; ++jj) {
+          const FineRow<T> q = fine_row(f, r + Ff, f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk));
+          const T rv[4] = {q.r0, q.r1, q.r2, q.r3};
+          for (int ii = 0; ii < 4; ++ii) acc += wc[ii] * wf[jj] * wc[kk] * rv[ii];
+        }
     }
     bc[Fc + s] = (T)(acc * T(0.125));
   }
@@ -488,9 +513,11 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
     T acc = T(0);
     if (c.uz_active(I, J, K)) {
       for (int kk = 0; kk < 3; ++kk)
-        for (int jj = 0; jj < 4; ++jj)
-          for (int ii = 0; ii < 4; ++ii)
-            acc += wc[ii] * wc[jj] * wf[kk] * (T)r[2 * Ff + f.at(f.idx(2 * I - 2 + ii, 2 * J - 2 + jj, 2 * K - 2 + kk))];
+        for (int jj = 0; jj < 4; ++jj) {
+          const FineRow<T> q = fine_row(f, r + 2 * Ff, f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk));
+          const T rv[4] = {q.r0, q.r1, q.r2, q.r3};
+          for (int ii = 0; ii < 4; ++ii) acc += wc[ii] * wc[jj] * wf[kk] * rv[ii];
+        }
     }
     bc[2 * Fc + s] = (T)(acc * T(0.125));
   }
@@ -499,8 +526,11 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
     T acc = T(0);
     if (c.p_active(I, J, K)) {
       for (int kk = 0; kk < 2; ++kk)
-        for (int jj = 0; jj < 2; ++jj)
-          for (int ii = 0; ii < 2; ++ii) acc += (T)r[3 * Ff + f.at(f.idx(2 * I - 1 + ii, 2 * J - 1 + jj, 2 * K - 1 + kk))];
+        for (int jj = 0; jj < 2; ++jj) {
+          const FineRow<T> q = fine_row(f, r + 3 * Ff, f.idx(2 * I - 2, 2 * J - 1 + jj, 2 * K - 1 + kk));
+          acc += q.r1;
+          acc += q.r2;
+        }
     }
     bc[3 * Fc + s] = (T)(acc * T(0.125));
   }
@@ -589,78 +619,190 @@ __device__ __forceinline__ void prolong_item(const Geom& f, const Geom& c, const
   }
 }
 
-// The same update, one thread per coarse cell for its eight fine children
-// (padded fine I = 2Ic-1+di, and so on, di, dj, dk in {0, 1}).  The
-// children's interpolation stencils overlap: the 55 coarse values they use
-// are loaded once (about 200 loads for eight one-child threads).  Each
-// value is formed by the expression prolong_item uses, with the same
-// operands in the same order (the face_w / cell_w indices, fixed for each
-// child), so the result is the same bit for bit.  Every fine unknown lies in
-// a child of an interior coarse cell, and each child belongs to one thread.
+// The same update, one thread per pair of coarse cells Ic, Ic+1 (Ic odd; the
+// second exists when Ic < nx) for their sixteen fine children (padded fine
+// I = 2Ic-1 .. 2Ic+2, J = 2Jc-1+dj, K = 2Kc-1+dk, dj, dk in {0, 1}), one field
+// at a time.  The children's interpolation stencils overlap, so the coarse
+// values are loaded once per pair; and slots Ic-1 and Ic+1 of a coarse row are
+// adjacent elements of one half field and Ic, Ic+2 of the other, so a coarse
+// row is two 16-byte loads (44 loads for two cells, where one-child threads
+// issue about 400).  The four fine children along x are likewise two loads and
+// two stores per fine row and field.  Each value is prolong_item's expression
+// with its face_w / cell_w indices fixed for the child (same operands, same
+// order).  Every fine unknown lies in a child of an interior coarse cell, and
+// each child belongs to one thread.  Each field's stage passes its base index
+// through an empty asm statement, so its coarse values are the only ones held
+// in registers.
 template <typename T>
-__device__ __forceinline__ void prolong_children_item(const Geom& f, const Geom& c, const T* __restrict__ e,
-                                                      T* __restrict__ x, int Ic, int Jc, int Kc) {
-  const int Fc = c.field, Ff = f.field;
-  // u_x at coarse faces Ic..Ic+1, rows Jc-1..Jc+1, planes Kc-1..Kc+1 (and so on)
-  T U[2][3][3], Vy[3][2][3], W[3][3][2];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int bj = 0; bj < 3; ++bj)
-#pragma unroll
-      for (int ck = 0; ck < 3; ++ck) {
-        if (a < 2) U[a][bj][ck] = e[c.at(c.idx(Ic + a, Jc - 1 + bj, Kc - 1 + ck))];
-        if (bj < 2) Vy[a][bj][ck] = e[Fc + c.at(c.idx(Ic - 1 + a, Jc + bj, Kc - 1 + ck))];
-        if (ck < 2) W[a][bj][ck] = e[2 * Fc + c.at(c.idx(Ic - 1 + a, Jc - 1 + bj, Kc + ck))];
-      }
-  const T pc = e[3 * Fc + c.at(c.idx(Ic, Jc, Kc))];
-#pragma unroll
-  for (int d = 0; d < 8; ++d) {
-    const int di = d & 1, dj = (d >> 1) & 1, dk = d >> 2;
-    const int I = 2 * Ic - 1 + di, J = 2 * Jc - 1 + dj, K = 2 * Kc - 1 + dk;
-    const int s = f.at(f.idx(I, J, K));
-    // face axis: weight 1 on the coarse face below an even fine face, 1/2 on
-    // both neighbours of an odd one; cell axes: 3/4 own coarse cell, 1/4 the
-    // one on the fine cell's side
-    const T w0 = di ? T(0.5) : T(1), w1 = di ? T(0.5) : T(0);
-    const int n1 = dj ? 2 : 0, m1 = dk ? 2 : 0, l1 = di ? 2 : 0;
-    if (f.ux_active(I, J, K)) {
-      const int a1 = di;
-      const T v = w0 * (T(0.75) * (T(0.75) * U[0][1][1] + T(0.25) * U[0][n1][1]) +
-                        T(0.25) * (T(0.75) * U[0][1][m1] + T(0.25) * U[0][n1][m1])) +
-                  w1 * (T(0.75) * (T(0.75) * U[a1][1][1] + T(0.25) * U[a1][n1][1]) +
-                        T(0.25) * (T(0.75) * U[a1][1][m1] + T(0.25) * U[a1][n1][m1]));
-      x[s] = x[s] + v;
-    }
-    if (f.uy_active(I, J, K)) {
-      const T v0 = dj ? T(0.5) : T(1), v1 = dj ? T(0.5) : T(0);
-      const int b1 = dj;
-      const T v = v0 * (T(0.75) * (T(0.75) * Vy[1][0][1] + T(0.25) * Vy[l1][0][1]) +
-                        T(0.25) * (T(0.75) * Vy[1][0][m1] + T(0.25) * Vy[l1][0][m1])) +
-                  v1 * (T(0.75) * (T(0.75) * Vy[1][b1][1] + T(0.25) * Vy[l1][b1][1]) +
-                        T(0.25) * (T(0.75) * Vy[1][b1][m1] + T(0.25) * Vy[l1][b1][m1]));
-      x[Ff + s] = x[Ff + s] + v;
-    }
-    if (f.uz_active(I, J, K)) {
-      const T z0 = dk ? T(0.5) : T(1), z1 = dk ? T(0.5) : T(0);
-      const int c1 = dk;
-      const T v = z0 * (T(0.75) * (T(0.75) * W[1][1][0] + T(0.25) * W[l1][1][0]) +
-                        T(0.25) * (T(0.75) * W[1][n1][0] + T(0.25) * W[l1][n1][0])) +
-                  z1 * (T(0.75) * (T(0.75) * W[1][1][c1] + T(0.25) * W[l1][1][c1]) +
-                        T(0.25) * (T(0.75) * W[1][n1][c1] + T(0.25) * W[l1][n1][c1]));
-      x[2 * Ff + s] = x[2 * Ff + s] + v;
-    }
-    if (f.p_active(I, J, K)) x[3 * Ff + s] = x[3 * Ff + s] + pc;
+struct Quad {
+  T v[4];  // slots i0, i0+1, i0+2, i0+3 of one row
+};
+
+template <typename T>
+__device__ __forceinline__ Quad<T> load_quad(const Geom& g, const T* __restrict__ a, int s) {
+  typedef T t2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+  const t2 p = *(const t2*)(a + g.at(s)), q = *(const t2*)(a + g.at(s + 1));
+  Quad<T> r;
+  r.v[0] = p.x; r.v[2] = p.y; r.v[1] = q.x; r.v[3] = q.y;
+  return r;
+}
+
+// fine row (J, K) of field `a`, slots 2Ic-1 .. 2Ic+2: add add[k] where act[k]
+template <typename T>
+__device__ __forceinline__ void add_quad(const Geom& f, T* __restrict__ a, int s, const T* add, const bool* act) {
+  typedef T t2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+  t2* pa = (t2*)(a + f.at(s));
+  t2* pb = (t2*)(a + f.at(s + 1));
+  t2 A = *pa, B = *pb;
+  if (act[0]) A.x = A.x + add[0];
+  if (act[2]) A.y = A.y + add[2];
+  if (act[1]) B.x = B.x + add[1];
+  if (act[3]) B.y = B.y + add[3];
+  if (act[0] && act[2]) {
+    *pa = A;
+  } else {
+    if (act[0]) a[f.at(s)] = A.x;
+    if (act[2]) a[f.at(s) + 1] = A.y;
+  }
+  if (act[1] && act[3]) {
+    *pb = B;
+  } else {
+    if (act[1]) a[f.at(s + 1)] = B.x;
+    if (act[3]) a[f.at(s + 1) + 1] = B.y;
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(BS) void k_prolong_children(Geom f, Geom c, const T* __restrict__ e,
-                                                         T* __restrict__ x) {
+__device__ __forceinline__ void prolong_pair_item(const Geom& f, const Geom& c, const T* __restrict__ e,
+                                                  T* __restrict__ x, int Ic, int Jc, int Kc) {
+  int Fc = c.field, Ff = f.field;
+  int base = 0;  // laundered between the field stages
+  const int nt = Ic + 1 <= c.nx ? 2 : 1;
+  auto stage = [&]() { asm volatile("" : "+v"(base), "+s"(Fc), "+s"(Ff)); };
+  // u_x: coarse faces Ic .. Ic+2 (U[a], a = face - Ic), rows Jc-1..Jc+1, planes Kc-1..Kc+1
+  {
+    T U[3][3][3];
+#pragma unroll
+    for (int bj = 0; bj < 3; ++bj)
+#pragma unroll
+      for (int ck = 0; ck < 3; ++ck) {
+        const Quad<T> q = load_quad(c, e + base, c.idx(Ic - 1, Jc - 1 + bj, Kc - 1 + ck));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) U[a][bj][ck] = q.v[a + 1];
+      }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int dj = d & 1, dk = d >> 1;
+      const int J = 2 * Jc - 1 + dj, K = 2 * Kc - 1 + dk;
+      const int n1 = dj ? 2 : 0, m1 = dk ? 2 : 0;
+      T add[4];
+      bool act[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int t = k >> 1, di = k & 1;
+        act[k] = t < nt && f.ux_active(2 * Ic - 1 + k, J, K);
+        const T w0 = di ? T(0.5) : T(1), w1 = di ? T(0.5) : T(0);
+        const int a1 = t + di;
+        add[k] = w0 * (T(0.75) * (T(0.75) * U[t][1][1] + T(0.25) * U[t][n1][1]) +
+                       T(0.25) * (T(0.75) * U[t][1][m1] + T(0.25) * U[t][n1][m1])) +
+                 w1 * (T(0.75) * (T(0.75) * U[a1][1][1] + T(0.25) * U[a1][n1][1]) +
+                       T(0.25) * (T(0.75) * U[a1][1][m1] + T(0.25) * U[a1][n1][m1]));
+      }
+      if (act[0] || act[1] || act[2] || act[3]) add_quad(f, x + base, f.idx(2 * Ic - 1, J, K), add, act);
+    }
+  }
+  stage();
+  // u_y: coarse cells Ic-1 .. Ic+2 (Vy[a], a = cell - Ic + 1), faces Jc, Jc+1, planes Kc-1..Kc+1
+  {
+    T Vy[4][2][3];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int ck = 0; ck < 3; ++ck) {
+        const Quad<T> q = load_quad(c, e + Fc + base, c.idx(Ic - 1, Jc + bj, Kc - 1 + ck));
+#pragma unroll
+        for (int a = 0; a < 4; ++a) Vy[a][bj][ck] = q.v[a];
+      }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int dj = d & 1, dk = d >> 1;
+      const int J = 2 * Jc - 1 + dj, K = 2 * Kc - 1 + dk;
+      const int m1 = dk ? 2 : 0, b1 = dj;
+      const T v0 = dj ? T(0.5) : T(1), v1 = dj ? T(0.5) : T(0);
+      T add[4];
+      bool act[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int t = k >> 1, di = k & 1;
+        act[k] = t < nt && f.uy_active(2 * Ic - 1 + k, J, K);
+        const int l1 = t + (di ? 2 : 0), c1 = t + 1;
+        add[k] = v0 * (T(0.75) * (T(0.75) * Vy[c1][0][1] + T(0.25) * Vy[l1][0][1]) +
+                       T(0.25) * (T(0.75) * Vy[c1][0][m1] + T(0.25) * Vy[l1][0][m1])) +
+                 v1 * (T(0.75) * (T(0.75) * Vy[c1][b1][1] + T(0.25) * Vy[l1][b1][1]) +
+                       T(0.25) * (T(0.75) * Vy[c1][b1][m1] + T(0.25) * Vy[l1][b1][m1]));
+      }
+      if (act[0] || act[1] || act[2] || act[3]) add_quad(f, x + Ff + base, f.idx(2 * Ic - 1, J, K), add, act);
+    }
+  }
+  stage();
+  // u_z: coarse cells Ic-1 .. Ic+2, rows Jc-1..Jc+1, faces Kc, Kc+1
+  {
+    T W[4][3][2];
+#pragma unroll
+    for (int bj = 0; bj < 3; ++bj)
+#pragma unroll
+      for (int ck = 0; ck < 2; ++ck) {
+        const Quad<T> q = load_quad(c, e + 2 * Fc + base, c.idx(Ic - 1, Jc - 1 + bj, Kc + ck));
+#pragma unroll
+        for (int a = 0; a < 4; ++a) W[a][bj][ck] = q.v[a];
+      }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int dj = d & 1, dk = d >> 1;
+      const int J = 2 * Jc - 1 + dj, K = 2 * Kc - 1 + dk;
+      const int n1 = dj ? 2 : 0, cz = dk;
+      const T z0 = dk ? T(0.5) : T(1), z1 = dk ? T(0.5) : T(0);
+      T add[4];
+      bool act[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int t = k >> 1, di = k & 1;
+        act[k] = t < nt && f.uz_active(2 * Ic - 1 + k, J, K);
+        const int l1 = t + (di ? 2 : 0), c1 = t + 1;
+        add[k] = z0 * (T(0.75) * (T(0.75) * W[c1][1][0] + T(0.25) * W[l1][1][0]) +
+                       T(0.25) * (T(0.75) * W[c1][n1][0] + T(0.25) * W[l1][n1][0])) +
+                 z1 * (T(0.75) * (T(0.75) * W[c1][1][cz] + T(0.25) * W[l1][1][cz]) +
+                       T(0.25) * (T(0.75) * W[c1][n1][cz] + T(0.25) * W[l1][n1][cz]));
+      }
+      if (act[0] || act[1] || act[2] || act[3]) add_quad(f, x + 2 * Ff + base, f.idx(2 * Ic - 1, J, K), add, act);
+    }
+  }
+  stage();
+  // p: constant over the eight children of each coarse cell
+  {
+    const Quad<T> q = load_quad(c, e + 3 * Fc + base, c.idx(Ic - 1, Jc, Kc));
+    const T pc[2] = {q.v[1], q.v[2]};
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int J = 2 * Jc - 1 + (d & 1), K = 2 * Kc - 1 + (d >> 1);
+      T add[4];
+      bool act[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        act[k] = (k >> 1) < nt && f.p_active(2 * Ic - 1 + k, J, K);
+        add[k] = pc[k >> 1];
+      }
+      if (act[0] || act[1] || act[2] || act[3]) add_quad(f, x + 3 * Ff + base, f.idx(2 * Ic - 1, J, K), add, act);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_prolong_pairs(Geom f, Geom c, const T* __restrict__ e, T* __restrict__ x) {
   int X, Jc, Kc;
-  if (!slab_item(c, c.nx, X, Jc, Kc)) return;
+  if (!slab_item(c, (c.nx + 1) >> 1, X, Jc, Kc)) return;
   if (Jc < 1 || Jc > c.ny || Kc < 1 || Kc > c.nz) return;
-  prolong_children_item<T>(f, c, e, x, X + 1, Jc, Kc);
+  prolong_pair_item<T>(f, c, e, x, 2 * X + 1, Jc, Kc);
 }
 
 // ---------------------------------------------------------------------------

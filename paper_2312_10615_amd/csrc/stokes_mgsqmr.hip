@@ -193,7 +193,7 @@ int dgs_grid(const Geom& g) {  // packed DGS kernels: packs of one colour per ro
 }
 
 int restrict_grid(const Geom& gc) { return slab_blocks(gc, gc.sy); }  // k_restrict: one item per coarse slot
-int prolong_grid(const Geom& gc) { return slab_blocks(gc, gc.nx); }  // k_prolong_children: one per coarse cell
+int prolong_grid(const Geom& gc) { return slab_blocks(gc, (gc.nx + 1) >> 1); }  // k_prolong_pairs: one per pair of coarse cells
 
 #define HIPCHK(call)                                  \
   do {                                                \
@@ -493,7 +493,7 @@ void vcycle(stokes_ctx* c, int l, const T* b, T* x, bool zero_init = true) {
   launch(c, STOKES_KC_RESTRICT, l, [=] { k_restrict<T><<<restrict_grid(gc), BS, 0, c->ks>>>(g, gc, r, bc); });
   vcycle(c, l + 1, (const T*)bc, xc);
   for (int i = 1; i < c->prm.cycle; ++i) vcycle(c, l + 1, (const T*)bc, xc, false);
-  launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_children<T><<<prolong_grid(gc), BS, 0, c->ks>>>(g, gc, xc, x); });
+  launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_pairs<T><<<prolong_grid(gc), BS, 0, c->ks>>>(g, gc, xc, x); });
   postsmooth(c, l, x, b);
 }
 
@@ -803,7 +803,7 @@ int stokes_prolong(stokes_ctx* c, const double* coarse, double* fine) {
   const Geom& g = c->lev[0].g;
   const Geom& gc = c->lev[1].g;
   k_fill<double><<<RED_BLOCKS, BS, 0, c->stream>>>(fine, 4L * g.field, 0.0);
-  k_prolong_children<double><<<prolong_grid(gc), BS, 0, c->stream>>>(g, gc, coarse, fine);
+  k_prolong_pairs<double><<<prolong_grid(gc), BS, 0, c->stream>>>(g, gc, coarse, fine);
   return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
 }
 

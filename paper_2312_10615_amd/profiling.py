@@ -49,7 +49,7 @@ def _largest_dispatches(path, counter):
 
 
 SHORT = {"k_dgs_u_v<": "dgs_u", "k_dgs_pr_v<": "dgs_pr", "k_dgs_pf_own_v<": "dgs_pf_own", "k_dgs_pf_nbr_v<": "dgs_pf_nbr",
-         "k_apply_v<1,": "apply", "k_restrict<": "restrict", "k_prolong_children<": "prolong"}
+         "k_apply_v<1,": "apply", "k_restrict<": "restrict", "k_prolong_pairs<": "prolong"}
 
 
 def summarize_counters(fetch_csv, write_csv, n, copy_bytes=1 << 30):

@@ -8,7 +8,7 @@ from tests.gpu_helpers import announce, cuda, random_fields, rel_err
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dims", [(16, 8, 12), (32, 32, 32)])
+@pytest.mark.parametrize("dims", [(16, 8, 12), (32, 32, 32), (10, 8, 8)])  # (10, 8, 8): odd coarse nx
 def test_restrict_and_prolong_match_oracle(dims):
     cuda()
     from oracle.domain import Domain, box_labels
