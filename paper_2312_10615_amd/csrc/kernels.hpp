@@ -265,9 +265,8 @@ __device__ __forceinline__ void dgs_pr_item(const Geom& g, T* __restrict__ x, co
 // elements of a half field, so neighbouring threads read neighbouring
 // elements on the planes normal to y and z.
 template <typename T, typename TB>
-__device__ __forceinline__ void vanka_delta_at(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
-                                               int s, const T* __restrict__ kinv, T* __restrict__ delta, int c,
-                                               int ncells) {
+__device__ __forceinline__ void vanka_delta_vals(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                                 int s, const T* __restrict__ kinv, T* __restrict__ out) {
   int I, J, K;
   slot_ijk(g, s, I, J, K);
   const int F = g.field;
@@ -291,8 +290,18 @@ __device__ __forceinline__ void vanka_delta_at(const Geom& g, const T* __restric
     T acc = T(0);
 #pragma unroll
     for (int j = 0; j < 7; ++j) acc += km[r * 8 + j] * res[j];
-    delta[(long)r * ncells + c] = acc;
+    out[r] = acc;
   }
+}
+
+template <typename T, typename TB>
+__device__ __forceinline__ void vanka_delta_at(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                               int s, const T* __restrict__ kinv, T* __restrict__ delta, int c,
+                                               int ncells) {
+  T d[7];
+  vanka_delta_vals<T, TB>(g, x, b, s, kinv, d);
+#pragma unroll
+  for (int r = 0; r < 7; ++r) delta[(long)r * ncells + c] = d[r];
 }
 
 // x[local DOF r of subdomain c] += delta_r, one thread per subdomain.
@@ -334,9 +343,9 @@ __device__ __forceinline__ void vanka_apply_item(const Geom& g, T* __restrict__ 
 // class (t & 7 must equal threadIdx.x & 7, and the eight lanes of a subdomain
 // share a wave); every lane of the wave must call it (shuffles).
 template <typename T, typename TB>
-__device__ __forceinline__ void vanka_delta8_item(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
-                                                  const int* __restrict__ cells, int ncells, const T* __restrict__ kinv,
-                                                  T* __restrict__ delta, int t) {
+__device__ __forceinline__ T vanka_delta8_lane(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                               const int* __restrict__ cells, int ncells, const T* __restrict__ kinv,
+                                               int t) {
   const int c = t >> 3;
   const int r = t & 7;
   const bool valid = c < ncells;
@@ -371,7 +380,16 @@ __device__ __forceinline__ void vanka_delta8_item(const Geom& g, const T* __rest
     const T rj = __shfl(res, base + j, 64);
     acc += km[j] * rj;
   }
-  if (valid && r < 7) delta[(long)r * ncells + c] = acc;
+  return acc;
+}
+
+template <typename T, typename TB>
+__device__ __forceinline__ void vanka_delta8_item(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                                  const int* __restrict__ cells, int ncells, const T* __restrict__ kinv,
+                                                  T* __restrict__ delta, int t) {
+  const T acc = vanka_delta8_lane<T, TB>(g, x, b, cells, ncells, kinv, t);
+  const int c = t >> 3, r = t & 7;
+  if (c < ncells && r < 7) delta[(long)r * ncells + c] = acc;
 }
 
 // Residual pass of one class: eight lanes per subdomain, or one thread per
@@ -398,6 +416,124 @@ template <typename T>
 __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
                                                     int ncells, const T* __restrict__ delta) {
   vanka_apply_item<T>(g, x, cells, ncells, delta, blockIdx.x * BS + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Multiplicative Vanka with two copies of the level's state (8 classes, levels
+// whose classes run as separate eight-lane passes).  Pass p reads copy R and writes copy
+// W: each active local unknown of a class-k cell becomes R + delta in W, so a
+// pass needs no separate correction launch.  W then lacks only the previous
+// pass's corrections (class kp), which the same launch copies over from R,
+// except where a class-k cell rewrites the unknown itself (a face shared with
+// a V1 cell of class k).  Same-class subdomains share no unknown and W is
+// never read, so every element of W has at most one writer and no launch
+// reads what it writes.  The values are those of the delta/apply passes, bit
+// for bit.  Before the first pass W is brought up to date on the boundary
+// band (k_vanka_band_copy); after the 16 passes the state is back in the
+// first copy.
+// ---------------------------------------------------------------------------
+
+// Element (in a state vector) of local unknown r of the subdomain of cell
+// (I, J, K) at slot s, whether it is an unknown, and the cell across it.
+struct VankaDof {
+  int e;
+  bool active;
+  int nI, nJ, nK;
+};
+
+__device__ __forceinline__ VankaDof vanka_dof(const Geom& g, int s, int I, int J, int K, int r) {
+  const int F = g.field;
+  VankaDof d{0, false, I, J, K};
+  switch (r) {
+    case 0: d.e = g.at(s); d.active = I >= 2; d.nI = I - 1; break;
+    case 1: d.e = g.at(s + 1); d.active = I + 1 <= g.nx; d.nI = I + 1; break;
+    case 2: d.e = F + g.at(s); d.active = J >= 2; d.nJ = J - 1; break;
+    case 3: d.e = F + g.at(s + g.sy); d.active = J + 1 <= g.ny; d.nJ = J + 1; break;
+    case 4: d.e = 2 * F + g.at(s); d.active = K >= 2; d.nK = K - 1; break;
+    case 5: d.e = 2 * F + g.at(s + g.sz); d.active = K + 1 <= g.nz; d.nK = K + 1; break;
+    default: d.e = 3 * F + g.at(s); d.active = true; break;  // the cell's own pressure
+  }
+  return d;
+}
+
+// Copy unknown r of previous-class cell s from R to W unless a V1 cell of
+// class k owns it too.
+template <typename T>
+__device__ __forceinline__ void vanka_copy_dof(const Geom& g, const T* __restrict__ R, T* __restrict__ W, int s,
+                                               int r, int k) {
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
+  const VankaDof d = vanka_dof(g, s, I, J, K, r);
+  if (!d.active) return;
+  if (r < 6 && !g.p_v2(d.nI, d.nJ, d.nK) && Geom::vanka_colour(d.nI, d.nJ, d.nK) == k) return;
+  W[d.e] = R[d.e];
+}
+
+// Eight lanes per class-k cell (lanes [0, copy0), copy0 = 8 ncells rounded up
+// to whole waves), then eight lanes per previous-class cell.
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_vanka_pp8(Geom g, const T* __restrict__ R, T* __restrict__ W,
+                                                  const TB* __restrict__ b, const int* __restrict__ cells, int ncells,
+                                                  const T* __restrict__ kinv, const int* __restrict__ prev, int nprev,
+                                                  int k, int copy0) {
+  const int t = blockIdx.x * BS + threadIdx.x;
+  if (t < copy0) {  // whole waves: the shuffles see only this part's lanes
+    const T d = vanka_delta8_lane<T, TB>(g, R, b, cells, ncells, kinv, t);
+    const int c = t >> 3, r = t & 7;
+    if (c < ncells && r < 7) {
+      const int s = cells[c];
+      int I, J, K;
+      slot_ijk(g, s, I, J, K);
+      const VankaDof dof = vanka_dof(g, s, I, J, K, r);
+      if (dof.active) W[dof.e] = R[dof.e] + d;
+    }
+  } else {
+    const int u = t - copy0, c = u >> 3, r = u & 7;
+    if (c < nprev && r < 7) vanka_copy_dof<T>(g, R, W, prev[c], r, k);
+  }
+}
+
+// W = R on every slot within four cells of the boundary (padded I <= 3 or
+// I >= nx-2, and so on): every value a V1 cell's local residuals read, and
+// every unknown a Vanka pass writes.  Needs nx, ny, nz >= 8 (else copy the
+// whole state).  Threads: first the full rows (planes K <= 3 or K >= nz-2,
+// then rows J <= 3 or J >= ny-2 of the other planes), nx+2 slots each; then
+// the eight band slots of every remaining row.
+__host__ __device__ inline long vanka_band_slots(const Geom& g) {
+  const long full = 8L * (g.ny + 2) + 8L * (g.nz - 6);
+  return full * (g.nx + 2) + 8L * (g.ny - 6) * (g.nz - 6);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_vanka_band_copy(Geom g, const T* __restrict__ R, T* __restrict__ W) {
+  const long t = (long)blockIdx.x * BS + threadIdx.x;
+  const long full = 8L * (g.ny + 2) + 8L * (g.nz - 6);
+  const long nA = full * (g.nx + 2);
+  int I, J, K;
+  if (t < nA) {
+    const int row = (int)(t / (g.nx + 2));
+    I = (int)(t - (long)row * (g.nx + 2));
+    if (row < 8 * (g.ny + 2)) {
+      const int pk = row / (g.ny + 2);
+      K = pk < 4 ? pk : g.nz - 6 + pk;
+      J = row - pk * (g.ny + 2);
+    } else {
+      const int r2 = row - 8 * (g.ny + 2);
+      K = 4 + r2 / 8;
+      const int jj = r2 % 8;
+      J = jj < 4 ? jj : g.ny - 6 + jj;
+    }
+  } else {
+    const long u = t - nA;
+    if (u >= 8L * (g.ny - 6) * (g.nz - 6)) return;
+    const int row = (int)(u / 8), ii = (int)(u % 8);
+    K = 4 + row / (g.ny - 6);
+    J = 4 + row % (g.ny - 6);
+    I = ii < 4 ? ii : g.nx - 6 + ii;
+  }
+  const int e = g.at(g.idx(I, J, K));
+#pragma unroll
+  for (int f = 0; f < 4; ++f) W[f * g.field + e] = R[f * g.field + e];
 }
 
 // A whole Vanka smoothing step on a small level in one workgroup: the class

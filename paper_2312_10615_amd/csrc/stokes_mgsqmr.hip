@@ -36,6 +36,8 @@ struct Level {
   int nv[27] = {};
   long doff[27] = {};     // class slice of the Vanka delta buffer (additive Vanka keeps all classes)
   void* kinv = nullptr;  // 64 x 8 x 8 Vanka local inverses
+  void* alt = nullptr;   // second copy of the state for the two-copy Vanka passes (k_vanka_pp*)
+  bool pp = false;       // this level runs them
 };
 
 struct Carver {
@@ -283,6 +285,11 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
         sum += 8L * lv.nv[k];
         vmax = std::max<long>(vmax, p.vanka == STOKES_VANKA_ADDITIVE ? sum / 8 : lv.nv[k]);
       }
+      // two-copy passes where a pass is a latency chain (eight lanes per subdomain);
+      // on larger levels the passes are bound by bandwidth and the copies cost more
+      lv.pp = p.vanka == STOKES_VANKA_MULT8 && !vsweep_level(lv, nc);
+      for (int k = 0; k < nc; ++k) lv.pp = lv.pp && lv.nv[k] <= VANKA_LANES_MAX;
+      if (lv.pp) lv.alt = cv.take<char>(tot * es);
     }
   }
   c->vdelta = cv.take<char>(8 * std::max<long>(vmax, 1) * es);
@@ -383,6 +390,37 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
   if (c->prm.vanka == STOKES_VANKA_ADDITIVE) {
     for (int k = 0; k < nc; ++k) vanka_delta<T>(c, l, x, b, k);
     for (int k = 0; k < nc; ++k) vanka_correct<T>(c, l, x, k);
+    return;
+  }
+  if (lv.pp) {  // two copies of the state; 2 nc (even) passes end in x
+    const Geom g = lv.g;
+    T* X[2] = {x, (T*)lv.alt};
+    T* alt = X[1];
+    if (std::min(g.nx, std::min(g.ny, g.nz)) >= 8) {
+      const int nb = (int)((vanka_band_slots(g) + BS - 1) / BS);
+      launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_vanka_band_copy<T><<<nb, BS, 0, c->ks>>>(g, x, alt); });
+    } else {
+      const long n = 4L * g.field;
+      launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_convert<T, T><<<RED_BLOCKS, BS, 0, c->ks>>>(x, alt, n); });
+    }
+    const T* kinv = (const T*)lv.kinv;
+    int kp = -1;
+    for (int pass = 0; pass < 2 * nc; ++pass) {
+      const int k = pass < nc ? pass : 2 * nc - 1 - pass;
+      const int n = lv.nv[k];
+      const int np = kp >= 0 && kp != k ? lv.nv[kp] : 0;  // same class twice: it rewrites all of its unknowns
+      const int* cells = lv.vcells[k];
+      const int* prev = kp >= 0 ? lv.vcells[kp] : cells;
+      const T* R = X[pass & 1];
+      T* W = X[(pass + 1) & 1];
+      kp = k;
+      if (n == 0 && np == 0) continue;
+      const int copy0 = (8 * n + 63) / 64 * 64;
+      const int nb = (copy0 + 8 * np + BS - 1) / BS;
+      launch(c, STOKES_KC_VANKA_DELTA, l, [=] {
+        k_vanka_pp8<T, T><<<nb, BS, 0, c->ks>>>(g, R, W, b, cells, n, kinv, prev, np, k, copy0);
+      });
+    }
     return;
   }
   for (int pass = 0; pass < 2 * nc; ++pass) {

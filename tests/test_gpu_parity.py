@@ -46,6 +46,9 @@ def test_operator_apply_matches_oracle(dims, penalized):
 @pytest.mark.parametrize("dims,levels,nu,nb,sched", [((32, 32, 32), 0, 2, 1, "split"), ((16, 24, 8), 0, 2, 1, "split"),
                                                     ((8, 8, 8), 2, 1, 1, "split"), ((16, 16, 16), 0, 3, 2, "split"),
                                                     ((12, 20, 16), 3, 2, 1, "split"),
+                                                    ((32, 32, 32), 0, 2, 2, "split"),
+                                                    # level-0 classes of ~20k cells: one thread per subdomain
+                                                    ((256, 256, 32), 5, 2, 1, "split"),
                                                     ((32, 32, 32), 0, 2, 1, "symmetric"),
                                                     ((16, 24, 8), 0, 4, 2, "symmetric")])
 def test_vcycle_matches_oracle(dims, levels, nu, nb, sched):
