@@ -377,7 +377,7 @@ void l_prolong(stokes_batch* c, int l, int v) {
 template <typename T>
 void b_vanka_symmetric(stokes_batch* c, int l) {
   const Tab& ts = c->tsweep[l];
-  if (ts.n) kb_vanka_sweep<T><<<ts.blocks, VSWEEP_BS, 0, c->ks>>>(c->tab(ts), ts.n, c->dlev[l], c->done, (T*)c->vdelta);
+  if (ts.n) kb_vanka_sweep<T><<<ts.blocks, VSWEEP_BS, 0, c->ks>>>(c->tab(ts), ts.n, c->dlev[l], c->done);
   for (int pass = 0; pass < 16; ++pass) {
     const int k = pass < 8 ? pass : 15 - pass;
     const Tab& t = c->tvanka[l][k];

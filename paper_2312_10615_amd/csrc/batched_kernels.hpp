@@ -218,23 +218,24 @@ __global__ __launch_bounds__(BS) void kb_vanka_apply(const BEnt* __restrict__ ta
 // workgroup (one block per box; k_vanka_sweep's passes with barriers).
 template <typename T>
 __global__ __launch_bounds__(VSWEEP_BS) void kb_vanka_sweep(const BEnt* __restrict__ tab, int nent,
-                                                            const BLev* __restrict__ lev, const int* __restrict__ done,
-                                                            T* __restrict__ delta) {
+                                                            const BLev* __restrict__ lev, const int* __restrict__ done) {
   const int d = tab[bent_find(tab, nent)].dom;
   if (done[d]) return;
   const Geom g = lev[d].g;
   T* x = (T*)lev[d].x;
   const T* b = (const T*)lev[d].b;
-  const T* kinv = (const T*)lev[d].kinv;
+  __shared__ T sk[64 * 64];                // local inverses
+  __shared__ T sd[7 * VSWEEP_MAX_CLASS];   // one class's corrections
   const int t = threadIdx.x;
+  for (int i = t; i < 64 * 64; i += VSWEEP_BS) sk[i] = ((const T*)lev[d].kinv)[i];
+  __syncthreads();
   for (int pass = 0; pass < 16; ++pass) {
     const int k = pass < 8 ? pass : 15 - pass;
     const int n = lev[d].nv[k];
     const int* cells = lev[d].vc[k];
-    T* vd = delta + lev[d].voff[k];
-    for (int c = t; c < n; c += VSWEEP_BS) vanka_delta_item<T, T>(g, x, b, cells, n, kinv, vd, c);
+    for (int c = t; c < n; c += VSWEEP_BS) vanka_delta_item<T, T>(g, x, b, cells, n, sk, sd, c);
     __syncthreads();
-    for (int c = t; c < n; c += VSWEEP_BS) vanka_apply_item<T>(g, x, cells, n, vd, c);
+    for (int c = t; c < n; c += VSWEEP_BS) vanka_apply_item<T>(g, x, cells, n, sd, c);
     __syncthreads();
   }
 }

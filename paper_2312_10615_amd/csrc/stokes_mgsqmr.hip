@@ -383,6 +383,10 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
       a.doff[k] = lv.doff[k];
     }
     a.kinv = lv.kinv;
+    if (!a.additive && 4L * lv.g.field <= vsweep_lds_elems<T>()) {  // the state fits in LDS
+      launch(c, STOKES_KC_VANKA_DELTA, l, [=] { k_vanka_sweep_lds<T><<<1, VSWEEP_BS, 0, c->ks>>>(a, x, b); });
+      return;
+    }
     T* vd = (T*)c->vdelta;
     launch(c, STOKES_KC_VANKA_DELTA, l, [=] { k_vanka_sweep<T><<<1, VSWEEP_BS, 0, c->ks>>>(a, x, b, vd); });
     return;
