@@ -388,13 +388,20 @@ void b_vanka_symmetric(stokes_batch* c, int l) {
   }
 }
 
+// red neighbour update and black own step in one pass (over the black packs of the CL_PFOWN layout)
+template <typename T>
+void l_pf_nbr_own(stokes_batch* c, int l, int v) {
+  const Tab& t = c->tcls[CL_PFOWN][l][v];
+  if (!t.n) return;
+  BX_CASE(v, kb_dgs_pf_nbr_own<T, BXT><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done))
+}
+
 template <typename T>
 void b_dgs_forward(stokes_batch* c, int l) {
   for (int col = 0; col < 2; ++col) l_dgs<T>(c, CL_DGSU, l, c->bx[CL_DGSU][l], col);
-  for (int col = 0; col < 2; ++col) {
-    l_dgs<T>(c, CL_PFOWN, l, c->bx[CL_PFOWN][l], col);
-    l_dgs<T>(c, CL_PFNBR, l, c->bx[CL_PFNBR][l], col);
-  }
+  l_dgs<T>(c, CL_PFOWN, l, c->bx[CL_PFOWN][l], 0);
+  l_pf_nbr_own<T>(c, l, c->bx[CL_PFOWN][l]);
+  l_dgs<T>(c, CL_PFNBR, l, c->bx[CL_PFNBR][l], 1);
 }
 
 template <typename T>

@@ -144,6 +144,20 @@ __global__ __launch_bounds__(BS) void kb_dgs_pf_own(const BEnt* __restrict__ tab
     dgs_pf_own_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].dscr, rp);
 }
 
+// red neighbour update and black own step in one pass (dgs_pf_nbr_own_pack)
+template <typename T, int BX>
+__global__ __launch_bounds__(BS) void kb_dgs_pf_nbr_own(const BEnt* __restrict__ tab, int nent,
+                                                        const BLev* __restrict__ lev, const int* __restrict__ done) {
+  SG_BATCH_ENTRY();
+  const Geom g = lev[d].g;
+  constexpr int V = bpack<T>();
+  int m, J, K;
+  if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
+  RowPack<V> rp;
+  if (row_pack_at<V>(g, 0, m, J, K, rp))
+    dgs_pf_nbr_own_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].dscr, rp);
+}
+
 template <typename T, int BX>
 __global__ __launch_bounds__(BS) void kb_dgs_pf_nbr(const BEnt* __restrict__ tab, int nent,
                                                     const BLev* __restrict__ lev, const int* __restrict__ done,

@@ -286,6 +286,97 @@ __global__ __launch_bounds__(BS) void k_dgs_pf_nbr_v(Geom g, T* __restrict__ x, 
   if (row_pack<V>(g, colour, rp)) dgs_pf_nbr_pack<T, V>(g, x, dscr, rp);
 }
 
+// Part 2 for the red pressures followed by part 1 for the black ones, in one
+// pass over the black cells (red = colour 0): the black pressure takes the
+// red neighbours' -(eta/h^2) sum delta first (dgs_pf_nbr_pack for colour 0,
+// every active black cell), then a black V2 cell makes its own step from that
+// pressure (dgs_pf_own_pack for colour 1).  The same operations in the same
+// order as the two launches; the black step reads no red value that it
+// writes, and writes no value another thread reads.
+template <typename T, typename TB, int V>
+__device__ __forceinline__ void dgs_pf_nbr_own_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b,
+                                                    T* __restrict__ dscr, const RowPack<V>& rp) {
+  bool actn[V], acto[V];
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    actn[i] = i < rp.n && g.p_active(rp.I0 + 2 * i, rp.J, rp.K);
+    acto[i] = i < rp.n && g.p_v2(rp.I0 + 2 * i, rp.J, rp.K);
+    any = any || actn[i];
+  }
+  if (!any) return;
+  const int F = g.field;
+  T* ux = x;
+  T* uy = x + F;
+  T* uz = x + 2 * F;
+  T* p = x + 3 * F;
+  const int eo = rp.el(0);
+  Pack<T, V> P = ldp<T, V>(p + eo);
+  {
+    const Pack<T, V> dxm = ldp<T, V>(dscr + rp.el(-1)), dxp = ldp<T, V>(dscr + rp.el(1));
+    const Pack<T, V> dym = ldp<T, V>(dscr + rp.el(-g.sy)), dyp = ldp<T, V>(dscr + rp.el(g.sy));
+    const Pack<T, V> dzm = ldp<T, V>(dscr + rp.el(-g.sz)), dzp = ldp<T, V>(dscr + rp.el(g.sz));
+    const int J = rp.J, K = rp.K;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      if (!actn[i]) continue;
+      const int I = rp.I0 + 2 * i;
+      T sum = T(0);
+      if (g.p_v2(I - 1, J, K)) sum += dxm.v[i];
+      if (g.p_v2(I + 1, J, K)) sum += dxp.v[i];
+      if (g.p_v2(I, J - 1, K)) sum += dym.v[i];
+      if (g.p_v2(I, J + 1, K)) sum += dyp.v[i];
+      if (g.p_v2(I, J, K - 1)) sum += dzm.v[i];
+      if (g.p_v2(I, J, K + 1)) sum += dzp.v[i];
+      if (sum != T(0)) P.v[i] = P.v[i] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
+    }
+  }
+  bool anyo = false;
+#pragma unroll
+  for (int i = 0; i < V; ++i) anyo = anyo || acto[i];
+  if (anyo) {
+    const double ih2 = g.inv_h * g.inv_h;
+    const int ex = rp.el(1), ey = rp.el(g.sy), ez = rp.el(g.sz);
+    Pack<T, V> X0 = ldp<T, V>(ux + eo), X1 = ldp<T, V>(ux + ex);
+    Pack<T, V> Y0 = ldp<T, V>(uy + eo), Y1 = ldp<T, V>(uy + ey);
+    Pack<T, V> Z0 = ldp<T, V>(uz + eo), Z1 = ldp<T, V>(uz + ez);
+    const Pack<TB, V> Bp = ldp<TB, V>(b + 3 * F + eo);
+    Pack<T, V> D;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      D.v[i] = T(0);
+      if (!acto[i]) continue;
+      const T div = (X1.v[i] - X0.v[i]) + (Y1.v[i] - Y0.v[i]) + (Z1.v[i] - Z0.v[i]);
+      const T r = (T)Bp.v[i] - (-div * (T)g.inv_h - (T)g.gamma * P.v[i]);
+      const T delta = r / (T)(-6.0 * (1.0 + g.gamma * g.eta) * ih2);
+      D.v[i] = delta;
+      const T dh = delta * (T)g.inv_h;
+      X0.v[i] = X0.v[i] - dh;
+      X1.v[i] = X1.v[i] + dh;
+      Y0.v[i] = Y0.v[i] - dh;
+      Y1.v[i] = Y1.v[i] + dh;
+      Z0.v[i] = Z0.v[i] - dh;
+      Z1.v[i] = Z1.v[i] + dh;
+      P.v[i] = P.v[i] + (T)(6.0 * g.eta * ih2) * delta;
+    }
+    stp_cells<T, V>(dscr + eo, D, rp.n, acto);
+    stp_cells<T, V>(ux + eo, X0, rp.n, acto);
+    stp_cells<T, V>(ux + ex, X1, rp.n, acto);
+    stp_cells<T, V>(uy + eo, Y0, rp.n, acto);
+    stp_cells<T, V>(uy + ey, Y1, rp.n, acto);
+    stp_cells<T, V>(uz + eo, Z0, rp.n, acto);
+    stp_cells<T, V>(uz + ez, Z1, rp.n, acto);
+  }
+  stp_cells<T, V>(p + eo, P, rp.n, actn);
+}
+
+template <typename T, typename TB, int V>
+__global__ __launch_bounds__(BS) void k_dgs_pf_nbr_own_v(Geom g, T* __restrict__ x, const TB* __restrict__ b,
+                                                         T* __restrict__ dscr) {
+  RowPack<V> rp;
+  if (row_pack<V>(g, 0, rp)) dgs_pf_nbr_own_pack<T, TB, V>(g, x, b, dscr, rp);
+}
+
 // Reverse-sweep pressure step (dgs_pr_item, V cells): 13 wide loads of b and
 // 7 of p per pack.
 template <typename T, typename TB, int V>

@@ -444,11 +444,10 @@ void dgs_forward(stokes_ctx* c, int l, T* x, const T* b) {
   const int hg = dgs_grid<T>(g);
   for (int col = 0; col < 2; ++col)
     launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
-  for (int col = 0; col < 2; ++col) {
-    launch(c, STOKES_KC_DGS_PF_OWN, l,
-           [=] { k_dgs_pf_own_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, dscr, col); });
-    launch(c, STOKES_KC_DGS_PF_NBR, l, [=] { k_dgs_pf_nbr_v<T, V><<<hg, BS, 0, c->ks>>>(g, x, dscr, col); });
-  }
+  // red own step; red neighbour update and black own step in one pass; black neighbour update
+  launch(c, STOKES_KC_DGS_PF_OWN, l, [=] { k_dgs_pf_own_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, dscr, 0); });
+  launch(c, STOKES_KC_DGS_PF_OWN, l, [=] { k_dgs_pf_nbr_own_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, dscr); });
+  launch(c, STOKES_KC_DGS_PF_NBR, l, [=] { k_dgs_pf_nbr_v<T, V><<<hg, BS, 0, c->ks>>>(g, x, dscr, 1); });
 }
 
 // Reverse sweep: Gauss-Seidel on M^T L~ (Eq. ldist) in exactly the reverse
