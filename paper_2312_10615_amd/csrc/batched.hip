@@ -116,12 +116,13 @@ struct stokes_batch {
   int* count = nullptr;
   int* hcount = nullptr;  // pinned
   BScal* hsc = nullptr;   // pinned
-  void* vdelta = nullptr;
   // tables
   std::vector<BEnt> harena;
   BEnt* arena = nullptr;
   Tab tcls[NCLS][MAXL][NBX];
-  Tab tvec, tfield, tzero[MAXL], tcoarse[MAXL], tvanka[MAXL][8], tvapply[MAXL][8];
+  Tab tvec, tfield, tzero[MAXL], tcoarse[MAXL], tvanka[MAXL][8], tvapply[MAXL][8], tband[MAXL], tpp[MAXL][16];
+  bool vpp[MAXL] = {};  // level runs the two-copy Vanka passes (else delta and apply launches)
+  void* vdelta = nullptr;
   Tab tsweep[MAXL];  // boxes whose Vanka step on the level runs in one workgroup
   int bx[NCLS][MAXL];
   int chunk_first = 10, chunk = 2;
@@ -228,19 +229,36 @@ void carve(stokes_batch* c, Carve& cv) {
         b.kinv = cv.take<char>(64 * 64 * es);
         std::vector<int> cells[8];
         vanka_cells(b.g, cells);
+        bool small = true;
         for (int k = 0; k < 8; ++k) {
           b.nv[k] = (int)cells[k].size();
           b.vc[k] = cv.take<int>(std::max<size_t>(cells[k].size(), 1));
-          b.voff[k] = vsum[k];
-          vsum[k] += 8L * b.nv[k];
+          small = small && b.nv[k] <= VSWEEP_MAX_CLASS;
         }
+        if (!small)
+          for (int k = 0; k < 8; ++k) {
+            b.voff[k] = vsum[k];
+            vsum[k] += 8L * b.nv[k];
+          }
       } else {
         b.nc = (int)dofs(b.g);
         b.cinv = cv.take<double>((size_t)b.nc * b.nc);
         b.cdof = cv.take<int>(b.nc);
       }
     }
+    // two copies where every class, summed over the boxes, fits the eight-lane size of a
+    // single box's latency-bound levels; larger levels keep the delta and apply launches
+    c->vpp[l] = true;
+    for (int k = 0; k < 8; ++k) c->vpp[l] = c->vpp[l] && vsum[k] / 8 <= VANKA_LANES_MAX;
     for (int k = 0; k < 8; ++k) vmax = std::max(vmax, vsum[k]);
+    for (int d : c->all[l]) {
+      BLev& b = c->hlev[l][d];
+      if (c->vpp[l] && l + 1 < c->L[d]) {
+        bool small = true;
+        for (int k = 0; k < 8; ++k) small = small && b.nv[k] <= VSWEEP_MAX_CLASS;
+        if (!small) b.alt = cv.take<char>(4L * b.g.field * es);
+      }
+    }
   }
   c->vdelta = cv.take<char>(vmax * es);
   for (int l = 0; l < c->Lmax; ++l) {
@@ -319,10 +337,26 @@ void carve(stokes_batch* c, Carve& cv) {
     c->tsweep[l] = add_table(c, c->smooth[l], [&](int d) { return small(d) ? 1 : 0; });
     for (int k = 0; k < 8; ++k) {
       c->tvanka[l][k] = add_table(c, c->smooth[l], [&](int d) {
-        return small(d) ? 0 : (8 * c->hlev[l][d].nv[k] + BS - 1) / BS;
+        return c->vpp[l] || small(d) ? 0 : (8 * c->hlev[l][d].nv[k] + BS - 1) / BS;
       });
       c->tvapply[l][k] = add_table(c, c->smooth[l], [&](int d) {
-        return small(d) ? 0 : (c->hlev[l][d].nv[k] + BS - 1) / BS;
+        return c->vpp[l] || small(d) ? 0 : (c->hlev[l][d].nv[k] + BS - 1) / BS;
+      });
+    }
+    // two-copy passes: the band copy, then pass p of class k with the previous class kp
+    c->tband[l] = add_table(c, c->smooth[l], [&](int d) {
+      const Geom& g = c->hlev[l][d].g;
+      if (!c->vpp[l] || small(d)) return 0;
+      const long n = (g.nx < 8 || g.ny < 8 || g.nz < 8) ? 4L * g.field : vanka_band_slots(g);
+      return (int)((n + BS - 1) / BS);
+    });
+    for (int pass = 0; pass < 16; ++pass) {
+      const int k = vanka_pass_class(pass), kp = vanka_pass_prev(pass);
+      c->tpp[l][pass] = add_table(c, c->smooth[l], [&](int d) {
+        if (!c->vpp[l] || small(d)) return 0;
+        const BLev& b = c->hlev[l][d];
+        const int lanes = (8 * b.nv[k] + 63) / 64 * 64 + (kp >= 0 ? 8 * b.nv[kp] : 0);
+        return (lanes + BS - 1) / BS;
       });
     }
   }
@@ -378,13 +412,27 @@ template <typename T>
 void b_vanka_symmetric(stokes_batch* c, int l) {
   const Tab& ts = c->tsweep[l];
   if (ts.n) kb_vanka_sweep<T><<<ts.blocks, VSWEEP_BS, 0, c->ks>>>(c->tab(ts), ts.n, c->dlev[l], c->done);
+  if (!c->vpp[l]) {  // the other boxes: residual and correction launches per class pass
+    for (int pass = 0; pass < 16; ++pass) {
+      const int k = vanka_pass_class(pass);
+      const Tab& t = c->tvanka[l][k];
+      const Tab& ta = c->tvapply[l][k];
+      if (!t.n) continue;
+      kb_vanka_delta<T><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done, k, (T*)c->vdelta);
+      kb_vanka_apply<T><<<ta.blocks, BS, 0, c->ks>>>(c->tab(ta), ta.n, c->dlev[l], c->done, k,
+                                                     (const T*)c->vdelta);
+    }
+    return;
+  }
+  // or two copies of the state, one launch per class pass; 16 passes end in x
+  const Tab& tb = c->tband[l];
+  if (!tb.n) return;
+  kb_vanka_band<T><<<tb.blocks, BS, 0, c->ks>>>(c->tab(tb), tb.n, c->dlev[l], c->done);
   for (int pass = 0; pass < 16; ++pass) {
-    const int k = pass < 8 ? pass : 15 - pass;
-    const Tab& t = c->tvanka[l][k];
-    const Tab& ta = c->tvapply[l][k];
+    const Tab& t = c->tpp[l][pass];
     if (!t.n) continue;
-    kb_vanka_delta<T><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done, k, (T*)c->vdelta);
-    kb_vanka_apply<T><<<ta.blocks, BS, 0, c->ks>>>(c->tab(ta), ta.n, c->dlev[l], c->done, k, (const T*)c->vdelta);
+    kb_vanka_pp<T><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done, vanka_pass_class(pass),
+                                               vanka_pass_prev(pass), pass & 1);
   }
 }
 

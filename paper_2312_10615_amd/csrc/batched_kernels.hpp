@@ -26,6 +26,7 @@ struct BLev {
   void* xc;                // next level's x and b
   void* bc;
   const void* kinv;        // Vanka inverses of this level
+  void* alt;               // second copy of x for the two-copy Vanka passes (boxes not run in one workgroup)
   const int* vc[8];        // V1 cells per colour
   int nv[8];
   long voff[8];            // this domain's slice of the shared Vanka delta buffer, per colour
@@ -226,6 +227,55 @@ __global__ __launch_bounds__(BS) void kb_vanka_apply(const BEnt* __restrict__ ta
   const Geom g = lev[d].g;
   vanka_apply_item<T>(g, (T*)lev[d].x, lev[d].vc[colour], lev[d].nv[colour], delta + lev[d].voff[colour],
                       lb * BS + (int)threadIdx.x);
+}
+
+// Two-copy Vanka pass of class k for every box (k_vanka_pp8; levels whose
+// classes, summed over the boxes, are small enough for the passes to be
+// latency chains): reads copy
+// `rd` (0: x, 1: alt), writes the other; lanes [0, copy0) take the class-k
+// cells eight lanes each (copy0 = 8 nv[k] rounded up to whole waves), the
+// rest copy the previous class kp's corrections (kp < 0: none).
+template <typename T>
+__global__ __launch_bounds__(BS) void kb_vanka_pp(const BEnt* __restrict__ tab, int nent, const BLev* __restrict__ lev,
+                                                  const int* __restrict__ done, int k, int kp, int rd) {
+  SG_BATCH_ENTRY();
+  const Geom g = lev[d].g;
+  const T* R = (const T*)(rd ? lev[d].alt : lev[d].x);
+  T* W = (T*)(rd ? lev[d].x : lev[d].alt);
+  const int n = lev[d].nv[k];
+  const int copy0 = (8 * n + 63) / 64 * 64;
+  const int t = lb * BS + (int)threadIdx.x;
+  if (t < copy0) {
+    const T dv = vanka_delta8_lane<T, T>(g, R, (const T*)lev[d].b, lev[d].vc[k], n, (const T*)lev[d].kinv, t);
+    const int c = t >> 3, r = t & 7;
+    if (c < n && r < 7) {
+      const int s = lev[d].vc[k][c];
+      int I, J, K;
+      slot_ijk(g, s, I, J, K);
+      const VankaDof dof = vanka_dof(g, s, I, J, K, r);
+      if (dof.active) W[dof.e] = R[dof.e] + dv;
+    }
+  } else if (kp >= 0) {
+    const int u = t - copy0, c = u >> 3, r = u & 7;
+    if (c < lev[d].nv[kp] && r < 7) vanka_copy_dof<T>(g, R, W, lev[d].vc[kp][c], r, k);
+  }
+}
+
+// alt = x on the boundary band of every box (k_vanka_band_copy), or on the
+// whole state of a box with a side below 8
+template <typename T>
+__global__ __launch_bounds__(BS) void kb_vanka_band(const BEnt* __restrict__ tab, int nent, const BLev* __restrict__ lev,
+                                                    const int* __restrict__ done) {
+  SG_BATCH_ENTRY();
+  const Geom g = lev[d].g;
+  const T* R = (const T*)lev[d].x;
+  T* W = (T*)lev[d].alt;
+  const long t = (long)lb * BS + threadIdx.x;
+  if (g.nx < 8 || g.ny < 8 || g.nz < 8) {
+    if (t < 4L * g.field) W[t] = R[t];
+    return;
+  }
+  vanka_band_copy_item<T>(g, R, W, t);
 }
 
 // The whole symmetric Vanka step of one small box in one 1024-thread

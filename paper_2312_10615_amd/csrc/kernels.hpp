@@ -433,6 +433,14 @@ __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, c
 // first copy.
 // ---------------------------------------------------------------------------
 
+// Symmetric order of the 8 classes (0..7, 7..0): the class of pass p, and the
+// class whose corrections pass p copies (none for the first pass and for the
+// second of the two class-7 passes, which rewrites all of its unknowns).
+__host__ __device__ inline int vanka_pass_class(int pass) { return pass < 8 ? pass : 15 - pass; }
+__host__ __device__ inline int vanka_pass_prev(int pass) {
+  return pass == 0 || pass == 8 ? -1 : vanka_pass_class(pass - 1);
+}
+
 // Element (in a state vector) of local unknown r of the subdomain of cell
 // (I, J, K) at slot s, whether it is an unknown, and the cell across it.
 struct VankaDof {
@@ -505,8 +513,7 @@ __host__ __device__ inline long vanka_band_slots(const Geom& g) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(BS) void k_vanka_band_copy(Geom g, const T* __restrict__ R, T* __restrict__ W) {
-  const long t = (long)blockIdx.x * BS + threadIdx.x;
+__device__ __forceinline__ void vanka_band_copy_item(const Geom& g, const T* __restrict__ R, T* __restrict__ W, long t) {
   const long full = 8L * (g.ny + 2) + 8L * (g.nz - 6);
   const long nA = full * (g.nx + 2);
   int I, J, K;
@@ -534,6 +541,11 @@ __global__ __launch_bounds__(BS) void k_vanka_band_copy(Geom g, const T* __restr
   const int e = g.at(g.idx(I, J, K));
 #pragma unroll
   for (int f = 0; f < 4; ++f) W[f * g.field + e] = R[f * g.field + e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_vanka_band_copy(Geom g, const T* __restrict__ R, T* __restrict__ W) {
+  vanka_band_copy_item<T>(g, R, W, (long)blockIdx.x * BS + threadIdx.x);
 }
 
 // A whole Vanka smoothing step on a small level in one workgroup: the class

@@ -396,7 +396,7 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
     for (int k = 0; k < nc; ++k) vanka_correct<T>(c, l, x, k);
     return;
   }
-  if (lv.pp) {  // two copies of the state; 2 nc (even) passes end in x
+  if (lv.pp) {  // two copies of the state; the 16 passes end in x
     const Geom g = lv.g;
     T* X[2] = {x, (T*)lv.alt};
     T* alt = X[1];
@@ -408,16 +408,14 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
       launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_convert<T, T><<<RED_BLOCKS, BS, 0, c->ks>>>(x, alt, n); });
     }
     const T* kinv = (const T*)lv.kinv;
-    int kp = -1;
-    for (int pass = 0; pass < 2 * nc; ++pass) {
-      const int k = pass < nc ? pass : 2 * nc - 1 - pass;
+    for (int pass = 0; pass < 16; ++pass) {
+      const int k = vanka_pass_class(pass), kp = vanka_pass_prev(pass);
       const int n = lv.nv[k];
-      const int np = kp >= 0 && kp != k ? lv.nv[kp] : 0;  // same class twice: it rewrites all of its unknowns
+      const int np = kp >= 0 ? lv.nv[kp] : 0;
       const int* cells = lv.vcells[k];
       const int* prev = kp >= 0 ? lv.vcells[kp] : cells;
       const T* R = X[pass & 1];
       T* W = X[(pass + 1) & 1];
-      kp = k;
       if (n == 0 && np == 0) continue;
       const int copy0 = (8 * n + 63) / 64 * 64;
       const int nb = (copy0 + 8 * np + BS - 1) / BS;

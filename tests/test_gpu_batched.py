@@ -14,6 +14,12 @@ from tests.gpu_helpers import announce, cuda, forcing_rhs, rel_err
 pytestmark = pytest.mark.gpu
 
 DIMS = [(8, 8, 8), (16, 8, 12), (12, 16, 8), (16, 16, 16), (8, 12, 16), (24, 8, 16), (6, 10, 8)]
+# Vanka forms on the largest level: DIMS run each box's step in one workgroup
+# (classes of at most 512 cells); MID the two-copy passes (classes summed over
+# the boxes within 16384 cells); BIG the residual and correction launches
+# (summed classes above that), with the two-copy passes one level down.
+MID = [(32, 32, 32), (48, 32, 40), (16, 16, 16)]
+BIG = [(128, 128, 128), (128, 128, 128)]
 H = 1.0 / 16
 
 
@@ -36,15 +42,16 @@ def _oracle_relres(dom, x, b):
     return np.sqrt(sum(float(np.sum(v ** 2)) for v in r)) / np.sqrt(sum(float(np.sum(v ** 2)) for v in b))
 
 
-@pytest.mark.parametrize("precision", [64, 32])
-def test_batch_matches_single_box_solves(precision):
+@pytest.mark.parametrize("precision,dims", [(64, DIMS), (32, DIMS), (64, MID), (32, MID), (64, BIG), (32, BIG)],
+                         ids=["small-fp64", "small-fp32", "mid-fp64", "mid-fp32", "big-fp64", "big-fp32"])
+def test_batch_matches_single_box_solves(precision, dims):
     cuda()
     from paper_2312_10615_amd.stokes import StokesSolver
-    announce(f"batched solve, {len(DIMS)} boxes, V-cycle FP{precision}")
-    bt, rhs, doms = _batch_problem(precision)
+    announce(f"batched solve, boxes {dims}, V-cycle FP{precision}")
+    bt, rhs, doms = _batch_problem(precision, dims=dims)
     b = bt.pack(rhs)
     x, infos = bt.solve(b, rtol=1e-8, maxit=100)
-    for d, dm in enumerate(DIMS):
+    for d, dm in enumerate(dims):
         lay = bt.layouts[d]
         single = StokesSolver(*dm, h=H, precision=precision, levels=lay.levels)
         xs, info = single.solve(single.pack(rhs[d]), rtol=1e-8, maxit=100)
