@@ -342,6 +342,32 @@ __device__ __forceinline__ void vanka_apply_item(const Geom& g, T* __restrict__ 
 // latency chain this form finishes sooner.  Output as above.  Lane t of the
 // class (t & 7 must equal threadIdx.x & 7, and the eight lanes of a subdomain
 // share a wave); every lane of the wave must call it (shuffles).
+// Local residual row r (0..6, as in vanka_delta_vals) of the subdomain of
+// cell (I, J, K) at slot s; zero for an inactive row, r = 7 or !valid.
+template <typename T, typename TB>
+__device__ __forceinline__ T vanka_row_residual(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b, int s,
+                                                int I, int J, int K, int r, bool valid) {
+  const int F = g.field;
+  const T* ux = x;
+  const T* uy = x + F;
+  const T* uz = x + 2 * F;
+  const T* p = x + 3 * F;
+  T res = T(0);
+  if (valid) {
+    switch (r) {
+      case 0: if (I >= 2) res = (T)b[g.at(s)] - row_u(g, ux, p, s, 1); break;
+      case 1: if (I + 1 <= g.nx) res = (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1); break;
+      case 2: if (J >= 2) res = (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy); break;
+      case 3: if (J + 1 <= g.ny) res = (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy); break;
+      case 4: if (K >= 2) res = (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz); break;
+      case 5: if (K + 1 <= g.nz) res = (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz); break;
+      case 6: res = (T)b[3 * F + g.at(s)] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
+      default: break;
+    }
+  }
+  return res;
+}
+
 template <typename T, typename TB>
 __device__ __forceinline__ T vanka_delta8_lane(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
                                                const int* __restrict__ cells, int ncells, const T* __restrict__ kinv,
@@ -352,33 +378,20 @@ __device__ __forceinline__ T vanka_delta8_lane(const Geom& g, const T* __restric
   const int s = valid ? cells[c] : 0;
   int I = 1, J = 1, K = 1;
   if (valid) slot_ijk(g, s, I, J, K);
-  const int F = g.field;
-  const T* ux = x;
-  const T* uy = x + F;
-  const T* uz = x + 2 * F;
-  const T* p = x + 3 * F;
+  // this lane's row of the local inverse is loaded before the residual
   const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
-  T res = T(0);
-  if (valid) {
-    switch (r) {
-      case 0: if (a0) res = (T)b[g.at(s)] - row_u(g, ux, p, s, 1); break;
-      case 1: if (a1) res = (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1); break;
-      case 2: if (a2) res = (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy); break;
-      case 3: if (a3) res = (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy); break;
-      case 4: if (a4) res = (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz); break;
-      case 5: if (a5) res = (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz); break;
-      case 6: res = (T)b[3 * F + g.at(s)] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
-      default: break;
-    }
-  }
   const int type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
   const T* km = kinv + type * 64 + r * 8;
+  T kr[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) kr[j] = km[j];
+  const T res = vanka_row_residual<T, TB>(g, x, b, s, I, J, K, r, valid);
   const int base = (int)(threadIdx.x & 63) & ~7;
   T acc = T(0);
 #pragma unroll
   for (int j = 0; j < 7; ++j) {
     const T rj = __shfl(res, base + j, 64);
-    acc += km[j] * rj;
+    acc += kr[j] * rj;
   }
   return acc;
 }
@@ -486,15 +499,31 @@ __global__ __launch_bounds__(BS) void k_vanka_pp8(Geom g, const T* __restrict__ 
                                                   int k, int copy0) {
   const int t = blockIdx.x * BS + threadIdx.x;
   if (t < copy0) {  // whole waves: the shuffles see only this part's lanes
-    const T d = vanka_delta8_lane<T, TB>(g, R, b, cells, ncells, kinv, t);
     const int c = t >> 3, r = t & 7;
-    if (c < ncells && r < 7) {
-      const int s = cells[c];
-      int I, J, K;
-      slot_ijk(g, s, I, J, K);
-      const VankaDof dof = vanka_dof(g, s, I, J, K, r);
-      if (dof.active) W[dof.e] = R[dof.e] + d;
+    const bool valid = c < ncells;
+    const int s = valid ? cells[c] : 0;
+    int I = 1, J = 1, K = 1;
+    if (valid) slot_ijk(g, s, I, J, K);
+    // loads that need only the cell go out before the residual and its shuffles:
+    // this lane's row of the local inverse and the value it corrects
+    const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
+    const int type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
+    const T* km = kinv + type * 64 + r * 8;
+    T kr[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) kr[j] = km[j];
+    const VankaDof dof = vanka_dof(g, s, I, J, K, r < 7 ? r : 6);
+    const bool wr = valid && r < 7 && dof.active;
+    const T old = wr ? R[dof.e] : T(0);
+    const T res = vanka_row_residual<T, TB>(g, R, b, s, I, J, K, r, valid);
+    const int base = (int)(threadIdx.x & 63) & ~7;
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      const T rj = __shfl(res, base + j, 64);
+      acc += kr[j] * rj;
     }
+    if (wr) W[dof.e] = old + acc;
   } else {
     const int u = t - copy0, c = u >> 3, r = u & 7;
     if (c < nprev && r < 7) vanka_copy_dof<T>(g, R, W, prev[c], r, k);
