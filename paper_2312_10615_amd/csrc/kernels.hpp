@@ -1,8 +1,10 @@
-// gfx950 kernels of the MG-SQMR hot path.  Bandwidth-bound stencil work:
-// no matrix cores, wave64 shuffles for reductions, padded x-fastest layout
-// (geom.hpp), one thread per slot, and block indices remapped so that each
-// of the 8 XCDs walks a contiguous slab of the grid (its L2 then serves the
-// y- and z-neighbour rows of its own rows).
+// gfx950 kernels of the MG-SQMR hot path.  Bandwidth- and latency-bound
+// stencil work: no matrix cores, wave64 shuffles for reductions and the Vanka
+// products, the padded red/black layout of geom.hpp, and block indices
+// remapped so that each of the 8 XCDs walks a contiguous slab of the grid
+// (its L2 then serves the y- and z-neighbour rows of its own rows).  The
+// one-cell items here are the reference arithmetic; packed_kernels.hpp
+// computes the hot ones with V cells per thread.
 #pragma once
 
 #include <hip/hip_runtime.h>

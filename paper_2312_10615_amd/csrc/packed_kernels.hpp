@@ -1,7 +1,8 @@
-// Distributive Gauss-Seidel (Alg. 2, Eq. dist, Eq. ldist) with V cells per
-// thread for the single-box solver.  The kernels compute exactly what the
-// one-cell items in kernels.hpp compute, cell by cell and in the same order
-// of operations; only the memory access is different.
+// The hot stencil passes with V cells per thread, for the single box and the
+// batch: the distributive Gauss-Seidel steps (Alg. 2, Eq. dist, Eq. ldist)
+// and the operator passes (Eq. 2).  They compute what the one-cell items in
+// kernels.hpp compute, cell by cell and in the same order of operations;
+// only the memory access is different.
 //
 // With the red/black split every stencil neighbour of a slot of parity par
 // sits in the other half, at an element shifted by a constant: slot s + o of

@@ -26,10 +26,29 @@ import os
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def kernel_source_hash():
+def code_lines(text):
+    """Source text without // comments, trailing blanks and empty lines: what
+    the counters depend on."""
+    out = []
+    for line in text.splitlines():
+        i = line.find("//")
+        if i >= 0:
+            line = line[:i]
+        line = line.rstrip()
+        if line:
+            out.append(line)
+    return "\n".join(out)
+
+
+def kernel_source_hash(read=None):
+    """Hash of the level-0 kernels' code (comments excluded); `read(name)`
+    returns a source file's text (default: the files in this tree)."""
+    if read is None:
+        def read(f):
+            return open(os.path.join(ROOT, "paper_2312_10615_amd", "csrc", f)).read()
     h = hashlib.sha256()
     for f in ("geom.hpp", "kernels.hpp", "packed_kernels.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2312_10615_amd", "csrc", f), "rb").read())
+        h.update(code_lines(read(f)).encode())
     return h.hexdigest()[:16]
 
 
