@@ -1059,11 +1059,17 @@ __global__ __launch_bounds__(BS) void k_convert(const Ti* __restrict__ in, To* _
 // partial[2*blk] = sum a.a, partial[2*blk+1] = sum a.c
 static __global__ __launch_bounds__(BS) void k_dot_aa_ac(const double* __restrict__ a, const double* __restrict__ c, long n,
                                                   double* __restrict__ partial) {
+  // n is even (whole fields of a multiple of 8 elements): 16-byte accesses
+  typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));
+  const d2* a2 = (const d2*)a;
+  const d2* c2 = (const d2*)c;
   double s0 = 0.0, s1 = 0.0;
-  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
-    const double av = a[i];
-    s0 += av * av;
-    s1 += av * c[i];
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n / 2; i += (long)gridDim.x * BS) {
+    const d2 av = a2[i], cv = c2[i];
+    s0 += av.x * av.x;
+    s0 += av.y * av.y;
+    s1 += av.x * cv.x;
+    s1 += av.y * cv.y;
   }
   const double t0 = block_sum(s0);
   const double t1 = block_sum(s1);
@@ -1111,7 +1117,16 @@ static __global__ __launch_bounds__(BS) void k_clear_ghosts(Geom g, double* __re
 // s -= a * t
 static __global__ __launch_bounds__(BS) void k_axpy_neg(double* __restrict__ s, const double* __restrict__ t, long n,
                                                  double a) {
-  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) s[i] -= a * t[i];
+  typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));  // n even: 16-byte accesses
+  d2* s2 = (d2*)s;
+  const d2* t2 = (const d2*)t;
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n / 2; i += (long)gridDim.x * BS) {
+    d2 sv = s2[i];
+    const d2 tv = t2[i];
+    sv.x -= a * tv.x;
+    sv.y -= a * tv.y;
+    s2[i] = sv;
+  }
 }
 
 // d = cd * d + cq * q;  x += d;  q = t + beta * q (the next direction, from the
@@ -1119,12 +1134,25 @@ static __global__ __launch_bounds__(BS) void k_axpy_neg(double* __restrict__ s, 
 static __global__ __launch_bounds__(BS) void k_update_dxq(double* __restrict__ d, double* __restrict__ q,
                                                    double* __restrict__ x, const double* __restrict__ t, long n,
                                                    double cd, double cq, double bt) {
-  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
-    const double qv = q[i];
-    const double dv = cd * d[i] + cq * qv;
-    d[i] = dv;
-    x[i] += dv;
-    q[i] = t[i] + bt * qv;
+  typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));  // n even: 16-byte accesses
+  d2* d_ = (d2*)d;
+  d2* q_ = (d2*)q;
+  d2* x_ = (d2*)x;
+  const d2* t_ = (const d2*)t;
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n / 2; i += (long)gridDim.x * BS) {
+    const d2 qv = q_[i], dold = d_[i], tv = t_[i];
+    d2 xv = x_[i];
+    d2 dv;
+    dv.x = cd * dold.x + cq * qv.x;
+    dv.y = cd * dold.y + cq * qv.y;
+    d_[i] = dv;
+    xv.x += dv.x;
+    xv.y += dv.y;
+    x_[i] = xv;
+    d2 qn;
+    qn.x = tv.x + bt * qv.x;
+    qn.y = tv.y + bt * qv.y;
+    q_[i] = qn;
   }
 }
 
