@@ -227,11 +227,13 @@ int stokes_solve(stokes_ctx* ctx, const double* b, double* x, double rtol, int32
 enum {
   STOKES_KC_APPLY = 0,        /* operator / residual / residual-norm passes */
   STOKES_KC_DGS_U = 1,        /* velocity Gauss-Seidel half sweep (one colour) */
-  STOKES_KC_DGS_PF_OWN = 2,   /* forward pressure step, own cell */
-  STOKES_KC_DGS_PF_NBR = 3,   /* forward pressure step, neighbours */
+  STOKES_KC_DGS_PF_OWN = 2,   /* forward pressure step, own cell (the red one; the black one fused with
+                                 the red neighbour update) */
+  STOKES_KC_DGS_PF_NBR = 3,   /* forward pressure step, neighbours of the black cells */
   STOKES_KC_DGS_PR = 4,       /* reverse (left-preconditioned) pressure step */
-  STOKES_KC_VANKA_DELTA = 5,  /* Vanka local solves of one colour */
-  STOKES_KC_VANKA_APPLY = 6,  /* Vanka corrections of one colour */
+  STOKES_KC_VANKA_DELTA = 5,  /* Vanka local solves of one colour (with their corrections on levels that
+                                 keep two copies of the state; a whole Vanka step on small levels) */
+  STOKES_KC_VANKA_APPLY = 6,  /* Vanka corrections of one colour, or the second copy's band update */
   STOKES_KC_RESTRICT = 7,
   STOKES_KC_PROLONG = 8,
   STOKES_KC_COARSE = 9,
