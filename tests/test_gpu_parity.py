@@ -24,7 +24,8 @@ from tests.gpu_helpers import announce, cuda, forcing_rhs, max_rel, random_field
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dims", [(32, 32, 32), (24, 16, 40), (6, 10, 8), (2, 2, 2)])
+# (96, 48, 32): a larger ragged box
+@pytest.mark.parametrize("dims", [(32, 32, 32), (24, 16, 40), (6, 10, 8), (2, 2, 2), (96, 48, 32)])
 @pytest.mark.parametrize("penalized", [0, 1])
 def test_operator_apply_matches_oracle(dims, penalized):
     torch = cuda()
@@ -49,6 +50,8 @@ def test_operator_apply_matches_oracle(dims, penalized):
                                                     ((32, 32, 32), 0, 2, 2, "split"),
                                                     # level-0 classes of ~20k cells: one thread per subdomain
                                                     ((256, 256, 32), 5, 2, 1, "split"),
+                                                    # a larger ragged box
+                                                    ((96, 48, 32), 0, 2, 1, "split"),
                                                     ((32, 32, 32), 0, 2, 1, "symmetric"),
                                                     ((16, 24, 8), 0, 4, 2, "symmetric")])
 def test_vcycle_matches_oracle(dims, levels, nu, nb, sched):
