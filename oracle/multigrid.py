@@ -8,17 +8,20 @@ linear in s (Section 3).
 
 Smoothing schedules.  `nu` counts DGS sweeps per smoothing phase (a
 "sweep" is one directional pass, Section 3.1), so nu = 2 is "2 pre / 2 post".
-  * "symmetric" - the paper's choice (Section 3): the same symmetric smoother
-    in both phases, Alg. 3 applied nu/2 times, each with one symmetric DGS
-    (forward sweep on L M, Eq. dist, then reverse sweep on M^T L, Eq. ldist).
+  * "symmetric" (default) - the paper's choice (Section 3): the same
+    symmetric smoother in both phases, Alg. 3 applied nu/2 times, each with
+    one symmetric DGS (forward sweep on L M, Eq. dist, then reverse sweep on
+    M^T L, Eq. ldist).
   * "split" - the other arrangement Section 3 allows: different smoothers in
     the two phases whose matrices are transposes of each other.  Pre-smoothing
     is Alg. 3 with nu reverse sweeps on V2, post-smoothing Alg. 3 with nu
     forward sweeps; the reverse sweep's error propagator is the L~-adjoint of
     the forward sweep's, symmetric Vanka is L~-self-adjoint, so the pair meets
-    the transpose condition and W stays symmetric.  Measured: with the same
-    work per level it contracts where "symmetric" does not (the product of a
-    forward and a reverse sweep amplifies the lowest V2 pressure modes).
+    the transpose condition and W stays symmetric.
+`order` is the DGS pressure traversal (smoother.pressure_classes): the eight
+colour classes by default; with red/black pressures the "symmetric" schedule
+loses its grid independence (a forward-then-reverse pair amplifies smooth
+interior pressure modes) and only "split" converges well.
 Reading (levels): with levels = 0 the hierarchy halves every axis while all
 axes are even and every halved axis keeps at least 4 cells; an explicit
 level count may go down to 2 cells per axis.
@@ -36,7 +39,7 @@ import numpy as np
 
 from .domain import Domain, box_labels
 from .operator import apply_operator, assemble, from_vector, residual, to_vector, zeros_like_state
-from .smoother import dgs_diagonals, dgs_forward, dgs_reverse, smooth
+from .smoother import PRESSURE_ORDERS, dgs_diagonals, dgs_forward, dgs_reverse, smooth
 from .transfer import prolong, restrict
 
 
@@ -57,8 +60,8 @@ def max_levels(dims) -> int:
 class Hierarchy:
     """Levels 0 (finest) .. levels-1 (coarsest) of a box domain."""
 
-    def __init__(self, dims, h, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1, schedule="split",
-                 vanka="mult8", cycle=1):
+    def __init__(self, dims, h, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1, schedule="symmetric",
+                 vanka="mult8", cycle=1, order="c8"):
         if levels == 0:
             levels = auto_levels(dims)
         if levels < 1 or levels > max_levels(dims):
@@ -67,7 +70,9 @@ class Hierarchy:
             raise ValueError("bad smoothing schedule")
         if vanka not in ("mult8", "mult27", "additive") or cycle not in (1, 2):
             raise ValueError("bad smoother variant or cycle")
-        self.nu, self.n_boundary, self.schedule = nu, n_boundary, schedule
+        if order not in PRESSURE_ORDERS:
+            raise ValueError("bad DGS pressure order")
+        self.nu, self.n_boundary, self.schedule, self.order = nu, n_boundary, schedule, order
         self.vanka, self.cycle = vanka, cycle
         self.doms = [Domain(box_labels(dims), h, eta, gamma)]
         for _ in range(levels - 1):
@@ -102,10 +107,10 @@ def vcycle(H: Hierarchy, b, level: int = 0, x=None):
     return postsmooth(H, level, x, b)
 
 
-def _sweeps(sweep, k):
+def _sweeps(sweep, k, order):
     def interior(dom, x, b, diags):
         for _ in range(k):
-            x = sweep(dom, x, b, diags)
+            x = sweep(dom, x, b, diags, order)
         return x
     return interior
 
@@ -114,18 +119,18 @@ def presmooth(H: Hierarchy, level: int, x, b):
     dom, diags = H.doms[level], H.diags[level]
     if H.schedule == "symmetric":
         for _ in range(H.nu // 2):
-            x = smooth(dom, x, b, H.n_boundary, diags, vanka=H.vanka)
+            x = smooth(dom, x, b, H.n_boundary, diags, vanka=H.vanka, order=H.order)
         return x
-    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_reverse, H.nu), vanka=H.vanka)
+    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_reverse, H.nu, H.order), vanka=H.vanka)
 
 
 def postsmooth(H: Hierarchy, level: int, x, b):
     dom, diags = H.doms[level], H.diags[level]
     if H.schedule == "symmetric":
         for _ in range(H.nu // 2):
-            x = smooth(dom, x, b, H.n_boundary, diags, vanka=H.vanka)
+            x = smooth(dom, x, b, H.n_boundary, diags, vanka=H.vanka, order=H.order)
         return x
-    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_forward, H.nu), vanka=H.vanka)
+    return smooth(dom, x, b, H.n_boundary, diags, _sweeps(dgs_forward, H.nu, H.order), vanka=H.vanka)
 
 
 def apply_L(H: Hierarchy, x):

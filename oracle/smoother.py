@@ -67,55 +67,81 @@ def dgs_diagonals(dom: Domain):
     return d_u, d_p
 
 
-def dgs_forward(dom: Domain, x, b, diags=None):
+PRESSURE_ORDERS = ("c8", "rb")
+
+
+def pressure_classes(dom: Domain, order: str = "c8"):
+    """The V2 pressure cells in forward traversal order, as a list of masks.
+
+    Reading (traversal order): the paper leaves the order in which Alg. 2
+    visits the unknowns open (the reverse sweep only has to run it
+    backwards).  Velocities go red,
+    black by lattice parity.  Pressures go by the 8 colour classes of the
+    paper's parallel Vanka scheme (Section 6), class (i&1) + 2(j&1) + 4(k&1),
+    taken 0..7 ("c8").  Cells of one class are never face neighbours, so a
+    class updates at once.  Red/black pressures ("rb") are kept as the
+    alternative: with them the forward-then-reverse pair of the symmetric
+    smoother amplifies smooth interior pressure modes, while with the eight
+    classes (as with a lexicographic order) it does not.
+    """
+    if order == "c8":
+        col = dom.vanka_colour(2)
+        return [dom.v2[3] & (col == k) for k in range(8)]
+    if order == "rb":
+        par = dom.parity(3)
+        return [dom.v2[3] & (par == k) for k in range(2)]
+    raise ValueError(order)
+
+
+def _velocity_class(dom: Domain, x, b, colour, d_u):
+    r = residual(dom, x, b, dom.gamma)
+    return tuple(np.where(dom.v2[a] & (dom.parity(a) == colour), x[a] + r[a] / np.where(d_u[a] != 0, d_u[a], 1.0), x[a])
+                 for a in range(3)) + (x[3],)
+
+
+def dgs_forward(dom: Domain, x, b, diags=None, order: str = "c8"):
     """One DGS sweep over the V2 unknowns (Alg. 2 with the right preconditioning of Eq. dist).
 
     Reading (order): L M is block lower triangular (Eq. disc), so the sweep is
-    a block forward substitution: all velocities first, then all pressures.
-    Each block goes red ((i+j+k) even) then black.  A velocity update is the
-    plain Gauss-Seidel step (velocity columns of M are unit vectors); a
-    pressure update moves x along the column m_j of M.
+    a block forward substitution: all velocities first (red, then black),
+    then all pressures (classes of `pressure_classes` in order).  A velocity
+    update is the plain Gauss-Seidel step (velocity columns of M are unit
+    vectors); a pressure update moves x along the column m_j of M.
     """
     d_u, d_p = diags if diags is not None else dgs_diagonals(dom)
-    gam = dom.gamma
     x = tuple(v.copy() for v in x)
     for colour in (0, 1):
-        r = residual(dom, x, b, gam)
-        x = tuple(np.where(dom.v2[a] & (dom.parity(a) == colour), x[a] + r[a] / np.where(d_u[a] != 0, d_u[a], 1.0), x[a])
-                  for a in range(3)) + (x[3],)
-    for colour in (0, 1):
-        r = residual(dom, x, b, gam)
-        sel = dom.v2[3] & (dom.parity(3) == colour) & (d_p != 0)
+        x = _velocity_class(dom, x, b, colour, d_u)
+    for cls in pressure_classes(dom, order):
+        r = residual(dom, x, b, dom.gamma)
+        sel = cls & (d_p != 0)
         delta = np.where(sel, r[3] / np.where(d_p != 0, d_p, 1.0), 0.0)
         dx = distribute(dom, delta)
         x = tuple(v + dv for v, dv in zip(x, dx))
     return x
 
 
-def dgs_reverse(dom: Domain, x, b, diags=None):
+def dgs_reverse(dom: Domain, x, b, diags=None, order: str = "c8"):
     """Gauss-Seidel on the left-preconditioned system M^T L~ (Eq. ldist), rows of V2, in
-    exactly the reverse order of `dgs_forward`: pressures black, red, then
-    velocities black, red.  Each step updates its own unknown by
+    exactly the reverse order of `dgs_forward`: pressure classes last to
+    first, then velocities black, red.  Each step updates its own unknown by
     (M^T r)_j / d_j; for velocities (M^T)_j = e_j^T."""
     d_u, d_p = diags if diags is not None else dgs_diagonals(dom)
-    gam = dom.gamma
     x = tuple(v.copy() for v in x)
-    for colour in (1, 0):
-        r = residual(dom, x, b, gam)
+    for cls in reversed(pressure_classes(dom, order)):
+        r = residual(dom, x, b, dom.gamma)
         rt = collect(dom, r)
-        sel = dom.v2[3] & (dom.parity(3) == colour) & (d_p != 0)
+        sel = cls & (d_p != 0)
         x = x[:3] + (x[3] + np.where(sel, rt / np.where(d_p != 0, d_p, 1.0), 0.0),)
     for colour in (1, 0):
-        r = residual(dom, x, b, gam)
-        x = tuple(np.where(dom.v2[a] & (dom.parity(a) == colour), x[a] + r[a] / np.where(d_u[a] != 0, d_u[a], 1.0), x[a])
-                  for a in range(3)) + (x[3],)
+        x = _velocity_class(dom, x, b, colour, d_u)
     return x
 
 
-def dgs_symmetric(dom: Domain, x, b, diags=None):
+def dgs_symmetric(dom: Domain, x, b, diags=None, order: str = "c8"):
     """Symmetric DGS (Section 3.1, Appendix A): forward sweep, then reverse."""
     diags = diags if diags is not None else dgs_diagonals(dom)
-    return dgs_reverse(dom, dgs_forward(dom, x, b, diags), b, diags)
+    return dgs_reverse(dom, dgs_forward(dom, x, b, diags, order), b, diags, order)
 
 
 # ---------------------------------------------------------------------------
@@ -238,7 +264,7 @@ def vanka_apply(dom: Domain, x, b, kind: str = "mult8"):
     raise ValueError(kind)
 
 
-def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None, interior=None, vanka: str = "mult8"):
+def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None, interior=None, vanka: str = "mult8", order: str = "c8"):
     """Alg. 3: symmetric Vanka on V1, an interior smoother on V2, symmetric
     Vanka on V1.  The interior smoother defaults to the symmetric DGS of
     Section 3.1; `interior(dom, x, b, diags)` replaces it.
@@ -249,7 +275,10 @@ def smooth(dom: Domain, x, b, n_boundary: int = 1, diags=None, interior=None, va
     """
     for _ in range(n_boundary):
         x = vanka_apply(dom, x, b, vanka)
-    x = (interior or dgs_symmetric)(dom, x, b, diags)
+    if interior is None:
+        x = dgs_symmetric(dom, x, b, diags, order)
+    else:
+        x = interior(dom, x, b, diags)
     for _ in range(n_boundary):
         x = vanka_apply(dom, x, b, vanka)
     return x
