@@ -372,7 +372,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded 8-mode sinusoid forcing per component, zero divergence RHS)",
         "config": {"workload": f"3D MAC Stokes {n}^3 cells unit cube, no-slip box, eta=1, gamma=1e-3, "
-                               f"{sol.layout.levels}-level V-cycle (split schedule, 2 pre + 2 post DGS sweeps, n_b=1), "
+                               f"{sol.layout.levels}-level V-cycle (the same Alg. 3 smoother before and after the coarse correction: symmetric Vanka, one symmetric DGS, symmetric Vanka; n_b=1), "
                                f"MG-SQMR to rtol {args.rtol:g}",
                    "unknowns": int(sol.layout.n_dofs), "seed": args.seed, "precision": "fp64 throughout"},
         "iterations": info["iters"],

@@ -67,13 +67,16 @@ enum {
 
 /* Smoothing schedules of the V-cycle (Section 3: the pre- and post-smoothing
  * matrices must be transposes of each other for W to be symmetric).
+ *  STOKES_SMOOTHER_SYMMETRIC: the paper's arrangement - the same symmetric
+ *    smoother (Alg. 3 with one symmetric DGS = forward + reverse sweep) in both
+ *    phases, nu/2 times (nu even).  Default.
  *  STOKES_SMOOTHER_SPLIT: pre-smoothing = Alg. 3 with nu reverse DGS sweeps
  *    (Gauss-Seidel on M^T L~, Eq. ldist) on V2 between symmetric Vanka on V1;
  *    post-smoothing = Alg. 3 with nu forward DGS sweeps (on L~ M, Eq. dist).
- *    The two are transposes of each other.  Default.
- *  STOKES_SMOOTHER_SYMMETRIC: the paper's arrangement - the same symmetric
- *    smoother (Alg. 3 with one symmetric DGS = forward + reverse sweep) in both
- *    phases, nu/2 times (nu even). */
+ *    The two are transposes of each other.
+ * Every DGS sweep takes the velocities red, black (lattice parity) and the
+ * pressures by the eight colour classes (i&1) + 2(j&1) + 4(k&1), 0..7 forward
+ * and 7..0 in the reverse sweep. */
 enum { STOKES_SMOOTHER_SPLIT = 0, STOKES_SMOOTHER_SYMMETRIC = 1 };
 
 /* The V1 (boundary) smoother of Alg. 3 (Section 3.2):
@@ -90,13 +93,14 @@ enum { STOKES_VANKA_MULT8 = 0, STOKES_VANKA_MULT27 = 1, STOKES_VANKA_ADDITIVE = 
 
 /* Solver parameters.  Defaults (stokes_default_params): eta = 1, gamma = 1e-3
  * (the penalty of Section 4; Section 6 uses 1e-3), levels = 0 (auto), nu = 2,
- * n_boundary = 1, vcycle_precision = 64, smoother = STOKES_SMOOTHER_SPLIT,
+ * n_boundary = 1, vcycle_precision = 64, smoother = STOKES_SMOOTHER_SYMMETRIC,
  * flags = STOKES_FLAG_REMOVE_MEAN, vanka = STOKES_VANKA_MULT8, cycle = 1. */
 typedef struct stokes_params {
   int32_t nx, ny, nz;         /* interior cells per axis, each >= 2 */
   double h;                   /* cell edge; > 0 */
   double eta;                 /* viscosity; > 0 */
-  double gamma;               /* penalty of L~ inside the V-cycle; >= 0 */
+  double gamma;               /* penalty of L~ inside the V-cycle; > 0 (with 0 the coarsest L~ of a
+                                 closed box is singular: constant pressure is in its null space) */
   int32_t levels;             /* multigrid levels; 0 = halve while all axes are even and
                                  every halved axis keeps >= 4 cells; explicit values may
                                  go down to 2 cells per axis */
@@ -123,11 +127,6 @@ typedef struct stokes_params {
  * profiling selection, on a private stream, and replays it on the caller's
  * stream). */
 #define STOKES_FLAG_NO_GRAPH 2
-/* Run the levels of <= 16^3 cells as one launch of one 1024-thread workgroup
- * (the same arithmetic as the per-level launches; results agree to rounding).
- * Off by default: replayed from a graph, the per-level launches of those
- * levels are faster. */
-#define STOKES_FLAG_TAIL 4
 
 /* A state vector holds u_x, u_y, u_z, p, each over the padded slots
  * s = I + sy J + sz K (I in [0, nx+1], ... ; cell (I,J,K) owns p(I,J,K) and
@@ -227,10 +226,10 @@ int stokes_solve(stokes_ctx* ctx, const double* b, double* x, double rtol, int32
 enum {
   STOKES_KC_APPLY = 0,        /* operator / residual / residual-norm passes */
   STOKES_KC_DGS_U = 1,        /* velocity Gauss-Seidel half sweep (one colour) */
-  STOKES_KC_DGS_PF_OWN = 2,   /* forward pressure step, own cell (the red one; the black one fused with
-                                 the red neighbour update) */
-  STOKES_KC_DGS_PF_NBR = 3,   /* forward pressure step, neighbours of the black cells */
-  STOKES_KC_DGS_PR = 4,       /* reverse (left-preconditioned) pressure step */
+  STOKES_KC_DGS_PF_OWN = 2,   /* forward pressure launches 0..3: own steps of one stage of pressure
+                                 classes, with the previous stage's neighbour updates */
+  STOKES_KC_DGS_PF_NBR = 3,   /* forward pressure launch 4: the last stage's neighbour updates */
+  STOKES_KC_DGS_PR = 4,       /* reverse (left-preconditioned) pressure step, one stage */
   STOKES_KC_VANKA_DELTA = 5,  /* Vanka local solves of one colour (with their corrections on levels that
                                  keep two copies of the state; a whole Vanka step on small levels) */
   STOKES_KC_VANKA_APPLY = 6,  /* Vanka corrections of one colour, or the second copy's band update */
@@ -238,8 +237,7 @@ enum {
   STOKES_KC_PROLONG = 8,
   STOKES_KC_COARSE = 9,
   STOKES_KC_BLAS = 10,        /* SQMR vector updates, dots, fills */
-  STOKES_KC_TAIL = 11,        /* all levels of <= 16^3 cells in one workgroup (attributed to its first level) */
-  STOKES_KC_COUNT = 12,
+  STOKES_KC_COUNT = 11,
   STOKES_KC_ALL = -1,
   STOKES_KC_OFF = -2
 };

@@ -72,7 +72,7 @@ int validate_batch(int n, const stokes_params* p) {
   if (n < 1 || !p) return STOKES_EINVAL;
   for (int i = 0; i < n; ++i) {
     const stokes_params& q = p[i];
-    if (q.nx < 2 || q.ny < 2 || q.nz < 2 || !(q.h > 0) || !(q.eta > 0) || !(q.gamma >= 0)) return STOKES_EINVAL;
+    if (q.nx < 2 || q.ny < 2 || q.nz < 2 || !(q.h > 0) || !(q.eta > 0) || !(q.gamma > 0)) return STOKES_EINVAL;
     if (q.nu < 1 || q.n_boundary < 1) return STOKES_EINVAL;
     if (q.smoother != STOKES_SMOOTHER_SPLIT && q.smoother != STOKES_SMOOTHER_SYMMETRIC) return STOKES_EINVAL;
     if (q.smoother == STOKES_SMOOTHER_SYMMETRIC && q.nu % 2) return STOKES_EINVAL;
@@ -382,17 +382,19 @@ void l_resid(stokes_batch* c, int l, int v) {
   if (!t.n) return;
   BX_CASE(v, kb_resid<T, BXT><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done))
 }
+// arg: the colour (CL_DGSU), the forward launch t = 0..3 (CL_PFOWN; CL_PFNBR is
+// launch 4, the last neighbour update) or the reverse stage (CL_PR)
 template <typename T>
-void l_dgs(stokes_batch* c, int cls, int l, int v, int colour) {
+void l_dgs(stokes_batch* c, int cls, int l, int v, int arg) {
   const Tab& t = c->tcls[cls][l][v];
   if (!t.n) return;
   const BEnt* tb = c->tab(t);
   BLev* lv = c->dlev[l];
   switch (cls) {
-    case CL_DGSU: BX_CASE(v, kb_dgs_u<T, BXT><<<t.blocks, BS, 0, c->ks>>>(tb, t.n, lv, c->done, colour)) break;
-    case CL_PFOWN: BX_CASE(v, kb_dgs_pf_own<T, BXT><<<t.blocks, BS, 0, c->ks>>>(tb, t.n, lv, c->done, colour)) break;
-    case CL_PFNBR: BX_CASE(v, kb_dgs_pf_nbr<T, BXT><<<t.blocks, BS, 0, c->ks>>>(tb, t.n, lv, c->done, colour)) break;
-    default: BX_CASE(v, kb_dgs_pr<T, BXT><<<t.blocks, BS, 0, c->ks>>>(tb, t.n, lv, c->done, colour)) break;
+    case CL_DGSU: BX_CASE(v, kb_dgs_u<T, BXT><<<t.blocks, BS, 0, c->ks>>>(tb, t.n, lv, c->done, arg)) break;
+    case CL_PFOWN: BX_CASE(v, kb_dgs_pf<T, BXT><<<t.blocks, BS, 0, c->ks>>>(tb, t.n, lv, c->done, arg)) break;
+    case CL_PFNBR: BX_CASE(v, kb_dgs_pf<T, BXT><<<t.blocks, BS, 0, c->ks>>>(tb, t.n, lv, c->done, 4)) break;
+    default: BX_CASE(v, kb_dgs_pr<T, BXT><<<t.blocks, BS, 0, c->ks>>>(tb, t.n, lv, c->done, arg)) break;
   }
 }
 template <typename T>
@@ -436,25 +438,19 @@ void b_vanka_symmetric(stokes_batch* c, int l) {
   }
 }
 
-// red neighbour update and black own step in one pass (over the black packs of the CL_PFOWN layout)
-template <typename T>
-void l_pf_nbr_own(stokes_batch* c, int l, int v) {
-  const Tab& t = c->tcls[CL_PFOWN][l][v];
-  if (!t.n) return;
-  BX_CASE(v, kb_dgs_pf_nbr_own<T, BXT><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done))
-}
-
+// Forward sweep: velocities red, black; the pressure stages in five launches
+// (packed_kernels.hpp, dgs_pf_stage_pack).
 template <typename T>
 void b_dgs_forward(stokes_batch* c, int l) {
   for (int col = 0; col < 2; ++col) l_dgs<T>(c, CL_DGSU, l, c->bx[CL_DGSU][l], col);
-  l_dgs<T>(c, CL_PFOWN, l, c->bx[CL_PFOWN][l], 0);
-  l_pf_nbr_own<T>(c, l, c->bx[CL_PFOWN][l]);
-  l_dgs<T>(c, CL_PFNBR, l, c->bx[CL_PFNBR][l], 1);
+  for (int t = 0; t < 4; ++t) l_dgs<T>(c, CL_PFOWN, l, c->bx[CL_PFOWN][l], t);
+  l_dgs<T>(c, CL_PFNBR, l, c->bx[CL_PFNBR][l], 4);
 }
 
+// Reverse sweep: pressure stages 3..0, then velocities black, red.
 template <typename T>
 void b_dgs_reverse(stokes_batch* c, int l) {
-  for (int col = 1; col >= 0; --col) l_dgs<T>(c, CL_PR, l, c->bx[CL_PR][l], col);
+  for (int st = 3; st >= 0; --st) l_dgs<T>(c, CL_PR, l, c->bx[CL_PR][l], st);
   for (int col = 1; col >= 0; --col) l_dgs<T>(c, CL_DGSU, l, c->bx[CL_DGSU][l], col);
 }
 

@@ -131,57 +131,32 @@ __global__ __launch_bounds__(BS) void kb_dgs_u(const BEnt* __restrict__ tab, int
   if (row_pack_at<V>(g, colour ^ 1, m, J, K, rp)) dgs_u_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, rp);
 }
 
+// launch t of the forward pressure sweep (dgs_pf_stage_pack)
 template <typename T, int BX>
-__global__ __launch_bounds__(BS) void kb_dgs_pf_own(const BEnt* __restrict__ tab, int nent,
-                                                    const BLev* __restrict__ lev, const int* __restrict__ done,
-                                                    int colour) {
+__global__ __launch_bounds__(BS) void kb_dgs_pf(const BEnt* __restrict__ tab, int nent, const BLev* __restrict__ lev,
+                                                const int* __restrict__ done, int t) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
   constexpr int V = bpack<T>();
   int m, J, K;
   if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
   RowPack<V> rp;
-  if (row_pack_at<V>(g, colour ^ 1, m, J, K, rp))
-    dgs_pf_own_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].dscr, rp);
+  if (row_pack_at<V>(g, (t & 1) ^ 1, m, J, K, rp))
+    dgs_pf_stage_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].dscr, rp, t);
 }
 
-// red neighbour update and black own step in one pass (dgs_pf_nbr_own_pack)
-template <typename T, int BX>
-__global__ __launch_bounds__(BS) void kb_dgs_pf_nbr_own(const BEnt* __restrict__ tab, int nent,
-                                                        const BLev* __restrict__ lev, const int* __restrict__ done) {
-  SG_BATCH_ENTRY();
-  const Geom g = lev[d].g;
-  constexpr int V = bpack<T>();
-  int m, J, K;
-  if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
-  RowPack<V> rp;
-  if (row_pack_at<V>(g, 0, m, J, K, rp))
-    dgs_pf_nbr_own_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, (T*)lev[d].dscr, rp);
-}
-
-template <typename T, int BX>
-__global__ __launch_bounds__(BS) void kb_dgs_pf_nbr(const BEnt* __restrict__ tab, int nent,
-                                                    const BLev* __restrict__ lev, const int* __restrict__ done,
-                                                    int colour) {
-  SG_BATCH_ENTRY();
-  const Geom g = lev[d].g;
-  constexpr int V = bpack<T>();
-  int m, J, K;
-  if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
-  RowPack<V> rp;
-  if (row_pack_at<V>(g, colour, m, J, K, rp)) dgs_pf_nbr_pack<T, V>(g, (T*)lev[d].x, (const T*)lev[d].dscr, rp);
-}
-
+// one stage of the reverse pressure sweep (dgs_pr_stage_pack)
 template <typename T, int BX>
 __global__ __launch_bounds__(BS) void kb_dgs_pr(const BEnt* __restrict__ tab, int nent, const BLev* __restrict__ lev,
-                                                const int* __restrict__ done, int colour) {
+                                                const int* __restrict__ done, int stage) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
   constexpr int V = bpack<T>();
   int m, J, K;
   if (!flat_item(g, pack_per_row<V>(g), lb, m, J, K)) return;
   RowPack<V> rp;
-  if (row_pack_at<V>(g, colour ^ 1, m, J, K, rp)) dgs_pr_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, rp);
+  if (row_pack_at<V>(g, (stage & 1) ^ 1, m, J, K, rp))
+    dgs_pr_stage_pack<T, T, V>(g, (T*)lev[d].x, (const T*)lev[d].b, rp, stage);
 }
 
 // restriction into the next level: one item per coarse slot

@@ -3,8 +3,8 @@
 // products, the padded red/black layout of geom.hpp, and block indices
 // remapped so that each of the 8 XCDs walks a contiguous slab of the grid
 // (its L2 then serves the y- and z-neighbour rows of its own rows).  The
-// one-cell items here are the reference arithmetic; packed_kernels.hpp
-// computes the hot ones with V cells per thread.
+// distributive Gauss-Seidel steps and the packed operator passes are in
+// packed_kernels.hpp (V cells per thread).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -140,116 +140,6 @@ __device__ __forceinline__ double apply_item(const Geom& g, const T* __restrict_
     }
   }
   return acc;
-}
-
-// ---------------------------------------------------------------------------
-// Distributive Gauss-Seidel on V2 (Alg. 2, Eq. dist, Eq. ldist, Appendix A).
-// ---------------------------------------------------------------------------
-// Velocity Gauss-Seidel step on the V2 faces of one colour: u += r / (6 eta/h^2).
-// Same-colour faces are not lattice neighbours and p is fixed, so the class
-// updates at once.
-template <typename T, typename TB>
-__device__ __forceinline__ void dgs_u_item(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, int I, int J,
-                                           int K) {
-  const int s = g.idx(I, J, K);
-  const int F = g.field;
-  T* ux = x;
-  T* uy = x + F;
-  T* uz = x + 2 * F;
-  const T* p = x + 3 * F;
-  const T dinv = (T)(1.0 / (6.0 * g.c));
-  const int e = g.at(s);
-  if (g.ux_v2(I, J, K)) ux[e] = ux[e] + ((T)b[e] - row_u(g, ux, p, s, 1)) * dinv;
-  if (g.uy_v2(I, J, K)) uy[e] = uy[e] + ((T)b[F + e] - row_u(g, uy, p, s, g.sy)) * dinv;
-  if (g.uz_v2(I, J, K)) uz[e] = uz[e] + ((T)b[2 * F + e] - row_u(g, uz, p, s, g.sz)) * dinv;
-}
-
-// Pressure step of the forward sweep, part 1, on the V2 cells of one colour:
-// delta = r_j / d_j with d_j = (L~ M)_jj = -6 (1 + gamma eta) / h^2, then move
-// x along the column m_j of M = [[I, -B^T], [0, eta B B^T]] (Eq. dist) as far
-// as the cell itself is concerned: its six faces get -+delta/h and p_j gets
-// 6 eta delta / h^2.  A V2 cell's six faces and six neighbours are all
-// unknowns, so m_j is the full interior column.  delta is kept for part 2.
-template <typename T, typename TB>
-__device__ __forceinline__ void dgs_pf_own_item(const Geom& g, T* __restrict__ x, const TB* __restrict__ b,
-                                                T* __restrict__ dscr, int I, int J, int K) {
-  if (!g.p_v2(I, J, K)) return;
-  const int s = g.idx(I, J, K);
-  const int F = g.field;
-  T* ux = x;
-  T* uy = x + F;
-  T* uz = x + 2 * F;
-  T* p = x + 3 * F;
-  const double ih2 = g.inv_h * g.inv_h;
-  const int e = g.at(s);
-  const T r = (T)b[3 * F + e] - row_p(g, ux, uy, uz, p, s, g.gamma);
-  const T delta = r / (T)(-6.0 * (1.0 + g.gamma * g.eta) * ih2);
-  dscr[e] = delta;
-  const T dh = delta * (T)g.inv_h;
-  const int ex = g.at(s + 1), ey = g.at(s + g.sy), ez = g.at(s + g.sz);
-  ux[e] = ux[e] - dh;
-  ux[ex] = ux[ex] + dh;
-  uy[e] = uy[e] - dh;
-  uy[ey] = uy[ey] + dh;
-  uz[e] = uz[e] - dh;
-  uz[ez] = uz[ez] + dh;
-  p[e] = p[e] + (T)(6.0 * g.eta * ih2) * delta;
-}
-
-// Part 2 on every cell of the other colour (V1 ring cells included): p_k -=
-// (eta/h^2) * sum of the deltas of its V2 neighbours (the off-diagonal
-// entries of eta B B^T in the columns m_j).
-template <typename T>
-__device__ __forceinline__ void dgs_pf_nbr_item(const Geom& g, T* __restrict__ x, const T* __restrict__ dscr, int I,
-                                                int J, int K) {
-  if (!g.p_active(I, J, K)) return;
-  const int s = g.idx(I, J, K);
-  T* p = x + 3 * g.field;
-  T sum = T(0);
-  if (g.p_v2(I - 1, J, K)) sum += dscr[g.at(s - 1)];
-  if (g.p_v2(I + 1, J, K)) sum += dscr[g.at(s + 1)];
-  if (g.p_v2(I, J - 1, K)) sum += dscr[g.at(s - g.sy)];
-  if (g.p_v2(I, J + 1, K)) sum += dscr[g.at(s + g.sy)];
-  if (g.p_v2(I, J, K - 1)) sum += dscr[g.at(s - g.sz)];
-  if (g.p_v2(I, J, K + 1)) sum += dscr[g.at(s + g.sz)];
-  const int e = g.at(s);
-  if (sum != T(0)) p[e] = p[e] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
-}
-
-// Pressure step of the reverse sweep (Gauss-Seidel on M^T L~, Eq. ldist) on
-// the V2 cells of one colour: p_j += (m_j . r) / d_j, r = b - L~ x, where
-// m_j = (-B^T e_j, eta B B^T e_j) is column j of M.  The row m_j^T L~ is
-// column j of L~ M: velocity part (-A B^T + eta B^T B B^T) e_j, pressure part
-// -(1 + gamma eta) B B^T e_j.  When the six faces and six neighbours of j are
-// unknowns (every V2 cell), B B^T e_j is the lattice stencil
-// (6 e_j - neighbours)/h^2 and A acts on the faces of j as the lattice
-// Laplacian; the lattice gradient commutes with the lattice Laplacian, so the
-// velocity part vanishes (A = -eta Lap_u, B B^T = -Lap_p there).  Hence
-//   m_j . r = m_j . b + (1 + gamma eta)(6 p_j - sum_k p_k)/h^2,
-//   m_j . b = (1/h) sum_a (b(plus face) - b(minus face)) + (eta/h^2)(6 b_j - sum_k b_k):
-// 13 values of b and 7 of p, where the thirteen local residuals of m_j . r
-// read ~56 operands.  Same update up to rounding (and without the residual
-// form's cancellation of the velocity terms).  Only p_j changes, and no value
-// read here is another same-colour pressure.
-template <typename T, typename TB>
-__device__ __forceinline__ void dgs_pr_item(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, int I, int J,
-                                            int K) {
-  if (!g.p_v2(I, J, K)) return;
-  const int s = g.idx(I, J, K);
-  const int F = g.field;
-  T* p = x + 3 * F;
-  const TB* bp = b + 3 * F;
-  const int e = g.at(s);
-  const int exm = g.at(s - 1), exp_ = g.at(s + 1), eym = g.at(s - g.sy), eyp = g.at(s + g.sy), ezm = g.at(s - g.sz),
-            ezp = g.at(s + g.sz);
-  const T fsum = ((T)b[exp_] - (T)b[e]) + ((T)b[F + eyp] - (T)b[F + e]) + ((T)b[2 * F + ezp] - (T)b[2 * F + e]);
-  const T bsum = (T)bp[exm] + (T)bp[exp_] + (T)bp[eym] + (T)bp[eyp] + (T)bp[ezm] + (T)bp[ezp];
-  const T psum = p[exm] + p[exp_] + p[eym] + p[eyp] + p[ezm] + p[ezp];
-  const T pj = p[e];
-  const double ih2 = g.inv_h * g.inv_h;
-  const double kap = 1.0 + g.gamma * g.eta;
-  const T rt = (fsum * (T)g.inv_h + (T)(g.eta * ih2) * (T(6) * (T)bp[e] - bsum)) + (T)(kap * ih2) * (T(6) * pj - psum);
-  p[e] = pj + rt / (T)(-6.0 * kap * ih2);
 }
 
 // ---------------------------------------------------------------------------

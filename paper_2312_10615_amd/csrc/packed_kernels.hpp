@@ -1,8 +1,8 @@
 // The hot stencil passes with V cells per thread, for the single box and the
 // batch: the distributive Gauss-Seidel steps (Alg. 2, Eq. dist, Eq. ldist)
-// and the operator passes (Eq. 2).  They compute what the one-cell items in
-// kernels.hpp compute, cell by cell and in the same order of operations;
-// only the memory access is different.
+// and the operator passes (Eq. 2).  The operator passes compute what the
+// one-cell apply_item in kernels.hpp computes, cell by cell and in the same
+// order of operations; only the memory access is different.
 //
 // With the red/black split every stencil neighbour of a slot of parity par
 // sits in the other half, at an element shifted by a constant: slot s + o of
@@ -144,7 +144,9 @@ __device__ __forceinline__ bool row_pack(const Geom& g, int par, RowPack<V>& rp)
   return row_pack_at<V>(g, par, m, J, K, rp);
 }
 
-// Velocity step on the V2 faces of one colour (dgs_u_item, V cells).
+// Velocity Gauss-Seidel step on the V2 faces of one colour: u += r / (6 eta/h^2).
+// Same-colour faces are not lattice neighbours and p is fixed, so the class
+// updates at once.
 template <typename T, typename TB, int V>
 __device__ __forceinline__ void dgs_u_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, const RowPack<V>& rp) {
   const int F = g.field;
@@ -188,36 +190,58 @@ __global__ __launch_bounds__(BS) void k_dgs_u_v(Geom g, T* __restrict__ x, const
   if (row_pack<V>(g, colour ^ 1, rp)) dgs_u_pack<T, TB, V>(g, x, b, rp);
 }
 
-// Forward-sweep pressure step, part 1 (dgs_pf_own_item, V cells).
+// ---------------------------------------------------------------------------
+// DGS pressure steps.  The pressures go by the eight colour classes
+// (i&1) + 2(j&1) + 4(k&1) (0-based cell indices), taken 0..7 in the forward
+// sweep and 7..0 in the reverse one.  Two cells are face neighbours only when
+// their classes differ in one bit, and then the class with that bit clear
+// comes first; so the classes of equal bit count are mutually independent and
+// may run together, and the sweep runs as four stages (bit count 0, 1, 2, 3)
+// with the same results.  Inside a row of one parity every cell has the same
+// i parity, so the whole row belongs to one class and one stage.
+// ---------------------------------------------------------------------------
+struct RowBits {
+  int bx, by, bz, stage;
+};
+
+template <int V>
+__device__ __forceinline__ RowBits row_bits(const RowPack<V>& rp) {
+  RowBits r;
+  r.bx = (rp.I0 - 1) & 1;
+  r.by = (rp.J - 1) & 1;
+  r.bz = (rp.K - 1) & 1;
+  r.stage = r.bx + r.by + r.bz;
+  return r;
+}
+
+// Forward-sweep pressure step on the V2 cells of a pack (Eq. dist): delta =
+// r_j / d_j with d_j = (L~ M)_jj = -6 (1 + gamma eta) / h^2, then x moves along
+// the column m_j of M = [[I, -B^T], [0, eta B B^T]]: the cell's six faces get
+// -+delta/h and p_j gets 6 eta delta / h^2 here; the -eta delta / h^2 of each
+// neighbour pressure is gathered by the neighbour in the next launch.  A V2
+// cell's six faces and six neighbours are all unknowns, so m_j is the full
+// interior column.  P holds p_j on entry (after any gather) and on exit.
 template <typename T, typename TB, int V>
-__device__ __forceinline__ void dgs_pf_own_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, T* __restrict__ dscr, const RowPack<V>& rp) {
-  bool act[V];
-  bool any = false;
-#pragma unroll
-  for (int i = 0; i < V; ++i) {
-    act[i] = i < rp.n && g.p_v2(rp.I0 + 2 * i, rp.J, rp.K);
-    any = any || act[i];
-  }
-  if (!any) return;
+__device__ __forceinline__ void dgs_pf_own_step(const Geom& g, T* __restrict__ x, const TB* __restrict__ b,
+                                                T* __restrict__ dscr, const RowPack<V>& rp, const bool* acto,
+                                                Pack<T, V>& P) {
   const int F = g.field;
   T* ux = x;
   T* uy = x + F;
   T* uz = x + 2 * F;
-  T* p = x + 3 * F;
   const double ih2 = g.inv_h * g.inv_h;
   const int eo = rp.el(0), ex = rp.el(1), ey = rp.el(g.sy), ez = rp.el(g.sz);
   Pack<T, V> X0 = ldp<T, V>(ux + eo), X1 = ldp<T, V>(ux + ex);
   Pack<T, V> Y0 = ldp<T, V>(uy + eo), Y1 = ldp<T, V>(uy + ey);
   Pack<T, V> Z0 = ldp<T, V>(uz + eo), Z1 = ldp<T, V>(uz + ez);
-  Pack<T, V> P0 = ldp<T, V>(p + eo);
   const Pack<TB, V> Bp = ldp<TB, V>(b + 3 * F + eo);
   Pack<T, V> D;
 #pragma unroll
   for (int i = 0; i < V; ++i) {
     D.v[i] = T(0);
-    if (!act[i]) continue;
+    if (!acto[i]) continue;
     const T div = (X1.v[i] - X0.v[i]) + (Y1.v[i] - Y0.v[i]) + (Z1.v[i] - Z0.v[i]);
-    const T r = (T)Bp.v[i] - (-div * (T)g.inv_h - (T)g.gamma * P0.v[i]);
+    const T r = (T)Bp.v[i] - (-div * (T)g.inv_h - (T)g.gamma * P.v[i]);
     const T delta = r / (T)(-6.0 * (1.0 + g.gamma * g.eta) * ih2);
     D.v[i] = delta;
     const T dh = delta * (T)g.inv_h;
@@ -227,159 +251,107 @@ __device__ __forceinline__ void dgs_pf_own_pack(const Geom& g, T* __restrict__ x
     Y1.v[i] = Y1.v[i] + dh;
     Z0.v[i] = Z0.v[i] - dh;
     Z1.v[i] = Z1.v[i] + dh;
-    P0.v[i] = P0.v[i] + (T)(6.0 * g.eta * ih2) * delta;
+    P.v[i] = P.v[i] + (T)(6.0 * g.eta * ih2) * delta;
   }
-  stp_cells<T, V>(dscr + eo, D, rp.n, act);
-  stp_cells<T, V>(ux + eo, X0, rp.n, act);
-  stp_cells<T, V>(ux + ex, X1, rp.n, act);
-  stp_cells<T, V>(uy + eo, Y0, rp.n, act);
-  stp_cells<T, V>(uy + ey, Y1, rp.n, act);
-  stp_cells<T, V>(uz + eo, Z0, rp.n, act);
-  stp_cells<T, V>(uz + ez, Z1, rp.n, act);
-  stp_cells<T, V>(p + eo, P0, rp.n, act);
+  stp_cells<T, V>(dscr + eo, D, rp.n, acto);
+  stp_cells<T, V>(ux + eo, X0, rp.n, acto);
+  stp_cells<T, V>(ux + ex, X1, rp.n, acto);
+  stp_cells<T, V>(uy + eo, Y0, rp.n, acto);
+  stp_cells<T, V>(uy + ey, Y1, rp.n, acto);
+  stp_cells<T, V>(uz + eo, Z0, rp.n, acto);
+  stp_cells<T, V>(uz + ez, Z1, rp.n, acto);
 }
 
+// Launch t (0..4) of the forward pressure sweep, over the rows of stage t
+// and stage t - 2 (both of colour t & 1).  First every active cell takes the
+// -(eta/h^2) delta of its V2 neighbours in stage t - 1 (along an axis the two
+// neighbours lie one stage down when the cell's bit for that axis is set, one
+// stage up otherwise); then a stage-t V2 cell makes its own step from that
+// pressure.  Every launch reads deltas written by the previous one only, and
+// its own steps touch faces of stage-t cells, which share none.
 template <typename T, typename TB, int V>
-__global__ __launch_bounds__(BS) void k_dgs_pf_own_v(Geom g, T* __restrict__ x, const TB* __restrict__ b,
-                                                     T* __restrict__ dscr, int colour) {
-  RowPack<V> rp;
-  if (row_pack<V>(g, colour ^ 1, rp)) dgs_pf_own_pack<T, TB, V>(g, x, b, dscr, rp);
-}
-
-// Forward-sweep pressure step, part 2 (dgs_pf_nbr_item, V cells of the other colour).
-template <typename T, int V>
-__device__ __forceinline__ void dgs_pf_nbr_pack(const Geom& g, T* __restrict__ x, const T* __restrict__ dscr, const RowPack<V>& rp) {
-  bool act[V];
-  bool any = false;
-#pragma unroll
-  for (int i = 0; i < V; ++i) {
-    act[i] = i < rp.n && g.p_active(rp.I0 + 2 * i, rp.J, rp.K);
-    any = any || act[i];
-  }
-  if (!any) return;
-  T* p = x + 3 * g.field;
-  const int eo = rp.el(0);
-  const Pack<T, V> dxm = ldp<T, V>(dscr + rp.el(-1)), dxp = ldp<T, V>(dscr + rp.el(1));
-  const Pack<T, V> dym = ldp<T, V>(dscr + rp.el(-g.sy)), dyp = ldp<T, V>(dscr + rp.el(g.sy));
-  const Pack<T, V> dzm = ldp<T, V>(dscr + rp.el(-g.sz)), dzp = ldp<T, V>(dscr + rp.el(g.sz));
-  Pack<T, V> P = ldp<T, V>(p + eo);
-  const int J = rp.J, K = rp.K;
-#pragma unroll
-  for (int i = 0; i < V; ++i) {
-    if (!act[i]) continue;
-    const int I = rp.I0 + 2 * i;
-    T sum = T(0);
-    if (g.p_v2(I - 1, J, K)) sum += dxm.v[i];
-    if (g.p_v2(I + 1, J, K)) sum += dxp.v[i];
-    if (g.p_v2(I, J - 1, K)) sum += dym.v[i];
-    if (g.p_v2(I, J + 1, K)) sum += dyp.v[i];
-    if (g.p_v2(I, J, K - 1)) sum += dzm.v[i];
-    if (g.p_v2(I, J, K + 1)) sum += dzp.v[i];
-    if (sum != T(0)) P.v[i] = P.v[i] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
-  }
-  stp_cells<T, V>(p + eo, P, rp.n, act);
-}
-
-template <typename T, int V>
-__global__ __launch_bounds__(BS) void k_dgs_pf_nbr_v(Geom g, T* __restrict__ x, const T* __restrict__ dscr,
-                                                     int colour) {
-  RowPack<V> rp;
-  if (row_pack<V>(g, colour, rp)) dgs_pf_nbr_pack<T, V>(g, x, dscr, rp);
-}
-
-// Part 2 for the red pressures followed by part 1 for the black ones, in one
-// pass over the black cells (red = colour 0): the black pressure takes the
-// red neighbours' -(eta/h^2) sum delta first (dgs_pf_nbr_pack for colour 0,
-// every active black cell), then a black V2 cell makes its own step from that
-// pressure (dgs_pf_own_pack for colour 1).  The same operations in the same
-// order as the two launches; the black step reads no red value that it
-// writes, and writes no value another thread reads.
-template <typename T, typename TB, int V>
-__device__ __forceinline__ void dgs_pf_nbr_own_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b,
-                                                    T* __restrict__ dscr, const RowPack<V>& rp) {
+__device__ __forceinline__ void dgs_pf_stage_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b,
+                                                  T* __restrict__ dscr, const RowPack<V>& rp, int t) {
+  const RowBits rb = row_bits<V>(rp);
+  if (rb.stage != t && rb.stage != t - 2) return;
+  const bool own = rb.stage == t;
+  const bool gx = t > 0 && (own ? rb.bx : !rb.bx), gy = t > 0 && (own ? rb.by : !rb.by),
+             gz = t > 0 && (own ? rb.bz : !rb.bz);
   bool actn[V], acto[V];
-  bool any = false;
+  bool any = false, anyo = false;
 #pragma unroll
   for (int i = 0; i < V; ++i) {
     actn[i] = i < rp.n && g.p_active(rp.I0 + 2 * i, rp.J, rp.K);
-    acto[i] = i < rp.n && g.p_v2(rp.I0 + 2 * i, rp.J, rp.K);
+    acto[i] = own && i < rp.n && g.p_v2(rp.I0 + 2 * i, rp.J, rp.K);
     any = any || actn[i];
+    anyo = anyo || acto[i];
   }
-  if (!any) return;
-  const int F = g.field;
-  T* ux = x;
-  T* uy = x + F;
-  T* uz = x + 2 * F;
-  T* p = x + 3 * F;
+  if (!any || (!anyo && !gx && !gy && !gz)) return;
+  T* p = x + 3 * g.field;
   const int eo = rp.el(0);
   Pack<T, V> P = ldp<T, V>(p + eo);
-  {
-    const Pack<T, V> dxm = ldp<T, V>(dscr + rp.el(-1)), dxp = ldp<T, V>(dscr + rp.el(1));
-    const Pack<T, V> dym = ldp<T, V>(dscr + rp.el(-g.sy)), dyp = ldp<T, V>(dscr + rp.el(g.sy));
-    const Pack<T, V> dzm = ldp<T, V>(dscr + rp.el(-g.sz)), dzp = ldp<T, V>(dscr + rp.el(g.sz));
-    const int J = rp.J, K = rp.K;
+  const int J = rp.J, K = rp.K;
+  Pack<T, V> sum;
+#pragma unroll
+  for (int i = 0; i < V; ++i) sum.v[i] = T(0);
+  if (gx) {
+    const Pack<T, V> dm = ldp<T, V>(dscr + rp.el(-1)), dp = ldp<T, V>(dscr + rp.el(1));
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      if (!actn[i]) continue;
       const int I = rp.I0 + 2 * i;
-      T sum = T(0);
-      if (g.p_v2(I - 1, J, K)) sum += dxm.v[i];
-      if (g.p_v2(I + 1, J, K)) sum += dxp.v[i];
-      if (g.p_v2(I, J - 1, K)) sum += dym.v[i];
-      if (g.p_v2(I, J + 1, K)) sum += dyp.v[i];
-      if (g.p_v2(I, J, K - 1)) sum += dzm.v[i];
-      if (g.p_v2(I, J, K + 1)) sum += dzp.v[i];
-      if (sum != T(0)) P.v[i] = P.v[i] - (T)(g.eta * g.inv_h * g.inv_h) * sum;
+      if (g.p_v2(I - 1, J, K)) sum.v[i] += dm.v[i];
+      if (g.p_v2(I + 1, J, K)) sum.v[i] += dp.v[i];
     }
   }
-  bool anyo = false;
-#pragma unroll
-  for (int i = 0; i < V; ++i) anyo = anyo || acto[i];
-  if (anyo) {
-    const double ih2 = g.inv_h * g.inv_h;
-    const int ex = rp.el(1), ey = rp.el(g.sy), ez = rp.el(g.sz);
-    Pack<T, V> X0 = ldp<T, V>(ux + eo), X1 = ldp<T, V>(ux + ex);
-    Pack<T, V> Y0 = ldp<T, V>(uy + eo), Y1 = ldp<T, V>(uy + ey);
-    Pack<T, V> Z0 = ldp<T, V>(uz + eo), Z1 = ldp<T, V>(uz + ez);
-    const Pack<TB, V> Bp = ldp<TB, V>(b + 3 * F + eo);
-    Pack<T, V> D;
+  if (gy) {
+    const Pack<T, V> dm = ldp<T, V>(dscr + rp.el(-g.sy)), dp = ldp<T, V>(dscr + rp.el(g.sy));
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      D.v[i] = T(0);
-      if (!acto[i]) continue;
-      const T div = (X1.v[i] - X0.v[i]) + (Y1.v[i] - Y0.v[i]) + (Z1.v[i] - Z0.v[i]);
-      const T r = (T)Bp.v[i] - (-div * (T)g.inv_h - (T)g.gamma * P.v[i]);
-      const T delta = r / (T)(-6.0 * (1.0 + g.gamma * g.eta) * ih2);
-      D.v[i] = delta;
-      const T dh = delta * (T)g.inv_h;
-      X0.v[i] = X0.v[i] - dh;
-      X1.v[i] = X1.v[i] + dh;
-      Y0.v[i] = Y0.v[i] - dh;
-      Y1.v[i] = Y1.v[i] + dh;
-      Z0.v[i] = Z0.v[i] - dh;
-      Z1.v[i] = Z1.v[i] + dh;
-      P.v[i] = P.v[i] + (T)(6.0 * g.eta * ih2) * delta;
+      const int I = rp.I0 + 2 * i;
+      if (g.p_v2(I, J - 1, K)) sum.v[i] += dm.v[i];
+      if (g.p_v2(I, J + 1, K)) sum.v[i] += dp.v[i];
     }
-    stp_cells<T, V>(dscr + eo, D, rp.n, acto);
-    stp_cells<T, V>(ux + eo, X0, rp.n, acto);
-    stp_cells<T, V>(ux + ex, X1, rp.n, acto);
-    stp_cells<T, V>(uy + eo, Y0, rp.n, acto);
-    stp_cells<T, V>(uy + ey, Y1, rp.n, acto);
-    stp_cells<T, V>(uz + eo, Z0, rp.n, acto);
-    stp_cells<T, V>(uz + ez, Z1, rp.n, acto);
   }
-  stp_cells<T, V>(p + eo, P, rp.n, actn);
+  if (gz) {
+    const Pack<T, V> dm = ldp<T, V>(dscr + rp.el(-g.sz)), dp = ldp<T, V>(dscr + rp.el(g.sz));
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int I = rp.I0 + 2 * i;
+      if (g.p_v2(I, J, K - 1)) sum.v[i] += dm.v[i];
+      if (g.p_v2(I, J, K + 1)) sum.v[i] += dp.v[i];
+    }
+  }
+  if (gx || gy || gz) {
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (actn[i] && sum.v[i] != T(0)) P.v[i] = P.v[i] - (T)(g.eta * g.inv_h * g.inv_h) * sum.v[i];
+  }
+  if (anyo) dgs_pf_own_step<T, TB, V>(g, x, b, dscr, rp, acto, P);
+  stp_cells<T, V>(p + eo, P, rp.n, (gx || gy || gz) ? actn : acto);
 }
 
 template <typename T, typename TB, int V>
-__global__ __launch_bounds__(BS) void k_dgs_pf_nbr_own_v(Geom g, T* __restrict__ x, const TB* __restrict__ b,
-                                                         T* __restrict__ dscr) {
+__global__ __launch_bounds__(BS) void k_dgs_pf_v(Geom g, T* __restrict__ x, const TB* __restrict__ b,
+                                                 T* __restrict__ dscr, int t) {
   RowPack<V> rp;
-  if (row_pack<V>(g, 0, rp)) dgs_pf_nbr_own_pack<T, TB, V>(g, x, b, dscr, rp);
+  if (row_pack<V>(g, (t & 1) ^ 1, rp)) dgs_pf_stage_pack<T, TB, V>(g, x, b, dscr, rp, t);
 }
 
-// Reverse-sweep pressure step (dgs_pr_item, V cells): 13 wide loads of b and
-// 7 of p per pack.
+// Reverse-sweep pressure step (Gauss-Seidel on M^T L~, Eq. ldist) on the V2
+// cells of a pack: p_j += (m_j . r) / d_j, r = b - L~ x, where m_j =
+// (-B^T e_j, eta B B^T e_j) is column j of M.  The row m_j^T L~ is column j
+// of L~ M: velocity part (-A B^T + eta B^T B B^T) e_j, pressure part
+// -(1 + gamma eta) B B^T e_j.  When the six faces and six neighbours of j are
+// unknowns (every V2 cell), B B^T e_j is the lattice stencil
+// (6 e_j - neighbours)/h^2 and A acts on the faces of j as the lattice
+// Laplacian; the lattice gradient commutes with the lattice Laplacian, so the
+// velocity part vanishes (A = -eta Lap_u, B B^T = -Lap_p there).  Hence
+//   m_j . r = m_j . b + (1 + gamma eta)(6 p_j - sum_k p_k)/h^2,
+//   m_j . b = (1/h) sum_a (b(plus face) - b(minus face)) + (eta/h^2)(6 b_j - sum_k b_k):
+// 13 wide loads of b and 7 of p per pack, where the thirteen local residuals
+// of m_j . r read ~56 operands.  Same update up to rounding (and without the
+// residual form's cancellation of the velocity terms).  Only p_j changes, and
+// no value read here is a pressure of the same stage.
 template <typename T, typename TB, int V>
 __device__ __forceinline__ void dgs_pr_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, const RowPack<V>& rp) {
   bool act[V];
@@ -419,10 +391,17 @@ __device__ __forceinline__ void dgs_pr_pack(const Geom& g, T* __restrict__ x, co
   stp_cells<T, V>(p + eo, P, rp.n, act);
 }
 
+// The rows of stage `stage` (colour stage & 1) of the reverse pressure sweep.
 template <typename T, typename TB, int V>
-__global__ __launch_bounds__(BS) void k_dgs_pr_v(Geom g, T* __restrict__ x, const TB* __restrict__ b, int colour) {
+__device__ __forceinline__ void dgs_pr_stage_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b,
+                                                  const RowPack<V>& rp, int stage) {
+  if (row_bits<V>(rp).stage == stage) dgs_pr_pack<T, TB, V>(g, x, b, rp);
+}
+
+template <typename T, typename TB, int V>
+__global__ __launch_bounds__(BS) void k_dgs_pr_v(Geom g, T* __restrict__ x, const TB* __restrict__ b, int stage) {
   RowPack<V> rp;
-  if (row_pack<V>(g, colour ^ 1, rp)) dgs_pr_pack<T, TB, V>(g, x, b, rp);
+  if (row_pack<V>(g, (stage & 1) ^ 1, rp)) dgs_pr_stage_pack<T, TB, V>(g, x, b, rp, stage);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,7 +18,6 @@
 #include "host_tables.hpp"
 #include "packed_kernels.hpp"
 #include "kernels.hpp"
-#include "tail_kernels.hpp"
 
 using namespace sg;
 
@@ -77,10 +76,6 @@ struct stokes_ctx {
   int nc = 0;
   // Vanka delta scratch (max colour count x 8)
   void* vdelta = nullptr;
-  // the small levels, run by one workgroup (tail < 0: none)
-  int tail = -1;
-  TailLev* tlev = nullptr;
-  TailArgs targs{};
   int prec = 64;  // V-cycle precision
   // kernel timing (diagnostics)
   int prof_class = STOKES_KC_OFF, prof_level = -1;
@@ -220,7 +215,7 @@ long coarse_dofs(const Geom& g) {
 int validate(const stokes_params* p, int* levels_out) {
   if (!p) return STOKES_EINVAL;
   if (p->nx < 2 || p->ny < 2 || p->nz < 2) return STOKES_EINVAL;
-  if (!(p->h > 0) || !(p->eta > 0) || !(p->gamma >= 0) || !std::isfinite(p->h) || !std::isfinite(p->eta) ||
+  if (!(p->h > 0) || !(p->eta > 0) || !(p->gamma > 0) || !std::isfinite(p->h) || !std::isfinite(p->eta) ||
       !std::isfinite(p->gamma))
     return STOKES_EINVAL;
   if (p->nu < 1 || p->n_boundary < 1) return STOKES_EINVAL;
@@ -293,7 +288,6 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
     }
   }
   c->vdelta = cv.take<char>(8 * std::max<long>(vmax, 1) * es);
-  c->tlev = cv.take<TailLev>(TAIL_MAX);
   const Geom& gc = c->lev[L - 1].g;
   c->nc = (int)coarse_dofs(gc);
   c->cinv = cv.take<double>((size_t)c->nc * c->nc);
@@ -433,7 +427,9 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
 }
 
 // Forward DGS sweep on L~ M (Alg. 2, Eq. dist) over the V2 unknowns:
-// velocities red, black; pressures red, black.
+// velocities red, black; then the pressures by the eight colour classes 0..7,
+// run as four stages of equal bit count (packed_kernels.hpp) in five launches:
+// launch t makes the stage-t own steps and the stage-(t-1) neighbour updates.
 template <typename T>
 void dgs_forward(stokes_ctx* c, int l, T* x, const T* b) {
   constexpr int V = dgs_pack<T>();
@@ -442,21 +438,20 @@ void dgs_forward(stokes_ctx* c, int l, T* x, const T* b) {
   const int hg = dgs_grid<T>(g);
   for (int col = 0; col < 2; ++col)
     launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
-  // red own step; red neighbour update and black own step in one pass; black neighbour update
-  launch(c, STOKES_KC_DGS_PF_OWN, l, [=] { k_dgs_pf_own_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, dscr, 0); });
-  launch(c, STOKES_KC_DGS_PF_OWN, l, [=] { k_dgs_pf_nbr_own_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, dscr); });
-  launch(c, STOKES_KC_DGS_PF_NBR, l, [=] { k_dgs_pf_nbr_v<T, V><<<hg, BS, 0, c->ks>>>(g, x, dscr, 1); });
+  for (int t = 0; t <= 4; ++t)
+    launch(c, t < 4 ? STOKES_KC_DGS_PF_OWN : STOKES_KC_DGS_PF_NBR, l,
+           [=] { k_dgs_pf_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, dscr, t); });
 }
 
 // Reverse sweep: Gauss-Seidel on M^T L~ (Eq. ldist) in exactly the reverse
-// order: pressures black, red; velocities black, red.
+// order: pressure stages 3, 2, 1, 0 (classes 7..0); velocities black, red.
 template <typename T>
 void dgs_reverse(stokes_ctx* c, int l, T* x, const T* b) {
   constexpr int V = dgs_pack<T>();
   const Geom g = c->lev[l].g;
   const int hg = dgs_grid<T>(g);
-  for (int col = 1; col >= 0; --col)
-    launch(c, STOKES_KC_DGS_PR, l, [=] { k_dgs_pr_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
+  for (int st = 3; st >= 0; --st)
+    launch(c, STOKES_KC_DGS_PR, l, [=] { k_dgs_pr_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, st); });
   for (int col = 1; col >= 0; --col)
     launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
 }
@@ -505,12 +500,6 @@ void fill_zero(stokes_ctx* c, T* x, long n, int level = 0) {
 // with cycle = 2 the coarse correction is two cycles (a W-cycle)
 template <typename T>
 void vcycle(stokes_ctx* c, int l, const T* b, T* x, bool zero_init = true) {
-  if (l == c->tail) {
-    const TailArgs a = c->targs;
-    const TailLev* tl = c->tlev;
-    launch(c, STOKES_KC_TAIL, l, [=] { k_tail<T><<<1, TAIL_BS, 0, c->ks>>>(a, tl, x, b); });
-    return;
-  }
   const Geom g = c->lev[l].g;
   if (zero_init) fill_zero(c, x, 4L * g.field, l);
   if (l == c->L - 1) {
@@ -654,7 +643,7 @@ int stokes_default_params(int32_t nx, int32_t ny, int32_t nz, double h, stokes_p
   p->nu = 2;
   p->n_boundary = 1;
   p->vcycle_precision = 64;
-  p->smoother = STOKES_SMOOTHER_SPLIT;
+  p->smoother = STOKES_SMOOTHER_SYMMETRIC;
   p->flags = STOKES_FLAG_REMOVE_MEAN;
   p->vanka = STOKES_VANKA_MULT8;
   p->cycle = 1;
@@ -733,46 +722,6 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
     if (hipMemcpyAsync(c->cinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
             hipSuccess ||
         hipMemcpyAsync(c->cdof, dof.data(), dof.size() * sizeof(int), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
-      return fail(STOKES_EDEVICE);
-  }
-  // the tail: the first level with at most TAIL_CELLS cells, down to the coarsest
-  if ((p->flags & STOKES_FLAG_TAIL) && p->vanka == STOKES_VANKA_MULT8 && p->cycle == 1) {
-    for (int l = 0; l < L; ++l) {
-      const Geom& g = c->lev[l].g;
-      if ((long)g.nx * g.ny * g.nz <= TAIL_CELLS && L - l <= TAIL_MAX) {
-        c->tail = l;
-        break;
-      }
-    }
-  }
-  if (c->tail >= 0) {
-    std::vector<TailLev> tl(L - c->tail);
-    for (int l = c->tail; l < L; ++l) {
-      TailLev& t = tl[l - c->tail];
-      const Level& lv = c->lev[l];
-      t = TailLev{};
-      t.g = lv.g;
-      if (l + 1 < L) t.gc = c->lev[l + 1].g;
-      t.x = lv.x;
-      t.b = lv.b;
-      t.r = lv.r;
-      t.dscr = lv.dscr;
-      t.kinv = lv.kinv;
-      for (int k = 0; k < 8; ++k) {
-        t.vc[k] = lv.vcells[k];
-        t.nv[k] = lv.nv[k];
-      }
-      if (l == L - 1) {
-        t.cinv = c->cinv;
-        t.cdof = c->cdof;
-        t.nc = c->nc;
-      }
-    }
-    c->targs = TailArgs{L - c->tail, p->nu, p->n_boundary, p->smoother == STOKES_SMOOTHER_SYMMETRIC ? 1 : 0,
-                        c->vdelta};
-    if (hipMemcpyAsync(c->tlev, tl.data(), sizeof(TailLev) * tl.size(), hipMemcpyHostToDevice, c->stream) !=
-            hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
       return fail(STOKES_EDEVICE);
   }

@@ -19,7 +19,6 @@ LIB_PATH = os.path.join(_PKG, "libstokes_mgsqmr.so")
 STOKES_OK, STOKES_EINVAL, STOKES_ENOCONV, STOKES_EBREAKDOWN, STOKES_ENONFINITE, STOKES_EDEVICE = range(6)
 STOKES_FLAG_REMOVE_MEAN = 1
 STOKES_FLAG_NO_GRAPH = 2
-STOKES_FLAG_TAIL = 4
 SMOOTHERS = {"split": 0, "symmetric": 1}
 VANKA = {"mult8": 0, "mult27": 1, "additive": 2}
 STATUS_NAMES = {0: "ok", 1: "einval", 2: "enoconv", 3: "ebreakdown", 4: "enonfinite", 5: "edevice"}
@@ -53,7 +52,7 @@ EXPORTS = ("stokes_default_params", "stokes_workspace_bytes", "stokes_setup", "s
 
 # kernel classes of stokes_profile()
 KC = {"apply": 0, "dgs_u": 1, "dgs_pf_own": 2, "dgs_pf_nbr": 3, "dgs_pr": 4, "vanka_delta": 5, "vanka_apply": 6,
-      "restrict": 7, "prolong": 8, "coarse": 9, "blas": 10, "tail": 11}
+      "restrict": 7, "prolong": 8, "coarse": 9, "blas": 10}
 KC_ALL, KC_OFF = -1, -2
 
 _lib = None
@@ -245,7 +244,7 @@ class StokesSolver:
     torch tensors of `layout.total` elements on the context's device."""
 
     def __init__(self, nx, ny, nz, h=None, *, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1,
-                 schedule="split", precision=64, remove_mean=True, graphs=True, tail=False, vanka="mult8",
+                 schedule="symmetric", precision=64, remove_mean=True, graphs=True, vanka="mult8",
                  cycle=1, device=None, stream=None):
         import torch
         self.torch = torch
@@ -255,8 +254,7 @@ class StokesSolver:
         p.smoother = SMOOTHERS[schedule]
         p.vcycle_precision = precision
         p.vanka, p.cycle = VANKA[vanka], int(cycle)
-        p.flags = (STOKES_FLAG_REMOVE_MEAN if remove_mean else 0) | (0 if graphs else STOKES_FLAG_NO_GRAPH) | \
-            (STOKES_FLAG_TAIL if tail else 0)
+        p.flags = (STOKES_FLAG_REMOVE_MEAN if remove_mean else 0) | (0 if graphs else STOKES_FLAG_NO_GRAPH)
         self.params = p
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -361,7 +359,7 @@ class StokesBatch:
     schedule and V-cycle precision.  Batch vectors are float64 tensors of
     `size` elements; box d's state is `vector[offset[d] : offset[d] + total]`."""
 
-    def __init__(self, dims, h=1.0 / 128, *, eta=1.0, gamma=1e-3, nu=2, n_boundary=1, schedule="split",
+    def __init__(self, dims, h=1.0 / 128, *, eta=1.0, gamma=1e-3, nu=2, n_boundary=1, schedule="symmetric",
                  precision=32, remove_mean=True, levels=None, device=None, stream=None):
         import torch
         self.torch = torch

@@ -44,15 +44,15 @@ def test_operator_apply_matches_oracle(dims, penalized):
     assert float(y[mask == 0].abs().max()) == 0.0
 
 
-@pytest.mark.parametrize("dims,levels,nu,nb,sched", [((32, 32, 32), 0, 2, 1, "split"), ((16, 24, 8), 0, 2, 1, "split"),
+@pytest.mark.parametrize("dims,levels,nu,nb,sched", [((32, 32, 32), 0, 2, 1, "symmetric"), ((16, 24, 8), 0, 2, 1, "symmetric"),
                                                     ((8, 8, 8), 2, 1, 1, "split"), ((16, 16, 16), 0, 3, 2, "split"),
-                                                    ((12, 20, 16), 3, 2, 1, "split"),
-                                                    ((32, 32, 32), 0, 2, 2, "split"),
+                                                    ((12, 20, 16), 3, 2, 1, "symmetric"),
+                                                    ((32, 32, 32), 0, 2, 2, "symmetric"),
                                                     # level-0 classes of ~20k cells: one thread per subdomain
-                                                    ((256, 256, 32), 5, 2, 1, "split"),
+                                                    ((256, 256, 32), 5, 2, 1, "symmetric"),
                                                     # a larger ragged box
-                                                    ((96, 48, 32), 0, 2, 1, "split"),
-                                                    ((32, 32, 32), 0, 2, 1, "symmetric"),
+                                                    ((96, 48, 32), 0, 2, 1, "symmetric"),
+                                                    ((32, 32, 32), 0, 2, 1, "split"),
                                                     ((16, 24, 8), 0, 4, 2, "symmetric")])
 def test_vcycle_matches_oracle(dims, levels, nu, nb, sched):
     torch = cuda()
@@ -109,9 +109,9 @@ def _oracle_runs(H, b, maxit):
     return xs, x, info, sens, info_p
 
 
-@pytest.mark.parametrize("dims,seed,sched", [((16, 16, 16), 3, "split"), ((32, 32, 32), 0, "split"),
-                                             ((32, 32, 32), 1, "split"), ((16, 24, 32), 2, "split"),
-                                             ((32, 32, 32), 0, "symmetric")])
+@pytest.mark.parametrize("dims,seed,sched", [((16, 16, 16), 3, "symmetric"), ((32, 32, 32), 0, "symmetric"),
+                                             ((32, 32, 32), 1, "symmetric"), ((16, 24, 32), 2, "symmetric"),
+                                             ((32, 32, 32), 0, "split")])
 def test_sqmr_iterates_match_oracle(dims, seed, sched):
     """Every checked iterate x_j agrees with the oracle's to 1e-10 (relative
     2-norm) while the oracle's own 1-ulp sensitivity is below 1e-12, and to
@@ -246,29 +246,3 @@ def test_vcycle_graph_replays_match_eager_launches():
         xg, ig = g_sol.solve(b)
         xe, ie = e_sol.solve(b)
         assert ig["iters"] == ie["iters"] and torch.equal(xg, xe)
-
-
-@pytest.mark.parametrize("dims,precision,sched", [((16, 16, 16), 64, "split"), ((32, 32, 32), 64, "split"),
-                                                  ((64, 48, 32), 64, "symmetric"), ((32, 32, 32), 32, "split"),
-                                                  ((64, 64, 64), 32, "split")])
-def test_one_workgroup_tail_matches_per_level_launches(dims, precision, sched):
-    """The levels of <= 16^3 cells run as one workgroup with the one-cell item
-    bodies; the per-level launches run packed kernels of the same arithmetic,
-    which the compiler may contract into fused multiply-adds differently.  So
-    the V-cycle agrees to rounding and the solve takes the same iterations."""
-    torch = cuda()
-    from paper_2312_10615_amd.stokes import StokesSolver
-    from oracle.domain import Domain, box_labels
-    announce(f"tail vs per-level launches {dims} FP{precision} {sched}")
-    h = 1.0 / max(dims)
-    a = StokesSolver(*dims, h=h, precision=precision, schedule=sched, tail=True)
-    b_ = StokesSolver(*dims, h=h, precision=precision, schedule=sched)
-    dom = Domain(box_labels(dims), h)
-    rhs = a.pack(forcing_rhs(dom.active, dims, h, seed=3))
-    va, vb = a.vcycle(rhs), b_.vcycle(rhs)
-    tol = 1e-12 if precision == 64 else 1e-5
-    assert float((va - vb).abs().max()) <= tol * float(vb.abs().max())
-    xa, ia = a.solve(rhs, rtol=1e-8, maxit=200)
-    xb, ib = b_.solve(rhs, rtol=1e-8, maxit=200)
-    assert ia["iters"] == ib["iters"]
-    assert float((xa - xb).abs().max()) <= (1e-10 if precision == 64 else 1e-6) * float(xb.abs().max())
