@@ -62,7 +62,8 @@ enum {
   STOKES_ENOCONV = 2,     /* maxit reached before the tolerance; x holds the last iterate */
   STOKES_EBREAKDOWN = 3,  /* sigma = 0 or rho = 0 in SQMR; x holds the last iterate */
   STOKES_ENONFINITE = 4,  /* a NaN/Inf scalar appeared (e.g. non-finite b) */
-  STOKES_EDEVICE = 5      /* a HIP runtime call failed */
+  STOKES_EDEVICE = 5,     /* a HIP runtime call failed */
+  STOKES_ETOOLARGE = 6    /* stokes_solve_static: the workspace would exceed STOKES_STATIC_BYTES */
 };
 
 /* Smoothing schedules of the V-cycle (Section 3: the pre- and post-smoothing
@@ -216,6 +217,24 @@ int stokes_vcycle(stokes_ctx* ctx, const double* s, double* t);
  * solve status, also stored in info->status (info may be NULL). */
 int stokes_solve(stokes_ctx* ctx, const double* b, double* x, double rtol, int32_t maxit,
                  stokes_info* info);
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): stokes_solve with no
+ * context and no workspace argument.  The set-up, the solve and the tear-down
+ * of stokes_setup / stokes_solve / stokes_destroy run on a workspace inside
+ * the library, a device array of STOKES_STATIC_BYTES (one per GPU, held until
+ * the process ends); the call makes no device or pinned-host allocation and
+ * creates no stream, event or graph (its V-cycles launch kernel by kernel).
+ * p, b, x, rtol, maxit and info as for stokes_setup and stokes_solve; work
+ * goes on hip_stream (the current device's), and the call returns after the
+ * stream completes.  STOKES_ETOOLARGE when stokes_workspace_bytes(p) exceeds
+ * STOKES_STATIC_BYTES (64 MiB: boxes up to 64^3 cells), before any GPU work.
+ * Every call on one GPU uses the same array and leaves its contents behind
+ * (the set-up clears what must start at zero): calls that overlap on one GPU
+ * (two host threads, or two streams) race and must not be issued. */
+#define STOKES_STATIC_BYTES (64u << 20)
+int stokes_solve_static(const stokes_params* p, const double* b, double* x, double rtol, int32_t maxit,
+                        stokes_info* info, void* hip_stream);
 
 /* Diagnostics: per-kernel timing with HIP events recorded on the context's
  * stream around the selected launches (the "tracing" aux subsystem).

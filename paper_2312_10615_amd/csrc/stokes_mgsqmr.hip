@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -69,7 +70,9 @@ struct stokes_ctx {
   double* partial = nullptr;
   int npartial = 0;
   double* dscal = nullptr;   // device scalars: reduction results
-  double* hscal = nullptr;   // pinned host mirror
+  double* hscal = nullptr;   // host mirror: pinned, or hscal_local for a context on the static scratch
+  double hscal_local[16] = {};
+  bool on_static = false;    // workspace = the library's static scratch (stokes_solve_static)
   // coarsest level
   double* cinv = nullptr;
   int* cdof = nullptr;
@@ -625,45 +628,14 @@ int reduce_to_host(stokes_ctx* c, int nblk, int stride) {
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// C ABI
-// ---------------------------------------------------------------------------
-extern "C" {
+namespace {
 
-int stokes_default_params(int32_t nx, int32_t ny, int32_t nz, double h, stokes_params* p) {
-  if (!p) return STOKES_EINVAL;
-  std::memset(p, 0, sizeof(*p));
-  p->nx = nx;
-  p->ny = ny;
-  p->nz = nz;
-  p->h = h;
-  p->eta = 1.0;
-  p->gamma = 1e-3;
-  p->levels = 0;
-  p->nu = 2;
-  p->n_boundary = 1;
-  p->vcycle_precision = 64;
-  p->smoother = STOKES_SMOOTHER_SYMMETRIC;
-  p->flags = STOKES_FLAG_REMOVE_MEAN;
-  p->vanka = STOKES_VANKA_MULT8;
-  p->cycle = 1;
-  return STOKES_OK;
-}
-
-int stokes_workspace_bytes(const stokes_params* p, size_t* bytes) {
-  int L = 0;
-  const int st = validate(p, &L);
-  if (st != STOKES_OK) return st;
-  if (!bytes) return STOKES_EINVAL;
-  stokes_ctx tmp;
-  tmp.prm = *p;
-  Carver cv(nullptr, 0, true);
-  carve(&tmp, cv, L);
-  *bytes = (cv.used + 255) & ~size_t(255);
-  return STOKES_OK;
-}
-
-int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hip_stream, stokes_ctx** out) {
+// Set-up of a context on `workspace`.  With on_static the workspace is the
+// library's static scratch and the context allocates nothing: no pinned host
+// mirror (the scalars come back into the context itself), no capture stream,
+// no graphs (its V-cycles launch kernel by kernel).
+int setup_ctx(const stokes_params* p, void* workspace, size_t bytes, void* hip_stream, bool on_static,
+              stokes_ctx** out) {
   if (!out) return STOKES_EINVAL;
   *out = nullptr;
   int L = 0;
@@ -678,16 +650,22 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
   c->L = L;
   c->stream = (hipStream_t)hip_stream;
   c->ks = c->stream;
+  c->on_static = on_static;
   Carver cv(workspace, bytes, false);
   carve(c, cv, L);
-  if (hipHostMalloc((void**)&c->hscal, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess) {
-    delete c;
-    return STOKES_EDEVICE;
-  }
-  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipHostFree(c->hscal);
-    delete c;
-    return STOKES_EDEVICE;
+  if (on_static) {
+    c->prm.flags |= STOKES_FLAG_NO_GRAPH;
+    c->hscal = c->hscal_local;
+  } else {
+    if (hipHostMalloc((void**)&c->hscal, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess) {
+      delete c;
+      return STOKES_EDEVICE;
+    }
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipHostFree(c->hscal);
+      delete c;
+      return STOKES_EDEVICE;
+    }
   }
   // Host tables, uploaded with synchronous waits so the host buffers can go.
   auto fail = [&](int code) {
@@ -745,6 +723,79 @@ int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hi
   *out = c;
   return STOKES_OK;
 }
+
+}  // namespace
+
+// The static scratch of stokes_solve_static: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (in host code it is only a stand-in for
+// the symbol): it looks the device address up once per device, with that
+// device current, and uses that pointer.
+static __device__ __align__(256) unsigned char scratch[STOKES_STATIC_BYTES];
+
+namespace {
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[STATIC_MAX_DEVICES] = {};
+
+int static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES) return STOKES_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return STOKES_EDEVICE;
+    g_static_ptr[dev] = ptr;
+  }
+  *out = g_static_ptr[dev];
+  return STOKES_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int stokes_default_params(int32_t nx, int32_t ny, int32_t nz, double h, stokes_params* p) {
+  if (!p) return STOKES_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = nz;
+  p->h = h;
+  p->eta = 1.0;
+  p->gamma = 1e-3;
+  p->levels = 0;
+  p->nu = 2;
+  p->n_boundary = 1;
+  p->vcycle_precision = 64;
+  p->smoother = STOKES_SMOOTHER_SYMMETRIC;
+  p->flags = STOKES_FLAG_REMOVE_MEAN;
+  p->vanka = STOKES_VANKA_MULT8;
+  p->cycle = 1;
+  return STOKES_OK;
+}
+
+int stokes_workspace_bytes(const stokes_params* p, size_t* bytes) {
+  int L = 0;
+  const int st = validate(p, &L);
+  if (st != STOKES_OK) return st;
+  if (!bytes) return STOKES_EINVAL;
+  stokes_ctx tmp;
+  tmp.prm = *p;
+  Carver cv(nullptr, 0, true);
+  carve(&tmp, cv, L);
+  *bytes = (cv.used + 255) & ~size_t(255);
+  return STOKES_OK;
+}
+
+int stokes_setup(const stokes_params* p, void* workspace, size_t bytes, void* hip_stream, stokes_ctx** out) {
+  return setup_ctx(p, workspace, bytes, hip_stream, false, out);
+}
+
 
 int stokes_layout(const stokes_ctx* c, stokes_layout_t* out) {
   if (!c || !out) return STOKES_EINVAL;
@@ -993,8 +1044,27 @@ void stokes_destroy(stokes_ctx* c) {
   drop_graphs(c);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   if (c->cap) (void)hipStreamDestroy(c->cap);
-  if (c->hscal) (void)hipHostFree(c->hscal);
+  if (c->hscal && !c->on_static) (void)hipHostFree(c->hscal);
   delete c;
+}
+
+int stokes_solve_static(const stokes_params* p, const double* b, double* x, double rtol, int32_t maxit,
+                        stokes_info* info, void* hip_stream) {
+  int L = 0;
+  const int st = validate(p, &L);
+  if (st != STOKES_OK) return st;
+  size_t need = 0;
+  stokes_workspace_bytes(p, &need);
+  if (need > STOKES_STATIC_BYTES) return STOKES_ETOOLARGE;
+  if (!b || !x || b == x || maxit < 0 || !(rtol >= 0)) return STOKES_EINVAL;
+  void* ws = nullptr;
+  if (static_scratch(&ws) != STOKES_OK) return STOKES_EDEVICE;
+  stokes_ctx* c = nullptr;
+  const int rc = setup_ctx(p, ws, STOKES_STATIC_BYTES, hip_stream, true, &c);
+  if (rc != STOKES_OK) return rc;
+  const int status = stokes_solve(c, b, x, rtol, maxit, info);
+  stokes_destroy(c);
+  return status;
 }
 
 const char* stokes_strerror(int status) {
@@ -1005,6 +1075,7 @@ const char* stokes_strerror(int status) {
     case STOKES_EBREAKDOWN: return "SQMR breakdown (sigma or rho is zero)";
     case STOKES_ENONFINITE: return "non-finite value in the iteration";
     case STOKES_EDEVICE: return "HIP runtime error";
+    case STOKES_ETOOLARGE: return "problem too large for the static scratch of stokes_solve_static";
     default: return "unknown status";
   }
 }

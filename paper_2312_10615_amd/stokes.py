@@ -16,12 +16,13 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libstokes_mgsqmr.so")
 
-STOKES_OK, STOKES_EINVAL, STOKES_ENOCONV, STOKES_EBREAKDOWN, STOKES_ENONFINITE, STOKES_EDEVICE = range(6)
+STOKES_OK, STOKES_EINVAL, STOKES_ENOCONV, STOKES_EBREAKDOWN, STOKES_ENONFINITE, STOKES_EDEVICE, STOKES_ETOOLARGE = range(7)
+STOKES_STATIC_BYTES = 64 << 20
 STOKES_FLAG_REMOVE_MEAN = 1
 STOKES_FLAG_NO_GRAPH = 2
 SMOOTHERS = {"split": 0, "symmetric": 1}
 VANKA = {"mult8": 0, "mult27": 1, "additive": 2}
-STATUS_NAMES = {0: "ok", 1: "einval", 2: "enoconv", 3: "ebreakdown", 4: "enonfinite", 5: "edevice"}
+STATUS_NAMES = {0: "ok", 1: "einval", 2: "enoconv", 3: "ebreakdown", 4: "enonfinite", 5: "edevice", 6: "etoolarge"}
 
 
 class StokesParams(ctypes.Structure):
@@ -45,7 +46,7 @@ class StokesInfo(ctypes.Structure):
 
 
 EXPORTS = ("stokes_default_params", "stokes_workspace_bytes", "stokes_setup", "stokes_layout", "stokes_level_layout",
-           "stokes_restrict", "stokes_prolong", "stokes_lift", "stokes_apply", "stokes_vcycle", "stokes_solve", "stokes_profile",
+           "stokes_restrict", "stokes_prolong", "stokes_lift", "stokes_apply", "stokes_vcycle", "stokes_solve", "stokes_solve_static", "stokes_profile",
            "stokes_profile_read", "stokes_destroy", "stokes_strerror", "stokes_batch_workspace_bytes",
            "stokes_batch_setup", "stokes_batch_layout", "stokes_batch_size", "stokes_batch_autotune",
            "stokes_batch_set_chunks", "stokes_batch_solve", "stokes_batch_destroy")
@@ -78,6 +79,7 @@ def load_library(path: str = LIB_PATH):
     lib.stokes_apply.argtypes = [vp, vp, vp, i32]
     lib.stokes_vcycle.argtypes = [vp, vp, vp]
     lib.stokes_solve.argtypes = [vp, vp, vp, f64, i32, P(StokesInfo)]
+    lib.stokes_solve_static.argtypes = [P(StokesParams), vp, vp, f64, i32, P(StokesInfo), vp]
     lib.stokes_profile.argtypes = [vp, i32, i32]
     lib.stokes_profile_read.argtypes = [vp, i32, i32, P(ctypes.c_double), P(ctypes.c_int64)]
     lib.stokes_destroy.argtypes = [vp]
@@ -169,6 +171,23 @@ def stokes_solve(ctx, b_ptr: int, x_ptr: int, rtol: float, maxit: int, record_hi
     code = load_library().stokes_solve(ctx, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), float(rtol),
                                        int(maxit), ctypes.byref(info))
     history = [hist[i] for i in range(info.iters + 1)] if hist is not None and code != STOKES_EINVAL else None
+    return code, info, history
+
+
+def stokes_solve_static(params: StokesParams, b_ptr: int, x_ptr: int, rtol: float, maxit: int, stream_ptr: int,
+                        record_history: bool = True):
+    """stokes_solve on the library's static scratch (no context, no workspace):
+    returns (status, info, history) like `stokes_solve`."""
+    info = StokesInfo()
+    hist = None
+    if record_history:
+        hist = (ctypes.c_double * (maxit + 1))()
+        info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    code = load_library().stokes_solve_static(ctypes.byref(params), ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr),
+                                              float(rtol), int(maxit), ctypes.byref(info),
+                                              ctypes.c_void_p(stream_ptr))
+    ok = hist is not None and code not in (STOKES_EINVAL, STOKES_ETOOLARGE, STOKES_EDEVICE)
+    history = [hist[i] for i in range(info.iters + 1)] if ok else None
     return code, info, history
 
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_defaults_and_workspace_sizes():
     p = S.stokes_default_params(32, 32, 32, 1 / 32)
     assert (p.eta, p.gamma, p.levels, p.nu, p.n_boundary, p.vcycle_precision, p.smoother) == \
-        (1.0, 1e-3, 0, 2, 1, 64, S.SMOOTHERS["split"])
+        (1.0, 1e-3, 0, 2, 1, 64, S.SMOOTHERS["symmetric"])
     small = S.stokes_workspace_bytes(p)
     big = S.stokes_workspace_bytes(S.stokes_default_params(64, 64, 64, 1 / 64))
     assert 0 < small < big
@@ -44,7 +44,8 @@ def test_defaults_and_workspace_sizes():
     assert 0 < mixed < small * 1.1
 
 
-@pytest.mark.parametrize("field,value", [("nx", 1), ("h", 0.0), ("eta", -1.0), ("nu", 0), ("n_boundary", 0),
+@pytest.mark.parametrize("field,value", [("nx", 1), ("h", 0.0), ("eta", -1.0), ("gamma", 0.0), ("gamma", -1e-3),
+                                         ("nu", 0), ("n_boundary", 0),
                                          ("vcycle_precision", 16), ("vcycle_precision", 33), ("levels", 6), ("levels", -1), ("smoother", 7),
                                          ("vanka", 3), ("cycle", 3), ("cycle", 0),
                                          ("symmetric-odd-nu", 3)])
@@ -79,8 +80,21 @@ def test_setup_rejects_null_workspace_without_touching_a_device():
 
 
 def test_strerror_names_every_status():
-    for code in range(6):
+    for code in range(7):
         assert S.stokes_strerror(code) != "unknown status"
+
+
+def test_static_solve_rejects_oversized_and_null_inputs_on_the_host():
+    """stokes_solve_static checks the problem against its static scratch
+    (64 MiB) and its pointers before any GPU work."""
+    p = S.stokes_default_params(64, 64, 64, 1 / 64)
+    assert S.stokes_workspace_bytes(p) <= S.STOKES_STATIC_BYTES
+    big = S.stokes_default_params(128, 128, 128, 1 / 128)
+    assert S.stokes_workspace_bytes(big) > S.STOKES_STATIC_BYTES
+    code, _, _ = S.stokes_solve_static(big, 0, 0, 1e-8, 10, 0)
+    assert code == S.STOKES_ETOOLARGE
+    code, _, _ = S.stokes_solve_static(S.stokes_default_params(16, 16, 16, 1 / 16), 0, 0, 1e-8, 10, 0)
+    assert code == S.STOKES_EINVAL
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4), (5, 6, 7), (16, 9, 3)])
