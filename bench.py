@@ -36,13 +36,13 @@ def dof_counts(n):
 
 
 def algorithmic_bytes(kernel, n):
-    """Compulsory bytes of one launch at level 0 (each operand streamed once)."""
+    """Compulsory bytes of one launch at level 0 (each operand streamed once).
+    dgs_pr: one colour's worth of the reverse pressure step (the stage
+    launches of one sweep split it unevenly)."""
     nu, npr = dof_counts(n)
     return {
         "dgs_u": (2 * nu + npr) * S,            # read u, p, b_u(colour); write u(colour)
         "dgs_pr": (nu + 2.5 * npr) * S,         # read b_u, b_p, p; write p(colour)
-        "dgs_pf_own": (2 * nu + 2 * npr) * S,   # read u, p/2, b_p/2; write u, p/2, delta/2
-        "dgs_pf_nbr": 1.5 * npr * S,            # read delta/2, p/2; write p/2
         "apply": 3 * (nu + npr) * S,            # residual: read x, b; write r
         "restrict": 1.125 * (nu + npr) * S,
         "prolong": 2.125 * (nu + npr) * S,
@@ -74,32 +74,162 @@ def counter_traffic(kernel, n):
     return round((k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0)
 
 
-def cpu_baseline(iters, n_full, seed):
-    """Oracle timed on the host: one V-cycle plus one operator application (the
-    work of one MG-SQMR iteration apart from vector updates) at 128^3, scaled by
-    8 (work is linear in the unknowns) to 256^3 and by the iteration count."""
+def vcycle_model_bytes(n, s=S, levels=7):
+    """Compulsory HBM bytes of one V-cycle on an n^3 box (per-sweep traffic
+    model: each dependent colour half-sweep streams its operands once).  Per
+    level: two symmetric DGS (forward + reverse sweep, (16 n_u + 14 n_p) s
+    each), four symmetric Vanka steps (~114 values per V1 cell each: 16 class
+    passes x 1/8 of the cells x ~57 values), residual + restriction and
+    prolongation + correction ((2 n + n/8) s each); the coarsest level's dense
+    solve reads its inverse once (8-byte values).  With 4-byte level values
+    (the FP32 V-cycle) the conversions of s to FP32 and of the result back to
+    FP64 add (8 + 4) bytes per unknown each."""
+    nu0, np0 = dof_counts(n)
+    total = 0.0 if s == 8 else 24.0 * (nu0 + np0)
+    m = n
+    for lev in range(levels):
+        nu, npr = dof_counts(m)
+        if lev == levels - 1:
+            total += (nu + npr) ** 2 * 8
+            break
+        v1_cells = m ** 3 - (m - 2) ** 3
+        total += 2 * (16 * nu + 14 * npr) * s + 4 * 114 * v1_cells * s + 2 * (2 + 1 / 8) * (nu + npr) * s
+        m //= 2
+    return total
+
+
+def cpu_baseline(iters, n_full, seed, gpu_small):
+    """The oracle timed on the host, one thread.
+    Measured: the complete oracle MG-SQMR solve of the 32^3 workload (4 levels,
+    seed 0, rtol 1e-8), median of 3, beside the GPU's time for the same solve.
+    Extrapolated to the headline 256^3 solve (labelled as such): one oracle
+    V-cycle, two operator applications and SQMR's vector passes of one
+    iteration at 128^3, scaled by 8 (work linear in the unknowns) and by the
+    number of V-cycles of the GPU solve (iterations + 1)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle.multigrid import Hierarchy, vcycle
-    from oracle.operator import apply_operator
+    from oracle.operator import apply_operator, to_vector
+    from oracle.sqmr import mg_sqmr
     from paper_2312_10615_amd.workloads import sinusoid_forcing
 
-    n = n_full // 2
-    with threadpool_limits(limits=1):
-        H = Hierarchy((n, n, n), 1.0 / n)
+    def rhs(H, m):
         dom = H.doms[0]
-        f = sinusoid_forcing(n, n, n, 1.0 / n, seed=seed)
-        b = tuple(np.where(dom.active[a], f[a], 0.0) for a in range(3)) + (np.zeros((n, n, n)),)
+        f = sinusoid_forcing(m, m, m, 1.0 / m, seed=seed)
+        return tuple(np.where(dom.active[a], f[a], 0.0) for a in range(3)) + (np.zeros((m, m, m)),)
+
+    with threadpool_limits(limits=1):
+        m = 32
+        H = Hierarchy((m, m, m), 1.0 / m)
+        b = rhs(H, m)
+        runs, it_small = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, inf = mg_sqmr(H, b, rtol=1e-8, maxit=200)
+            runs.append(time.perf_counter() - t0)
+            it_small = inf["iters"]
+        t_small = float(np.median(runs))
+        n = n_full // 2
+        H = Hierarchy((n, n, n), 1.0 / n)
+        b = rhs(H, n)
+        bv = to_vector(H.doms[0], b)
         t0 = time.perf_counter()
         vcycle(H, b)
-        apply_operator(dom, b, 0.0)
+        apply_operator(H.doms[0], b, 0.0)
+        apply_operator(H.doms[0], b, 0.0)
+        q, t, d, x, r = bv.copy(), bv.copy(), bv.copy(), bv.copy(), bv.copy()
+        for _ in range(3):   # dots (sigma, ||t||, rho, ||r||) and updates (s, d, x, q): ~16 vector passes
+            r = r - 0.5 * t
+            d = 0.3 * d + 0.2 * q
+            x = x + d
+            q = t + 0.7 * q
+            float(np.dot(q, t))
         t1 = time.perf_counter()
     per_iter = (t1 - t0) * (n_full / n) ** 3
-    return {"value": per_iter * (iters + 1), "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"one oracle V-cycle + one operator apply at {n}^3 (seed {seed}, 1 thread) took "
-                      f"{t1 - t0:.1f} s; scaled x{(n_full // n) ** 3} to {n_full}^3 and x{iters + 1} "
-                      f"V-cycles of the GPU solve", "host_cpus": os.cpu_count()}
+    return {"value": round(per_iter * (iters + 1), 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"extrapolated: one oracle V-cycle, two operator applications and one iteration's SQMR "
+                      f"vector passes at {n}^3 (seed {seed}, 1 thread) took {t1 - t0:.1f} s, scaled x"
+                      f"{(n_full // n) ** 3} to {n_full}^3 and x{iters + 1} V-cycles of the GPU solve",
+            "measured_32": {"oracle_s": round(t_small, 3), "oracle_iterations": it_small,
+                            "gpu_s": gpu_small["s"], "gpu_iterations": gpu_small["iters"],
+                            "ratio": round(t_small / gpu_small["s"], 1),
+                            "what": "complete MG-SQMR solve of the 32^3 workload (4 levels, seed 0, rtol 1e-8); "
+                                    "oracle median of 3 on 1 thread, GPU median of 5"},
+            "host_cpus": os.cpu_count()}
+
+
+def gpu_small_solve(seed, rtol):
+    """The 32^3 workload on the GPU (the size the oracle finishes in seconds)."""
+    import numpy as np
+    import torch
+
+    from paper_2312_10615_amd.stokes import StokesSolver
+    from paper_2312_10615_amd.workloads import sinusoid_forcing
+    m = 32
+    sol = StokesSolver(m, m, m, h=1.0 / m)
+    f = sinusoid_forcing(m, m, m, 1.0 / m, seed=seed)
+    b = sol.pack((f[0], f[1], f[2], np.zeros((m, m, m))))
+    sol.solve(b, rtol=rtol, maxit=200)
+    ts = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = sol.solve(b, rtol=rtol, maxit=200)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    sol.close()
+    return {"s": round(float(np.median(ts)), 5), "iters": info["iters"]}
+
+
+def mixed_384_leg(steps, rtol, seed):
+    """FP32 V-cycle at 384^3 (7 levels down to 6^3, 756 coarsest unknowns)
+    against the FP64 GPU solve of the same problem (the error reference)."""
+    import numpy as np
+    import torch
+
+    from paper_2312_10615_amd.stokes import StokesSolver
+    from paper_2312_10615_amd.workloads import sinusoid_forcing_device
+    n = 384
+    h = 1.0 / n
+    out = {}
+    x64 = None
+    for prec in (64, 32):
+        sol = StokesSolver(n, n, n, h=h, precision=prec)
+        f = sinusoid_forcing_device(n, n, n, h, seed, sol.device)
+        b = sol.pack(f + (torch.zeros((n, n, n), dtype=torch.float64, device=sol.device),))
+        del f
+        x, info = sol.solve(b, rtol=rtol, maxit=500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = steps if prec == 32 else 1
+        for _ in range(k):
+            x, info = sol.solve(b, rtol=rtol, maxit=500)
+        torch.cuda.synchronize()
+        out[prec] = {"s": (time.perf_counter() - t0) / k, "iters": info["iters"], "relres": info["relres"],
+                     "status": info["status"], "levels": sol.layout.levels}
+        if prec == 64:
+            x64 = x
+        else:
+            out["err"] = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+            g = torch.Generator(device=sol.device).manual_seed(5)
+            shapes = [(n + 1, n, n), (n, n + 1, n), (n, n, n + 1), (n, n, n)]
+            xa = sol.pack(tuple(torch.randn(sh, generator=g, dtype=torch.float64, device=sol.device) for sh in shapes))
+            ya = sol.pack(tuple(torch.randn(sh, generator=g, dtype=torch.float64, device=sol.device) for sh in shapes))
+            wa, wb = float(torch.dot(xa, sol.vcycle(ya))), float(torch.dot(sol.vcycle(xa), ya))
+            out["asym"] = abs(wa - wb) / abs(wa)
+            del xa, ya
+        sol.close()
+        del sol, b, x
+        torch.cuda.empty_cache()
+    print(f"[bench] 384^3: fp64 {out[64]['s'] * 1e3:.1f} ms ({out[64]['iters']} it), fp32 V-cycle "
+          f"{out[32]['s'] * 1e3:.1f} ms ({out[32]['iters']} it), err {out['err']:.2e}", file=sys.stderr, flush=True)
+    return {"value": round(out[32]["s"], 6), "unit": "s", "n": n, "levels": out[32]["levels"],
+            "iterations": out[32]["iters"], "final_relres": out[32]["relres"], "status": out[32]["status"],
+            "fp64_s": round(out[64]["s"], 6), "fp64_iterations": out[64]["iters"],
+            "speedup_vs_fp64": round(out[64]["s"] / out[32]["s"], 3),
+            "rel_err_vs_fp64_solution": out["err"], "vcycle_asymmetry": out["asym"],
+            "error_reference": "the FP64 GPU solve of the same problem (the oracle at 384^3 needs ~40 GB and hours)"}
 
 
 def batched_leg(steps, rtol, seed):
@@ -247,6 +377,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-V-cycle (mixed precision) leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-box batched leg")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--no-384", action="store_true", help="skip the 384^3 FP32-V-cycle leg")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-schedule leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
@@ -267,6 +399,8 @@ def main():
     t_setup = time.perf_counter()
     sol = StokesSolver(n, n, n, h=h)
     t_setup = time.perf_counter() - t_setup
+    layout_levels = sol.layout.levels
+    n_dofs = int(sol.layout.n_dofs)
     f = sinusoid_forcing(n, n, n, h, seed=args.seed)
     b = sol.pack((f[0], f[1], f[2], np.zeros((n, n, n))))
     del f
@@ -308,6 +442,31 @@ def main():
     torch.cuda.synchronize()
     vcycle_ms = ev0.elapsed_time(ev1) / nvc
 
+    split = None
+    if not args.no_split:
+        # the other arrangement Section 3 allows: reverse sweeps before, forward sweeps after
+        ssp = StokesSolver(n, n, n, h=h, schedule="split")
+        xs, isp = ssp.solve(b, rtol=args.rtol, maxit=500)
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        for _ in range(args.steps):
+            xs, isp = ssp.solve(b, rtol=args.rtol, maxit=500)
+        torch.cuda.synchronize()
+        tsp = (time.perf_counter() - tm0) / args.steps
+        ev0.record()
+        for _ in range(nvc):
+            ssp.vcycle(s, out=t)
+        ev1.record()
+        torch.cuda.synchronize()
+        split = {"value": round(tsp, 6), "unit": "s", "iterations": isp["iters"], "final_relres": isp["relres"],
+                 "status": isp["status"], "vcycle_ms": round(ev0.elapsed_time(ev1) / nvc, 3),
+                 "rel_diff_vs_default_solution": float(torch.linalg.vector_norm(xs - x) / torch.linalg.vector_norm(x)),
+                 "form": "pre-smoothing: Vanka, 2 reverse DGS sweeps, Vanka; post-smoothing: Vanka, 2 forward "
+                         "sweeps, Vanka (Section 3's transposed pair)"}
+        ssp.close()
+        del ssp, xs
+        print(f"[bench] split schedule: {tsp * 1e3:.1f} ms, iters={isp['iters']}", file=sys.stderr, flush=True)
+
     warm = None
     if not args.no_warm_start and os.path.exists(WEIGHTS):
         warm = warm_start_leg(sol, b, args.steps, args.rtol, ms_per_step, info["iters"])
@@ -347,6 +506,17 @@ def main():
     if not args.no_batched:
         batched = batched_leg(args.steps, args.rtol, args.seed)
 
+    m384 = None
+    if not args.no_384 and n == 256:
+        sol.close()
+        del sol, x, s, t, b
+        torch.cuda.empty_cache()
+        m384 = mixed_384_leg(args.steps, args.rtol, args.seed)
+
+    gsmall = None
+    if not args.no_cpu_baseline:
+        gsmall = gpu_small_solve(args.seed, args.rtol)
+
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -354,6 +524,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    levels = layout_levels
+    vbytes = vcycle_model_bytes(n, S, levels)
     avg_ms = kms / max(klaunch, 1)
     abytes = algorithmic_bytes(args.kernel, n)
     achieved = abytes / (avg_ms * 1e-3) / 1e9
@@ -372,27 +544,39 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded 8-mode sinusoid forcing per component, zero divergence RHS)",
         "config": {"workload": f"3D MAC Stokes {n}^3 cells unit cube, no-slip box, eta=1, gamma=1e-3, "
-                               f"{sol.layout.levels}-level V-cycle (the same Alg. 3 smoother before and after the coarse correction: symmetric Vanka, one symmetric DGS, symmetric Vanka; n_b=1), "
+                               f"{layout_levels}-level V-cycle (the same Alg. 3 smoother before and after the coarse correction: symmetric Vanka, one symmetric DGS, symmetric Vanka; n_b=1), "
                                f"MG-SQMR to rtol {args.rtol:g}",
-                   "unknowns": int(sol.layout.n_dofs), "seed": args.seed, "precision": "fp64 throughout"},
+                   "unknowns": n_dofs, "seed": args.seed, "precision": "fp64 throughout"},
         "iterations": info["iters"],
         "final_relres": info["relres"],
         "vcycle_ms": round(vcycle_ms, 3),
+        "vcycle_model_bytes": round(vbytes),
+        "vcycle_gbps": round(vbytes / (vcycle_ms * 1e-3) / 1e9, 1),
+        "vcycle_frac": round(vbytes / (vcycle_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "setup_s": round(t_setup, 3),
-        "roofline": {"bound": "hbm", "kernel": f"k_{args.kernel} (level 0)", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "scope": "dominant kernel of the V-cycle (per kernel; the whole V-cycle "
+                     "is vcycle_gbps / vcycle_frac)", "kernel": f"k_{args.kernel} (level 0)", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": klaunch,
                      "algorithmic_bytes_per_launch": abytes},
     }
+    if split is not None:
+        line["split_schedule"] = split
     if mixed is not None:
+        vb32 = vcycle_model_bytes(n, 4, levels)
+        mixed["vcycle_model_bytes"] = round(vb32)
+        mixed["vcycle_gbps"] = round(vb32 / (mixed["vcycle_ms"] * 1e-3) / 1e9, 1)
+        mixed["vcycle_frac"] = round(vb32 / (mixed["vcycle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
         line["mixed_precision"] = mixed
+    if m384 is not None:
+        line["mixed_precision_384"] = m384
     if batched is not None:
         line["batched"] = batched
     if warm is not None:
         line["warm_start"] = warm
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(info["iters"], n, args.seed)
+        line["cpu_baseline"] = cpu_baseline(info["iters"], n, args.seed, gsmall)
     print(json.dumps(line), flush=True)
 
 

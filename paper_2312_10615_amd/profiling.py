@@ -67,7 +67,7 @@ def _largest_dispatches(path, counter):
     return best
 
 
-SHORT = {"k_dgs_u_v<": "dgs_u", "k_dgs_pr_v<": "dgs_pr", "k_dgs_pf_own_v<": "dgs_pf_own", "k_dgs_pf_nbr_v<": "dgs_pf_nbr",
+SHORT = {"k_dgs_u_v<": "dgs_u", "k_dgs_pr_v<": "dgs_pr", "k_dgs_pf_v<": "dgs_pf",
          "k_apply_v<1,": "apply", "k_restrict<": "restrict", "k_prolong_pairs<": "prolong"}
 
 
