@@ -87,6 +87,13 @@ def residual(dom: Domain, x, b, gamma: float):
     return tuple(np.where(m, bb - yy, 0.0) for m, bb, yy in zip(dom.active, b, y))
 
 
+def continuity_residual(dom: Domain, x, b, gamma: float):
+    """The pressure rows of `residual` alone: b_p - (B u - gamma p)."""
+    x = masked(dom, x)
+    y = neg_div(dom, x[:3]) - np.where(dom.active[3], gamma * x[3], 0.0)
+    return np.where(dom.active[3], b[3] - y, 0.0)
+
+
 def to_vector(dom: Domain, x) -> np.ndarray:
     """Active entries of (ux, uy, uz, p), each in C order, concatenated."""
     return np.concatenate([v[m] for m, v in zip(dom.active, x)])

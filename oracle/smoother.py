@@ -4,8 +4,9 @@ their symmetric composition (Alg. 3).  All of them act on the penalised matrix
 L~ of Section 4 (the V-cycle only ever sees L~).
 
 Every smoother is written as the relaxation x <- x + S (b - L~ x) of Eq.
-relaxation, one colour class at a time, with the residual recomputed in full
-before each class.  Inside one colour class the updates do not influence each
+relaxation, one colour class at a time, with the residual recomputed before
+each class (in full for DGS; for Vanka its rows at the class's local
+unknowns, pinned against the full residual).  Inside one colour class the updates do not influence each
 other's residuals (checked by a test that runs the literal one-unknown-at-a-
 time loop of Alg. 2), so applying a class at once equals visiting its members
 in any order.
@@ -15,7 +16,7 @@ from __future__ import annotations
 import numpy as np
 
 from .domain import Domain
-from .operator import apply_operator, grad, neg_div, residual
+from .operator import apply_operator, continuity_residual, grad, neg_div, residual
 
 
 # ---------------------------------------------------------------------------
@@ -113,9 +114,9 @@ def dgs_forward(dom: Domain, x, b, diags=None, order: str = "c8"):
     for colour in (0, 1):
         x = _velocity_class(dom, x, b, colour, d_u)
     for cls in pressure_classes(dom, order):
-        r = residual(dom, x, b, dom.gamma)
+        r3 = continuity_residual(dom, x, b, dom.gamma)
         sel = cls & (d_p != 0)
-        delta = np.where(sel, r[3] / np.where(d_p != 0, d_p, 1.0), 0.0)
+        delta = np.where(sel, r3 / np.where(d_p != 0, d_p, 1.0), 0.0)
         dx = distribute(dom, delta)
         x = tuple(v + dv for v, dv in zip(x, dx))
     return x
@@ -200,21 +201,52 @@ def vanka_local_matrix(eta: float, h: float, gamma: float, act: np.ndarray) -> n
     return K
 
 
+def local_residual(dom: Domain, x, b, idx, act):
+    """C_i (b - L~ x) for a set of subdomains: the rows of the residual at
+    their local unknowns (slot s of cell c is row idx[s][c]), each row written
+    from Eq. 2 / Section 4 with the neighbours that are not unknowns taken as
+    zero - the same rows `residual` evaluates over the whole grid.  Rows of
+    slots that are not unknowns are 0."""
+    c = dom.eta / dom.h ** 2
+    up = [np.pad(np.where(dom.active[a], x[a], 0.0), 1) for a in range(3)]
+    pp = np.pad(np.where(dom.active[3], x[3], 0.0), 1)
+    rows = []
+    for s in range(7):
+        f = _SLOT_FIELD[s]
+        i, j, k = (t + 1 for t in idx[s])   # padded indices
+        if f < 3:
+            u = up[f]
+            nb = u[i - 1, j, k] + u[i + 1, j, k] + u[i, j - 1, k] + u[i, j + 1, k] + u[i, j, k - 1] + u[i, j, k + 1]
+            m = [i, j, k]
+            m[f] = m[f] - 1                 # the cell on the minus side of the face
+            row = c * (6.0 * u[i, j, k] - nb) + (pp[i, j, k] - pp[tuple(m)]) / dom.h
+        else:
+            div = ((up[0][i + 1, j, k] - up[0][i, j, k]) + (up[1][i, j + 1, k] - up[1][i, j, k]) +
+                   (up[2][i, j, k + 1] - up[2][i, j, k]))
+            row = -div / dom.h - dom.gamma * pp[i, j, k]
+        rows.append(np.where(act[:, s], b[f][idx[s]] - row, 0.0))
+    return np.stack(rows, axis=1)
+
+
+def _vanka_cells_into(dom: Domain, x: list, b, cells: np.ndarray):
+    """The class step of `vanka_cells_step`, updating the list x in place."""
+    if cells.shape[0] == 0:
+        return
+    idx, act = vanka_slots(dom, cells)
+    rloc = local_residual(dom, x, b, idx, act)
+    K = vanka_local_matrix(dom.eta, dom.h, dom.gamma, act)
+    delta = np.linalg.solve(K, rloc[:, :, None])[:, :, 0]
+    for s in range(7):
+        f = _SLOT_FIELD[s]
+        np.add.at(x[f], idx[s], np.where(act[:, s], delta[:, s], 0.0))
+
+
 def vanka_cells_step(dom: Domain, x, b, cells: np.ndarray):
     """x <- x + sum_i C_i^T K_i^{-1} C_i (b - L~ x) over the given V1 cells, every
     local residual taken from the same state; corrections of subdomains that
     share an unknown add up (Eq. av when the cells are all of V1)."""
-    if cells.shape[0] == 0:
-        return x
-    idx, act = vanka_slots(dom, cells)
-    r = residual(dom, x, b, dom.gamma)
-    rloc = np.stack([np.where(act[:, s], r[_SLOT_FIELD[s]][idx[s]], 0.0) for s in range(7)], axis=1)
-    K = vanka_local_matrix(dom.eta, dom.h, dom.gamma, act)
-    delta = np.linalg.solve(K, rloc[:, :, None])[:, :, 0]
     x = [v.copy() for v in x]
-    for s in range(7):
-        f = _SLOT_FIELD[s]
-        np.add.at(x[f], idx[s], np.where(act[:, s], delta[:, s], 0.0))
+    _vanka_cells_into(dom, x, b, cells)
     return tuple(x)
 
 
@@ -234,13 +266,15 @@ def vanka_color(dom: Domain, x, b, colour: int, period: int = 2):
 
 
 def vanka_symmetric(dom: Domain, x, b, period: int = 2):
-    """Symmetric multiplicative Vanka (Section 3.2): classes 0..n-1, then n-1..0."""
+    """Symmetric multiplicative Vanka (Section 3.2): classes 0..n-1, then n-1..0,
+    each one step of `vanka_color`."""
     n = period ** 3
-    for colour in range(n):
-        x = vanka_color(dom, x, b, colour, period)
-    for colour in reversed(range(n)):
-        x = vanka_color(dom, x, b, colour, period)
-    return x
+    col = dom.vanka_colour(period)
+    cells = [np.argwhere(dom.v1[3] & (col == k)) for k in range(n)]
+    x = [v.copy() for v in x]
+    for colour in list(range(n)) + list(reversed(range(n))):
+        _vanka_cells_into(dom, x, b, cells[colour])
+    return tuple(x)
 
 
 def vanka_additive(dom: Domain, x, b):

@@ -1,5 +1,7 @@
 """Batched MG-SQMR (stokes_batch_*): every box of a mixed batch against the
-single-box GPU solver and against the oracle's operator.
+oracle's MG-SQMR solution of that box (FP64 form, element by element, same
+iteration count), against the single-box GPU solver, and against the
+oracle's operator.
 
 The batch runs the same per-item arithmetic as the single-box kernels; its
 inner products are summed in a different (fixed) block order, so iterates
@@ -61,12 +63,39 @@ def test_batch_matches_single_box_solves(precision, dims):
         announce(f"  box {dm} levels {lay.levels}: iters {infos[d]['iters']} (single {info['iters']}), "
                  f"|batch - single| {e:.1e}, oracle relres {rr:.2e}")
         assert infos[d]["status"] == "ok" and info["status"] == "ok"
-        assert abs(infos[d]["iters"] - info["iters"]) <= 1
+        # FP64: the same count and iterates to rounding; FP32 V-cycle: +-1 where a
+        # residual sits at the tolerance (the envelope of the single-box parity tests)
+        assert abs(infos[d]["iters"] - info["iters"]) <= (0 if precision == 64 else 1)
         assert rr <= 1e-8 * (1 + 1e-6)
         if infos[d]["iters"] == info["iters"]:
             assert e <= (1e-9 if precision == 64 else 1e-6), e
         # pressure mean removed, walls zero
         assert abs(float(np.mean(got[3]))) <= 1e-12 * max(1.0, float(np.abs(got[3]).max()))
+
+
+@pytest.mark.parametrize("dims", [DIMS, MID], ids=["small", "mid"])
+def test_batch_fp64_boxes_match_oracle_solves(dims):
+    """Each box of an FP64 batch against oracle.mg_sqmr on that box (its
+    level count, h = 1/16, seed 10 + d): the same iteration count and the
+    converged, mean-removed solution within 1e-10."""
+    cuda()
+    from oracle.multigrid import Hierarchy
+    from oracle.sqmr import mg_sqmr, remove_pressure_mean
+    announce(f"batched FP64 vs oracle, boxes {dims}")
+    bt, rhs, doms = _batch_problem(64, dims=dims)
+    x, infos = bt.solve(bt.pack(rhs), rtol=1e-8, maxit=100)
+    for d, dm in enumerate(dims):
+        Hd = Hierarchy(dm, H, levels=bt.layouts[d].levels)
+        xo, io = mg_sqmr(Hd, rhs[d], rtol=1e-8, maxit=100)
+        assert io["status"] == "converged"
+        want = remove_pressure_mean(Hd.doms[0], xo)
+        got = bt.unpack(x, d)
+        e = rel_err(got, want)
+        announce(f"  box {dm} levels {bt.layouts[d].levels}: iters {infos[d]['iters']} (oracle {io['iters']}), "
+                 f"|batch - oracle| {e:.1e}")
+        assert infos[d]["status"] == "ok"
+        assert infos[d]["iters"] == io["iters"]
+        assert e <= 1e-10, e
 
 
 def test_batch_edge_cases_and_replays():

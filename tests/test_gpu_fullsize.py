@@ -1,18 +1,23 @@
 """Full-size (256^3, 7 levels) checks of the GPU path, in the launch
-configuration bench.py times.  The oracle cannot iterate at this size within a
-test, so the checks are (a) the operator element by element against the
-oracle's, (b) the converged solution's residual recomputed by the oracle's
-operator on the host, (c) symmetry of the V-cycle, and (d) the manufactured
-solution's O(h^2) error between 128^3 and 256^3."""
+configuration bench.py times: (a) the operator element by element against
+the oracle's; (b) one FP64 V-cycle and the first MG-SQMR iterate element by
+element against the oracle's first iteration (two oracle V-cycles, about a
+minute of host time), and the FP32 V-cycle against the same oracle V-cycle;
+(c) the converged solution's residual recomputed by the oracle's operator on
+the host; (d) symmetry of the V-cycle; (e) the manufactured solution's O(h^2)
+error between 128^3 and 256^3.  A complete oracle solve at this size (15
+iterations) would take about half an hour, so later iterates are checked at
+smaller sizes (test_gpu_parity.py)."""
 import numpy as np
 import pytest
 
 from oracle.domain import Domain, box_labels
-from oracle.operator import apply_operator
-from oracle.sqmr import remove_pressure_mean
+from oracle.multigrid import Hierarchy, vcycle
+from oracle.operator import apply_operator, from_vector, to_vector
+from oracle.sqmr import remove_pressure_mean, sqmr
 from paper_2312_10615_amd.stokes import StokesSolver
 from paper_2312_10615_amd.workloads import mms_fields
-from tests.gpu_helpers import announce, cuda, forcing_rhs, max_rel, random_fields
+from tests.gpu_helpers import announce, cuda, forcing_rhs, max_rel, random_fields, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +30,71 @@ def big():
     sol = StokesSolver(N, N, N, h=1.0 / N)
     dom = Domain(box_labels((N, N, N)), 1.0 / N)
     return sol, dom
+
+
+@pytest.fixture(scope="module")
+def oracle_first_iteration():
+    """The oracle's MG-SQMR (Alg. 4) on the seed-0 workload, stopped after
+    its first iteration: the first V-cycle t0 = W b and the iterate x_1."""
+    announce("oracle: hierarchy and the first MG-SQMR iteration at 256^3 (two V-cycles)")
+    H = Hierarchy((N, N, N), 1.0 / N)
+    dom = H.doms[0]
+    b = forcing_rhs(dom.active, (N, N, N), 1.0 / N, 0)
+    outs, iterates = [], {}
+
+    def apply_W(v):
+        w = to_vector(dom, vcycle(H, from_vector(dom, v)))
+        outs.append(w)
+        announce(f"oracle: V-cycle {len(outs)} done")
+        return w
+
+    def apply_A(v):
+        return to_vector(dom, apply_operator(dom, from_vector(dom, v), 0.0))
+
+    sqmr(apply_A, apply_W, to_vector(dom, b), np.zeros(dom.n_dofs()), rtol=1e-8, maxit=1,
+         on_iterate=lambda j, x, s_: iterates.__setitem__(j, from_vector(dom, x)))
+    return b, from_vector(dom, outs[0]), iterates[1]
+
+
+def test_256_vcycle_matches_oracle(big, oracle_first_iteration):
+    torch = cuda()
+    sol, dom = big
+    b, t0, _ = oracle_first_iteration
+    announce("256^3 FP64 V-cycle vs oracle")
+    t = sol.vcycle(sol.pack(b))
+    torch.cuda.synchronize()
+    err = max_rel(sol.unpack(t), t0)
+    announce(f"  max-rel difference {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_256_first_sqmr_iterate_matches_oracle(big, oracle_first_iteration):
+    torch = cuda()
+    sol, dom = big
+    b, _, x1 = oracle_first_iteration
+    announce("256^3 first MG-SQMR iterate vs oracle")
+    x, info = sol.solve(sol.pack(b), rtol=1e-8, maxit=1)
+    torch.cuda.synchronize()
+    assert info["iters"] == 1 and info["status"] == "enoconv"
+    err = rel_err(sol.unpack(x), x1)
+    announce(f"  relative difference {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_256_fp32_vcycle_matches_oracle(oracle_first_iteration):
+    """The FP32 V-cycle against the FP64 oracle's, to FP32 accuracy: unit
+    roundoff 6e-8 times the growth through one V-cycle (the same bar as at
+    32^3, where the observed difference is ~1e-6)."""
+    torch = cuda()
+    b, t0, _ = oracle_first_iteration
+    announce("256^3 FP32 V-cycle vs oracle")
+    s32 = StokesSolver(N, N, N, h=1.0 / N, precision=32)
+    t = s32.vcycle(s32.pack(b))
+    torch.cuda.synchronize()
+    err = max_rel(s32.unpack(t), t0)
+    announce(f"  max-rel difference {err:.2e}")
+    s32.close()
+    assert err <= 2e-5
 
 
 def test_256_solve_reaches_tolerance_checked_by_the_oracle_operator(big):

@@ -175,6 +175,27 @@ def test_solve_is_bitwise_reproducible():
     assert torch.equal(x1, x2) and i1["history"] == i2["history"]
 
 
+def test_breakdown_forced_by_an_fp32_underflow():
+    """Alg. 4's breakdown (sigma = q . L q = 0) forced from the host: every
+    entry of b is 1e-50, below FP32's range, so the FP32 V-cycle receives a
+    zero vector, t = W s = 0, q = 0 and sigma = 0 exactly.  The solve stops with
+    EBREAKDOWN after 0 iterations and leaves x at x0; with the FP64 V-cycle the
+    same b is solved."""
+    torch = cuda()
+    announce("breakdown via an FP32 underflow")
+    n = 16
+    dom = Domain(box_labels((n, n, n)), 1 / n)
+    b = tuple(np.where(m, 1e-50, 0.0) for m in dom.active[:3]) + (np.zeros((n, n, n)),)
+    s32 = StokesSolver(n, n, n, precision=32)
+    x, info = s32.solve(s32.pack(b), rtol=1e-8, maxit=50)
+    torch.cuda.synchronize()
+    assert info["status"] == "ebreakdown" and info["iters"] == 0
+    assert float(x.abs().max()) == 0.0 and info["relres"] == 1.0
+    s64 = StokesSolver(n, n, n)
+    x, info = s64.solve(s64.pack(b), rtol=1e-8, maxit=50)
+    assert info["status"] == "ok" and info["relres"] <= 1e-8
+
+
 def test_edge_cases():
     torch = cuda()
     announce("edge cases")

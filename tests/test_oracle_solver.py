@@ -495,3 +495,18 @@ def test_manufactured_solution_converges_at_second_order():
     for (u0, p0), (u1, p1) in zip(errs, errs[1:]):
         assert np.log2(u0 / u1) >= 1.8
         assert np.log2(p0 / p1) >= 1.5
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2), (5, 6, 7), (8, 4, 6)])
+def test_local_residual_rows_equal_the_full_residual(dims):
+    """The Vanka local residual C_i (b - L~ x), evaluated row by row at the
+    V1 cells' unknowns, equals the full residual at those rows."""
+    from oracle.smoother import _SLOT_FIELD, local_residual
+    dom = dom_of(dims, eta=0.7, gamma=0.05)
+    x, b = rand_state(dom, 31), rand_state(dom, 32)
+    cells = np.argwhere(dom.v1[3])
+    idx, act = vanka_slots(dom, cells)
+    got = local_residual(dom, x, b, idx, act)
+    r = residual(dom, x, b, dom.gamma)
+    want = np.stack([np.where(act[:, s], r[_SLOT_FIELD[s]][idx[s]], 0.0) for s in range(7)], axis=1)
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
