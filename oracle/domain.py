@@ -2,21 +2,25 @@
 
 Every cell carries a label: interior, Dirichlet or exterior.  From the labels
 the paper derives which variables are unknowns:
-  * a velocity on the face between two interior cells is active;
   * a velocity on a face of a Dirichlet cell is a Dirichlet value (not solved);
+  * a velocity on the face between two interior cells is active;
+  * a velocity on the face between an interior and an exterior cell carries a
+    Neumann condition; reading: it is an unknown too (its momentum row sees
+    zero pressure in the exterior cell and zero-Neumann velocity stencils);
+  * faces with no interior cell and no Dirichlet cell are outside the solve;
   * a pressure at an interior cell centre is active.
 Coarse labels: a coarse cell is Dirichlet if it encloses any fine Dirichlet
 cell, otherwise interior if it encloses any fine interior cell, otherwise
 exterior.  The boundary set V1 holds all degrees of freedom of the cells that
 are proximal to a Dirichlet or exterior cell; V2 holds the rest.
 
-Reading (proximal): a cell is proximal when it shares a face with a
-non-interior cell.  For a box padded by one Dirichlet layer this equals
-sharing a vertex, and it reproduces the boundary-DOF counts of Table 1 for the
-driven-cavity rows exactly.
-
-Exterior cells (and the Neumann faces they create) are outside the scope of
-this oracle: `Domain` rejects them.
+Readings, both pinned by Table 1: the rows of the 2D cylinder channel (no-slip
+walls and obstacle, an outflow of exterior cells) come out exactly, total and
+boundary DOFs at all four resolutions, when (a) interior-exterior faces are
+unknowns, and (b) "proximal" means within one cell (sharing a face, edge or
+corner) of a Dirichlet cell or within two cells of an exterior cell.  For a
+box padded by Dirichlet cells (b) is the face-sharing rule, which reproduces
+the driven-cavity rows.
 
 The labelled arrays are padded: padded index = cell index + 1, so a box of n
 cells per axis has label arrays of n+2 per axis whose outer layer is
@@ -44,13 +48,14 @@ def coarsen_labels(lab: np.ndarray) -> np.ndarray:
 
     Coarse cell I covers fine cells 2I and 2I+1 (cell indices).  In padded
     indices this means coarse padded index c covers fine padded 2c-1 and 2c;
-    an extra Dirichlet layer stands in for the fine cells beyond the padding.
+    an extra layer repeating the outer layer stands in for the fine cells
+    beyond the padding (a padding of exterior cells stays exterior).
     """
     d = lab.ndim
     dims = [s - 2 for s in lab.shape]
     if any(n % 2 for n in dims):
         raise ValueError("label coarsening needs an even number of cells per axis")
-    ext = np.pad(lab, 1, constant_values=DIRICHLET)  # ext index = padded + 1
+    ext = np.pad(lab, 1, mode="edge")  # ext index = padded + 1
     cdims = [n // 2 for n in dims]
     # fine padded indices 2c-1, 2c  ->  ext indices 2c, 2c+1, for c = 0 .. n/2+1
     blocks = ext.reshape(tuple(x for n in cdims for x in (n + 2, 2)))
@@ -58,6 +63,20 @@ def coarsen_labels(lab: np.ndarray) -> np.ndarray:
     any_dir = (blocks == DIRICHLET).any(axis=axes)
     any_int = (blocks == INTERIOR).any(axis=axes)
     out = np.where(any_dir, DIRICHLET, np.where(any_int, INTERIOR, EXTERIOR)).astype(np.int8)
+    return out
+
+
+def _dilate(mask: np.ndarray, reach: int) -> np.ndarray:
+    """Cells within `reach` steps of `mask`, a step reaching all 3^d - 1 cells
+    that share a face, edge or corner (no wrap-around at the array ends)."""
+    d = mask.ndim
+    out = mask.copy()
+    for _ in range(reach):
+        pad = np.pad(out, 1, constant_values=False)
+        nxt = out.copy()
+        for off in np.ndindex(*(3,) * d):
+            nxt |= pad[tuple(slice(o, o + n) for o, n in zip(off, out.shape))]
+        out = nxt
     return out
 
 
@@ -72,14 +91,10 @@ def classify(lab: np.ndarray):
     dims = [s - 2 for s in lab.shape]
     inner = tuple(slice(1, n + 1) for n in dims)
     interior = lab == INTERIOR
+    dirichlet = lab == DIRICHLET
     cell_active = interior[inner]
 
-    # proximal cells: interior cells with a face neighbour that is not interior
-    prox = np.zeros_like(interior)
-    for a in range(d):
-        for s in (-1, 1):
-            prox |= np.roll(~interior, s, axis=a)
-    prox &= interior
+    prox = (_dilate(dirichlet, 1) | _dilate(lab == EXTERIOR, 2)) & interior
     cell_v1 = prox[inner]
 
     face_active, face_v1 = [], []
@@ -90,10 +105,46 @@ def classify(lab: np.ndarray):
         lo[a] = slice(0, dims[a] + 1)
         hi[a] = slice(1, dims[a] + 2)
         lo, hi = tuple(lo), tuple(hi)
-        act = interior[lo] & interior[hi]
+        act = (interior[lo] | interior[hi]) & ~dirichlet[lo] & ~dirichlet[hi]
         face_active.append(act)
         face_v1.append(act & (prox[lo] | prox[hi]))
     return face_active + [cell_active], face_v1 + [cell_v1]
+
+
+def viscous_diagonals(lab: np.ndarray):
+    """For each velocity component, the count n_f of lattice neighbours that
+    enter the diagonal of A at face f: A u_f = (eta/h^2)(n_f u_f - sum of the
+    neighbours that are unknowns).
+
+    Reading (zero Neumann): a lattice neighbour that is an unknown or a
+    Dirichlet value counts (a Dirichlet value sits in the right-hand side); a
+    neighbour with no interior and no Dirichlet cell beside it lies on the
+    exterior side of a Neumann boundary, and the zero normal derivative there
+    sets it equal to u_f, which removes it from both sides of the stencil.
+    Inside a Dirichlet box every n_f is 6.  Labels beyond the array repeat its
+    outer layer."""
+    if lab.ndim != 3:
+        raise ValueError("3D labels only")
+    dims = [s - 2 for s in lab.shape]
+    ext = np.pad(lab, 1, mode="edge")          # ext index = padded index + 1 = cell index + 2
+    out = []
+    for a in range(3):
+        # kinds of the lattice positions of u_a for face index -1..n_a+1 and cell index -1..n
+        lo = [slice(1, n + 3) for n in dims]
+        hi = [slice(1, n + 3) for n in dims]
+        lo[a] = slice(0, dims[a] + 3)
+        hi[a] = slice(1, dims[a] + 4)
+        L, H = ext[tuple(lo)], ext[tuple(hi)]
+        counts = ((L == DIRICHLET) | (H == DIRICHLET) | (L == INTERIOR) | (H == INTERIOR)).astype(np.int64)
+        n = np.zeros(tuple(dims[b] + (1 if b == a else 0) for b in range(3)), dtype=np.int64)
+        core = tuple(slice(1, m - 1) for m in counts.shape)
+        for b in range(3):
+            for sgn in (-1, 1):
+                sl = list(core)
+                sl[b] = slice(1 + sgn, counts.shape[b] - 1 + sgn)
+                n += counts[tuple(sl)]
+        out.append(n)
+    return out
 
 
 def dof_counts(lab: np.ndarray):
@@ -107,7 +158,8 @@ class Domain:
     """One level of the hierarchy: a labelled 3D grid of spacing h.
 
     Holds the constants of the discrete Stokes operator (Eq. 2): viscosity
-    eta and the penalty gamma of the preconditioner matrix (Section 4).
+    eta and the penalty gamma of the preconditioner matrix (Section 4).  The
+    outer layer of the labels must hold no interior cell.
     """
     labels: np.ndarray
     h: float
@@ -116,14 +168,32 @@ class Domain:
     active: list = field(init=False)
     v1: list = field(init=False)
     v2: list = field(init=False)
+    ndiag: list = field(init=False)
 
     def __post_init__(self):
         if self.labels.ndim != 3:
             raise ValueError("the oracle's Stokes operator is 3D")
-        if (self.labels == EXTERIOR).any():
-            raise ValueError("exterior cells (Neumann faces) are outside this oracle's scope")
+        inner = self.labels[1:-1, 1:-1, 1:-1]
+        if (self.labels == INTERIOR).sum() != (inner == INTERIOR).sum():
+            raise ValueError("the outer layer of the labels must hold no interior cell")
         self.active, self.v1 = classify(self.labels)
         self.v2 = [a & ~v for a, v in zip(self.active, self.v1)]
+        self.ndiag = viscous_diagonals(self.labels)
+
+    @property
+    def has_neumann(self):
+        """True when some unknown face borders an exterior cell (the pressure is
+        then unique: exterior pressures are zero)."""
+        ext = self.labels == EXTERIOR
+        inter = self.labels == INTERIOR
+        for a in range(3):
+            lo = [slice(None)] * 3
+            hi = [slice(None)] * 3
+            lo[a] = slice(0, -1)
+            hi[a] = slice(1, None)
+            if ((ext[tuple(lo)] & inter[tuple(hi)]) | (inter[tuple(lo)] & ext[tuple(hi)])).any():
+                return True
+        return False
 
     @property
     def dims(self):

@@ -61,7 +61,11 @@ class Hierarchy:
     """Levels 0 (finest) .. levels-1 (coarsest) of a box domain."""
 
     def __init__(self, dims, h, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1, schedule="symmetric",
-                 vanka="mult8", cycle=1, order="c8"):
+                 vanka="mult8", cycle=1, order="c8", labels=None):
+        """`labels`: optional (nx+2, ny+2, nz+2) cell labels of Section 5 (a box
+        padded by Dirichlet cells when None); `dims` must match them."""
+        if labels is not None and tuple(s - 2 for s in labels.shape) != tuple(dims):
+            raise ValueError("labels do not match dims")
         if levels == 0:
             levels = auto_levels(dims)
         if levels < 1 or levels > max_levels(dims):
@@ -74,7 +78,7 @@ class Hierarchy:
             raise ValueError("bad DGS pressure order")
         self.nu, self.n_boundary, self.schedule, self.order = nu, n_boundary, schedule, order
         self.vanka, self.cycle = vanka, cycle
-        self.doms = [Domain(box_labels(dims), h, eta, gamma)]
+        self.doms = [Domain(box_labels(dims) if labels is None else np.asarray(labels, dtype=np.int8), h, eta, gamma)]
         for _ in range(levels - 1):
             self.doms.append(self.doms[-1].coarsen())
         self.diags = [dgs_diagonals(d) for d in self.doms[:-1]]

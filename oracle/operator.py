@@ -15,6 +15,9 @@ the re-discretised coarse operator.  Neighbours that are not unknowns
 (Dirichlet faces, including the tangential ghost at the face centre of a
 Dirichlet cell) hold zero and are simply dropped, so the diagonal stays
 6 eta/h^2.  Homogeneous Dirichlet data only; non-zero data belongs in b.
+Next to exterior cells (Section 5's Neumann faces) the pressure of an
+exterior cell is zero and a velocity neighbour on the exterior side is
+dropped from the diagonal as well (zero normal derivative, Domain.ndiag).
 """
 from __future__ import annotations
 
@@ -64,13 +67,14 @@ def neg_div(dom: Domain, u):
 
 
 def viscous(dom: Domain, u_a: np.ndarray, a: int):
-    """A on one velocity component: (eta/h^2)(6u - sum of 6 lattice neighbours)."""
+    """A on one velocity component: (eta/h^2)(n_f u - sum of the lattice
+    neighbours), n_f = 6 except next to exterior cells (Domain.ndiag)."""
     c = dom.eta / dom.h ** 2
     up = np.pad(np.where(dom.active[a], u_a, 0.0), 1)
     core = up[1:-1, 1:-1, 1:-1]
     nb = (up[2:, 1:-1, 1:-1] + up[:-2, 1:-1, 1:-1] + up[1:-1, 2:, 1:-1]
           + up[1:-1, :-2, 1:-1] + up[1:-1, 1:-1, 2:] + up[1:-1, 1:-1, :-2])
-    return np.where(dom.active[a], c * (6.0 * core - nb), 0.0)
+    return np.where(dom.active[a], c * (dom.ndiag[a] * core - nb), 0.0)
 
 
 def apply_operator(dom: Domain, x, gamma: float = 0.0):

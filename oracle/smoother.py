@@ -169,24 +169,31 @@ def vanka_slots(dom: Domain, cells: np.ndarray):
     return idx, np.stack(act, axis=1)
 
 
-def vanka_local_matrix(eta: float, h: float, gamma: float, act: np.ndarray) -> np.ndarray:
+def vanka_diagonals(dom: Domain, idx):
+    """n_f of the six local faces of each subdomain (Domain.ndiag)."""
+    return np.stack([dom.ndiag[_SLOT_FIELD[s]][idx[s]].astype(float) for s in range(6)], axis=1)
+
+
+def vanka_local_matrix(eta: float, h: float, gamma: float, act: np.ndarray, nd=None) -> np.ndarray:
     """K_i = C_i L~ C_i^T for each subdomain (Eq. mv), written out.
 
     Reading (subdomain): one V1 cell - its pressure and its active faces, at
     most 7 unknowns, matching the prefactorised 3^6 local problems keyed on
-    the six neighbour labels (Section 6).  Entries: 6 eta/h^2 on velocity
-    diagonals, -eta/h^2 between the two faces of one axis (lattice neighbours),
-    +1/h (minus face) and -1/h (plus face) between a face and the pressure,
-    -gamma on the pressure diagonal.  Slots that are not unknowns get an
-    identity row and column, so their update is zero.
+    the six neighbour labels (Section 6).  Entries: n_f eta/h^2 on velocity
+    diagonals (n_f = nd[:, slot], 6 unless an exterior cell is near:
+    Domain.ndiag), -eta/h^2 between the two faces of one axis (lattice
+    neighbours), +1/h (minus face) and -1/h (plus face) between a face and the
+    pressure, -gamma on the pressure diagonal.  Slots that are not unknowns
+    get an identity row and column, so their update is zero.
     """
     n = act.shape[0]
+    nd = np.full((n, 6), 6.0) if nd is None else nd
     K = np.zeros((n, 7, 7))
     c = eta / h ** 2
     for a in range(3):
         lo, hi = 2 * a, 2 * a + 1
-        K[:, lo, lo] = 6.0 * c
-        K[:, hi, hi] = 6.0 * c
+        K[:, lo, lo] = nd[:, lo] * c
+        K[:, hi, hi] = nd[:, hi] * c
         both = act[:, lo] & act[:, hi]
         K[:, lo, hi] = np.where(both, -c, 0.0)
         K[:, hi, lo] = K[:, lo, hi]
@@ -219,7 +226,8 @@ def local_residual(dom: Domain, x, b, idx, act):
             nb = u[i - 1, j, k] + u[i + 1, j, k] + u[i, j - 1, k] + u[i, j + 1, k] + u[i, j, k - 1] + u[i, j, k + 1]
             m = [i, j, k]
             m[f] = m[f] - 1                 # the cell on the minus side of the face
-            row = c * (6.0 * u[i, j, k] - nb) + (pp[i, j, k] - pp[tuple(m)]) / dom.h
+            n_f = dom.ndiag[f][idx[s]]
+            row = c * (n_f * u[i, j, k] - nb) + (pp[i, j, k] - pp[tuple(m)]) / dom.h
         else:
             div = ((up[0][i + 1, j, k] - up[0][i, j, k]) + (up[1][i, j + 1, k] - up[1][i, j, k]) +
                    (up[2][i, j, k + 1] - up[2][i, j, k]))
@@ -234,7 +242,7 @@ def _vanka_cells_into(dom: Domain, x: list, b, cells: np.ndarray):
         return
     idx, act = vanka_slots(dom, cells)
     rloc = local_residual(dom, x, b, idx, act)
-    K = vanka_local_matrix(dom.eta, dom.h, dom.gamma, act)
+    K = vanka_local_matrix(dom.eta, dom.h, dom.gamma, act, vanka_diagonals(dom, idx))
     delta = np.linalg.solve(K, rloc[:, :, None])[:, :, 0]
     for s in range(7):
         f = _SLOT_FIELD[s]
