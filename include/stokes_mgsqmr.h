@@ -118,6 +118,20 @@ typedef struct stokes_params {
   int32_t cycle;              /* 1: V-cycle (Alg. 1).  2: W-cycle - the coarse correction of every
                                  level above the coarsest is two cycles of the next level, the
                                  second starting from the first's result (Section 2) */
+  const uint8_t* labels;      /* NULL: the box of nx*ny*nz interior cells padded by Dirichlet cells.
+                                 Else host cell labels of Section 5 for the padded box, one byte per
+                                 cell, x fastest ((nx+2)(ny+2)(nz+2) bytes): 0 interior, 1 Dirichlet,
+                                 2 exterior; the outer layer holds no interior cell.  Read during
+                                 stokes_workspace_bytes / stokes_setup only (the caller keeps
+                                 ownership).  Faces of Dirichlet cells hold Dirichlet values; a face
+                                 with an interior cell beside it and no Dirichlet cell is an unknown
+                                 (between an interior and an exterior cell it carries the Neumann
+                                 condition: zero exterior pressure, zero normal derivative of the
+                                 velocity); V1 = interior cells within one cell (face, edge or
+                                 corner) of a Dirichlet cell or two of an exterior cell.  Coarse
+                                 labels follow Section 5.  Single-box solver only (the batch calls
+                                 reject labels).  With an exterior cell beside an unknown face the
+                                 pressure is unique and STOKES_FLAG_REMOVE_MEAN does nothing. */
 } stokes_params;
 
 /* After convergence subtract the mean pressure over the cells (the closed box

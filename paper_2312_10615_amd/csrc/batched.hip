@@ -72,7 +72,7 @@ int validate_batch(int n, const stokes_params* p) {
   if (n < 1 || !p) return STOKES_EINVAL;
   for (int i = 0; i < n; ++i) {
     const stokes_params& q = p[i];
-    if (q.nx < 2 || q.ny < 2 || q.nz < 2 || !(q.h > 0) || !(q.eta > 0) || !(q.gamma > 0)) return STOKES_EINVAL;
+    if (q.nx < 2 || q.ny < 2 || q.nz < 2 || !(q.h > 0) || !(q.eta > 0) || !(q.gamma > 0) || q.labels) return STOKES_EINVAL;
     if (q.nu < 1 || q.n_boundary < 1) return STOKES_EINVAL;
     if (q.smoother != STOKES_SMOOTHER_SPLIT && q.smoother != STOKES_SMOOTHER_SYMMETRIC) return STOKES_EINVAL;
     if (q.smoother == STOKES_SMOOTHER_SYMMETRIC && q.nu % 2) return STOKES_EINVAL;

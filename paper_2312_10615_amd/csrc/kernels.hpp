@@ -78,13 +78,14 @@ __device__ __forceinline__ double block_sum(double v) {
 // ---------------------------------------------------------------------------
 // Rows of the operator (Eq. 2 / Section 4).  s = slot of the row; T is both
 // the storage and the arithmetic type (FP64, or FP32 inside an FP32 V-cycle).
-//   u_x row: (eta/h^2)(6u - 6 lattice neighbours) + (p(I,J,K) - p(I-1,J,K))/h
+//   u_x row: (eta/h^2)(n_f u - 6 lattice neighbours) + (p(I,J,K) - p(I-1,J,K))/h
+//            (n_f = 6 in a box; g.nd beside exterior cells)
 //   p row  : -(1/h) sum_a (u_a(plus face) - u_a(minus face)) - gamma p
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T row_u(const Geom& g, const T* __restrict__ u, const T* __restrict__ p, int s,
-                                        int pstride) {
-  const T lap = T(6) * u[g.at(s)] - u[g.at(s - 1)] - u[g.at(s + 1)] - u[g.at(s - g.sy)] - u[g.at(s + g.sy)] -
+                                        int pstride, int f) {
+  const T lap = T(g.nd(f, s)) * u[g.at(s)] - u[g.at(s - 1)] - u[g.at(s + 1)] - u[g.at(s - g.sy)] - u[g.at(s + g.sy)] -
                 u[g.at(s - g.sz)] - u[g.at(s + g.sz)];
   return (T)g.c * lap + (p[g.at(s)] - p[g.at(s - pstride)]) * (T)g.inv_h;
 }
@@ -124,9 +125,9 @@ __device__ __forceinline__ double apply_item(const Geom& g, const T* __restrict_
     act[2] = g.uz_active(I, J, K);
     act[3] = g.p_active(I, J, K);
     if (MODE != AP_BNORM) {
-      if (act[0]) o[0] = row_u(g, ux, p, s, 1);
-      if (act[1]) o[1] = row_u(g, uy, p, s, g.sy);
-      if (act[2]) o[2] = row_u(g, uz, p, s, g.sz);
+      if (act[0]) o[0] = row_u(g, ux, p, s, 1, 0);
+      if (act[1]) o[1] = row_u(g, uy, p, s, g.sy, 1);
+      if (act[2]) o[2] = row_u(g, uz, p, s, g.sz, 2);
       if (act[3]) o[3] = row_p(g, ux, uy, uz, p, s, gamma);
     }
 #pragma unroll
@@ -147,7 +148,8 @@ __device__ __forceinline__ double apply_item(const Geom& g, const T* __restrict_
 // one V1 cell with its pressure and active faces; the class takes all its
 // local residuals from the state at the start of the class (part 1), then
 // applies the corrections (part 2).  K^-1 of the local saddle problem comes
-// from a per-level table indexed by the 6-bit face-activity type.
+// from a per-level table indexed by the 6-bit face-activity type (a box), or
+// by the type the flag word of a labelled domain holds.
 // ---------------------------------------------------------------------------
 // One thread per subdomain: thread c evaluates the cell's seven local
 // residual rows (0: u_x minus face, 1: u_x plus face, 2/3: u_y, 4/5: u_z,
@@ -166,17 +168,16 @@ __device__ __forceinline__ void vanka_delta_vals(const Geom& g, const T* __restr
   const T* uy = x + F;
   const T* uz = x + 2 * F;
   const T* p = x + 3 * F;
-  const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
+  const int fb = g.vface_bits(I, J, K);
   T res[7];
-  res[0] = a0 ? (T)b[g.at(s)] - row_u(g, ux, p, s, 1) : T(0);
-  res[1] = a1 ? (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1) : T(0);
-  res[2] = a2 ? (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy) : T(0);
-  res[3] = a3 ? (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy) : T(0);
-  res[4] = a4 ? (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz) : T(0);
-  res[5] = a5 ? (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz) : T(0);
+  res[0] = (fb & 1) ? (T)b[g.at(s)] - row_u(g, ux, p, s, 1, 0) : T(0);
+  res[1] = (fb & 2) ? (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1, 0) : T(0);
+  res[2] = (fb & 4) ? (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy, 1) : T(0);
+  res[3] = (fb & 8) ? (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy, 1) : T(0);
+  res[4] = (fb & 16) ? (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz, 2) : T(0);
+  res[5] = (fb & 32) ? (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz, 2) : T(0);
   res[6] = (T)b[3 * F + g.at(s)] - row_p(g, ux, uy, uz, p, s, g.gamma);
-  const int type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
-  const T* km = kinv + type * 64;
+  const T* km = kinv + g.vtype(I, J, K, fb) * 64;
 #pragma unroll
   for (int r = 0; r < 7; ++r) {
     T acc = T(0);
@@ -205,12 +206,13 @@ __device__ __forceinline__ void vanka_apply_at(const Geom& g, T* __restrict__ x,
   const int F = g.field;
   const T* d = delta + c;
   const long n = ncells;
-  if (I >= 2) x[g.at(s)] += d[0];
-  if (I + 1 <= g.nx) x[g.at(s + 1)] += d[n];
-  if (J >= 2) x[F + g.at(s)] += d[2 * n];
-  if (J + 1 <= g.ny) x[F + g.at(s + g.sy)] += d[3 * n];
-  if (K >= 2) x[2 * F + g.at(s)] += d[4 * n];
-  if (K + 1 <= g.nz) x[2 * F + g.at(s + g.sz)] += d[5 * n];
+  const int fb = g.vface_bits(I, J, K);
+  if (fb & 1) x[g.at(s)] += d[0];
+  if (fb & 2) x[g.at(s + 1)] += d[n];
+  if (fb & 4) x[F + g.at(s)] += d[2 * n];
+  if (fb & 8) x[F + g.at(s + g.sy)] += d[3 * n];
+  if (fb & 16) x[2 * F + g.at(s)] += d[4 * n];
+  if (fb & 32) x[2 * F + g.at(s + g.sz)] += d[5 * n];
   x[3 * F + g.at(s)] += d[6 * n];
 }
 
@@ -246,13 +248,14 @@ __device__ __forceinline__ T vanka_row_residual(const Geom& g, const T* __restri
   const T* p = x + 3 * F;
   T res = T(0);
   if (valid) {
+    const int fb = r < 6 ? g.vface_bits(I, J, K) : 0;
     switch (r) {
-      case 0: if (I >= 2) res = (T)b[g.at(s)] - row_u(g, ux, p, s, 1); break;
-      case 1: if (I + 1 <= g.nx) res = (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1); break;
-      case 2: if (J >= 2) res = (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy); break;
-      case 3: if (J + 1 <= g.ny) res = (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy); break;
-      case 4: if (K >= 2) res = (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz); break;
-      case 5: if (K + 1 <= g.nz) res = (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz); break;
+      case 0: if (fb & 1) res = (T)b[g.at(s)] - row_u(g, ux, p, s, 1, 0); break;
+      case 1: if (fb & 2) res = (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1, 0); break;
+      case 2: if (fb & 4) res = (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy, 1); break;
+      case 3: if (fb & 8) res = (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy, 1); break;
+      case 4: if (fb & 16) res = (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz, 2); break;
+      case 5: if (fb & 32) res = (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz, 2); break;
       case 6: res = (T)b[3 * F + g.at(s)] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
       default: break;
     }
@@ -271,9 +274,7 @@ __device__ __forceinline__ T vanka_delta8_lane(const Geom& g, const T* __restric
   int I = 1, J = 1, K = 1;
   if (valid) slot_ijk(g, s, I, J, K);
   // this lane's row of the local inverse is loaded before the residual
-  const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
-  const int type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
-  const T* km = kinv + type * 64 + r * 8;
+  const T* km = kinv + g.vtype(I, J, K, g.vface_bits(I, J, K)) * 64 + r * 8;
   T kr[7];
 #pragma unroll
   for (int j = 0; j < 7; ++j) kr[j] = km[j];
@@ -357,13 +358,14 @@ struct VankaDof {
 __device__ __forceinline__ VankaDof vanka_dof(const Geom& g, int s, int I, int J, int K, int r) {
   const int F = g.field;
   VankaDof d{0, false, I, J, K};
+  const int fb = r < 6 ? g.vface_bits(I, J, K) : 0;
   switch (r) {
-    case 0: d.e = g.at(s); d.active = I >= 2; d.nI = I - 1; break;
-    case 1: d.e = g.at(s + 1); d.active = I + 1 <= g.nx; d.nI = I + 1; break;
-    case 2: d.e = F + g.at(s); d.active = J >= 2; d.nJ = J - 1; break;
-    case 3: d.e = F + g.at(s + g.sy); d.active = J + 1 <= g.ny; d.nJ = J + 1; break;
-    case 4: d.e = 2 * F + g.at(s); d.active = K >= 2; d.nK = K - 1; break;
-    case 5: d.e = 2 * F + g.at(s + g.sz); d.active = K + 1 <= g.nz; d.nK = K + 1; break;
+    case 0: d.e = g.at(s); d.active = fb & 1; d.nI = I - 1; break;
+    case 1: d.e = g.at(s + 1); d.active = fb & 2; d.nI = I + 1; break;
+    case 2: d.e = F + g.at(s); d.active = fb & 4; d.nJ = J - 1; break;
+    case 3: d.e = F + g.at(s + g.sy); d.active = fb & 8; d.nJ = J + 1; break;
+    case 4: d.e = 2 * F + g.at(s); d.active = fb & 16; d.nK = K - 1; break;
+    case 5: d.e = 2 * F + g.at(s + g.sz); d.active = fb & 32; d.nK = K + 1; break;
     default: d.e = 3 * F + g.at(s); d.active = true; break;  // the cell's own pressure
   }
   return d;
@@ -378,7 +380,9 @@ __device__ __forceinline__ void vanka_copy_dof(const Geom& g, const T* __restric
   slot_ijk(g, s, I, J, K);
   const VankaDof d = vanka_dof(g, s, I, J, K, r);
   if (!d.active) return;
-  if (r < 6 && !g.p_v2(d.nI, d.nJ, d.nK) && Geom::vanka_colour(d.nI, d.nJ, d.nK) == k) return;
+  if (r < 6 && g.p_active(d.nI, d.nJ, d.nK) && !g.p_v2(d.nI, d.nJ, d.nK) &&
+      Geom::vanka_colour(d.nI, d.nJ, d.nK) == k)
+    return;
   W[d.e] = R[d.e];
 }
 
@@ -398,9 +402,7 @@ __global__ __launch_bounds__(BS) void k_vanka_pp8(Geom g, const T* __restrict__ 
     if (valid) slot_ijk(g, s, I, J, K);
     // loads that need only the cell go out before the residual and its shuffles:
     // this lane's row of the local inverse and the value it corrects
-    const bool a0 = I >= 2, a1 = I + 1 <= g.nx, a2 = J >= 2, a3 = J + 1 <= g.ny, a4 = K >= 2, a5 = K + 1 <= g.nz;
-    const int type = (int)a0 | ((int)a1 << 1) | ((int)a2 << 2) | ((int)a3 << 3) | ((int)a4 << 4) | ((int)a5 << 5);
-    const T* km = kinv + type * 64 + r * 8;
+    const T* km = kinv + g.vtype(I, J, K, g.vface_bits(I, J, K)) * 64 + r * 8;
     T kr[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) kr[j] = km[j];
@@ -587,7 +589,11 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
   const int Ff = f.field, Fc = c.field;
   const T wf[3] = {0.5, 1.0, 0.5};          // face axis: fine 2I-2, 2I-1, 2I
   const T wc[4] = {0.25, 0.75, 0.75, 0.25};  // cell axis: fine 2J-2 .. 2J+1
-  // u_x
+  // u_x.  A coarse face on the last face plane (I = nx+1: an unknown only
+  // beside an exterior layer) has no fine face beyond the lattice: the third
+  // fine face of its stencil is dropped, and so are the two more that the
+  // paired loads read past the row.
+  const bool xe = I == c.nx + 1, ye = J == c.ny + 1, ze = K == c.nz + 1;
   {
     T acc = T(0);
     if (c.ux_active(I, J, K)) {
@@ -595,7 +601,7 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
         for (int jj = 0; jj < 4; ++jj) {
           const T w = wc[jj] * wc[kk];
           const FineRow<T> q = fine_row(f, r, f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk));
-          acc += w * (wf[0] * q.r0 + wf[1] * q.r1 + wf[2] * q.r2);
+          acc += w * (wf[0] * q.r0 + wf[1] * q.r1 + (xe ? T(0) : wf[2] * q.r2));
         }
     }
     bc[s] = (T)(acc * T(0.125));
@@ -605,7 +611,7 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
     T acc = T(0);
     if (c.uy_active(I, J, K)) {
       for (int kk = 0; kk < 4; ++kk)
-        for (int jj = 0; jj < 3; ++jj) {
+        for (int jj = 0; jj < (ye ? 2 : 3); ++jj) {
           const FineRow<T> q = fine_row(f, r + Ff, f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk));
           const T rv[4] = {q.r0, q.r1, q.r2, q.r3};
           for (int ii = 0; ii < 4; ++ii) acc += wc[ii] * wf[jj] * wc[kk] * rv[ii];
@@ -617,7 +623,7 @@ __device__ __forceinline__ void restrict_item(const Geom& f, const Geom& c, cons
   {
     T acc = T(0);
     if (c.uz_active(I, J, K)) {
-      for (int kk = 0; kk < 3; ++kk)
+      for (int kk = 0; kk < (ze ? 2 : 3); ++kk)
         for (int jj = 0; jj < 4; ++jj) {
           const FineRow<T> q = fine_row(f, r + 2 * Ff, f.idx(2 * I - 2, 2 * J - 2 + jj, 2 * K - 2 + kk));
           const T rv[4] = {q.r0, q.r1, q.r2, q.r3};
@@ -908,6 +914,53 @@ __global__ __launch_bounds__(BS) void k_prolong_pairs(Geom f, Geom c, const T* _
   if (!slab_item(c, (c.nx + 1) >> 1, X, Jc, Kc)) return;
   if (Jc < 1 || Jc > c.ny || Kc < 1 || Kc > c.nz) return;
   prolong_pair_item<T>(f, c, e, x, 2 * X + 1, Jc, Kc);
+}
+
+// The fine faces on the last face plane of each velocity lattice (u_x at
+// I = nx+1, u_y at J = ny+1, u_z at K = nz+1), unknowns only beside an
+// exterior layer (labelled domains), which the paired items above do not
+// reach.  Such a fine face coincides with the coarse face on the coarse last
+// plane (weight 1 along its axis) and takes 3/4, 1/4 along the other two.
+// One thread per face of the three planes: t < ny nz for u_x, then nx nz for
+// u_y, then nx ny for u_z.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_prolong_edge(Geom f, Geom c, const T* __restrict__ e, T* __restrict__ x) {
+  long t = (long)blockIdx.x * BS + threadIdx.x;
+  const long nyz = (long)f.ny * f.nz, nxz = (long)f.nx * f.nz, nxy = (long)f.nx * f.ny;
+  int a, I, J, K;
+  if (t < nyz) {
+    a = 0; I = f.nx + 1; J = 1 + (int)(t % f.ny); K = 1 + (int)(t / f.ny);
+  } else if ((t -= nyz) < nxz) {
+    a = 1; J = f.ny + 1; I = 1 + (int)(t % f.nx); K = 1 + (int)(t / f.nx);
+  } else if ((t -= nxz) < nxy) {
+    a = 2; K = f.nz + 1; I = 1 + (int)(t % f.nx); J = 1 + (int)(t / f.nx);
+  } else {
+    return;
+  }
+  if (!(a == 0 ? f.ux_active(I, J, K) : a == 1 ? f.uy_active(I, J, K) : f.uz_active(I, J, K))) return;
+  // coarse index along each axis: the last face plane on axis a, near/far cells (3/4, 1/4) on the others
+  int n0[3], n1[3];
+  const int fi[3] = {I, J, K};
+  const int cl[3] = {c.nx + 1, c.ny + 1, c.nz + 1};
+  for (int b = 0; b < 3; ++b) {
+    if (b == a) {
+      n0[b] = n1[b] = cl[b];
+    } else {
+      cell_w(fi[b], n0[b], n1[b]);
+    }
+  }
+  const T* ea = e + (long)a * c.field;
+  T acc = T(0);
+  for (int q = 0; q < 8; ++q) {
+    const int ib = q & 1, jb = (q >> 1) & 1, kb = q >> 2;
+    if ((a == 0 && ib) || (a == 1 && jb) || (a == 2 && kb)) continue;
+    const T w = (a == 0 ? T(1) : (ib ? T(0.25) : T(0.75))) * (a == 1 ? T(1) : (jb ? T(0.25) : T(0.75))) *
+                (a == 2 ? T(1) : (kb ? T(0.25) : T(0.75)));
+    const int Ic = ib ? n1[0] : n0[0], Jc = jb ? n1[1] : n0[1], Kc = kb ? n1[2] : n0[2];
+    acc += w * ea[c.at(c.idx(Ic, Jc, Kc))];
+  }
+  T* xa = x + (long)a * f.field;
+  xa[f.at(f.idx(I, J, K))] += acc;
 }
 
 // ---------------------------------------------------------------------------

@@ -146,7 +146,9 @@ __device__ __forceinline__ bool row_pack(const Geom& g, int par, RowPack<V>& rp)
 
 // Velocity Gauss-Seidel step on the V2 faces of one colour: u += r / (6 eta/h^2).
 // Same-colour faces are not lattice neighbours and p is fixed, so the class
-// updates at once.
+// updates at once.  Every lattice neighbour of a V2 face is an unknown (V2
+// faces lie two cells or more from Dirichlet and three or more from exterior
+// cells), so its diagonal is 6 eta/h^2 in a labelled domain as in a box.
 template <typename T, typename TB, int V>
 __device__ __forceinline__ void dgs_u_pack(const Geom& g, T* __restrict__ x, const TB* __restrict__ b, const RowPack<V>& rp) {
   const int F = g.field;
@@ -515,7 +517,7 @@ __device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict_
                              pm = L(3, -ps);
 #pragma unroll
             for (int i = 0; i < V; ++i) {
-              // row_u's order: 6c - x- - x+ - y- - y+ - z- - z+
+              // row_u's order: n_f c - x- - x+ - y- - y+ - z- - z+
               T xm, xp, ym, yp, zm, zp;
               if (f == 0) {
                 xm = um.v[i]; xp = up.v[i]; ym = am.v[i]; yp = ap.v[i]; zm = bm.v[i]; zp = bp.v[i];
@@ -524,7 +526,8 @@ __device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict_
               } else {
                 xm = am.v[i]; xp = ap.v[i]; ym = bm.v[i]; yp = bp.v[i]; zm = um.v[i]; zp = up.v[i];
               }
-              const T lap = T(6) * c0.v[i] - xm - xp - ym - yp - zm - zp;
+              const T nd = g.flags ? T(g.nd(f, g.idx(rp.I0 + 2 * i, J, K))) : T(6);
+              const T lap = nd * c0.v[i] - xm - xp - ym - yp - zm - zp;
               o[i] = (T)g.c * lap + (pcv[i] - pm.v[i]) * (T)g.inv_h;
             }
           }

@@ -35,9 +35,11 @@ struct Level {
   int* vcells[27] = {};   // V1 cells per colour class (8 or 27 classes)
   int nv[27] = {};
   long doff[27] = {};     // class slice of the Vanka delta buffer (additive Vanka keeps all classes)
-  void* kinv = nullptr;  // 64 x 8 x 8 Vanka local inverses
+  void* kinv = nullptr;  // Vanka local inverses, 8 x 8 per type (64 types for a box)
   void* alt = nullptr;   // second copy of the state for the two-copy Vanka passes (k_vanka_pp*)
   bool pp = false;       // this level runs them
+  bool sweep_ok = true;  // the one-workgroup Vanka step may run here (its LDS holds 64 types)
+  uint32_t* flags = nullptr;  // labelled domain: the level's flag words (device)
 };
 
 struct Carver {
@@ -80,6 +82,11 @@ struct stokes_ctx {
   // Vanka delta scratch (max colour count x 8)
   void* vdelta = nullptr;
   int prec = 64;  // V-cycle precision
+  // labelled domain (stokes_params.labels): per-level labels and host tables
+  bool labelled = false;
+  bool neumann = false;           // some unknown face borders an exterior cell: pressure is unique
+  std::vector<Labels> labs;
+  std::vector<LevelLabels> ll;
   // kernel timing (diagnostics)
   int prof_class = STOKES_KC_OFF, prof_level = -1;
   struct Pending { int k, l; hipEvent_t a, b; };
@@ -194,6 +201,10 @@ int dgs_grid(const Geom& g) {  // packed DGS kernels: packs of one colour per ro
 
 int restrict_grid(const Geom& gc) { return slab_blocks(gc, gc.sy); }  // k_restrict: one item per coarse slot
 int prolong_grid(const Geom& gc) { return slab_blocks(gc, (gc.nx + 1) >> 1); }  // k_prolong_pairs: one per pair of coarse cells
+int prolong_edge_grid(const Geom& g) {  // k_prolong_edge: one per face of the three last face planes
+  const long n = (long)g.ny * g.nz + (long)g.nx * g.nz + (long)g.nx * g.ny;
+  return (int)((n + BS - 1) / BS);
+}
 
 #define HIPCHK(call)                                  \
   do {                                                \
@@ -205,6 +216,7 @@ int vanka_classes(const stokes_params& p) { return p.vanka == STOKES_VANKA_MULT2
 
 // Levels whose Vanka step runs in one workgroup (k_vanka_sweep).
 bool vsweep_level(const Level& lv, int nc) {
+  if (!lv.sweep_ok) return false;
   for (int k = 0; k < nc; ++k)
     if (lv.nv[k] > VSWEEP_MAX_CLASS) return false;
   return true;
@@ -228,6 +240,19 @@ int validate(const stokes_params* p, int* levels_out) {
   if (p->vanka != STOKES_VANKA_MULT8 && p->vanka != STOKES_VANKA_MULT27 && p->vanka != STOKES_VANKA_ADDITIVE)
     return STOKES_EINVAL;
   if (p->cycle != 1 && p->cycle != 2) return STOKES_EINVAL;
+  if (p->labels) {  // Section 5 labels: values 0..2, no interior cell on the outer layer, some interior cell
+    long interior = 0;
+    for (int k = 0; k < p->nz + 2; ++k)
+      for (int j = 0; j < p->ny + 2; ++j)
+        for (int i = 0; i < p->nx + 2; ++i) {
+          const uint8_t v = p->labels[i + (long)(p->nx + 2) * (j + (long)(p->ny + 2) * k)];
+          if (v > CELL_EXTERIOR) return STOKES_EINVAL;
+          const bool outer = i == 0 || j == 0 || k == 0 || i == p->nx + 1 || j == p->ny + 1 || k == p->nz + 1;
+          if (v == CELL_INTERIOR && outer) return STOKES_EINVAL;
+          interior += v == CELL_INTERIOR;
+        }
+    if (interior == 0) return STOKES_EINVAL;
+  }
   int L = p->levels;
   if (L == 0) L = count_levels(p->nx, p->ny, p->nz, 4);
   if (L < 1 || L > count_levels(p->nx, p->ny, p->nz, 2)) return STOKES_EINVAL;
@@ -248,6 +273,21 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
   const size_t es = c->prec == 32 ? sizeof(float) : sizeof(double);
   c->lev.assign(L, Level{});
   for (int l = 0; l < L; ++l) c->lev[l].g = make_geom(p.nx, p.ny, p.nz, p.h, p.eta, p.gamma, l);
+  c->labelled = p.labels != nullptr;
+  if (c->labelled && (int)c->ll.size() != L) {
+    c->labs.assign(L, Labels{});
+    c->ll.assign(L, LevelLabels{});
+    Labels& l0 = c->labs[0];
+    l0.nx = p.nx;
+    l0.ny = p.ny;
+    l0.nz = p.nz;
+    l0.v.assign(p.labels, p.labels + (size_t)(p.nx + 2) * (p.ny + 2) * (p.nz + 2));
+    for (int l = 0; l < L; ++l) {
+      if (l > 0) c->labs[l] = coarsen(c->labs[l - 1]);
+      label_tables(c->lev[l].g, c->labs[l], c->ll[l]);
+    }
+    c->neumann = c->ll[0].neumann;
+  }
   const Geom& g0 = c->lev[0].g;
   c->total = 4L * g0.field;
   c->s = cv.take<double>(c->total);
@@ -268,13 +308,21 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
       lv.b = cv.take<char>(tot * es);
       lv.x = cv.take<char>(tot * es);
     }
+    if (c->labelled) lv.flags = cv.take<uint32_t>(lv.g.field);
     if (l < L - 1) {
       lv.r = cv.take<char>(tot * es);
       lv.dscr = cv.take<char>(lv.g.field * es);
-      lv.kinv = cv.take<char>(64 * 64 * es);
+      // at least 64 types: the one-workgroup step loads a table of 64
+      const int ntypes = c->labelled ? std::max(c->ll[l].ntypes, 64) : 64;
+      lv.kinv = cv.take<char>((size_t)ntypes * 64 * es);
       std::vector<int> cells[27];
       const int nc = vanka_classes(p);
-      vanka_cells(lv.g, cells, nc == 27 ? 3 : 2);
+      Geom gh = lv.g;
+      if (c->labelled) gh.flags = c->ll[l].flags.data();
+      vanka_cells(gh, cells, nc == 27 ? 3 : 2);
+      // the one-workgroup step keeps 64 types in LDS; the two-copy passes
+      // resynchronise a band along the box walls only
+      lv.sweep_ok = !c->labelled || c->ll[l].ntypes <= 64;
       long sum = 0;
       for (int k = 0; k < nc; ++k) {
         lv.nv[k] = (int)cells[k].size();
@@ -285,14 +333,14 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
       }
       // two-copy passes where a pass is a latency chain (eight lanes per subdomain);
       // on larger levels the passes are bound by bandwidth and the copies cost more
-      lv.pp = p.vanka == STOKES_VANKA_MULT8 && !vsweep_level(lv, nc);
+      lv.pp = p.vanka == STOKES_VANKA_MULT8 && !c->labelled && !vsweep_level(lv, nc);
       for (int k = 0; k < nc; ++k) lv.pp = lv.pp && lv.nv[k] <= VANKA_LANES_MAX;
       if (lv.pp) lv.alt = cv.take<char>(tot * es);
     }
   }
   c->vdelta = cv.take<char>(8 * std::max<long>(vmax, 1) * es);
   const Geom& gc = c->lev[L - 1].g;
-  c->nc = (int)coarse_dofs(gc);
+  c->nc = c->labelled ? (int)c->ll[L - 1].n_dofs : (int)coarse_dofs(gc);
   c->cinv = cv.take<double>((size_t)c->nc * c->nc);
   c->cdof = cv.take<int>(c->nc);
 }
@@ -525,6 +573,8 @@ void vcycle(stokes_ctx* c, int l, const T* b, T* x, bool zero_init = true) {
   vcycle(c, l + 1, (const T*)bc, xc);
   for (int i = 1; i < c->prm.cycle; ++i) vcycle(c, l + 1, (const T*)bc, xc, false);
   launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_pairs<T><<<prolong_grid(gc), BS, 0, c->ks>>>(g, gc, xc, x); });
+  if (c->labelled)
+    launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_edge<T><<<prolong_edge_grid(g), BS, 0, c->ks>>>(g, gc, xc, x); });
   postsmooth(c, l, x, b);
 }
 
@@ -672,10 +722,25 @@ int setup_ctx(const stokes_params* p, void* workspace, size_t bytes, void* hip_s
     stokes_destroy(c);
     return code;
   };
+  if (c->labelled) {
+    for (int l = 0; l < L; ++l) {
+      Level& lv = c->lev[l];
+      if (c->ll[l].ntypes > 1024 ||
+          hipMemcpyAsync(lv.flags, c->ll[l].flags.data(), sizeof(uint32_t) * lv.g.field, hipMemcpyHostToDevice,
+                         c->stream) != hipSuccess)
+        return fail(STOKES_EDEVICE);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(STOKES_EDEVICE);
+  }
   for (int l = 0; l < L - 1; ++l) {
     Level& lv = c->lev[l];
     std::vector<double> kinv;
-    if (!vanka_inverses(lv.g, kinv)) return fail(STOKES_EINVAL);
+    if (c->labelled) {
+      kinv = c->ll[l].kinv;
+      if (kinv.empty()) kinv.assign(64, 0.0);
+    } else if (!vanka_inverses(lv.g, kinv)) {
+      return fail(STOKES_EINVAL);
+    }
     std::vector<float> kinv_f(kinv.begin(), kinv.end());
     const void* src = c->prec == 32 ? (const void*)kinv_f.data() : (const void*)kinv.data();
     const size_t nbytes = kinv.size() * (c->prec == 32 ? sizeof(float) : sizeof(double));
@@ -684,7 +749,9 @@ int setup_ctx(const stokes_params* p, void* workspace, size_t bytes, void* hip_s
       return fail(STOKES_EDEVICE);
     std::vector<int> cells[27];
     const int nc = vanka_classes(c->prm);
-    vanka_cells(lv.g, cells, nc == 27 ? 3 : 2);
+    Geom gh = lv.g;
+    if (c->labelled) gh.flags = c->ll[l].flags.data();
+    vanka_cells(gh, cells, nc == 27 ? 3 : 2);
     for (int k = 0; k < nc; ++k) {
       if (cells[k].empty()) continue;
       if (hipMemcpyAsync(lv.vcells[k], cells[k].data(), cells[k].size() * sizeof(int), hipMemcpyHostToDevice,
@@ -696,12 +763,24 @@ int setup_ctx(const stokes_params* p, void* workspace, size_t bytes, void* hip_s
   {
     std::vector<int> dof;
     std::vector<double> inv;
-    if (!coarse_inverse(c->lev[L - 1].g, dof, inv) || (int)dof.size() != c->nc) return fail(STOKES_EINVAL);
+    Geom gh = c->lev[L - 1].g;
+    if (c->labelled) gh.flags = c->ll[L - 1].flags.data();
+    if (!coarse_inverse(gh, dof, inv) || (int)dof.size() != c->nc) return fail(STOKES_EINVAL);
     if (hipMemcpyAsync(c->cinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
             hipSuccess ||
         hipMemcpyAsync(c->cdof, dof.data(), dof.size() * sizeof(int), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
       return fail(STOKES_EDEVICE);
+  }
+  // kernels of a labelled domain read its flag words
+  if (c->labelled)
+    for (int l = 0; l < L; ++l) c->lev[l].g.flags = c->lev[l].flags;
+  c->labs.clear();
+  c->labs.shrink_to_fit();
+  for (auto& t : c->ll) {
+    t.flags.clear();
+    t.flags.shrink_to_fit();
+    t.kinv.clear();
   }
   // workspace vectors start from zero (their ghost slots are never written otherwise)
   for (int l = 0; l < L; ++l) {
@@ -808,7 +887,7 @@ int stokes_layout(const stokes_ctx* c, stokes_layout_t* out) {
   for (int f = 0; f < 4; ++f) out->off[f] = (int64_t)f * g.field;
   out->field = g.field;
   out->total = c->total;
-  out->n_dofs = coarse_dofs(g);
+  out->n_dofs = c->labelled ? c->ll[0].n_dofs : coarse_dofs(g);
   out->levels = c->L;
   return STOKES_OK;
 }
@@ -824,7 +903,7 @@ int stokes_level_layout(const stokes_ctx* c, int32_t level, stokes_layout_t* out
   for (int f = 0; f < 4; ++f) out->off[f] = (int64_t)f * g.field;
   out->field = g.field;
   out->total = 4L * g.field;
-  out->n_dofs = coarse_dofs(g);
+  out->n_dofs = c->labelled ? c->ll[level].n_dofs : coarse_dofs(g);
   out->levels = c->L - level;
   return STOKES_OK;
 }
@@ -843,6 +922,7 @@ int stokes_prolong(stokes_ctx* c, const double* coarse, double* fine) {
   const Geom& gc = c->lev[1].g;
   k_fill<double><<<RED_BLOCKS, BS, 0, c->stream>>>(fine, 4L * g.field, 0.0);
   k_prolong_pairs<double><<<prolong_grid(gc), BS, 0, c->stream>>>(g, gc, coarse, fine);
+  if (c->labelled) k_prolong_edge<double><<<prolong_edge_grid(g), BS, 0, c->stream>>>(g, gc, coarse, fine);
   return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
 }
 
@@ -917,7 +997,7 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
   double relres = std::sqrt(c->hscal[0]) / bnorm;
   if (info && info->history) info->history[0] = relres;
   auto finish = [&](int iters, int status) {
-    if (status == STOKES_OK && (c->prm.flags & STOKES_FLAG_REMOVE_MEAN)) {
+    if (status == STOKES_OK && (c->prm.flags & STOKES_FLAG_REMOVE_MEAN) && !c->neumann) {
       {
         Prof pf(c, STOKES_KC_BLAS, 0);
         k_sum_p<<<gf, BS, 0, c->stream>>>(g, x, c->partial);
@@ -926,7 +1006,7 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
         Prof pf(c, STOKES_KC_BLAS, 0);
         k_reduce<<<1, 1024, 0, c->stream>>>(c->partial, gf, 1, c->dscal);
       }
-      const double ncell = (double)g.nx * g.ny * g.nz;
+      const double ncell = c->labelled ? (double)c->ll[0].n_cells : (double)g.nx * g.ny * g.nz;
       // mean = sum / ncell, computed on the host to keep one rounding
       if (hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
           hipStreamSynchronize(c->stream) != hipSuccess)

@@ -30,7 +30,7 @@ class StokesParams(ctypes.Structure):
                 ("h", ctypes.c_double), ("eta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("levels", ctypes.c_int32), ("nu", ctypes.c_int32), ("n_boundary", ctypes.c_int32),
                 ("vcycle_precision", ctypes.c_int32), ("smoother", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("vanka", ctypes.c_int32), ("cycle", ctypes.c_int32)]
+                ("vanka", ctypes.c_int32), ("cycle", ctypes.c_int32), ("labels", ctypes.c_void_p)]
 
 
 class StokesLayout(ctypes.Structure):
@@ -225,10 +225,27 @@ def field_index(layout, device):
     return (s & 1) * (L.field // 2) + (s >> 1)
 
 
-def pack_fields(layout, fields, out, device):
+def unknown_masks(labels):
+    """The unknowns of a labelled domain (the rule of stokes_params.labels) as
+    boolean arrays of the natural shapes: ux (nx+1, ny, nz), uy, uz, p.
+    `labels` is indexed [i, j, k] over the padded box."""
+    lab = np.asarray(labels)
+    inter, dirc = lab == 0, lab == 1
+    out = []
+    for a in range(3):
+        lo = [slice(1, -1)] * 3
+        hi = [slice(1, -1)] * 3
+        lo[a], hi[a] = slice(0, -1), slice(1, None)
+        lo, hi = tuple(lo), tuple(hi)
+        out.append((inter[lo] | inter[hi]) & ~dirc[lo] & ~dirc[hi])
+    out.append(inter[1:-1, 1:-1, 1:-1].copy())
+    return out
+
+
+def pack_fields(layout, fields, out, device, masks=None):
     """Natural arrays (ux (nx+1,ny,nz), uy, uz, p), numpy or torch, indexed
-    [i,j,k] -> the padded state `out`; only unknowns are copied, every other
-    slot is 0."""
+    [i,j,k] -> the padded state `out`; only unknowns are copied (the box's, or
+    those of `masks` for a labelled domain), every other slot is 0."""
     import torch
     L = layout
     nx, ny, nz = L.nx, L.ny, L.nz
@@ -236,6 +253,13 @@ def pack_fields(layout, fields, out, device):
     e = field_index(L, st.device)
     t = [torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
                          dtype=torch.float64).to(device) for a in fields]
+    if masks is not None:
+        t = [v * torch.as_tensor(m, device=v.device) for v, m in zip(t, masks)]
+        st[L.off[0] + e[1:nz + 1, 1:ny + 1, 1:nx + 2]] = t[0].permute(2, 1, 0)
+        st[L.off[1] + e[1:nz + 1, 1:ny + 2, 1:nx + 1]] = t[1].permute(2, 1, 0)
+        st[L.off[2] + e[1:nz + 2, 1:ny + 1, 1:nx + 1]] = t[2].permute(2, 1, 0)
+        st[L.off[3] + e[1:nz + 1, 1:ny + 1, 1:nx + 1]] = t[3].permute(2, 1, 0)
+        return st
     st[L.off[0] + e[1:nz + 1, 1:ny + 1, 2:nx + 1]] = t[0][1:nx].permute(2, 1, 0)
     st[L.off[1] + e[1:nz + 1, 2:ny + 1, 1:nx + 1]] = t[1][:, 1:ny].permute(2, 1, 0)
     st[L.off[2] + e[2:nz + 1, 1:ny + 1, 1:nx + 1]] = t[2][:, :, 1:nz].permute(2, 1, 0)
@@ -243,8 +267,9 @@ def pack_fields(layout, fields, out, device):
     return st
 
 
-def unpack_fields(layout, state):
-    """Padded state -> natural numpy arrays (walls included, zero)."""
+def unpack_fields(layout, state, masks=None):
+    """Padded state -> natural numpy arrays (walls included, zero; for a
+    labelled domain every slot that is not an unknown of `masks` is zero)."""
     L = layout
     nx, ny, nz = L.nx, L.ny, L.nz
     e = field_index(L, state.device)
@@ -252,6 +277,8 @@ def unpack_fields(layout, state):
     uy = state[L.off[1] + e[1:nz + 1, 1:ny + 2, 1:nx + 1]].permute(2, 1, 0).cpu().numpy().copy()
     uz = state[L.off[2] + e[1:nz + 2, 1:ny + 1, 1:nx + 1]].permute(2, 1, 0).cpu().numpy().copy()
     p = state[L.off[3] + e[1:nz + 1, 1:ny + 1, 1:nx + 1]].permute(2, 1, 0).cpu().numpy().copy()
+    if masks is not None:
+        return tuple(np.where(m, v, 0.0) for m, v in zip(masks, (ux, uy, uz, p)))
     ux[0] = ux[-1] = 0.0
     uy[:, 0] = uy[:, -1] = 0.0
     uz[:, :, 0] = uz[:, :, -1] = 0.0
@@ -264,11 +291,22 @@ class StokesSolver:
 
     def __init__(self, nx, ny, nz, h=None, *, eta=1.0, gamma=1e-3, levels=0, nu=2, n_boundary=1,
                  schedule="symmetric", precision=64, remove_mean=True, graphs=True, vanka="mult8",
-                 cycle=1, device=None, stream=None):
+                 cycle=1, labels=None, device=None, stream=None):
+        """`labels`: optional cell labels of Section 5 indexed [i, j, k] over the
+        padded box ((nx+2, ny+2, nz+2); 0 interior, 1 Dirichlet, 2 exterior)."""
         import torch
         self.torch = torch
         h = 1.0 / max(nx, ny, nz) if h is None else h
         p = stokes_default_params(nx, ny, nz, h)
+        self.masks = None
+        lab_c = None
+        if labels is not None:
+            labels = np.asarray(labels)
+            if labels.shape != (nx + 2, ny + 2, nz + 2):
+                raise ValueError("labels must have shape (nx+2, ny+2, nz+2)")
+            lab_c = np.ascontiguousarray(labels.transpose(2, 1, 0), dtype=np.uint8)   # x fastest
+            p.labels = lab_c.ctypes.data
+            self.masks = unknown_masks(labels)
         p.eta, p.gamma, p.levels, p.nu, p.n_boundary = eta, gamma, levels, nu, n_boundary
         p.smoother = SMOOTHERS[schedule]
         p.vcycle_precision = precision
@@ -284,6 +322,8 @@ class StokesSolver:
         self._ws_ptr, self._ws_bytes = base + off, nbytes
         with torch.cuda.device(self.device):
             self.ctx = stokes_setup(p, self._ws_ptr, nbytes, self.stream.cuda_stream)
+        p.labels = None   # read during set-up only
+        del lab_c
         self.layout = stokes_layout(self.ctx)
 
     def close(self):
@@ -304,11 +344,11 @@ class StokesSolver:
     def pack(self, fields, out=None):
         """Natural arrays (ux (nx+1,ny,nz), uy, uz, p), numpy or torch, indexed
         [i,j,k] -> padded state; only unknowns are copied, every other slot is 0."""
-        return pack_fields(self.layout, fields, self.new_state() if out is None else out, self.device)
+        return pack_fields(self.layout, fields, self.new_state() if out is None else out, self.device, self.masks)
 
     def unpack(self, state):
         """Padded state -> natural numpy arrays (walls included, zero)."""
-        return unpack_fields(self.layout, state)
+        return unpack_fields(self.layout, state, self.masks)
 
     # operations
     def apply(self, x, penalized=False, out=None):

@@ -119,3 +119,34 @@ def test_red_black_field_index_is_a_bijection_split_by_colour(dims):
     assert bool(((e >= lay.field // 2) == (colour == 1)).all())
     # along a row, same-colour cells are neighbours in memory
     assert bool((e[1, 1, 3::2][:-1] + 1 == e[1, 1, 3::2][1:]).all())
+
+
+def test_labels_are_validated_on_the_host():
+    """Labelled domains: a valid label array is sized like the box; a label
+    value above 2, an interior cell on the outer layer, or labels passed to the
+    batch calls are rejected without a device."""
+    import ctypes
+
+    import numpy as np
+    n = 8
+    lab = np.ones((n + 2,) * 3, dtype=np.uint8)
+    lab[1:-1, 1:-1, 1:-1] = 0
+    lab[-1, 1:-1, 1:-1] = 2
+    p = S.stokes_default_params(n, n, n, 1 / n)
+    box = S.stokes_workspace_bytes(p)
+    p.labels = lab.ctypes.data
+    assert S.stokes_workspace_bytes(p) > box     # the flag words
+    bad = lab.copy()
+    bad[0, 3, 3] = 0
+    p.labels = bad.ctypes.data
+    with pytest.raises(S.StokesError):
+        S.stokes_workspace_bytes(p)
+    bad = lab.copy()
+    bad[4, 4, 4] = 3
+    p.labels = bad.ctypes.data
+    with pytest.raises(S.StokesError):
+        S.stokes_workspace_bytes(p)
+    p.labels = lab.ctypes.data
+    arr = (S.StokesParams * 1)(p)
+    nbytes = ctypes.c_size_t(0)
+    assert S.load_library().stokes_batch_workspace_bytes(1, arr, ctypes.byref(nbytes)) == S.STOKES_EINVAL
