@@ -182,6 +182,56 @@ def gpu_small_solve(seed, rtol):
     return {"s": round(float(np.median(ts)), 5), "iters": info["iters"]}
 
 
+def channel_labels(n):
+    """A 256^3-style channel of Section 5 labels: Dirichlet walls and inflow
+    side, a Dirichlet block obstacle, one layer of exterior cells on the +x
+    (outflow) side.  Indexed [i, j, k] over the padded box."""
+    import numpy as np
+    lab = np.ones((n + 2,) * 3, dtype=np.uint8)
+    lab[1:-1, 1:-1, 1:-1] = 0
+    lab[-1, 1:-1, 1:-1] = 2
+    q = n // 4
+    lab[q + 1:2 * q + 1, q + 1:2 * q + 1, q + 1:2 * q + 1] = 1
+    return lab
+
+
+def labelled_leg(n, steps, rtol, seed):
+    """The same solve on a labelled domain (obstacle + outflow, Section 5):
+    time, iterations and V-cycle time, FP64."""
+    import numpy as np
+    import torch
+
+    from paper_2312_10615_amd.stokes import StokesSolver
+    from paper_2312_10615_amd.workloads import sinusoid_forcing
+    lab = channel_labels(n)
+    sol = StokesSolver(n, n, n, h=1.0 / n, labels=lab)
+    f = sinusoid_forcing(n, n, n, 1.0 / n, seed=seed)
+    b = sol.pack((f[0], f[1], f[2], np.zeros((n, n, n))))
+    del f
+    x, info = sol.solve(b, rtol=rtol, maxit=500)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x, info = sol.solve(b, rtol=rtol, maxit=500)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / steps
+    t = sol.new_state()
+    sol.vcycle(b, out=t)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        sol.vcycle(b, out=t)
+    e1.record()
+    torch.cuda.synchronize()
+    out = {"value": round(ts, 6), "unit": "s", "iterations": info["iters"], "final_relres": info["relres"],
+           "status": info["status"], "vcycle_ms": round(e0.elapsed_time(e1) / 5, 3), "unknowns": int(sol.layout.n_dofs),
+           "domain": f"{n}^3 labelled channel: no-slip walls and inflow side, a {n // 4}^3 Dirichlet block obstacle, "
+                     f"an exterior (outflow, Neumann) layer on the +x side"}
+    sol.close()
+    print(f"[bench] labelled {n}^3: {ts * 1e3:.1f} ms, iters={info['iters']}", file=sys.stderr, flush=True)
+    return out
+
+
 def mixed_384_leg(steps, rtol, seed):
     """FP32 V-cycle at 384^3 (7 levels down to 6^3, 756 coarsest unknowns)
     against the FP64 GPU solve of the same problem (the error reference)."""
@@ -379,6 +429,7 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--no-384", action="store_true", help="skip the 384^3 FP32-V-cycle leg")
     ap.add_argument("--no-split", action="store_true", help="skip the split-schedule leg")
+    ap.add_argument("--no-labelled", action="store_true", help="skip the labelled-domain (obstacle + outflow) leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
@@ -507,10 +558,15 @@ def main():
         batched = batched_leg(args.steps, args.rtol, args.seed)
 
     m384 = None
-    if not args.no_384 and n == 256:
+    labelled = None
+    if (not args.no_384 and n == 256) or not args.no_labelled:
         sol.close()
         del sol, x, s, t, b
         torch.cuda.empty_cache()
+    if not args.no_labelled:
+        labelled = labelled_leg(n, args.steps, args.rtol, args.seed)
+        torch.cuda.empty_cache()
+    if not args.no_384 and n == 256:
         m384 = mixed_384_leg(args.steps, args.rtol, args.seed)
 
     gsmall = None
@@ -570,6 +626,8 @@ def main():
         line["mixed_precision"] = mixed
     if m384 is not None:
         line["mixed_precision_384"] = m384
+    if labelled is not None:
+        line["labelled_domain"] = labelled
     if batched is not None:
         line["batched"] = batched
     if warm is not None:
