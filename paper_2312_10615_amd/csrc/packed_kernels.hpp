@@ -453,14 +453,19 @@ __device__ __forceinline__ bool slot_pack(const Geom& g, RowPack<V>& rp) {
 // anyway: the pressure centre and the divergence, summed in the order of
 // row_p, are carried from stage to stage (25 wide loads of x per pack
 // instead of 34).
-template <int MODE, typename T, typename TB, int V>
-__device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
-                                             T* __restrict__ y, double gamma, const RowPack<V>& rp) {
+// The values of a pack go to sink(f, v) (field f, V values; ghost and
+// non-unknown slots 0) in the modes that produce y.
+// STAGED = false drops the stage fences, so that every load of the pack may
+// issue at once (for kernels that run few waves per SIMD).
+template <int MODE, typename T, typename TB, int V, bool STAGED = true, typename Sink>
+__device__ __forceinline__ double apply_pack_to(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                                double gamma, const RowPack<V>& rp, Sink&& sink) {
   double acc = 0.0;
   int F = g.field;
   int sy = g.sy, sz = g.sz, hf = g.half;
   int eb = rp.e0;
   auto stage = [&](const T* dep) {
+    if constexpr (!STAGED) return;
 #pragma unroll
     for (int i = 0; i < V; ++i) asm volatile("" : "+v"(eb) : "v"(dep[i]));
     asm volatile("" : "+v"(eb), "+s"(F), "+s"(sy), "+s"(sz), "+s"(hf));
@@ -552,19 +557,7 @@ __device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict_
 #pragma unroll
       for (int i = 0; i < V; ++i) v[i] = act[i] ? o[i] : T(0);
     }
-    if (MODE == AP_APPLY || MODE == AP_RESID || MODE == AP_APPLY_DOT) {
-      T* yo = y + f * F + rp.el(0);
-      if (rp.n == V) {
-        Pack<T, V> w;
-#pragma unroll
-        for (int i = 0; i < V; ++i) w.v[i] = v[i];
-        stp<T, V>(yo, w);
-      } else {
-#pragma unroll
-        for (int i = 0; i < V; ++i)
-          if (i < rp.n) yo[i] = v[i];
-      }
-    }
+    if (MODE == AP_APPLY || MODE == AP_RESID || MODE == AP_APPLY_DOT) sink(f, v);
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       if (i >= rp.n) continue;
@@ -577,6 +570,25 @@ __device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict_
 }
 
 template <int MODE, typename T, typename TB, int V>
+__device__ __forceinline__ double apply_pack(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b,
+                                             T* __restrict__ y, double gamma, const RowPack<V>& rp) {
+  const int F = g.field;
+  return apply_pack_to<MODE, T, TB, V>(g, x, b, gamma, rp, [&](int f, const T* v) {
+    T* yo = y + f * F + rp.el(0);
+    if (rp.n == V) {
+      Pack<T, V> w;
+#pragma unroll
+      for (int i = 0; i < V; ++i) w.v[i] = v[i];
+      stp<T, V>(yo, w);
+    } else {
+#pragma unroll
+      for (int i = 0; i < V; ++i)
+        if (i < rp.n) yo[i] = v[i];
+    }
+  });
+}
+
+template <int MODE, typename T, typename TB, int V>
 __global__ __launch_bounds__(BS) void k_apply_v(Geom g, const T* __restrict__ x, const TB* __restrict__ b,
                                                 T* __restrict__ y, double gamma, double* __restrict__ partial) {
   double acc = 0.0;
@@ -586,6 +598,145 @@ __global__ __launch_bounds__(BS) void k_apply_v(Geom g, const T* __restrict__ x,
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Residual and restriction without the fine residual in memory (Alg. 1:
+// r = b - L~ x on level l, then the coarse right-hand side R r).  The
+// restriction (the transposed prolongation over 8, Section 3.2) is a tensor
+// product of 1D weights: (1/2, 1, 1/2) along a velocity component's own axis,
+// (1/4, 3/4, 3/4, 1/4) along the other two, 1 over the 2x2 fine cells of a
+// pressure in each direction.  Two passes:
+//   k_resid_restrict_xy: a workgroup takes one fine plane under a tile of
+//     RR_TX x RR_TY coarse columns; the residual over the tile's fine window
+//     (its fine columns and one more on each side) goes to LDS, computed pack
+//     by pack as the operator pass computes it, and each thread restricts its
+//     coarse column in x and y: S[f][Kf][J][I], one value per component, fine
+//     plane and coarse column (a quarter of a fine field per component);
+//   k_restrict_z: the coarse unknown sums its fine planes' S with the z weights
+//     (in increasing Kf) and the 1/8.
+// Fine slots outside the lattice hold 0 in the window, which drops the terms
+// the two-pass restriction drops at the last face planes.  The sums run in a
+// different order from k_restrict, so the two differ by rounding.
+// ---------------------------------------------------------------------------
+constexpr int RR_TX = 16, RR_TY = 16;  // coarse columns of a workgroup: one per thread
+constexpr int RR_WX = 2 * RR_TX + 2, RR_WY = 2 * RR_TY + 2;
+static_assert(RR_TX * RR_TY == BS, "one coarse column per thread");
+
+// Elements of S: 4 components x (fine planes) x (coarse rows) x (coarse row pitch).
+__host__ __device__ inline long rr_plane(const Geom& f, const Geom& c) { return (long)(c.ny + 2) * c.sy; }
+__host__ __device__ inline long rr_elems(const Geom& f, const Geom& c) { return 4L * (f.nz + 2) * rr_plane(f, c); }
+
+// Workgroups: XCD x (blockIdx % NXCD) takes a run of consecutive fine planes
+// and goes through it strip by strip (a row of tiles), plane by plane, tile by
+// tile, so that the lines two neighbouring tiles share and the planes below
+// and above a stencil are read by the same XCD close in time (one L2).
+// Returns false for the padding blocks past the last plane or strip.
+__host__ __device__ inline int rr_cols_x(const Geom& c) { return (c.sy + RR_TX - 1) / RR_TX; }
+__host__ __device__ inline int rr_cols_y(const Geom& c) { return (c.ny + 2 + RR_TY - 1) / RR_TY; }
+__host__ __device__ inline int rr_run(const Geom& f) { return (f.nz + 2 + NXCD - 1) / NXCD; }
+__host__ __device__ inline long rr_blocks(const Geom& f, const Geom& c) {
+  return (long)NXCD * rr_cols_x(c) * rr_cols_y(c) * rr_run(f);
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(BS) void k_resid_restrict_xy(Geom f, Geom c, const T* __restrict__ x,
+                                                          const T* __restrict__ b, T* __restrict__ S) {
+  __shared__ T sr[4][RR_WY][RR_WX];
+  const int cx = rr_cols_x(c), run = rr_run(f);
+  const int l = blockIdx.x / NXCD;
+  const int xt = l % cx, rest = l / cx;
+  const int Kf = (blockIdx.x % NXCD) * run + rest % run, yt = rest / run;
+  if (Kf > f.nz + 1 || yt >= rr_cols_y(c)) return;
+  const int I0 = xt * RR_TX, J0 = yt * RR_TY;
+  const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
+  // the fine window clipped to the lattice; the rest of it holds 0
+  const int ilo = max(fi0, 0), ihi = min(fi0 + RR_WX, f.nx + 2);
+  const int jlo = max(fj0, 0), jhi = min(fj0 + RR_WY, f.ny + 2);
+  if (ilo > fi0 || ihi < fi0 + RR_WX || jlo > fj0 || jhi < fj0 + RR_WY) {
+    for (int t = threadIdx.x; t < 4 * RR_WY * RR_WX; t += BS) (&sr[0][0][0])[t] = T(0);
+    __syncthreads();
+  }
+  constexpr int PPQ = (RR_TX + 1 + V - 1) / V;  // packs per parity of a window row
+  const int npk = (jhi - jlo) * 2 * PPQ;
+  for (int P = threadIdx.x; P < npk; P += BS) {
+    const int row = P / (2 * PPQ), rem = P - row * (2 * PPQ);
+    const int q = rem / PPQ, m = rem - q * PPQ;
+    const int Jf = jlo + row;
+    const int first = ilo + ((q - ilo) & 1) + 2 * V * m;  // slots of I-parity q from ilo
+    if (first >= ihi) continue;
+    RowPack<V> rp;
+    rp.n = min(V, (ihi - first + 1) >> 1);
+    rp.I0 = first;
+    rp.J = Jf;
+    rp.K = Kf;
+    const int s0 = first + f.sy * Jf + f.sz * Kf;
+    rp.e0 = s0 >> 1;
+    rp.par = s0 & 1;
+    rp.half = f.half;
+    T* dst = &sr[0][Jf - fj0][first - fi0];
+    apply_pack_to<AP_RESID, T, T, V, false>(f, x, b, f.gamma, rp, [&](int fld, const T* v) {
+#pragma unroll
+      for (int i = 0; i < V; ++i)
+        if (i < rp.n) dst[fld * (RR_WY * RR_WX) + 2 * i] = v[i];
+    });
+  }
+  __syncthreads();
+  const int tI = threadIdx.x % RR_TX, tJ = threadIdx.x / RR_TX;
+  const int I = I0 + tI, J = J0 + tJ;
+  if (I >= c.sy || J >= c.ny + 2) return;
+  const T wc[4] = {T(0.25), T(0.75), T(0.75), T(0.25)};
+  const T wf[3] = {T(0.5), T(1), T(0.5)};
+  const int li = 2 * tI, lj = 2 * tJ;  // window position of fine 2I-2, 2J-2
+  T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    const T* rx = &sr[0][lj + jj][li];
+    const T* rz = &sr[2][lj + jj][li];
+    s0 += wc[jj] * (wf[0] * rx[0] + wf[1] * rx[1] + wf[2] * rx[2]);
+    s2 += wc[jj] * (wc[0] * rz[0] + wc[1] * rz[1] + wc[2] * rz[2] + wc[3] * rz[3]);
+  }
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj) {
+    const T* ry = &sr[1][lj + jj][li];
+    s1 += wf[jj] * (wc[0] * ry[0] + wc[1] * ry[1] + wc[2] * ry[2] + wc[3] * ry[3]);
+  }
+  const T s3 = sr[3][lj + 1][li + 1] + sr[3][lj + 1][li + 2] + sr[3][lj + 2][li + 1] + sr[3][lj + 2][li + 2];
+  const long pl = rr_plane(f, c), comp = (long)(f.nz + 2) * pl;
+  const long o = Kf * pl + (long)J * c.sy + I;
+  S[o] = s0;
+  S[comp + o] = s1;
+  S[2 * comp + o] = s2;
+  S[3 * comp + o] = s3;
+}
+
+// One thread per coarse slot (slab mapping).  Coarse plane K takes fine planes
+// 2K-2 .. 2K+1 (u_x, u_y: 1/4, 3/4, 3/4, 1/4), 2K-2 .. 2K (u_z: 1/2, 1, 1/2),
+// 2K-1 .. 2K (p: 1, 1); planes outside the lattice add nothing.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_restrict_z(Geom f, Geom c, const T* __restrict__ S, T* __restrict__ bc) {
+  int I, J, K;
+  if (!slab_item(c, c.sy, I, J, K)) return;
+  const T wc[4] = {T(0.25), T(0.75), T(0.75), T(0.25)};
+  const T wf[3] = {T(0.5), T(1), T(0.5)};
+  const long pl = rr_plane(f, c), comp = (long)(f.nz + 2) * pl;
+  const long o = (long)J * c.sy + I;
+  T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int Kf = 2 * K - 2 + kk;
+    if (Kf < 0 || Kf > f.nz + 1) continue;
+    const long e = Kf * pl + o;
+    a0 += wc[kk] * S[e];
+    a1 += wc[kk] * S[comp + e];
+    if (kk < 3) a2 += wf[kk] * S[2 * comp + e];
+    if (kk == 1 || kk == 2) a3 += S[3 * comp + e];
+  }
+  const int s = c.at(c.idx(I, J, K)), Fc = c.field;
+  bc[s] = c.ux_active(I, J, K) ? a0 * T(0.125) : T(0);
+  bc[Fc + s] = c.uy_active(I, J, K) ? a1 * T(0.125) : T(0);
+  bc[2 * Fc + s] = c.uz_active(I, J, K) ? a2 * T(0.125) : T(0);
+  bc[3 * Fc + s] = c.p_active(I, J, K) ? a3 * T(0.125) : T(0);
 }
 
 }  // namespace sg

@@ -310,7 +310,8 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
     }
     if (c->labelled) lv.flags = cv.take<uint32_t>(lv.g.field);
     if (l < L - 1) {
-      lv.r = cv.take<char>(tot * es);
+      // residual scratch, also the plane sums of k_resid_restrict_xy
+      lv.r = cv.take<char>(std::max<long>(tot, rr_elems(lv.g, c->lev[l + 1].g)) * es);
       lv.dscr = cv.take<char>(lv.g.field * es);
       // at least 64 types: the one-workgroup step loads a table of 64
       const int ntypes = c->labelled ? std::max(c->ll[l].ntypes, 64) : 64;
@@ -562,14 +563,17 @@ void vcycle(stokes_ctx* c, int l, const T* b, T* x, bool zero_init = true) {
     return;
   }
   presmooth(c, l, x, b);
-  T* r = (T*)c->lev[l].r;
   const Geom gc = c->lev[l + 1].g;
   T* bc = (T*)c->lev[l + 1].b;
   T* xc = (T*)c->lev[l + 1].x;
-  launch(c, STOKES_KC_APPLY, l, [=] {
-    k_apply_v<AP_RESID, T, T, dgs_pack<T>()><<<apply_grid<T>(g), BS, 0, c->ks>>>(g, x, b, r, g.gamma, nullptr);
-  });
-  launch(c, STOKES_KC_RESTRICT, l, [=] { k_restrict<T><<<restrict_grid(gc), BS, 0, c->ks>>>(g, gc, r, bc); });
+  {  // coarse b = R (b - L~ x) without the fine residual in memory
+    T* S = (T*)c->lev[l].r;
+    const int gxy = (int)rr_blocks(g, gc);
+    launch(c, STOKES_KC_RESTRICT, l, [=] {
+      k_resid_restrict_xy<T, dgs_pack<T>()><<<gxy, BS, 0, c->ks>>>(g, gc, x, b, S);
+    });
+    launch(c, STOKES_KC_RESTRICT, l, [=] { k_restrict_z<T><<<restrict_grid(gc), BS, 0, c->ks>>>(g, gc, S, bc); });
+  }
   vcycle(c, l + 1, (const T*)bc, xc);
   for (int i = 1; i < c->prm.cycle; ++i) vcycle(c, l + 1, (const T*)bc, xc, false);
   launch(c, STOKES_KC_PROLONG, l, [=] { k_prolong_pairs<T><<<prolong_grid(gc), BS, 0, c->ks>>>(g, gc, xc, x); });
