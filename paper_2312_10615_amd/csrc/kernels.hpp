@@ -325,6 +325,191 @@ __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, c
 }
 
 // ---------------------------------------------------------------------------
+// Multiplicative Vanka on a large box level with the x-slabs set apart.  In
+// the x-fastest layout a class of cells on an x = const wall has every cell in
+// a row of its own, so each of its loads touches a cache line for one or two
+// values.  For the length of a Vanka step the slots of the four padded planes
+// at each x end (I <= 3, I >= nx-2: every slot an x-wall cell reads or writes)
+// move to a slab with y fastest: element ((f (nz+2) + K) 8 + L) (ny+2) + J,
+// layer L = I (low end) or I - nx + 6 (high end).  Every Vanka load and store
+// goes to the slab or to the level's array by the slot's I, with the same
+// arithmetic as vanka_delta_vals and vanka_apply_at: the results are those
+// of the unslabbed passes bit for bit.  Needs nx >= 8 (the two ends apart
+// from the cells between) and a box (n_f = 6).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline long xslab_elems(const Geom& g) { return 4L * (g.nz + 2) * 8 * (g.ny + 2); }
+
+template <typename T>
+__device__ __forceinline__ T* xslab_ptr(const Geom& g, T* x, T* xs, int f, int I, int J, int K) {
+  if (I <= 3 || I >= g.nx - 2) {
+    const int L = I <= 3 ? I : I - g.nx + 6;
+    return xs + ((long)(f * (g.nz + 2) + K) * 8 + L) * (g.ny + 2) + J;
+  }
+  return x + (long)f * g.field + g.at(g.idx(I, J, K));
+}
+
+// Slab transfers.  XS_IN: slab = x; XS_ZERO: slab = 0 (x is 0); XS_OUT: x =
+// slab on the layers a Vanka step changes (I = 1..3, nx-2..nx; the ghost
+// planes I = 0, nx+1 hold no unknown).  (A partial refresh would not pay: a
+// row's end slots share their cache lines whatever layers are copied.)
+enum XSlabCopy { XS_IN = 0, XS_ZERO = 2, XS_OUT = 3 };
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_xslab_copy(Geom g, T* __restrict__ x, T* __restrict__ xs, int mode) {
+  const long t = (long)blockIdx.x * BS + threadIdx.x;
+  if (t >= xslab_elems(g)) return;
+  const int J = (int)(t % (g.ny + 2));
+  long r = t / (g.ny + 2);
+  const int L = (int)(r % 8);
+  r /= 8;
+  const int K = (int)(r % (g.nz + 2)), f = (int)(r / (g.nz + 2));
+  const int I = L < 4 ? L : g.nx - 6 + L;
+  T* m = x + (long)f * g.field + g.at(g.idx(I, J, K));
+  if (mode == XS_IN)
+    xs[t] = *m;
+  else if (mode == XS_ZERO)
+    xs[t] = T(0);
+  else if (mode == XS_OUT && L >= 1 && L <= 6)
+    *m = xs[t];
+}
+
+// vanka_delta_vals with the slab (same order of operations)
+template <typename T, typename TB>
+__device__ __forceinline__ void vanka_delta_vals_xs(const Geom& g, T* x, T* xs, const TB* __restrict__ b, int s,
+                                                    const T* __restrict__ kinv, T* __restrict__ out) {
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
+  const int F = g.field;
+  auto X = [&](int f, int i, int j, int k) -> T { return *xslab_ptr<T>(g, x, xs, f, i, j, k); };
+  // row_u of component f at face (i, j, k); its pressure neighbour is one step back along f
+  auto RU = [&](int f, int i, int j, int k) -> T {
+    const T lap = T(6) * X(f, i, j, k) - X(f, i - 1, j, k) - X(f, i + 1, j, k) - X(f, i, j - 1, k) -
+                  X(f, i, j + 1, k) - X(f, i, j, k - 1) - X(f, i, j, k + 1);
+    const T pm = f == 0 ? X(3, i - 1, j, k) : f == 1 ? X(3, i, j - 1, k) : X(3, i, j, k - 1);
+    return (T)g.c * lap + (X(3, i, j, k) - pm) * (T)g.inv_h;
+  };
+  const int fb = g.vface_bits(I, J, K);
+  T res[7];
+  res[0] = (fb & 1) ? (T)b[g.at(s)] - RU(0, I, J, K) : T(0);
+  res[1] = (fb & 2) ? (T)b[g.at(s + 1)] - RU(0, I + 1, J, K) : T(0);
+  res[2] = (fb & 4) ? (T)b[F + g.at(s)] - RU(1, I, J, K) : T(0);
+  res[3] = (fb & 8) ? (T)b[F + g.at(s + g.sy)] - RU(1, I, J + 1, K) : T(0);
+  res[4] = (fb & 16) ? (T)b[2 * F + g.at(s)] - RU(2, I, J, K) : T(0);
+  res[5] = (fb & 32) ? (T)b[2 * F + g.at(s + g.sz)] - RU(2, I, J, K + 1) : T(0);
+  {
+    const T div = (X(0, I + 1, J, K) - X(0, I, J, K)) + (X(1, I, J + 1, K) - X(1, I, J, K)) +
+                  (X(2, I, J, K + 1) - X(2, I, J, K));
+    res[6] = (T)b[3 * F + g.at(s)] - (-div * (T)g.inv_h - (T)g.gamma * X(3, I, J, K));
+  }
+  const T* km = kinv + g.vtype(I, J, K, fb) * 64;
+#pragma unroll
+  for (int r = 0; r < 7; ++r) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) acc += km[r * 8 + j] * res[j];
+    out[r] = acc;
+  }
+}
+
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_vanka_delta1_xs(Geom g, T* x, T* xs, const TB* __restrict__ b,
+                                                        const int* __restrict__ cells, int ncells,
+                                                        const T* __restrict__ kinv, T* __restrict__ delta) {
+  const int c = blockIdx.x * BS + threadIdx.x;
+  if (c >= ncells) return;
+  T d[7];
+  vanka_delta_vals_xs<T, TB>(g, x, xs, b, cells[c], kinv, d);
+#pragma unroll
+  for (int r = 0; r < 7; ++r) delta[(long)r * ncells + c] = d[r];
+}
+
+// The same corrections with eight lanes per subdomain (as k_vanka_delta): lane
+// r < 7 forms local residual row r from nine loads that every lane issues in
+// the same order (a velocity row: its face, the six lattice neighbours, the
+// two pressures across it; the pressure row: the six faces and the pressure),
+// then delta_r from the group's residuals by shuffles.  Same values as
+// vanka_delta_vals_xs.
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_vanka_delta8_xs(Geom g, T* x, T* xs, const TB* __restrict__ b,
+                                                        const int* __restrict__ cells, int ncells,
+                                                        const T* __restrict__ kinv, T* __restrict__ delta) {
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int c = t >> 3, r = t & 7;
+  const bool valid = c < ncells;
+  const int s = valid ? cells[c] : 0;
+  int I = 1, J = 1, K = 1;
+  if (valid) slot_ijk(g, s, I, J, K);
+  const int fb = g.vface_bits(I, J, K);
+  const T* km = kinv + g.vtype(I, J, K, fb) * 64 + r * 8;
+  T kr[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) kr[j] = km[j];
+  const bool act = valid && r < 7 && (r == 6 || ((fb >> r) & 1));
+  T res = T(0);
+  if (act) {
+    const int F = g.field;
+    T v[9];
+    T bv;
+    if (r < 6) {
+      const int f = r >> 1, o = r & 1;
+      const int di = f == 0, dj = f == 1, dk = f == 2;
+      const int i = I + o * di, j = J + o * dj, k = K + o * dk;
+      v[0] = *xslab_ptr<T>(g, x, xs, f, i, j, k);
+      v[1] = *xslab_ptr<T>(g, x, xs, f, i - 1, j, k);
+      v[2] = *xslab_ptr<T>(g, x, xs, f, i + 1, j, k);
+      v[3] = *xslab_ptr<T>(g, x, xs, f, i, j - 1, k);
+      v[4] = *xslab_ptr<T>(g, x, xs, f, i, j + 1, k);
+      v[5] = *xslab_ptr<T>(g, x, xs, f, i, j, k - 1);
+      v[6] = *xslab_ptr<T>(g, x, xs, f, i, j, k + 1);
+      v[7] = *xslab_ptr<T>(g, x, xs, 3, i, j, k);
+      v[8] = *xslab_ptr<T>(g, x, xs, 3, i - di, j - dj, k - dk);
+      bv = (T)b[(long)f * F + g.at(g.idx(i, j, k))];
+      const T lap = T(6) * v[0] - v[1] - v[2] - v[3] - v[4] - v[5] - v[6];
+      res = bv - ((T)g.c * lap + (v[7] - v[8]) * (T)g.inv_h);
+    } else {
+      v[0] = *xslab_ptr<T>(g, x, xs, 0, I + 1, J, K);
+      v[1] = *xslab_ptr<T>(g, x, xs, 0, I, J, K);
+      v[2] = *xslab_ptr<T>(g, x, xs, 1, I, J + 1, K);
+      v[3] = *xslab_ptr<T>(g, x, xs, 1, I, J, K);
+      v[4] = *xslab_ptr<T>(g, x, xs, 2, I, J, K + 1);
+      v[5] = *xslab_ptr<T>(g, x, xs, 2, I, J, K);
+      v[6] = *xslab_ptr<T>(g, x, xs, 3, I, J, K);
+      bv = (T)b[3L * F + g.at(s)];
+      const T div = (v[0] - v[1]) + (v[2] - v[3]) + (v[4] - v[5]);
+      res = bv - (-div * (T)g.inv_h - (T)g.gamma * v[6]);
+    }
+  }
+  const int base = (int)(threadIdx.x & 63) & ~7;
+  T acc = T(0);
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    const T rj = __shfl(res, base + j, 64);
+    acc += kr[j] * rj;
+  }
+  if (valid && r < 7) delta[(long)r * ncells + c] = acc;
+}
+
+// vanka_apply_at with the slab
+template <typename T>
+__global__ __launch_bounds__(BS) void k_vanka_apply_xs(Geom g, T* x, T* xs, const int* __restrict__ cells,
+                                                       int ncells, const T* __restrict__ delta) {
+  const int c = blockIdx.x * BS + threadIdx.x;
+  if (c >= ncells) return;
+  int I, J, K;
+  slot_ijk(g, cells[c], I, J, K);
+  const T* d = delta + c;
+  const long n = ncells;
+  const int fb = g.vface_bits(I, J, K);
+  if (fb & 1) *xslab_ptr<T>(g, x, xs, 0, I, J, K) += d[0];
+  if (fb & 2) *xslab_ptr<T>(g, x, xs, 0, I + 1, J, K) += d[n];
+  if (fb & 4) *xslab_ptr<T>(g, x, xs, 1, I, J, K) += d[2 * n];
+  if (fb & 8) *xslab_ptr<T>(g, x, xs, 1, I, J + 1, K) += d[3 * n];
+  if (fb & 16) *xslab_ptr<T>(g, x, xs, 2, I, J, K) += d[4 * n];
+  if (fb & 32) *xslab_ptr<T>(g, x, xs, 2, I, J, K + 1) += d[5 * n];
+  *xslab_ptr<T>(g, x, xs, 3, I, J, K) += d[6 * n];
+}
+
+// ---------------------------------------------------------------------------
 // Multiplicative Vanka with two copies of the level's state (8 classes, levels
 // whose classes run as separate eight-lane passes).  Pass p reads copy R and writes copy
 // W: each active local unknown of a class-k cell becomes R + delta in W, so a

@@ -38,6 +38,7 @@ struct Level {
   void* kinv = nullptr;  // Vanka local inverses, 8 x 8 per type (64 types for a box)
   void* alt = nullptr;   // second copy of the state for the two-copy Vanka passes (k_vanka_pp*)
   bool pp = false;       // this level runs them
+  void* xs = nullptr;    // x-slab of the one-thread-per-subdomain Vanka passes (k_vanka_*_xs)
   bool sweep_ok = true;  // the one-workgroup Vanka step may run here (its LDS holds 64 types)
   uint32_t* flags = nullptr;  // labelled domain: the level's flag words (device)
 };
@@ -337,6 +338,11 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
       lv.pp = p.vanka == STOKES_VANKA_MULT8 && !c->labelled && !vsweep_level(lv, nc);
       for (int k = 0; k < nc; ++k) lv.pp = lv.pp && lv.nv[k] <= VANKA_LANES_MAX;
       if (lv.pp) lv.alt = cv.take<char>(tot * es);
+      // the one-thread passes of a large box level run with the x-slabs set apart
+      bool big = false;
+      for (int k = 0; k < nc; ++k) big = big || lv.nv[k] > VANKA_LANES_MAX;
+      if (big && p.vanka == STOKES_VANKA_MULT8 && !c->labelled && lv.g.nx >= 8)
+        lv.xs = cv.take<char>(xslab_elems(lv.g) * es);
     }
   }
   c->vdelta = cv.take<char>(8 * std::max<long>(vmax, 1) * es);
@@ -415,7 +421,7 @@ void vanka_correct(stokes_ctx* c, int l, T* x, int k) {
 // state at its start), or additive Vanka (Eq. av: every class from the same
 // state, the corrections then added class by class in a fixed order).
 template <typename T>
-void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
+void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_IN, bool xout = true) {
   const int nc = vanka_classes(c->prm);
   const Level& lv = c->lev[l];
   if (vsweep_level(lv, nc)) {  // small level: the whole step in one workgroup
@@ -471,6 +477,29 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b) {
     }
     return;
   }
+  if (lv.xs) {  // classes forward then backward on the x-slabbed state
+    const Geom g = lv.g;
+    T* xs = (T*)lv.xs;
+    const T* kinv = (const T*)lv.kinv;
+    const int nbc = (int)((xslab_elems(g) + BS - 1) / BS);
+    if (xin != XS_OUT)  // XS_OUT as the way in: the slab is current
+      launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_xslab_copy<T><<<nbc, BS, 0, c->ks>>>(g, x, xs, xin); });
+    for (int pass = 0; pass < 2 * nc; ++pass) {
+      const int k = pass < nc ? pass : 2 * nc - 1 - pass;
+      const int n = lv.nv[k];
+      if (n == 0) continue;
+      const int* cells = lv.vcells[k];
+      T* vd = (T*)c->vdelta + lv.doff[k];
+      const int nb = (n + BS - 1) / BS;
+      launch(c, STOKES_KC_VANKA_DELTA, l, [=] {
+        k_vanka_delta8_xs<T, T><<<(8 * n + BS - 1) / BS, BS, 0, c->ks>>>(g, x, xs, b, cells, n, kinv, vd);
+      });
+      launch(c, STOKES_KC_VANKA_APPLY, l,
+             [=] { k_vanka_apply_xs<T><<<nb, BS, 0, c->ks>>>(g, x, xs, cells, n, vd); });
+    }
+    if (xout) launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_xslab_copy<T><<<nbc, BS, 0, c->ks>>>(g, x, xs, XS_OUT); });
+    return;
+  }
   for (int pass = 0; pass < 2 * nc; ++pass) {
     const int k = pass < nc ? pass : 2 * nc - 1 - pass;
     vanka_delta<T>(c, l, x, b, k);
@@ -511,9 +540,15 @@ void dgs_reverse(stokes_ctx* c, int l, T* x, const T* b) {
 enum Interior { INT_SYMMETRIC, INT_REVERSE, INT_FORWARD };
 
 // Alg. 3: symmetric Vanka on V1, interior smoother on V2, symmetric Vanka on V1.
+// On a level with an x-slab, `first` says what the slab needs before the
+// first Vanka step: XS_ZERO (x is 0), XS_IN (x changed) or XS_OUT (nothing
+// changed since the last step wrote the slab back).  Consecutive Vanka steps
+// share the slab; the DGS sweeps between change it (the pressure steps of V2
+// cells move the faces and pressures beside them).
 template <typename T>
-void smooth(stokes_ctx* c, int l, T* x, const T* b, Interior kind, int sweeps) {
-  for (int i = 0; i < c->prm.n_boundary; ++i) vanka_symmetric(c, l, x, b);
+void smooth(stokes_ctx* c, int l, T* x, const T* b, Interior kind, int sweeps, XSlabCopy first) {
+  const int nb = c->prm.n_boundary;
+  for (int i = 0; i < nb; ++i) vanka_symmetric(c, l, x, b, i == 0 ? first : XS_OUT, i == nb - 1);
   for (int i = 0; i < sweeps; ++i) {
     if (kind != INT_FORWARD) {
       if (kind == INT_SYMMETRIC) dgs_forward(c, l, x, b);
@@ -522,24 +557,26 @@ void smooth(stokes_ctx* c, int l, T* x, const T* b, Interior kind, int sweeps) {
       dgs_forward(c, l, x, b);
     }
   }
-  for (int i = 0; i < c->prm.n_boundary; ++i) vanka_symmetric(c, l, x, b);
+  for (int i = 0; i < nb; ++i)
+    vanka_symmetric(c, l, x, b, i == 0 && sweeps > 0 ? XS_IN : XS_OUT, i == nb - 1);
 }
 
 template <typename T>
-void presmooth(stokes_ctx* c, int l, T* x, const T* b) {
+void presmooth(stokes_ctx* c, int l, T* x, const T* b, bool x_zero) {
+  const XSlabCopy first = x_zero ? XS_ZERO : XS_IN;
   if (c->prm.smoother == STOKES_SMOOTHER_SYMMETRIC) {
-    for (int i = 0; i < c->prm.nu / 2; ++i) smooth(c, l, x, b, INT_SYMMETRIC, 1);
+    for (int i = 0; i < c->prm.nu / 2; ++i) smooth(c, l, x, b, INT_SYMMETRIC, 1, i == 0 ? first : XS_OUT);
   } else {
-    smooth(c, l, x, b, INT_REVERSE, c->prm.nu);
+    smooth(c, l, x, b, INT_REVERSE, c->prm.nu, first);
   }
 }
 
 template <typename T>
 void postsmooth(stokes_ctx* c, int l, T* x, const T* b) {
   if (c->prm.smoother == STOKES_SMOOTHER_SYMMETRIC) {
-    for (int i = 0; i < c->prm.nu / 2; ++i) smooth(c, l, x, b, INT_SYMMETRIC, 1);
+    for (int i = 0; i < c->prm.nu / 2; ++i) smooth(c, l, x, b, INT_SYMMETRIC, 1, i == 0 ? XS_IN : XS_OUT);
   } else {
-    smooth(c, l, x, b, INT_FORWARD, c->prm.nu);
+    smooth(c, l, x, b, INT_FORWARD, c->prm.nu, XS_IN);
   }
 }
 
@@ -562,7 +599,7 @@ void vcycle(stokes_ctx* c, int l, const T* b, T* x, bool zero_init = true) {
     launch(c, STOKES_KC_COARSE, l, [=] { k_coarse_solve<T><<<nb, BS, 0, c->ks>>>(cinv, cdof, nc, b, x); });
     return;
   }
-  presmooth(c, l, x, b);
+  presmooth(c, l, x, b, zero_init);
   const Geom gc = c->lev[l + 1].g;
   T* bc = (T*)c->lev[l + 1].b;
   T* xc = (T*)c->lev[l + 1].x;
