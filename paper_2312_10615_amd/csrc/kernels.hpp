@@ -237,30 +237,24 @@ __device__ __forceinline__ void vanka_apply_item(const Geom& g, T* __restrict__ 
 // class (t & 7 must equal threadIdx.x & 7, and the eight lanes of a subdomain
 // share a wave); every lane of the wave must call it (shuffles).
 // Local residual row r (0..6, as in vanka_delta_vals) of the subdomain of
-// cell (I, J, K) at slot s; zero for an inactive row, r = 7 or !valid.
+// cell (I, J, K) at slot s; zero for an inactive row, r = 7 or !valid.  The
+// six velocity rows run one code path (the lane's face and axis picked by r,
+// then row_u's loads in row_u's order), so a wave issues the loads of two
+// paths rather than seven.
 template <typename T, typename TB>
 __device__ __forceinline__ T vanka_row_residual(const Geom& g, const T* __restrict__ x, const TB* __restrict__ b, int s,
                                                 int I, int J, int K, int r, bool valid) {
   const int F = g.field;
-  const T* ux = x;
-  const T* uy = x + F;
-  const T* uz = x + 2 * F;
+  const int fb = g.vface_bits(I, J, K);
+  if (!valid || r > 6 || (r < 6 && !((fb >> r) & 1))) return T(0);
   const T* p = x + 3 * F;
-  T res = T(0);
-  if (valid) {
-    const int fb = r < 6 ? g.vface_bits(I, J, K) : 0;
-    switch (r) {
-      case 0: if (fb & 1) res = (T)b[g.at(s)] - row_u(g, ux, p, s, 1, 0); break;
-      case 1: if (fb & 2) res = (T)b[g.at(s + 1)] - row_u(g, ux, p, s + 1, 1, 0); break;
-      case 2: if (fb & 4) res = (T)b[F + g.at(s)] - row_u(g, uy, p, s, g.sy, 1); break;
-      case 3: if (fb & 8) res = (T)b[F + g.at(s + g.sy)] - row_u(g, uy, p, s + g.sy, g.sy, 1); break;
-      case 4: if (fb & 16) res = (T)b[2 * F + g.at(s)] - row_u(g, uz, p, s, g.sz, 2); break;
-      case 5: if (fb & 32) res = (T)b[2 * F + g.at(s + g.sz)] - row_u(g, uz, p, s + g.sz, g.sz, 2); break;
-      case 6: res = (T)b[3 * F + g.at(s)] - row_p(g, ux, uy, uz, p, s, g.gamma); break;
-      default: break;
-    }
+  if (r < 6) {
+    const int f = r >> 1;
+    const int ps = f == 0 ? 1 : f == 1 ? g.sy : g.sz;
+    const int sf = s + (r & 1) * ps;  // the face: minus (own slot) or plus
+    return (T)b[f * F + g.at(sf)] - row_u(g, x + f * F, p, sf, ps, f);
   }
-  return res;
+  return (T)b[3 * F + g.at(s)] - row_p(g, x, x + F, x + 2 * F, p, s, g.gamma);
 }
 
 template <typename T, typename TB>
@@ -663,7 +657,7 @@ __global__ __launch_bounds__(BS) void k_vanka_band_copy(Geom g, const T* __restr
 // bit for bit.  On a level whose classes hold a few thousand cells, a pass
 // costs the workgroup one or two memory round trips, where two graph-replayed
 // launches cost several microseconds each.
-constexpr int VSWEEP_BS = 1024;
+constexpr int VSWEEP_BS = 512;  // 256 VGPRs a thread
 constexpr int VSWEEP_MAX_CLASS = 512;  // largest class a level may have to use it (one CU streams it)
 
 struct VSweep {
@@ -676,12 +670,69 @@ struct VSweep {
   const void* kinv;
 };
 
+// Multiplicative class passes inside one workgroup, the class lists of an
+// 8-class step in LDS for the whole step.  Each subdomain's new values are
+// formed from the class-start state before a barrier and written after it
+// (the values of the delta and apply passes, bit for bit).
+constexpr int VSWEEP_LIST = 8 * VSWEEP_MAX_CLASS;
+
+__device__ __forceinline__ void vsweep_load_lists(const VSweep& a, int* __restrict__ scell) {
+  if (a.nc != 8) return;
+  for (int k = 0; k < 8; ++k)
+    for (int c = threadIdx.x; c < a.nv[k]; c += blockDim.x) scell[k * VSWEEP_MAX_CLASS + c] = a.vc[k][c];
+  __syncthreads();
+}
+
+__device__ __forceinline__ int vsweep_cell(const VSweep& a, const int* __restrict__ scell, int k, int c) {
+  return a.nc == 8 ? scell[k * VSWEEP_MAX_CLASS + c] : a.vc[k][c];
+}
+
+// One thread per subdomain (a class has at most VSWEEP_MAX_CLASS cells, the
+// workgroup as many threads): the seven corrections and the values they add
+// to stay in registers.  (Eight lanes per subdomain, with the new values
+// waiting in LDS, measured slower here: 93 against 71 us per step at 16^3.)
+static_assert(VSWEEP_MAX_CLASS <= VSWEEP_BS, "a thread per subdomain");
+
+template <typename T>
+__device__ __forceinline__ void vanka_sweep_passes1(const VSweep& a, T* __restrict__ x, const T* __restrict__ b,
+                                                    const T* __restrict__ sk, int* __restrict__ scell) {
+  vsweep_load_lists(a, scell);
+  const int t = threadIdx.x;
+  for (int pass = 0; pass < 2 * a.nc; ++pass) {
+    const int k = pass < a.nc ? pass : 2 * a.nc - 1 - pass;
+    const bool mine = t < a.nv[k];
+    T d[7], old[7];
+    int e[7];
+    bool act[7];
+    if (mine) {
+      const int s = vsweep_cell(a, scell, k, t);
+      vanka_delta_vals<T, T>(a.g, x, b, s, sk, d);
+      int I, J, K;
+      slot_ijk(a.g, s, I, J, K);
+#pragma unroll
+      for (int r = 0; r < 7; ++r) {
+        const VankaDof v = vanka_dof(a.g, s, I, J, K, r);
+        e[r] = v.e;
+        act[r] = v.active;
+        old[r] = v.active ? x[v.e] : T(0);
+      }
+    }
+    __syncthreads();
+    if (mine) {
+#pragma unroll
+      for (int r = 0; r < 7; ++r)
+        if (act[r]) x[e[r]] = old[r] + d[r];
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(VSWEEP_BS) void k_vanka_sweep(VSweep a, T* __restrict__ x, const T* __restrict__ b,
                                                           T* __restrict__ vd) {
-  // the local inverses and one class's corrections live in LDS for the whole step
+  // the local inverses live in LDS for the whole step
   __shared__ T sk[64 * 64];
-  __shared__ T sd[7 * VSWEEP_MAX_CLASS];
+  __shared__ int scell[VSWEEP_LIST];
   const int t = threadIdx.x;
   for (int i = t; i < 64 * 64; i += VSWEEP_BS) sk[i] = ((const T*)a.kinv)[i];
   __syncthreads();
@@ -696,45 +747,30 @@ __global__ __launch_bounds__(VSWEEP_BS) void k_vanka_sweep(VSweep a, T* __restri
     }
     return;
   }
-  for (int pass = 0; pass < 2 * a.nc; ++pass) {
-    const int k = pass < a.nc ? pass : 2 * a.nc - 1 - pass;
-    const int n = a.nv[k];
-    for (int c = t; c < n; c += VSWEEP_BS) vanka_delta_item<T, T>(a.g, x, b, a.vc[k], n, sk, sd, c);
-    __syncthreads();
-    for (int c = t; c < n; c += VSWEEP_BS) vanka_apply_item<T>(a.g, x, a.vc[k], n, sd, c);
-    __syncthreads();
-  }
+  vanka_sweep_passes1<T>(a, x, b, sk, scell);
 }
 
 // The multiplicative step of k_vanka_sweep on a level whose whole state fits
-// in LDS next to the inverses and corrections (gfx950: 160 KB per
+// in LDS next to the inverses and the class lists (gfx950: 160 KB per
 // workgroup): the state is loaded once, the 16 class passes read and write
-// it there, and it is written back at the end.  Same values.  (Eight lanes
-// per subdomain measured slower here: 0.28 against 0.20 ms per V-cycle on
-// the 8^3 level.)
+// it there, and it is written back at the end.  Same values.
 template <typename T>
 constexpr int vsweep_lds_elems() {
-  return sizeof(T) == 8 ? 12288 : 32768;  // 96 KB of FP64 or 128 KB of FP32
+  return sizeof(T) == 8 ? 12288 : 24576;  // 96 KB of FP64 or of FP32
 }
 
 template <typename T>
-__global__ __launch_bounds__(VSWEEP_BS) void k_vanka_sweep_lds(VSweep a, T* __restrict__ x, const T* __restrict__ b) {
+__global__ __launch_bounds__(VSWEEP_BS) void k_vanka_sweep_lds(VSweep a, T* __restrict__ x,
+                                                                  const T* __restrict__ b) {
   __shared__ T sk[64 * 64];
-  __shared__ T sd[7 * VSWEEP_MAX_CLASS];
+  __shared__ int scell[VSWEEP_LIST];
   __shared__ T sx[vsweep_lds_elems<T>()];
   const int t = threadIdx.x;
   const int n4 = 4 * a.g.field;
   for (int i = t; i < 64 * 64; i += VSWEEP_BS) sk[i] = ((const T*)a.kinv)[i];
   for (int i = t; i < n4; i += VSWEEP_BS) sx[i] = x[i];
   __syncthreads();
-  for (int pass = 0; pass < 2 * a.nc; ++pass) {
-    const int k = pass < a.nc ? pass : 2 * a.nc - 1 - pass;
-    const int n = a.nv[k];
-    for (int c = t; c < n; c += VSWEEP_BS) vanka_delta_item<T, T>(a.g, sx, b, a.vc[k], n, sk, sd, c);
-    __syncthreads();
-    for (int c = t; c < n; c += VSWEEP_BS) vanka_apply_item<T>(a.g, sx, a.vc[k], n, sd, c);
-    __syncthreads();
-  }
+  vanka_sweep_passes1<T>(a, sx, b, sk, scell);
   for (int i = t; i < n4; i += VSWEEP_BS) x[i] = sx[i];
 }
 
