@@ -236,6 +236,30 @@ __device__ __forceinline__ void vanka_apply_item(const Geom& g, T* __restrict__ 
 // latency chain this form finishes sooner.  Output as above.  Lane t of the
 // class (t & 7 must equal threadIdx.x & 7, and the eight lanes of a subdomain
 // share a wave); every lane of the wave must call it (shuffles).
+// Element (in a state vector) of local unknown r of the subdomain of cell
+// (I, J, K) at slot s, whether it is an unknown, and the cell across it.
+struct VankaDof {
+  int e;
+  bool active;
+  int nI, nJ, nK;
+};
+
+__device__ __forceinline__ VankaDof vanka_dof(const Geom& g, int s, int I, int J, int K, int r) {
+  const int F = g.field;
+  VankaDof d{0, false, I, J, K};
+  const int fb = r < 6 ? g.vface_bits(I, J, K) : 0;
+  switch (r) {
+    case 0: d.e = g.at(s); d.active = fb & 1; d.nI = I - 1; break;
+    case 1: d.e = g.at(s + 1); d.active = fb & 2; d.nI = I + 1; break;
+    case 2: d.e = F + g.at(s); d.active = fb & 4; d.nJ = J - 1; break;
+    case 3: d.e = F + g.at(s + g.sy); d.active = fb & 8; d.nJ = J + 1; break;
+    case 4: d.e = 2 * F + g.at(s); d.active = fb & 16; d.nK = K - 1; break;
+    case 5: d.e = 2 * F + g.at(s + g.sz); d.active = fb & 32; d.nK = K + 1; break;
+    default: d.e = 3 * F + g.at(s); d.active = true; break;  // the cell's own pressure
+  }
+  return d;
+}
+
 // Local residual row r (0..6, as in vanka_delta_vals) of the subdomain of
 // cell (I, J, K) at slot s; zero for an inactive row, r = 7 or !valid.  The
 // six velocity rows run one code path (the lane's face and axis picked by r,
@@ -312,10 +336,19 @@ __global__ __launch_bounds__(BS) void k_vanka_delta1(Geom g, const T* __restrict
   vanka_delta_item<T, TB>(g, x, b, cells, ncells, kinv, delta, blockIdx.x * BS + threadIdx.x);
 }
 
+// Eight lanes per subdomain: lane r < 7 adds delta_r to local unknown r (each
+// add goes to its own element; the values of vanka_apply_at).
 template <typename T>
 __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
                                                     int ncells, const T* __restrict__ delta) {
-  vanka_apply_item<T>(g, x, cells, ncells, delta, blockIdx.x * BS + threadIdx.x);
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int c = t >> 3, r = t & 7;
+  if (c >= ncells || r == 7) return;
+  const int s = cells[c];
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
+  const VankaDof d = vanka_dof(g, s, I, J, K, r);
+  if (d.active) x[d.e] += delta[(long)r * ncells + c];
 }
 
 // ---------------------------------------------------------------------------
@@ -483,24 +516,22 @@ __global__ __launch_bounds__(BS) void k_vanka_delta8_xs(Geom g, T* x, T* xs, con
   if (valid && r < 7) delta[(long)r * ncells + c] = acc;
 }
 
-// vanka_apply_at with the slab
+// vanka_apply_at with the slab, eight lanes per subdomain: lane r < 7 adds
+// delta_r to local unknown r (the order of the seven adds does not matter:
+// each goes to its own element).
 template <typename T>
 __global__ __launch_bounds__(BS) void k_vanka_apply_xs(Geom g, T* x, T* xs, const int* __restrict__ cells,
                                                        int ncells, const T* __restrict__ delta) {
-  const int c = blockIdx.x * BS + threadIdx.x;
-  if (c >= ncells) return;
+  const int t = blockIdx.x * BS + threadIdx.x;
+  const int c = t >> 3, r = t & 7;
+  if (c >= ncells || r == 7) return;
   int I, J, K;
   slot_ijk(g, cells[c], I, J, K);
-  const T* d = delta + c;
-  const long n = ncells;
   const int fb = g.vface_bits(I, J, K);
-  if (fb & 1) *xslab_ptr<T>(g, x, xs, 0, I, J, K) += d[0];
-  if (fb & 2) *xslab_ptr<T>(g, x, xs, 0, I + 1, J, K) += d[n];
-  if (fb & 4) *xslab_ptr<T>(g, x, xs, 1, I, J, K) += d[2 * n];
-  if (fb & 8) *xslab_ptr<T>(g, x, xs, 1, I, J + 1, K) += d[3 * n];
-  if (fb & 16) *xslab_ptr<T>(g, x, xs, 2, I, J, K) += d[4 * n];
-  if (fb & 32) *xslab_ptr<T>(g, x, xs, 2, I, J, K + 1) += d[5 * n];
-  *xslab_ptr<T>(g, x, xs, 3, I, J, K) += d[6 * n];
+  if (r < 6 && !((fb >> r) & 1)) return;
+  const int f = r < 6 ? r >> 1 : 3, o = r < 6 ? r & 1 : 0;
+  T* e = xslab_ptr<T>(g, x, xs, f, I + (f == 0) * o, J + (f == 1) * o, K + (f == 2) * o);
+  *e += delta[(long)r * ncells + c];
 }
 
 // ---------------------------------------------------------------------------
@@ -524,30 +555,6 @@ __global__ __launch_bounds__(BS) void k_vanka_apply_xs(Geom g, T* x, T* xs, cons
 __host__ __device__ inline int vanka_pass_class(int pass) { return pass < 8 ? pass : 15 - pass; }
 __host__ __device__ inline int vanka_pass_prev(int pass) {
   return pass == 0 || pass == 8 ? -1 : vanka_pass_class(pass - 1);
-}
-
-// Element (in a state vector) of local unknown r of the subdomain of cell
-// (I, J, K) at slot s, whether it is an unknown, and the cell across it.
-struct VankaDof {
-  int e;
-  bool active;
-  int nI, nJ, nK;
-};
-
-__device__ __forceinline__ VankaDof vanka_dof(const Geom& g, int s, int I, int J, int K, int r) {
-  const int F = g.field;
-  VankaDof d{0, false, I, J, K};
-  const int fb = r < 6 ? g.vface_bits(I, J, K) : 0;
-  switch (r) {
-    case 0: d.e = g.at(s); d.active = fb & 1; d.nI = I - 1; break;
-    case 1: d.e = g.at(s + 1); d.active = fb & 2; d.nI = I + 1; break;
-    case 2: d.e = F + g.at(s); d.active = fb & 4; d.nJ = J - 1; break;
-    case 3: d.e = F + g.at(s + g.sy); d.active = fb & 8; d.nJ = J + 1; break;
-    case 4: d.e = 2 * F + g.at(s); d.active = fb & 16; d.nK = K - 1; break;
-    case 5: d.e = 2 * F + g.at(s + g.sz); d.active = fb & 32; d.nK = K + 1; break;
-    default: d.e = 3 * F + g.at(s); d.active = true; break;  // the cell's own pressure
-  }
-  return d;
 }
 
 // Copy unknown r of previous-class cell s from R to W unless a V1 cell of

@@ -409,7 +409,7 @@ void vanka_correct(stokes_ctx* c, int l, T* x, int k) {
   const Level& lv = c->lev[l];
   const int n = lv.nv[k];
   if (n == 0) return;
-  const int nb = (n + BS - 1) / BS;
+  const int nb = (8 * n + BS - 1) / BS;
   const Geom g = lv.g;
   const int* cells = lv.vcells[k];
   const T* vd = (const T*)c->vdelta + lv.doff[k];
@@ -490,12 +490,11 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
       if (n == 0) continue;
       const int* cells = lv.vcells[k];
       T* vd = (T*)c->vdelta + lv.doff[k];
-      const int nb = (n + BS - 1) / BS;
       launch(c, STOKES_KC_VANKA_DELTA, l, [=] {
         k_vanka_delta8_xs<T, T><<<(8 * n + BS - 1) / BS, BS, 0, c->ks>>>(g, x, xs, b, cells, n, kinv, vd);
       });
       launch(c, STOKES_KC_VANKA_APPLY, l,
-             [=] { k_vanka_apply_xs<T><<<nb, BS, 0, c->ks>>>(g, x, xs, cells, n, vd); });
+             [=] { k_vanka_apply_xs<T><<<(8 * n + BS - 1) / BS, BS, 0, c->ks>>>(g, x, xs, cells, n, vd); });
     }
     if (xout) launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_xslab_copy<T><<<nbc, BS, 0, c->ks>>>(g, x, xs, XS_OUT); });
     return;

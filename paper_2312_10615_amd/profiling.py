@@ -68,7 +68,10 @@ def _largest_dispatches(path, counter):
 
 
 SHORT = {"k_dgs_u_v<": "dgs_u", "k_dgs_pr_v<": "dgs_pr", "k_dgs_pf_v<": "dgs_pf",
-         "k_apply_v<1,": "apply", "k_restrict<": "restrict", "k_prolong_pairs<": "prolong"}
+         "k_apply_v<1,": "apply", "k_restrict<": "restrict", "k_prolong_pairs<": "prolong",
+         "k_resid_restrict_xy<": "resid_restrict_xy", "k_restrict_z<": "restrict_z",
+         "k_vanka_delta8_xs<": "vanka_delta8_xs", "k_vanka_apply_xs<": "vanka_apply_xs",
+         "k_xslab_copy<": "xslab_copy", "k_vanka_pp8<": "vanka_pp8"}
 
 
 def summarize_counters(fetch_csv, write_csv, n, copy_bytes=1 << 30):
