@@ -340,7 +340,7 @@ void carve(stokes_batch* c, Carve& cv) {
         return c->vpp[l] || small(d) ? 0 : (8 * c->hlev[l][d].nv[k] + BS - 1) / BS;
       });
       c->tvapply[l][k] = add_table(c, c->smooth[l], [&](int d) {
-        return c->vpp[l] || small(d) ? 0 : (c->hlev[l][d].nv[k] + BS - 1) / BS;
+        return c->vpp[l] || small(d) ? 0 : (8 * c->hlev[l][d].nv[k] + BS - 1) / BS;
       });
     }
     // two-copy passes: the band copy, then pass p of class k with the previous class kp

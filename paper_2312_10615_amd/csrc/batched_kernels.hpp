@@ -182,8 +182,8 @@ __global__ __launch_bounds__(BS) void kb_prolong(const BEnt* __restrict__ tab, i
 }
 
 // Vanka, one colour class of each domain: eight lanes per V1 cell for the
-// residuals (one thread per cell measured no faster on the batch's boxes),
-// one thread per cell for the corrections
+// residuals (one thread per cell measured no faster on the batch's boxes)
+// and for the corrections
 template <typename T>
 __global__ __launch_bounds__(BS) void kb_vanka_delta(const BEnt* __restrict__ tab, int nent,
                                                      const BLev* __restrict__ lev, const int* __restrict__ done,
@@ -200,8 +200,8 @@ __global__ __launch_bounds__(BS) void kb_vanka_apply(const BEnt* __restrict__ ta
                                                      int colour, const T* __restrict__ delta) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
-  vanka_apply_item<T>(g, (T*)lev[d].x, lev[d].vc[colour], lev[d].nv[colour], delta + lev[d].voff[colour],
-                      lb * BS + (int)threadIdx.x);
+  vanka_apply8_item<T>(g, (T*)lev[d].x, lev[d].vc[colour], lev[d].nv[colour], delta + lev[d].voff[colour],
+                       lb * BS + (int)threadIdx.x);
 }
 
 // Two-copy Vanka pass of class k for every box (k_vanka_pp8; levels whose
@@ -253,30 +253,26 @@ __global__ __launch_bounds__(BS) void kb_vanka_band(const BEnt* __restrict__ tab
   vanka_band_copy_item<T>(g, R, W, t);
 }
 
-// The whole symmetric Vanka step of one small box in one 1024-thread
-// workgroup (one block per box; k_vanka_sweep's passes with barriers).
+// The whole symmetric Vanka step of one small box in one workgroup (one block
+// per box; k_vanka_sweep's passes with barriers, corrections held in registers).
+struct BLevLists {
+  const BLev& l;
+  int nc;
+  __device__ __forceinline__ const int* cells(int k) const { return l.vc[k]; }
+  __device__ __forceinline__ int count(int k) const { return l.nv[k]; }
+};
+
 template <typename T>
 __global__ __launch_bounds__(VSWEEP_BS) void kb_vanka_sweep(const BEnt* __restrict__ tab, int nent,
                                                             const BLev* __restrict__ lev, const int* __restrict__ done) {
   const int d = tab[bent_find(tab, nent)].dom;
   if (done[d]) return;
   const Geom g = lev[d].g;
-  T* x = (T*)lev[d].x;
-  const T* b = (const T*)lev[d].b;
-  __shared__ T sk[64 * 64];                // local inverses
-  __shared__ T sd[7 * VSWEEP_MAX_CLASS];   // one class's corrections
-  const int t = threadIdx.x;
-  for (int i = t; i < 64 * 64; i += VSWEEP_BS) sk[i] = ((const T*)lev[d].kinv)[i];
+  __shared__ T sk[64 * 64];  // local inverses
+  __shared__ int scell[VSWEEP_LIST];
+  for (int i = threadIdx.x; i < 64 * 64; i += VSWEEP_BS) sk[i] = ((const T*)lev[d].kinv)[i];
   __syncthreads();
-  for (int pass = 0; pass < 16; ++pass) {
-    const int k = pass < 8 ? pass : 15 - pass;
-    const int n = lev[d].nv[k];
-    const int* cells = lev[d].vc[k];
-    for (int c = t; c < n; c += VSWEEP_BS) vanka_delta_item<T, T>(g, x, b, cells, n, sk, sd, c);
-    __syncthreads();
-    for (int c = t; c < n; c += VSWEEP_BS) vanka_apply_item<T>(g, x, cells, n, sd, c);
-    __syncthreads();
-  }
+  vanka_sweep_passes1<T>(g, BLevLists{lev[d], 8}, (T*)lev[d].x, (const T*)lev[d].b, sk, scell);
 }
 
 // coarsest level of each domain: one wave per row of its dense inverse

@@ -336,12 +336,12 @@ __global__ __launch_bounds__(BS) void k_vanka_delta1(Geom g, const T* __restrict
   vanka_delta_item<T, TB>(g, x, b, cells, ncells, kinv, delta, blockIdx.x * BS + threadIdx.x);
 }
 
-// Eight lanes per subdomain: lane r < 7 adds delta_r to local unknown r (each
-// add goes to its own element; the values of vanka_apply_at).
+// Eight lanes per subdomain: lane t = 8 c + r (r < 7) adds delta_r to local
+// unknown r of cell c (each add goes to its own element; the values of
+// vanka_apply_at).
 template <typename T>
-__global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
-                                                    int ncells, const T* __restrict__ delta) {
-  const int t = blockIdx.x * BS + threadIdx.x;
+__device__ __forceinline__ void vanka_apply8_item(const Geom& g, T* __restrict__ x, const int* __restrict__ cells,
+                                                  int ncells, const T* __restrict__ delta, int t) {
   const int c = t >> 3, r = t & 7;
   if (c >= ncells || r == 7) return;
   const int s = cells[c];
@@ -349,6 +349,12 @@ __global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, c
   slot_ijk(g, s, I, J, K);
   const VankaDof d = vanka_dof(g, s, I, J, K, r);
   if (d.active) x[d.e] += delta[(long)r * ncells + c];
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_vanka_apply(Geom g, T* __restrict__ x, const int* __restrict__ cells,
+                                                    int ncells, const T* __restrict__ delta) {
+  vanka_apply8_item<T>(g, x, cells, ncells, delta, blockIdx.x * BS + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -683,15 +689,25 @@ struct VSweep {
 // (the values of the delta and apply passes, bit for bit).
 constexpr int VSWEEP_LIST = 8 * VSWEEP_MAX_CLASS;
 
-__device__ __forceinline__ void vsweep_load_lists(const VSweep& a, int* __restrict__ scell) {
+// The class lists of a step: lists.nc, lists.cells(k), lists.count(k).
+struct VSweepLists {
+  const VSweep& a;
+  int nc;
+  __device__ __forceinline__ const int* cells(int k) const { return a.vc[k]; }
+  __device__ __forceinline__ int count(int k) const { return a.nv[k]; }
+};
+
+template <typename Lists>
+__device__ __forceinline__ void vsweep_load_lists(const Lists& a, int* __restrict__ scell) {
   if (a.nc != 8) return;
   for (int k = 0; k < 8; ++k)
-    for (int c = threadIdx.x; c < a.nv[k]; c += blockDim.x) scell[k * VSWEEP_MAX_CLASS + c] = a.vc[k][c];
+    for (int c = threadIdx.x; c < a.count(k); c += blockDim.x) scell[k * VSWEEP_MAX_CLASS + c] = a.cells(k)[c];
   __syncthreads();
 }
 
-__device__ __forceinline__ int vsweep_cell(const VSweep& a, const int* __restrict__ scell, int k, int c) {
-  return a.nc == 8 ? scell[k * VSWEEP_MAX_CLASS + c] : a.vc[k][c];
+template <typename Lists>
+__device__ __forceinline__ int vsweep_cell(const Lists& a, const int* __restrict__ scell, int k, int c) {
+  return a.nc == 8 ? scell[k * VSWEEP_MAX_CLASS + c] : a.cells(k)[c];
 }
 
 // One thread per subdomain (a class has at most VSWEEP_MAX_CLASS cells, the
@@ -700,25 +716,26 @@ __device__ __forceinline__ int vsweep_cell(const VSweep& a, const int* __restric
 // waiting in LDS, measured slower here: 93 against 71 us per step at 16^3.)
 static_assert(VSWEEP_MAX_CLASS <= VSWEEP_BS, "a thread per subdomain");
 
-template <typename T>
-__device__ __forceinline__ void vanka_sweep_passes1(const VSweep& a, T* __restrict__ x, const T* __restrict__ b,
-                                                    const T* __restrict__ sk, int* __restrict__ scell) {
+template <typename T, typename Lists>
+__device__ __forceinline__ void vanka_sweep_passes1(const Geom& g, const Lists& a, T* __restrict__ x,
+                                                    const T* __restrict__ b, const T* __restrict__ sk,
+                                                    int* __restrict__ scell) {
   vsweep_load_lists(a, scell);
   const int t = threadIdx.x;
   for (int pass = 0; pass < 2 * a.nc; ++pass) {
     const int k = pass < a.nc ? pass : 2 * a.nc - 1 - pass;
-    const bool mine = t < a.nv[k];
+    const bool mine = t < a.count(k);
     T d[7], old[7];
     int e[7];
     bool act[7];
     if (mine) {
       const int s = vsweep_cell(a, scell, k, t);
-      vanka_delta_vals<T, T>(a.g, x, b, s, sk, d);
+      vanka_delta_vals<T, T>(g, x, b, s, sk, d);
       int I, J, K;
-      slot_ijk(a.g, s, I, J, K);
+      slot_ijk(g, s, I, J, K);
 #pragma unroll
       for (int r = 0; r < 7; ++r) {
-        const VankaDof v = vanka_dof(a.g, s, I, J, K, r);
+        const VankaDof v = vanka_dof(g, s, I, J, K, r);
         e[r] = v.e;
         act[r] = v.active;
         old[r] = v.active ? x[v.e] : T(0);
@@ -754,7 +771,7 @@ __global__ __launch_bounds__(VSWEEP_BS) void k_vanka_sweep(VSweep a, T* __restri
     }
     return;
   }
-  vanka_sweep_passes1<T>(a, x, b, sk, scell);
+  vanka_sweep_passes1<T>(a.g, VSweepLists{a, a.nc}, x, b, sk, scell);
 }
 
 // The multiplicative step of k_vanka_sweep on a level whose whole state fits
@@ -777,7 +794,7 @@ __global__ __launch_bounds__(VSWEEP_BS) void k_vanka_sweep_lds(VSweep a, T* __re
   for (int i = t; i < 64 * 64; i += VSWEEP_BS) sk[i] = ((const T*)a.kinv)[i];
   for (int i = t; i < n4; i += VSWEEP_BS) sx[i] = x[i];
   __syncthreads();
-  vanka_sweep_passes1<T>(a, sx, b, sk, scell);
+  vanka_sweep_passes1<T>(a.g, VSweepLists{a, a.nc}, sx, b, sk, scell);
   for (int i = t; i < n4; i += VSWEEP_BS) x[i] = sx[i];
 }
 
