@@ -406,62 +406,12 @@ __global__ __launch_bounds__(BS) void k_xslab_copy(Geom g, T* __restrict__ x, T*
     *m = xs[t];
 }
 
-// vanka_delta_vals with the slab (same order of operations)
-template <typename T, typename TB>
-__device__ __forceinline__ void vanka_delta_vals_xs(const Geom& g, T* x, T* xs, const TB* __restrict__ b, int s,
-                                                    const T* __restrict__ kinv, T* __restrict__ out) {
-  int I, J, K;
-  slot_ijk(g, s, I, J, K);
-  const int F = g.field;
-  auto X = [&](int f, int i, int j, int k) -> T { return *xslab_ptr<T>(g, x, xs, f, i, j, k); };
-  // row_u of component f at face (i, j, k); its pressure neighbour is one step back along f
-  auto RU = [&](int f, int i, int j, int k) -> T {
-    const T lap = T(6) * X(f, i, j, k) - X(f, i - 1, j, k) - X(f, i + 1, j, k) - X(f, i, j - 1, k) -
-                  X(f, i, j + 1, k) - X(f, i, j, k - 1) - X(f, i, j, k + 1);
-    const T pm = f == 0 ? X(3, i - 1, j, k) : f == 1 ? X(3, i, j - 1, k) : X(3, i, j, k - 1);
-    return (T)g.c * lap + (X(3, i, j, k) - pm) * (T)g.inv_h;
-  };
-  const int fb = g.vface_bits(I, J, K);
-  T res[7];
-  res[0] = (fb & 1) ? (T)b[g.at(s)] - RU(0, I, J, K) : T(0);
-  res[1] = (fb & 2) ? (T)b[g.at(s + 1)] - RU(0, I + 1, J, K) : T(0);
-  res[2] = (fb & 4) ? (T)b[F + g.at(s)] - RU(1, I, J, K) : T(0);
-  res[3] = (fb & 8) ? (T)b[F + g.at(s + g.sy)] - RU(1, I, J + 1, K) : T(0);
-  res[4] = (fb & 16) ? (T)b[2 * F + g.at(s)] - RU(2, I, J, K) : T(0);
-  res[5] = (fb & 32) ? (T)b[2 * F + g.at(s + g.sz)] - RU(2, I, J, K + 1) : T(0);
-  {
-    const T div = (X(0, I + 1, J, K) - X(0, I, J, K)) + (X(1, I, J + 1, K) - X(1, I, J, K)) +
-                  (X(2, I, J, K + 1) - X(2, I, J, K));
-    res[6] = (T)b[3 * F + g.at(s)] - (-div * (T)g.inv_h - (T)g.gamma * X(3, I, J, K));
-  }
-  const T* km = kinv + g.vtype(I, J, K, fb) * 64;
-#pragma unroll
-  for (int r = 0; r < 7; ++r) {
-    T acc = T(0);
-#pragma unroll
-    for (int j = 0; j < 7; ++j) acc += km[r * 8 + j] * res[j];
-    out[r] = acc;
-  }
-}
-
-template <typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_vanka_delta1_xs(Geom g, T* x, T* xs, const TB* __restrict__ b,
-                                                        const int* __restrict__ cells, int ncells,
-                                                        const T* __restrict__ kinv, T* __restrict__ delta) {
-  const int c = blockIdx.x * BS + threadIdx.x;
-  if (c >= ncells) return;
-  T d[7];
-  vanka_delta_vals_xs<T, TB>(g, x, xs, b, cells[c], kinv, d);
-#pragma unroll
-  for (int r = 0; r < 7; ++r) delta[(long)r * ncells + c] = d[r];
-}
-
-// The same corrections with eight lanes per subdomain (as k_vanka_delta): lane
-// r < 7 forms local residual row r from nine loads that every lane issues in
-// the same order (a velocity row: its face, the six lattice neighbours, the
-// two pressures across it; the pressure row: the six faces and the pressure),
-// then delta_r from the group's residuals by shuffles.  Same values as
-// vanka_delta_vals_xs.
+// A class's corrections with eight lanes per subdomain (as k_vanka_delta):
+// lane r < 7 forms local residual row r from nine loads that every lane
+// issues in the same order (a velocity row: its face, the six lattice
+// neighbours, the two pressures across it; the pressure row: the six faces
+// and the pressure), then delta_r from the group's residuals by shuffles.
+// Same values as vanka_delta_vals on the unslabbed state.
 template <typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_vanka_delta8_xs(Geom g, T* x, T* xs, const TB* __restrict__ b,
                                                         const int* __restrict__ cells, int ncells,
