@@ -48,8 +48,10 @@ def test_operator_apply_matches_oracle(dims, penalized):
                                                     ((8, 8, 8), 2, 1, 1, "split"), ((16, 16, 16), 0, 3, 2, "split"),
                                                     ((12, 20, 16), 3, 2, 1, "symmetric"),
                                                     ((32, 32, 32), 0, 2, 2, "symmetric"),
-                                                    # level-0 classes of ~20k cells: one thread per subdomain
+                                                    # level-0 classes of ~20k cells: the x-slab Vanka step
                                                     ((256, 256, 32), 5, 2, 1, "symmetric"),
+                                                    # the same with two Vanka steps in a row sharing the slab
+                                                    ((32, 256, 256), 5, 2, 2, "symmetric"),
                                                     # a larger ragged box
                                                     ((96, 48, 32), 0, 2, 1, "symmetric"),
                                                     ((32, 32, 32), 0, 2, 1, "split"),
