@@ -39,21 +39,52 @@ def test_guess_beats_the_zero_guess_in_error_at_128():
         assert err < 0.6
 
 
-def test_fewer_iterations_at_256_with_the_guess_from_128():
+def _iterations(n, coarse_net, seeds):
     torch = cuda()
+    import time
     from paper_2312_10615_amd.warmstart import EVAL_SEED0, _forcing_state
-    announce("warm start 256^3 (network on the 128^3 level): iterations vs zero guess")
-    sol, lay, net = _setup(256, True)
-    xc = torch.zeros(lay.total, dtype=torch.float64, device="cuda")
-    zero, warm = [], []
-    for s in range(EVAL_SEED0, EVAL_SEED0 + 4):
-        b = _forcing_state(sol, 256, s, "cuda")
+    sol, lay, net = _setup(n, coarse_net)
+    xc = torch.zeros(lay.total, dtype=torch.float64, device="cuda") if coarse_net else sol.new_state()
+    zero, warm, tz, tw = [], [], 0.0, 0.0
+    for s in range(EVAL_SEED0, EVAL_SEED0 + seeds):
+        b = _forcing_state(sol, n, s, "cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         _, i0 = sol.solve(b, rtol=1e-8, maxit=200)
-        net.initial_guess(sol.restrict(b), lay, xc)
-        x0 = sol.prolong(xc)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if coarse_net:
+            net.initial_guess(sol.restrict(b), lay, xc)
+            x0 = sol.prolong(xc)
+        else:
+            x0 = net.initial_guess(b, lay, xc)
         _, i1 = sol.solve(b, x0=x0, rtol=1e-8, maxit=200)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         assert i0["status"] == "ok" and i1["status"] == "ok"
         zero.append(i0["iters"])
         warm.append(i1["iters"])
-    announce(f"  iterations zero guess {zero}, network guess {warm}")
-    assert sum(warm) < sum(zero)
+        tz += t1 - t0
+        tw += t2 - t1
+    announce(f"  iterations zero guess {zero}, network guess {warm}; time to 1e-8 {1e3 * tz / seeds:.1f} ms "
+             f"vs {1e3 * tw / seeds:.1f} ms with the guess")
+    return zero, warm
+
+
+# Over 200 held-out seeds (profiles/warmstart_eval.md) the guess saves 1.02
+# iterations on average at 128^3 and is never worse; at 256^3, from the 128^3
+# level, 0.92, and one iteration worse on 2 seeds of 200.  The seeds are fixed
+# and the solver deterministic, so these are regression bars on the first
+# eight held-out seeds (observed: 5 iterations fewer at either size).
+def test_fewer_iterations_at_128_with_the_guess():
+    announce("warm start 128^3: iterations and time vs zero guess")
+    zero, warm = _iterations(128, False, 8)
+    assert all(w <= z for z, w in zip(zero, warm))
+    assert sum(zero) - sum(warm) >= 4
+
+
+def test_fewer_iterations_at_256_with_the_guess_from_128():
+    announce("warm start 256^3 (network on the 128^3 level): iterations and time vs zero guess")
+    zero, warm = _iterations(256, True, 8)
+    assert all(w <= z + 1 for z, w in zip(zero, warm))
+    assert sum(zero) - sum(warm) >= 3
