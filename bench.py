@@ -342,10 +342,12 @@ def batched_leg(steps, rtol, seed):
                     "then 2 iterations per replay"}
 
 
-def warm_start_leg(sol, b, steps, rtol, zero_ms, zero_iters):
+def warm_start_leg(sol, b, steps, rtol, zero_ms, zero_iters, held_out=16):
     """The learned warm start at 256^3: the network runs on the 128^3 level
     (R b there), its guess is prolonged with P and SQMR starts from it.  Time
-    includes the guess.  Also the network forward's matrix-core throughput."""
+    includes the guess.  Also the network forward's matrix-core throughput,
+    and zero guess vs network guess on the first `held_out` held-out seeds at
+    128^3 and 256^3 (iterations and time to the tolerance, means)."""
     import torch
 
     from paper_2312_10615_amd import unet as U
@@ -400,9 +402,21 @@ def warm_start_leg(sol, b, steps, rtol, zero_ms, zero_iters):
     tf = flops / (fwd_ms * 1e-3) / 1e12
     print(f"[bench] warm start: {t_warm * 1e3:.1f} ms, iters {info['iters']} (zero guess {zero_iters})",
           file=sys.stderr, flush=True)
+    held = {}
+    if held_out > 0:
+        from paper_2312_10615_amd.warmstart import evaluate
+        for n, coarse in ((128, False), (sol.layout.nx, True)):
+            summ, _ = evaluate(WEIGHTS, n=n, seeds=held_out, rtol=rtol, coarse_net=coarse, log=lambda m: None)
+            held[f"{n}^3"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in summ.items()
+                              if k in ("seeds", "iters_zero_mean", "iters_warm_mean", "time_zero_mean_s",
+                                       "time_warm_mean_s", "speedup", "guess_rel_residual_median", "all_converged")}
+            print(f"[bench] warm start, {held_out} held-out seeds at {n}^3: iterations {summ['iters_zero_mean']:.2f} -> "
+                  f"{summ['iters_warm_mean']:.2f}, {summ['speedup']:.3f}x", file=sys.stderr, flush=True)
+        held["note"] = "means over the first held-out seeds; 200 seeds: profiles/warmstart_eval.md"
+        torch.cuda.empty_cache()
     return {"value": round(t_warm, 6), "unit": "s", "iterations": info["iters"], "zero_guess_iterations": zero_iters,
             "final_relres": info["relres"], "status": info["status"],
-            "speedup_vs_fp64": round(zero_ms / 1000.0 / t_warm, 3), "guess_relres": r0,
+            "speedup_vs_fp64": round(zero_ms / 1000.0 / t_warm, 3), "guess_relres": r0, "held_out": held,
             "network": f"3-level U-Net 16/32/64 channels on the {lay1.nx}^3 level, bf16 on matrix cores",
             "training": {k: record.get(k) for k in ("n", "pairs", "epochs", "lr", "train_seconds", "sigma")}
             | {"final_loss": record.get("loss_history", [[0, None]])[-1][1]},
