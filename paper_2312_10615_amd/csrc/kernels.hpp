@@ -1194,16 +1194,33 @@ __global__ __launch_bounds__(BS) void k_convert(const Ti* __restrict__ in, To* _
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) out[i] = (To)in[i];
 }
 
+// Pairs of elements (n is even: whole fields of a multiple of 8 elements),
+// as doubles: 16-byte accesses of doubles, 8-byte ones of floats (the FP32
+// V-cycle's output read where it lies; float -> double is exact).
+typedef double pair_d2 __attribute__((ext_vector_type(2), aligned(8)));
+
+template <typename TT>
+__device__ __forceinline__ pair_d2 pair_load(const TT* __restrict__ p, long i) {
+  if constexpr (sizeof(TT) == 8) {
+    return ((const pair_d2*)p)[i];
+  } else {
+    typedef float f2 __attribute__((ext_vector_type(2), aligned(4)));
+    const f2 v = ((const f2*)p)[i];
+    pair_d2 r;
+    r.x = (double)v.x;
+    r.y = (double)v.y;
+    return r;
+  }
+}
+
 // partial[2*blk] = sum a.a, partial[2*blk+1] = sum a.c
-static __global__ __launch_bounds__(BS) void k_dot_aa_ac(const double* __restrict__ a, const double* __restrict__ c, long n,
+template <typename TT>
+__global__ __launch_bounds__(BS) void k_dot_aa_ac(const TT* __restrict__ a, const double* __restrict__ c, long n,
                                                   double* __restrict__ partial) {
-  // n is even (whole fields of a multiple of 8 elements): 16-byte accesses
-  typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));
-  const d2* a2 = (const d2*)a;
-  const d2* c2 = (const d2*)c;
+  const pair_d2* c2 = (const pair_d2*)c;
   double s0 = 0.0, s1 = 0.0;
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n / 2; i += (long)gridDim.x * BS) {
-    const d2 av = a2[i], cv = c2[i];
+    const pair_d2 av = pair_load<TT>(a, i), cv = c2[i];
     s0 += av.x * av.x;
     s0 += av.y * av.y;
     s1 += av.x * cv.x;
@@ -1252,10 +1269,12 @@ static __global__ __launch_bounds__(BS) void k_clear_ghosts(Geom g, double* __re
   if (!g.p_active(I, J, K)) x[3 * F + e] = 0.0;
 }
 
-// s -= a * t
+// s -= a t; with bf != nullptr also bf = (float) s, the right-hand side of
+// the FP32 V-cycle that follows (what k_convert would write)
 static __global__ __launch_bounds__(BS) void k_axpy_neg(double* __restrict__ s, const double* __restrict__ t, long n,
-                                                 double a) {
+                                                 double a, float* __restrict__ bf) {
   typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));  // n even: 16-byte accesses
+  typedef float f2 __attribute__((ext_vector_type(2), aligned(4)));
   d2* s2 = (d2*)s;
   const d2* t2 = (const d2*)t;
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n / 2; i += (long)gridDim.x * BS) {
@@ -1264,21 +1283,27 @@ static __global__ __launch_bounds__(BS) void k_axpy_neg(double* __restrict__ s, 
     sv.x -= a * tv.x;
     sv.y -= a * tv.y;
     s2[i] = sv;
+    if (bf) {
+      f2 fv;
+      fv.x = (float)sv.x;
+      fv.y = (float)sv.y;
+      ((f2*)bf)[i] = fv;
+    }
   }
 }
 
 // d = cd * d + cq * q;  x += d;  q = t + beta * q (the next direction, from the
 // same q): the iterate update and the direction update in one pass over q
-static __global__ __launch_bounds__(BS) void k_update_dxq(double* __restrict__ d, double* __restrict__ q,
-                                                   double* __restrict__ x, const double* __restrict__ t, long n,
+template <typename TT>
+__global__ __launch_bounds__(BS) void k_update_dxq(double* __restrict__ d, double* __restrict__ q,
+                                                   double* __restrict__ x, const TT* __restrict__ t, long n,
                                                    double cd, double cq, double bt) {
   typedef double d2 __attribute__((ext_vector_type(2), aligned(8)));  // n even: 16-byte accesses
   d2* d_ = (d2*)d;
   d2* q_ = (d2*)q;
   d2* x_ = (d2*)x;
-  const d2* t_ = (const d2*)t;
   for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n / 2; i += (long)gridDim.x * BS) {
-    const d2 qv = q_[i], dold = d_[i], tv = t_[i];
+    const d2 qv = q_[i], dold = d_[i], tv = pair_load<TT>(t, i);
     d2 xv = x_[i];
     d2 dv;
     dv.x = cd * dold.x + cq * qv.x;

@@ -103,6 +103,7 @@ struct stokes_ctx {
     const double* s;
     double* t;
     int pc, pl;
+    int io;  // PC_* flags the V-cycle was captured with
     std::vector<Step> steps;
   };
   std::vector<GraphEntry> graphs;
@@ -618,11 +619,17 @@ void vcycle(stokes_ctx* c, int l, const T* b, T* x, bool zero_init = true) {
   postsmooth(c, l, x, b);
 }
 
+// FP32 V-cycle: its right-hand side is already in the float level buffer
+// (written with s), and/or its result is left there for the SQMR passes,
+// which read it as float, instead of converting it into t.
+enum { PC_IN_READY = 1, PC_OUT_FLOAT = 2 };
+
 // The whole preconditioner application t = W s: FP64 runs the V-cycle on the
 // caller's vectors; FP32 converts s once, runs the V-cycle on float level
 // buffers (all smoother, transfer and stencil arithmetic in FP32; the
-// coarsest solve accumulates in FP64) and converts the result back.
-void precondition(stokes_ctx* c, const double* s, double* t) {
+// coarsest solve accumulates in FP64) and converts the result back (io: the
+// PC_* flags).
+void precondition(stokes_ctx* c, const double* s, double* t, int io = 0) {
   if (c->prec == 64) {
     vcycle<double>(c, 0, s, t);
     return;
@@ -630,9 +637,11 @@ void precondition(stokes_ctx* c, const double* s, double* t) {
   float* b0 = (float*)c->lev[0].b;
   float* x0 = (float*)c->lev[0].x;
   const long n = c->total;
-  launch(c, STOKES_KC_BLAS, 0, [=] { k_convert<double, float><<<RED_BLOCKS, BS, 0, c->ks>>>(s, b0, n); });
+  if (!(io & PC_IN_READY))
+    launch(c, STOKES_KC_BLAS, 0, [=] { k_convert<double, float><<<RED_BLOCKS, BS, 0, c->ks>>>(s, b0, n); });
   vcycle<float>(c, 0, b0, x0);
-  launch(c, STOKES_KC_BLAS, 0, [=] { k_convert<float, double><<<RED_BLOCKS, BS, 0, c->ks>>>(x0, t, n); });
+  if (!(io & PC_OUT_FLOAT))
+    launch(c, STOKES_KC_BLAS, 0, [=] { k_convert<float, double><<<RED_BLOCKS, BS, 0, c->ks>>>(x0, t, n); });
 }
 
 void seg_open(stokes_ctx* c) {
@@ -660,15 +669,16 @@ void seg_close(stokes_ctx* c) {
 // is captured once per (s, t, profiling selection) into graph segments that
 // are replayed on the caller's stream; STOKES_FLAG_NO_GRAPH launches it
 // kernel by kernel instead.
-int run_vcycle(stokes_ctx* c, const double* s, double* t) {
+int run_vcycle(stokes_ctx* c, const double* s, double* t, int io = 0) {
+  if (c->prec == 64) io = 0;
   if (c->prm.flags & STOKES_FLAG_NO_GRAPH) {
     c->ks = c->stream;
-    precondition(c, s, t);
+    precondition(c, s, t, io);
     return hipGetLastError() == hipSuccess ? STOKES_OK : STOKES_EDEVICE;
   }
   stokes_ctx::GraphEntry* hit = nullptr;
   for (auto& e : c->graphs)
-    if (e.s == s && e.t == t && e.pc == c->prof_class && e.pl == c->prof_level) hit = &e;
+    if (e.s == s && e.t == t && e.pc == c->prof_class && e.pl == c->prof_level && e.io == io) hit = &e;
   if (!hit) {
     if (c->graphs.size() >= 4) {
       (void)hipStreamSynchronize(c->stream);
@@ -679,11 +689,11 @@ int run_vcycle(stokes_ctx* c, const double* s, double* t) {
     c->capturing = true;
     c->ks = c->cap;
     seg_open(c);
-    precondition(c, s, t);
+    precondition(c, s, t, io);
     seg_close(c);
     c->capturing = false;
     c->ks = c->stream;
-    stokes_ctx::GraphEntry e{s, t, c->prof_class, c->prof_level, std::move(c->steps)};
+    stokes_ctx::GraphEntry e{s, t, c->prof_class, c->prof_level, io, std::move(c->steps)};
     c->steps.clear();
     c->graphs.push_back(std::move(e));
     hit = &c->graphs.back();
@@ -1067,7 +1077,7 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
   if (run_vcycle(c, c->s, c->t) != STOKES_OK) return finish(0, STOKES_EDEVICE);
   {
     Prof pf(c, STOKES_KC_BLAS, 0);
-    k_dot_aa_ac<<<RED_BLOCKS, BS, 0, c->stream>>>(c->t, c->s, n, c->partial);
+    k_dot_aa_ac<double><<<RED_BLOCKS, BS, 0, c->stream>>>(c->t, c->s, n, c->partial);
   }
   if (reduce_to_host(c, RED_BLOCKS, 2) != STOKES_OK) return finish(0, STOKES_EDEVICE);
   double tau = std::sqrt(c->hscal[0]);
@@ -1087,15 +1097,22 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
     if (!std::isfinite(sigma)) return finish(j - 1, STOKES_ENONFINITE);
     if (sigma == 0.0) return finish(j - 1, STOKES_EBREAKDOWN);
     const double alpha = rho / sigma;
+    // FP32 V-cycle: the s update also writes its float right-hand side, and
+    // W s stays in the float level buffer, where the next two passes read it
+    float* const wf = c->prec == 32 ? (float*)c->lev[0].x : nullptr;
     {
       Prof pf(c, STOKES_KC_BLAS, 0);
-      k_axpy_neg<<<RED_BLOCKS, BS, 0, c->stream>>>(c->s, c->t, n, alpha);
+      k_axpy_neg<<<RED_BLOCKS, BS, 0, c->stream>>>(c->s, c->t, n, alpha, wf ? (float*)c->lev[0].b : nullptr);
     }
     // t = W s
-    if (run_vcycle(c, c->s, c->t) != STOKES_OK) return finish(j - 1, STOKES_EDEVICE);
+    if (run_vcycle(c, c->s, c->t, wf ? PC_IN_READY | PC_OUT_FLOAT : 0) != STOKES_OK)
+      return finish(j - 1, STOKES_EDEVICE);
     {
       Prof pf(c, STOKES_KC_BLAS, 0);
-      k_dot_aa_ac<<<RED_BLOCKS, BS, 0, c->stream>>>(c->t, c->s, n, c->partial);
+      if (wf)
+        k_dot_aa_ac<float><<<RED_BLOCKS, BS, 0, c->stream>>>(wf, c->s, n, c->partial);
+      else
+        k_dot_aa_ac<double><<<RED_BLOCKS, BS, 0, c->stream>>>(c->t, c->s, n, c->partial);
     }
     if (reduce_to_host(c, RED_BLOCKS, 2) != STOKES_OK) return finish(j - 1, STOKES_EDEVICE);
     const double tnorm = std::sqrt(c->hscal[0]);
@@ -1106,8 +1123,12 @@ int stokes_solve(stokes_ctx* c, const double* b, double* x, double rtol, int32_t
     {
       Prof pf(c, STOKES_KC_BLAS, 0);
       // with the next direction q = t + (rho_new / rho) q in the same pass (unused when the loop ends here)
-      k_update_dxq<<<RED_BLOCKS, BS, 0, c->stream>>>(c->d, c->q, x, c->t, n, cc * cc * nu_prev * nu_prev,
-                                                      cc * cc * alpha, rho_new / rho);
+      if (wf)
+        k_update_dxq<float><<<RED_BLOCKS, BS, 0, c->stream>>>(c->d, c->q, x, wf, n, cc * cc * nu_prev * nu_prev,
+                                                              cc * cc * alpha, rho_new / rho);
+      else
+        k_update_dxq<double><<<RED_BLOCKS, BS, 0, c->stream>>>(c->d, c->q, x, c->t, n, cc * cc * nu_prev * nu_prev,
+                                                               cc * cc * alpha, rho_new / rho);
     }
     nu_prev = nu;
     // true residual
