@@ -509,18 +509,22 @@ void b_vcycle(stokes_batch* c, int l) {
   b_postsmooth<T>(c, l);
 }
 
-// t = W s for every active domain
-void b_precondition(stokes_batch* c) {
+// t = W s for every active domain.  FP32 V-cycle inside the iterations: s's
+// update has already written the float right-hand sides, and the SQMR passes
+// read the float result where it lies (fused = true); else both conversions.
+void b_precondition(stokes_batch* c, bool fused = false) {
   if (c->prec == 64) {
     b_vcycle<double>(c, 0);
     return;
   }
   const Tab& tv = c->tvec;
-  kb_convert<double, float, true><<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen,
-                                                               c->dlev[0], c->s, (float*)nullptr);
+  if (!fused)
+    kb_convert<double, float, true><<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen,
+                                                                 c->dlev[0], c->s, (float*)nullptr);
   b_vcycle<float>(c, 0);
-  kb_convert<float, double, false><<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen,
-                                                                c->dlev[0], (const float*)nullptr, c->t);
+  if (!fused)
+    kb_convert<float, double, false><<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen,
+                                                                  c->dlev[0], (const float*)nullptr, c->t);
 }
 
 // ----------------------------------------------------- device SQMR scalars
@@ -678,7 +682,8 @@ void phase_init(stokes_batch* c, const double* b, double* x) {
   seg(c, RED0, 1, ta, c->done);
   kb_sq_r0<<<dgrid(D), 64, 0, c->ks>>>(c->sc, c->done, D);
   b_precondition(c);
-  kb_dot2<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->t, c->s, c->partial);
+  kb_dot2<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->t, c->s, c->partial,
+                                       (const BLev*)nullptr);
   seg(c, RED0, 2, tv, c->done);
   kb_sq_start<<<dgrid(D), 64, 0, c->ks>>>(c->sc, c->done, D);
   kb_init_qd<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->q, c->dv, c->t);
@@ -691,13 +696,14 @@ void phase_iteration(stokes_batch* c, const double* b, double* x) {
   apply0<AP_APPLY_DOT>(c, c->q, nullptr, c->t);
   seg(c, RED0, 1, ta, c->done);
   kb_sq_alpha<<<dgrid(D), 64, 0, c->ks>>>(c->sc, c->done, D);
-  kb_axpy_neg<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->sc, c->s, c->t);
-  b_precondition(c);
-  kb_dot2<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->t, c->s, c->partial);
+  const BLev* l0 = c->prec == 32 ? c->dlev[0] : nullptr;  // FP32 V-cycle: its float level-0 vectors
+  kb_axpy_neg<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->sc, c->s, c->t, l0);
+  b_precondition(c, l0 != nullptr);
+  kb_dot2<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->t, c->s, c->partial, l0);
   seg(c, RED0, 2, tv, c->done);
   kb_sq_nu<<<dgrid(D), 64, 0, c->ks>>>(c->sc, c->done, D);
   kb_update_dxq<<<tv.blocks, BS, 0, c->ks>>>(c->tab(tv), tv.n, c->done, c->voff, c->vlen, c->sc, c->dv, c->q, x,
-                                             c->t);
+                                             c->t, l0);
   apply0<AP_RESNORM>(c, x, b, nullptr);
   seg(c, RED0, 1, ta, c->done);
   kb_sq_check<<<dgrid(D), 64, 0, c->ks>>>(c->sc, c->done, D);

@@ -336,25 +336,32 @@ __global__ __launch_bounds__(BS) void kb_apply_vec(const BEnt* __restrict__ tab,
     }                                                        \
   }
 
+// s -= alpha t; with lev != nullptr (FP32 V-cycle) also the domain's float
+// level-0 right-hand side = (float) s (what kb_convert would write)
 __global__ __launch_bounds__(BS) void kb_axpy_neg(const BEnt* __restrict__ tab, int nent, const int* __restrict__ done,
                                                   const long* __restrict__ voff, const long* __restrict__ vlen,
                                                   const BScal* __restrict__ sc, double* __restrict__ s,
-                                                  const double* __restrict__ t) {
+                                                  const double* __restrict__ t, const BLev* __restrict__ lev) {
   SG_BATCH_ENTRY();
   const double a = sc[d].alpha;
-  SG_VEC_LOOP(s[i] -= a * t[i]);
+  float* bf = lev ? (float*)lev[d].b : nullptr;
+  SG_VEC_LOOP(const double v = s[i] - a * t[i]; s[i] = v; if (bf) bf[j_] = (float)v);
 }
 
-// d = cd d + cq q; x += d; q = t + beta q (the next direction from the same q)
+// d = cd d + cq q; x += d; q = t + beta q (the next direction from the same q);
+// with lev != nullptr t is read from the domain's float level-0 result of the
+// FP32 V-cycle (float -> double is exact: the values of the converted t)
 __global__ __launch_bounds__(BS) void kb_update_dxq(const BEnt* __restrict__ tab, int nent,
                                                     const int* __restrict__ done, const long* __restrict__ voff,
                                                     const long* __restrict__ vlen, const BScal* __restrict__ sc,
                                                     double* __restrict__ dv, double* __restrict__ q,
-                                                    double* __restrict__ x, const double* __restrict__ t) {
+                                                    double* __restrict__ x, const double* __restrict__ t,
+                                                    const BLev* __restrict__ lev) {
   SG_BATCH_ENTRY();
   const double cd = sc[d].cd, cq = sc[d].cq, bt = sc[d].beta;
+  const float* tf = lev ? (const float*)lev[d].x : nullptr;
   SG_VEC_LOOP(const double qv = q[i]; const double v = cd * dv[i] + cq * qv; dv[i] = v; x[i] += v;
-              q[i] = t[i] + bt * qv);
+              q[i] = (tf ? (double)tf[j_] : t[i]) + bt * qv);
 }
 
 // q = t, d = 0 (start of SQMR)
@@ -378,13 +385,15 @@ __global__ __launch_bounds__(BS) void kb_zero_flagged(const BEnt* __restrict__ t
 }
 
 // partial[2 blk] = sum a.a, partial[2 blk + 1] = sum a.c over the domain's slice
+// (with lev != nullptr, a is the domain's float level-0 result, as above)
 __global__ __launch_bounds__(BS) void kb_dot2(const BEnt* __restrict__ tab, int nent, const int* __restrict__ done,
                                               const long* __restrict__ voff, const long* __restrict__ vlen,
                                               const double* __restrict__ a, const double* __restrict__ c,
-                                              double* __restrict__ partial) {
+                                              double* __restrict__ partial, const BLev* __restrict__ lev) {
   SG_BATCH_ENTRY();
   double s0 = 0.0, s1 = 0.0;
-  SG_VEC_LOOP(const double av = a[i]; s0 += av * av; s1 += av * c[i]);
+  const float* af = lev ? (const float*)lev[d].x : nullptr;
+  SG_VEC_LOOP(const double av = af ? (double)af[j_] : a[i]; s0 += av * av; s1 += av * c[i]);
   const double t0 = block_sum(s0);
   const double t1 = block_sum(s1);
   if (threadIdx.x == 0) {
