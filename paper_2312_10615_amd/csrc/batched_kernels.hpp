@@ -232,7 +232,7 @@ __global__ __launch_bounds__(BS) void kb_vanka_pp(const BEnt* __restrict__ tab, 
     }
   } else if (kp >= 0) {
     const int u = t - copy0, c = u >> 3, r = u & 7;
-    if (c < lev[d].nv[kp] && r < 7) vanka_copy_dof<T>(g, R, W, lev[d].vc[kp][c], r, k);
+    if (c < lev[d].nv[kp] && r < 7) vanka_copy_dof<T>(g, R, W, lev[d].vc[kp][c], r, 1 << k);
   }
 }
 

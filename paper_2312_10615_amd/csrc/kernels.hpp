@@ -513,17 +513,41 @@ __host__ __device__ inline int vanka_pass_prev(int pass) {
   return pass == 0 || pass == 8 ? -1 : vanka_pass_class(pass - 1);
 }
 
-// Copy unknown r of previous-class cell s from R to W unless a V1 cell of
-// class k owns it too.
+// The same order with the passes of classes 3 and 4 run as one pass (forward
+// 0 1 2 {3,4} 5 6 7, backward 7 6 5 {4,3} 2 1 0: 14 passes).  Classes 3 and 4
+// differ in all three parity bits, so their cells meet only at edges and
+// corners: a class-3 subdomain's local residuals read no unknown of a class-4
+// subdomain (the face stencils reach the faces of face neighbours, a pressure
+// row only its own cell's faces) and the two share none, so running them
+// together gives the values of running them one after the other, bit for
+// bit.  Returns the pass's first class (3 for the merged one); *merged says
+// whether class 4 comes with it.  The class lists of classes 3 and 4 are
+// stored one after the other, so the merged pass reads one list.
+constexpr int VANKA_PASSES8 = 14;
+__host__ __device__ inline int vanka_pass8(int pass, bool* merged) {
+  const int q = pass < 7 ? pass : pass - 7;
+  *merged = q == 3;
+  if (pass < 7) return q < 3 ? q : q == 3 ? 3 : q + 1;
+  return q < 3 ? 7 - q : q == 3 ? 3 : 6 - q;
+}
+// bit mask of the classes of a pass
+__host__ __device__ inline int vanka_pass8_mask(int pass) {
+  bool m;
+  const int k = vanka_pass8(pass, &m);
+  return m ? (1 << 3) | (1 << 4) : 1 << k;
+}
+
+// Copy unknown r of previous-class cell s from R to W unless a V1 cell of a
+// class in the pass's mask kmask owns it too.
 template <typename T>
 __device__ __forceinline__ void vanka_copy_dof(const Geom& g, const T* __restrict__ R, T* __restrict__ W, int s,
-                                               int r, int k) {
+                                               int r, int kmask) {
   int I, J, K;
   slot_ijk(g, s, I, J, K);
   const VankaDof d = vanka_dof(g, s, I, J, K, r);
   if (!d.active) return;
   if (r < 6 && g.p_active(d.nI, d.nJ, d.nK) && !g.p_v2(d.nI, d.nJ, d.nK) &&
-      Geom::vanka_colour(d.nI, d.nJ, d.nK) == k)
+      ((kmask >> Geom::vanka_colour(d.nI, d.nJ, d.nK)) & 1))
     return;
   W[d.e] = R[d.e];
 }
@@ -534,7 +558,7 @@ template <typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_vanka_pp8(Geom g, const T* __restrict__ R, T* __restrict__ W,
                                                   const TB* __restrict__ b, const int* __restrict__ cells, int ncells,
                                                   const T* __restrict__ kinv, const int* __restrict__ prev, int nprev,
-                                                  int k, int copy0) {
+                                                  int kmask, int copy0) {
   const int t = blockIdx.x * BS + threadIdx.x;
   if (t < copy0) {  // whole waves: the shuffles see only this part's lanes
     const int c = t >> 3, r = t & 7;
@@ -562,7 +586,7 @@ __global__ __launch_bounds__(BS) void k_vanka_pp8(Geom g, const T* __restrict__ 
     if (wr) W[dof.e] = old + acc;
   } else {
     const int u = t - copy0, c = u >> 3, r = u & 7;
-    if (c < nprev && r < 7) vanka_copy_dof<T>(g, R, W, prev[c], r, k);
+    if (c < nprev && r < 7) vanka_copy_dof<T>(g, R, W, prev[c], r, kmask);
   }
 }
 
@@ -672,14 +696,19 @@ __device__ __forceinline__ void vanka_sweep_passes1(const Geom& g, const Lists& 
                                                     int* __restrict__ scell) {
   vsweep_load_lists(a, scell);
   const int t = threadIdx.x;
-  for (int pass = 0; pass < 2 * a.nc; ++pass) {
-    const int k = pass < a.nc ? pass : 2 * a.nc - 1 - pass;
-    const bool mine = t < a.count(k);
+  // 8 classes: classes 3 and 4 in one pass (vanka_pass8) when a thread each covers them
+  const bool m34 = a.nc == 8 && a.count(3) + a.count(4) <= (int)blockDim.x;
+  const int npass = m34 ? VANKA_PASSES8 : 2 * a.nc;
+  for (int pass = 0; pass < npass; ++pass) {
+    bool merged = false;
+    const int k = m34 ? vanka_pass8(pass, &merged) : pass < a.nc ? pass : 2 * a.nc - 1 - pass;
+    const int n3 = a.count(k);
+    const bool mine = t < n3 + (merged ? a.count(4) : 0);
     T d[7], old[7];
     int e[7];
     bool act[7];
     if (mine) {
-      const int s = vsweep_cell(a, scell, k, t);
+      const int s = t < n3 ? vsweep_cell(a, scell, k, t) : vsweep_cell(a, scell, 4, t - n3);
       vanka_delta_vals<T, T>(g, x, b, s, sk, d);
       int I, J, K;
       slot_ijk(g, s, I, J, K);

@@ -329,11 +329,17 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
       long sum = 0;
       for (int k = 0; k < nc; ++k) {
         lv.nv[k] = (int)cells[k].size();
-        lv.vcells[k] = cv.take<int>(std::max<size_t>(cells[k].size(), 1));
+        if (nc == 8 && k == 3)  // classes 3 and 4 back to back: their merged pass reads one list
+          lv.vcells[3] = cv.take<int>(std::max<size_t>(cells[3].size() + cells[4].size(), 1));
+        else if (nc == 8 && k == 4)
+          lv.vcells[4] = lv.vcells[3] ? lv.vcells[3] + lv.nv[3] : nullptr;
+        else
+          lv.vcells[k] = cv.take<int>(std::max<size_t>(cells[k].size(), 1));
         lv.doff[k] = p.vanka == STOKES_VANKA_ADDITIVE ? sum : 0;
         sum += 8L * lv.nv[k];
         vmax = std::max<long>(vmax, p.vanka == STOKES_VANKA_ADDITIVE ? sum / 8 : lv.nv[k]);
       }
+      if (nc == 8 && p.vanka != STOKES_VANKA_ADDITIVE) vmax = std::max<long>(vmax, (long)lv.nv[3] + lv.nv[4]);
       // two-copy passes where a pass is a latency chain (eight lanes per subdomain);
       // on larger levels the passes are bound by bandwidth and the copies cost more
       lv.pp = p.vanka == STOKES_VANKA_MULT8 && !c->labelled && !vsweep_level(lv, nc);
@@ -385,15 +391,26 @@ void launch(stokes_ctx* c, int cls, int level, F f) {
   f();
 }
 
+// The cells of one multiplicative pass (8 classes, 14 passes: vanka_pass8),
+// and the class mask of the pass.
+struct VPass {
+  const int* cells;
+  int n;
+  int mask;
+};
+VPass vanka_pass_list(const Level& lv, int pass) {
+  bool merged;
+  const int k = vanka_pass8(pass, &merged);
+  return VPass{lv.vcells[k], merged ? lv.nv[3] + lv.nv[4] : lv.nv[k], vanka_pass8_mask(pass)};
+}
+
+// Residual pass over n cells; corrections to vd (delta[r * n + c]).
 template <typename T>
-void vanka_delta(stokes_ctx* c, int l, const T* x, const T* b, int k) {
+void vanka_delta_list(stokes_ctx* c, int l, const T* x, const T* b, const int* cells, int n, T* vd) {
   const Level& lv = c->lev[l];
-  const int n = lv.nv[k];
   if (n == 0) return;
   const Geom g = lv.g;
-  const int* cells = lv.vcells[k];
   const T* kinv = (const T*)lv.kinv;
-  T* vd = (T*)c->vdelta + lv.doff[k];
   if (n > VANKA_LANES_MAX) {  // one thread per subdomain
     const int nb = (n + BS - 1) / BS;
     launch(c, STOKES_KC_VANKA_DELTA, l,
@@ -406,15 +423,23 @@ void vanka_delta(stokes_ctx* c, int l, const T* x, const T* b, int k) {
 }
 
 template <typename T>
-void vanka_correct(stokes_ctx* c, int l, T* x, int k) {
+void vanka_delta(stokes_ctx* c, int l, const T* x, const T* b, int k) {
   const Level& lv = c->lev[l];
-  const int n = lv.nv[k];
+  vanka_delta_list<T>(c, l, x, b, lv.vcells[k], lv.nv[k], (T*)c->vdelta + lv.doff[k]);
+}
+
+template <typename T>
+void vanka_correct_list(stokes_ctx* c, int l, T* x, const int* cells, int n, const T* vd) {
   if (n == 0) return;
   const int nb = (8 * n + BS - 1) / BS;
-  const Geom g = lv.g;
-  const int* cells = lv.vcells[k];
-  const T* vd = (const T*)c->vdelta + lv.doff[k];
+  const Geom g = c->lev[l].g;
   launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_vanka_apply<T><<<nb, BS, 0, c->ks>>>(g, x, cells, n, vd); });
+}
+
+template <typename T>
+void vanka_correct(stokes_ctx* c, int l, T* x, int k) {
+  const Level& lv = c->lev[l];
+  vanka_correct_list<T>(c, l, x, lv.vcells[k], lv.nv[k], (const T*)c->vdelta + lv.doff[k]);
 }
 
 // One application of the V1 smoother in a Vanka slot of Alg. 3: symmetric
@@ -449,7 +474,7 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
     for (int k = 0; k < nc; ++k) vanka_correct<T>(c, l, x, k);
     return;
   }
-  if (lv.pp) {  // two copies of the state; the 16 passes end in x
+  if (lv.pp) {  // two copies of the state; the 14 passes end in x
     const Geom g = lv.g;
     T* X[2] = {x, (T*)lv.alt};
     T* alt = X[1];
@@ -461,19 +486,22 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
       launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_convert<T, T><<<RED_BLOCKS, BS, 0, c->ks>>>(x, alt, n); });
     }
     const T* kinv = (const T*)lv.kinv;
-    for (int pass = 0; pass < 16; ++pass) {
-      const int k = vanka_pass_class(pass), kp = vanka_pass_prev(pass);
-      const int n = lv.nv[k];
-      const int np = kp >= 0 ? lv.nv[kp] : 0;
-      const int* cells = lv.vcells[k];
-      const int* prev = kp >= 0 ? lv.vcells[kp] : cells;
+    for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
+      const VPass cur = vanka_pass_list(lv, pass);
+      // the previous pass's corrections to copy: none before the first pass,
+      // nor before the second class-7 pass, which rewrites all of its unknowns
+      const bool fresh = pass == 0 || pass == VANKA_PASSES8 / 2;
+      const VPass prv = fresh ? VPass{cur.cells, 0, 0} : vanka_pass_list(lv, pass - 1);
+      const int n = cur.n, np = prv.n, kmask = cur.mask;
+      const int* cells = cur.cells;
+      const int* prev = prv.cells;
       const T* R = X[pass & 1];
       T* W = X[(pass + 1) & 1];
       if (n == 0 && np == 0) continue;
       const int copy0 = (8 * n + 63) / 64 * 64;
       const int nb = (copy0 + 8 * np + BS - 1) / BS;
       launch(c, STOKES_KC_VANKA_DELTA, l, [=] {
-        k_vanka_pp8<T, T><<<nb, BS, 0, c->ks>>>(g, R, W, b, cells, n, kinv, prev, np, k, copy0);
+        k_vanka_pp8<T, T><<<nb, BS, 0, c->ks>>>(g, R, W, b, cells, n, kinv, prev, np, kmask, copy0);
       });
     }
     return;
@@ -485,12 +513,12 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
     const int nbc = (int)((xslab_elems(g) + BS - 1) / BS);
     if (xin != XS_OUT)  // XS_OUT as the way in: the slab is current
       launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_xslab_copy<T><<<nbc, BS, 0, c->ks>>>(g, x, xs, xin); });
-    for (int pass = 0; pass < 2 * nc; ++pass) {
-      const int k = pass < nc ? pass : 2 * nc - 1 - pass;
-      const int n = lv.nv[k];
+    for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
+      const VPass cur = vanka_pass_list(lv, pass);
+      const int n = cur.n;
       if (n == 0) continue;
-      const int* cells = lv.vcells[k];
-      T* vd = (T*)c->vdelta + lv.doff[k];
+      const int* cells = cur.cells;
+      T* vd = (T*)c->vdelta;
       launch(c, STOKES_KC_VANKA_DELTA, l, [=] {
         k_vanka_delta8_xs<T, T><<<(8 * n + BS - 1) / BS, BS, 0, c->ks>>>(g, x, xs, b, cells, n, kinv, vd);
       });
@@ -498,6 +526,14 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
              [=] { k_vanka_apply_xs<T><<<(8 * n + BS - 1) / BS, BS, 0, c->ks>>>(g, x, xs, cells, n, vd); });
     }
     if (xout) launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_xslab_copy<T><<<nbc, BS, 0, c->ks>>>(g, x, xs, XS_OUT); });
+    return;
+  }
+  if (nc == 8) {
+    for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
+      const VPass cur = vanka_pass_list(lv, pass);
+      vanka_delta_list<T>(c, l, x, b, cur.cells, cur.n, (T*)c->vdelta);
+      vanka_correct_list<T>(c, l, x, cur.cells, cur.n, (const T*)c->vdelta);
+    }
     return;
   }
   for (int pass = 0; pass < 2 * nc; ++pass) {
