@@ -82,8 +82,12 @@ enum { STOKES_SMOOTHER_SPLIT = 0, STOKES_SMOOTHER_SYMMETRIC = 1 };
 
 /* The V1 (boundary) smoother of Alg. 3 (Section 3.2):
  *  STOKES_VANKA_MULT8: symmetric multiplicative Vanka, the paper's 8 colour
- *    classes (i&1) + 2(j&1) + 4(k&1), classes 0..7 then 7..0, each class
- *    updated at once from the state at its start.  Default.
+ *    classes (i&1) + 2(j&1) + 4(k&1) in the order 0 7 1 6 2 5 3 4 and then
+ *    the reverse (the paper fixes no order of the classes; here each class is
+ *    followed by its complement), each class updated at once from the state
+ *    at its start.  Complementary classes share no unknown and read none of
+ *    each other's, so each pair runs as one pass with the same values.
+ *    Default.
  *  STOKES_VANKA_MULT27: the same with 27 classes (i%3) + 3(j%3) + 9(k%3);
  *    same-class cells are three apart and share no stencil entry, so a class
  *    step equals solving its subdomains one after another (Eq. mv).

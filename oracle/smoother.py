@@ -273,14 +273,29 @@ def vanka_color(dom: Domain, x, b, colour: int, period: int = 2):
     return vanka_cells_step(dom, x, b, cells)
 
 
+# Forward order of the 8 classes.  Section 3.2 takes the subdomains in one
+# order and then in its reverse, and Section 6 colours them with 8 classes
+# without fixing an order of the classes.  Reading: each class is followed by
+# its complement (the class whose parity bits all differ), 0 7 1 6 2 5 3 4.
+VANKA_ORDER8 = (0, 7, 1, 6, 2, 5, 3, 4)
+
+
+def vanka_class_order(period: int = 2) -> list:
+    """Forward order of the colour classes: VANKA_ORDER8 for 8 classes,
+    0..26 for 27."""
+    return list(VANKA_ORDER8) if period == 2 else list(range(period ** 3))
+
+
 def vanka_symmetric(dom: Domain, x, b, period: int = 2):
-    """Symmetric multiplicative Vanka (Section 3.2): classes 0..n-1, then n-1..0,
-    each one step of `vanka_color`."""
+    """Symmetric multiplicative Vanka (Section 3.2): the classes in the order
+    of `vanka_class_order`, then in the reverse order, each one step of
+    `vanka_color`."""
     n = period ** 3
     col = dom.vanka_colour(period)
     cells = [np.argwhere(dom.v1[3] & (col == k)) for k in range(n)]
     x = [v.copy() for v in x]
-    for colour in list(range(n)) + list(reversed(range(n))):
+    order = vanka_class_order(period)
+    for colour in order + order[::-1]:
         _vanka_cells_into(dom, x, b, cells[colour])
     return tuple(x)
 

@@ -120,7 +120,7 @@ struct stokes_batch {
   std::vector<BEnt> harena;
   BEnt* arena = nullptr;
   Tab tcls[NCLS][MAXL][NBX];
-  Tab tvec, tfield, tzero[MAXL], tcoarse[MAXL], tvanka[MAXL][8], tvapply[MAXL][8], tband[MAXL], tpp[MAXL][16];
+  Tab tvec, tfield, tzero[MAXL], tcoarse[MAXL], tvanka[MAXL][4], tvapply[MAXL][4], tband[MAXL], tpp[MAXL][8];
   bool vpp[MAXL] = {};  // level runs the two-copy Vanka passes (else delta and apply launches)
   void* vdelta = nullptr;
   Tab tsweep[MAXL];  // boxes whose Vanka step on the level runs in one workgroup
@@ -212,7 +212,8 @@ void carve(stokes_batch* c, Carve& cv) {
   // per-domain level data
   long vmax = 1;
   for (int l = 0; l < c->Lmax; ++l) {
-    long vsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long vsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // cells per class over the boxes (eight lanes each)
+    long psum[4] = {0, 0, 0, 0};              // their corrections per pair
     for (int d : c->all[l]) {
       BLev& b = c->hlev[l][d];
       const long tot = 4L * b.g.field;
@@ -230,16 +231,22 @@ void carve(stokes_batch* c, Carve& cv) {
         std::vector<int> cells[8];
         vanka_cells(b.g, cells);
         bool small = true;
+        // classes q and 7-q back to back: their pair pass (vanka_pair8) reads one list
         for (int k = 0; k < 8; ++k) {
           b.nv[k] = (int)cells[k].size();
-          b.vc[k] = cv.take<int>(std::max<size_t>(cells[k].size(), 1));
+          if (k < 4)
+            b.vc[k] = cv.take<int>(std::max<size_t>(cells[k].size() + cells[7 - k].size(), 1));
+          else
+            b.vc[k] = b.vc[7 - k] ? b.vc[7 - k] + b.nv[7 - k] : nullptr;
           small = small && b.nv[k] <= VSWEEP_MAX_CLASS;
         }
-        if (!small)
-          for (int k = 0; k < 8; ++k) {
-            b.voff[k] = vsum[k];
-            vsum[k] += 8L * b.nv[k];
+        if (!small) {
+          for (int k = 0; k < 8; ++k) vsum[k] += 8L * b.nv[k];
+          for (int q = 0; q < 4; ++q) {
+            b.voff[q] = psum[q];
+            psum[q] += 8L * (b.nv[q] + b.nv[7 - q]);
           }
+        }
       } else {
         b.nc = (int)dofs(b.g);
         b.cinv = cv.take<double>((size_t)b.nc * b.nc);
@@ -250,7 +257,7 @@ void carve(stokes_batch* c, Carve& cv) {
     // single box's latency-bound levels; larger levels keep the delta and apply launches
     c->vpp[l] = true;
     for (int k = 0; k < 8; ++k) c->vpp[l] = c->vpp[l] && vsum[k] / 8 <= VANKA_LANES_MAX;
-    for (int k = 0; k < 8; ++k) vmax = std::max(vmax, vsum[k]);
+    for (int q = 0; q < 4; ++q) vmax = std::max(vmax, psum[q]);
     for (int d : c->all[l]) {
       BLev& b = c->hlev[l][d];
       if (c->vpp[l] && l + 1 < c->L[d]) {
@@ -335,27 +342,27 @@ void carve(stokes_batch* c, Carve& cv) {
       return true;
     };
     c->tsweep[l] = add_table(c, c->smooth[l], [&](int d) { return small(d) ? 1 : 0; });
-    for (int k = 0; k < 8; ++k) {
-      c->tvanka[l][k] = add_table(c, c->smooth[l], [&](int d) {
-        return c->vpp[l] || small(d) ? 0 : (8 * c->hlev[l][d].nv[k] + BS - 1) / BS;
-      });
-      c->tvapply[l][k] = add_table(c, c->smooth[l], [&](int d) {
-        return c->vpp[l] || small(d) ? 0 : (8 * c->hlev[l][d].nv[k] + BS - 1) / BS;
-      });
+    for (int q = 0; q < 4; ++q) {
+      auto blocks = [&](int d) {
+        const BLev& b = c->hlev[l][d];
+        return c->vpp[l] || small(d) ? 0 : (8 * (b.nv[q] + b.nv[7 - q]) + BS - 1) / BS;
+      };
+      c->tvanka[l][q] = add_table(c, c->smooth[l], blocks);
+      c->tvapply[l][q] = add_table(c, c->smooth[l], blocks);
     }
-    // two-copy passes: the band copy, then pass p of class k with the previous class kp
+    // two-copy passes: the band copy, then pass p of pair q with the previous pair qp
     c->tband[l] = add_table(c, c->smooth[l], [&](int d) {
       const Geom& g = c->hlev[l][d].g;
       if (!c->vpp[l] || small(d)) return 0;
       const long n = (g.nx < 8 || g.ny < 8 || g.nz < 8) ? 4L * g.field : vanka_band_slots(g);
       return (int)((n + BS - 1) / BS);
     });
-    for (int pass = 0; pass < 16; ++pass) {
-      const int k = vanka_pass_class(pass), kp = vanka_pass_prev(pass);
+    for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
+      const int q = vanka_pair8(pass), qp = vanka_pair8_prev(pass);
       c->tpp[l][pass] = add_table(c, c->smooth[l], [&](int d) {
         if (!c->vpp[l] || small(d)) return 0;
         const BLev& b = c->hlev[l][d];
-        const int lanes = (8 * b.nv[k] + 63) / 64 * 64 + (kp >= 0 ? 8 * b.nv[kp] : 0);
+        const int lanes = (8 * (b.nv[q] + b.nv[7 - q]) + 63) / 64 * 64 + (qp >= 0 ? 8 * (b.nv[qp] + b.nv[7 - qp]) : 0);
         return (lanes + BS - 1) / BS;
       });
     }
@@ -414,27 +421,27 @@ template <typename T>
 void b_vanka_symmetric(stokes_batch* c, int l) {
   const Tab& ts = c->tsweep[l];
   if (ts.n) kb_vanka_sweep<T><<<ts.blocks, VSWEEP_BS, 0, c->ks>>>(c->tab(ts), ts.n, c->dlev[l], c->done);
-  if (!c->vpp[l]) {  // the other boxes: residual and correction launches per class pass
-    for (int pass = 0; pass < 16; ++pass) {
-      const int k = vanka_pass_class(pass);
-      const Tab& t = c->tvanka[l][k];
-      const Tab& ta = c->tvapply[l][k];
+  if (!c->vpp[l]) {  // the other boxes: residual and correction launches per pair pass
+    for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
+      const int q = vanka_pair8(pass);
+      const Tab& t = c->tvanka[l][q];
+      const Tab& ta = c->tvapply[l][q];
       if (!t.n) continue;
-      kb_vanka_delta<T><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done, k, (T*)c->vdelta);
-      kb_vanka_apply<T><<<ta.blocks, BS, 0, c->ks>>>(c->tab(ta), ta.n, c->dlev[l], c->done, k,
+      kb_vanka_delta<T><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done, q, (T*)c->vdelta);
+      kb_vanka_apply<T><<<ta.blocks, BS, 0, c->ks>>>(c->tab(ta), ta.n, c->dlev[l], c->done, q,
                                                      (const T*)c->vdelta);
     }
     return;
   }
-  // or two copies of the state, one launch per class pass; 16 passes end in x
+  // or two copies of the state, one launch per pair pass; the 8 passes end in x
   const Tab& tb = c->tband[l];
   if (!tb.n) return;
   kb_vanka_band<T><<<tb.blocks, BS, 0, c->ks>>>(c->tab(tb), tb.n, c->dlev[l], c->done);
-  for (int pass = 0; pass < 16; ++pass) {
+  for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
     const Tab& t = c->tpp[l][pass];
     if (!t.n) continue;
-    kb_vanka_pp<T><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done, vanka_pass_class(pass),
-                                               vanka_pass_prev(pass), pass & 1);
+    kb_vanka_pp<T><<<t.blocks, BS, 0, c->ks>>>(c->tab(t), t.n, c->dlev[l], c->done, vanka_pair8(pass),
+                                               vanka_pair8_prev(pass), pass & 1);
   }
 }
 

@@ -27,9 +27,9 @@ struct BLev {
   void* bc;
   const void* kinv;        // Vanka inverses of this level
   void* alt;               // second copy of x for the two-copy Vanka passes (boxes not run in one workgroup)
-  const int* vc[8];        // V1 cells per colour
+  const int* vc[8];        // V1 cells per colour (classes q and 7-q back to back)
   int nv[8];
-  long voff[8];            // this domain's slice of the shared Vanka delta buffer, per colour
+  long voff[4];            // this domain's slice of the shared Vanka delta buffer, per class pair
   const double* cinv;      // coarsest level: dense inverse and its DOF slots
   const int* cdof;
   int nc;
@@ -181,58 +181,59 @@ __global__ __launch_bounds__(BS) void kb_prolong(const BEnt* __restrict__ tab, i
   prolong_pair_item<T>(lev[d].g, gc, (const T*)lev[d].xc, (T*)lev[d].x, 2 * X + 1, Jc, Kc);
 }
 
-// Vanka, one colour class of each domain: eight lanes per V1 cell for the
-// residuals (one thread per cell measured no faster on the batch's boxes)
-// and for the corrections
+// Vanka, one pair of colour classes of each domain (classes q and 7-q, one
+// list: vanka_pair8): eight lanes per V1 cell for the residuals (one thread
+// per cell measured no faster on the batch's boxes) and for the corrections
 template <typename T>
 __global__ __launch_bounds__(BS) void kb_vanka_delta(const BEnt* __restrict__ tab, int nent,
                                                      const BLev* __restrict__ lev, const int* __restrict__ done,
-                                                     int colour, T* __restrict__ delta) {
+                                                     int q, T* __restrict__ delta) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
-  vanka_delta8_item<T, T>(g, (const T*)lev[d].x, (const T*)lev[d].b, lev[d].vc[colour], lev[d].nv[colour],
-                         (const T*)lev[d].kinv, delta + lev[d].voff[colour], lb * BS + (int)threadIdx.x);
+  vanka_delta8_item<T, T>(g, (const T*)lev[d].x, (const T*)lev[d].b, lev[d].vc[q], lev[d].nv[q] + lev[d].nv[7 - q],
+                         (const T*)lev[d].kinv, delta + lev[d].voff[q], lb * BS + (int)threadIdx.x);
 }
 
 template <typename T>
 __global__ __launch_bounds__(BS) void kb_vanka_apply(const BEnt* __restrict__ tab, int nent,
                                                      const BLev* __restrict__ lev, const int* __restrict__ done,
-                                                     int colour, const T* __restrict__ delta) {
+                                                     int q, const T* __restrict__ delta) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
-  vanka_apply8_item<T>(g, (T*)lev[d].x, lev[d].vc[colour], lev[d].nv[colour], delta + lev[d].voff[colour],
+  vanka_apply8_item<T>(g, (T*)lev[d].x, lev[d].vc[q], lev[d].nv[q] + lev[d].nv[7 - q], delta + lev[d].voff[q],
                        lb * BS + (int)threadIdx.x);
 }
 
-// Two-copy Vanka pass of class k for every box (k_vanka_pp8; levels whose
+// Two-copy Vanka pass of pair q for every box (k_vanka_pp8; levels whose
 // classes, summed over the boxes, are small enough for the passes to be
-// latency chains): reads copy
-// `rd` (0: x, 1: alt), writes the other; lanes [0, copy0) take the class-k
-// cells eight lanes each (copy0 = 8 nv[k] rounded up to whole waves), the
-// rest copy the previous class kp's corrections (kp < 0: none).
+// latency chains): reads copy `rd` (0: x, 1: alt), writes the other; lanes
+// [0, copy0) take the pair's cells eight lanes each (copy0 = 8 cells rounded
+// up to whole waves), the rest copy the previous pair qp's corrections
+// (qp < 0: none).
 template <typename T>
 __global__ __launch_bounds__(BS) void kb_vanka_pp(const BEnt* __restrict__ tab, int nent, const BLev* __restrict__ lev,
-                                                  const int* __restrict__ done, int k, int kp, int rd) {
+                                                  const int* __restrict__ done, int q, int qp, int rd) {
   SG_BATCH_ENTRY();
   const Geom g = lev[d].g;
   const T* R = (const T*)(rd ? lev[d].alt : lev[d].x);
   T* W = (T*)(rd ? lev[d].x : lev[d].alt);
-  const int n = lev[d].nv[k];
+  const int n = lev[d].nv[q] + lev[d].nv[7 - q];
   const int copy0 = (8 * n + 63) / 64 * 64;
   const int t = lb * BS + (int)threadIdx.x;
   if (t < copy0) {
-    const T dv = vanka_delta8_lane<T, T>(g, R, (const T*)lev[d].b, lev[d].vc[k], n, (const T*)lev[d].kinv, t);
+    const T dv = vanka_delta8_lane<T, T>(g, R, (const T*)lev[d].b, lev[d].vc[q], n, (const T*)lev[d].kinv, t);
     const int c = t >> 3, r = t & 7;
     if (c < n && r < 7) {
-      const int s = lev[d].vc[k][c];
+      const int s = lev[d].vc[q][c];
       int I, J, K;
       slot_ijk(g, s, I, J, K);
       const VankaDof dof = vanka_dof(g, s, I, J, K, r);
       if (dof.active) W[dof.e] = R[dof.e] + dv;
     }
-  } else if (kp >= 0) {
+  } else if (qp >= 0) {
     const int u = t - copy0, c = u >> 3, r = u & 7;
-    if (c < lev[d].nv[kp] && r < 7) vanka_copy_dof<T>(g, R, W, lev[d].vc[kp][c], r, 1 << k);
+    if (c < lev[d].nv[qp] + lev[d].nv[7 - qp] && r < 7)
+      vanka_copy_dof<T>(g, R, W, lev[d].vc[qp][c], r, vanka_pair8_mask(q));
   }
 }
 

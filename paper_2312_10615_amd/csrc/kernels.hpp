@@ -492,52 +492,41 @@ __global__ __launch_bounds__(BS) void k_vanka_apply_xs(Geom g, T* x, T* xs, cons
 
 // ---------------------------------------------------------------------------
 // Multiplicative Vanka with two copies of the level's state (8 classes, levels
-// whose classes run as separate eight-lane passes).  Pass p reads copy R and writes copy
-// W: each active local unknown of a class-k cell becomes R + delta in W, so a
-// pass needs no separate correction launch.  W then lacks only the previous
-// pass's corrections (class kp), which the same launch copies over from R,
-// except where a class-k cell rewrites the unknown itself (a face shared with
-// a V1 cell of class k).  Same-class subdomains share no unknown and W is
-// never read, so every element of W has at most one writer and no launch
-// reads what it writes.  The values are those of the delta/apply passes, bit
-// for bit.  Before the first pass W is brought up to date on the boundary
-// band (k_vanka_band_copy); after the 16 passes the state is back in the
-// first copy.
+// whose passes run as eight-lane launches).  Pass p reads copy R and writes
+// copy W: each active local unknown of a cell of the pass becomes R + delta
+// in W, so a pass needs no separate correction launch.  W then lacks only the
+// previous pass's corrections, which the same launch copies over from R,
+// except where a cell of the pass rewrites the unknown itself (a face shared
+// with a V1 cell of one of the pass's classes).  The subdomains of one pass
+// share no unknown and W is never read, so every element of W has at most one
+// writer and no launch reads what it writes.  The values are those of the
+// delta/apply passes, bit for bit.  Before the first pass W is brought up to
+// date on the boundary band (k_vanka_band_copy); after the 8 passes the state
+// is back in the first copy.
 // ---------------------------------------------------------------------------
 
-// Symmetric order of the 8 classes (0..7, 7..0): the class of pass p, and the
-// class whose corrections pass p copies (none for the first pass and for the
-// second of the two class-7 passes, which rewrites all of its unknowns).
-__host__ __device__ inline int vanka_pass_class(int pass) { return pass < 8 ? pass : 15 - pass; }
-__host__ __device__ inline int vanka_pass_prev(int pass) {
-  return pass == 0 || pass == 8 ? -1 : vanka_pass_class(pass - 1);
+// Symmetric order of the 8 classes, taken as complementary pairs {q, 7-q}:
+// forward {0,7} {1,6} {2,5} {3,4}, then backward {3,4} {2,5} {1,6} {0,7}.
+// Complementary classes differ in all three parity bits, so their cells meet
+// only at edges and corners: a subdomain's local residuals read no unknown of
+// a subdomain of the other class (a face row reaches the faces of face
+// neighbours, a pressure row only its own cell's faces) and the two share
+// none.  A pair therefore runs as one pass with the values of its two classes
+// run one after the other, bit for bit: 8 passes for the 16 class steps.  The
+// class lists of a pair are stored one after the other, so a pass reads one
+// list.  vanka_pair8(p) is the pair (its lower class q) of pass p;
+// vanka_pair8_prev(p) the pair whose corrections pass p copies in the
+// two-copy passes: none for the first pass, nor for the second {3,4} pass,
+// which rewrites all of the unknowns the first one changed.
+constexpr int VANKA_PASSES8 = 8;
+__host__ __device__ inline int vanka_pair8(int pass) { return pass < 4 ? pass : 7 - pass; }
+__host__ __device__ inline int vanka_pair8_prev(int pass) {
+  return pass == 0 || pass == 4 ? -1 : vanka_pair8(pass - 1);
 }
+// bit mask of the two classes of pair q
+__host__ __device__ inline int vanka_pair8_mask(int q) { return (1 << q) | (1 << (7 - q)); }
 
-// The same order with the passes of classes 3 and 4 run as one pass (forward
-// 0 1 2 {3,4} 5 6 7, backward 7 6 5 {4,3} 2 1 0: 14 passes).  Classes 3 and 4
-// differ in all three parity bits, so their cells meet only at edges and
-// corners: a class-3 subdomain's local residuals read no unknown of a class-4
-// subdomain (the face stencils reach the faces of face neighbours, a pressure
-// row only its own cell's faces) and the two share none, so running them
-// together gives the values of running them one after the other, bit for
-// bit.  Returns the pass's first class (3 for the merged one); *merged says
-// whether class 4 comes with it.  The class lists of classes 3 and 4 are
-// stored one after the other, so the merged pass reads one list.
-constexpr int VANKA_PASSES8 = 14;
-__host__ __device__ inline int vanka_pass8(int pass, bool* merged) {
-  const int q = pass < 7 ? pass : pass - 7;
-  *merged = q == 3;
-  if (pass < 7) return q < 3 ? q : q == 3 ? 3 : q + 1;
-  return q < 3 ? 7 - q : q == 3 ? 3 : 6 - q;
-}
-// bit mask of the classes of a pass
-__host__ __device__ inline int vanka_pass8_mask(int pass) {
-  bool m;
-  const int k = vanka_pass8(pass, &m);
-  return m ? (1 << 3) | (1 << 4) : 1 << k;
-}
-
-// Copy unknown r of previous-class cell s from R to W unless a V1 cell of a
+// Copy unknown r of previous-pass cell s from R to W unless a V1 cell of a
 // class in the pass's mask kmask owns it too.
 template <typename T>
 __device__ __forceinline__ void vanka_copy_dof(const Geom& g, const T* __restrict__ R, T* __restrict__ W, int s,
@@ -552,8 +541,8 @@ __device__ __forceinline__ void vanka_copy_dof(const Geom& g, const T* __restric
   W[d.e] = R[d.e];
 }
 
-// Eight lanes per class-k cell (lanes [0, copy0), copy0 = 8 ncells rounded up
-// to whole waves), then eight lanes per previous-class cell.
+// Eight lanes per cell of the pass (lanes [0, copy0), copy0 = 8 ncells
+// rounded up to whole waves), then eight lanes per previous-pass cell.
 template <typename T, typename TB>
 __global__ __launch_bounds__(BS) void k_vanka_pp8(Geom g, const T* __restrict__ R, T* __restrict__ W,
                                                   const TB* __restrict__ b, const int* __restrict__ cells, int ncells,
@@ -690,43 +679,64 @@ __device__ __forceinline__ int vsweep_cell(const Lists& a, const int* __restrict
 // waiting in LDS, measured slower here: 93 against 71 us per step at 16^3.)
 static_assert(VSWEEP_MAX_CLASS <= VSWEEP_BS, "a thread per subdomain");
 
+// One barrier-separated step of the one-workgroup passes: the subdomains of
+// class ka (na cells) and of class kb (nb cells, none when nb = 0), a thread
+// each; every subdomain's new values are formed before the first barrier and
+// written after it.
+template <typename T, typename Lists>
+__device__ __forceinline__ void vsweep_step(const Geom& g, const Lists& a, const int* __restrict__ scell,
+                                            T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ sk,
+                                            int ka, int na, int kb, int nb) {
+  const int t = threadIdx.x;
+  const bool mine = t < na + nb;
+  T d[7], old[7];
+  int e[7];
+  bool act[7];
+  if (mine) {
+    const int s = t < na ? vsweep_cell(a, scell, ka, t) : vsweep_cell(a, scell, kb, t - na);
+    vanka_delta_vals<T, T>(g, x, b, s, sk, d);
+    int I, J, K;
+    slot_ijk(g, s, I, J, K);
+#pragma unroll
+    for (int r = 0; r < 7; ++r) {
+      const VankaDof v = vanka_dof(g, s, I, J, K, r);
+      e[r] = v.e;
+      act[r] = v.active;
+      old[r] = v.active ? x[v.e] : T(0);
+    }
+  }
+  __syncthreads();
+  if (mine) {
+#pragma unroll
+    for (int r = 0; r < 7; ++r)
+      if (act[r]) x[e[r]] = old[r] + d[r];
+  }
+  __syncthreads();
+}
+
+// 8 classes: the 8 pair passes (vanka_pair8), a pair in one step when a
+// thread each covers its cells, else its two classes one after the other
+// (the same values); 27 classes: 0..26 then 26..0.
 template <typename T, typename Lists>
 __device__ __forceinline__ void vanka_sweep_passes1(const Geom& g, const Lists& a, T* __restrict__ x,
                                                     const T* __restrict__ b, const T* __restrict__ sk,
                                                     int* __restrict__ scell) {
   vsweep_load_lists(a, scell);
-  const int t = threadIdx.x;
-  // 8 classes: classes 3 and 4 in one pass (vanka_pass8) when a thread each covers them
-  const bool m34 = a.nc == 8 && a.count(3) + a.count(4) <= (int)blockDim.x;
-  const int npass = m34 ? VANKA_PASSES8 : 2 * a.nc;
-  for (int pass = 0; pass < npass; ++pass) {
-    bool merged = false;
-    const int k = m34 ? vanka_pass8(pass, &merged) : pass < a.nc ? pass : 2 * a.nc - 1 - pass;
-    const int n3 = a.count(k);
-    const bool mine = t < n3 + (merged ? a.count(4) : 0);
-    T d[7], old[7];
-    int e[7];
-    bool act[7];
-    if (mine) {
-      const int s = t < n3 ? vsweep_cell(a, scell, k, t) : vsweep_cell(a, scell, 4, t - n3);
-      vanka_delta_vals<T, T>(g, x, b, s, sk, d);
-      int I, J, K;
-      slot_ijk(g, s, I, J, K);
-#pragma unroll
-      for (int r = 0; r < 7; ++r) {
-        const VankaDof v = vanka_dof(g, s, I, J, K, r);
-        e[r] = v.e;
-        act[r] = v.active;
-        old[r] = v.active ? x[v.e] : T(0);
+  if (a.nc == 8) {
+    for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
+      const int q = vanka_pair8(pass), nq = a.count(q), nr = a.count(7 - q);
+      if (nq + nr <= (int)blockDim.x) {
+        vsweep_step<T>(g, a, scell, x, b, sk, q, nq, 7 - q, nr);
+      } else {
+        vsweep_step<T>(g, a, scell, x, b, sk, q, nq, q, 0);
+        vsweep_step<T>(g, a, scell, x, b, sk, 7 - q, nr, 7 - q, 0);
       }
     }
-    __syncthreads();
-    if (mine) {
-#pragma unroll
-      for (int r = 0; r < 7; ++r)
-        if (act[r]) x[e[r]] = old[r] + d[r];
-    }
-    __syncthreads();
+    return;
+  }
+  for (int pass = 0; pass < 2 * a.nc; ++pass) {
+    const int k = pass < a.nc ? pass : 2 * a.nc - 1 - pass;
+    vsweep_step<T>(g, a, scell, x, b, sk, k, a.count(k), k, 0);
   }
 }
 
@@ -755,7 +765,7 @@ __global__ __launch_bounds__(VSWEEP_BS) void k_vanka_sweep(VSweep a, T* __restri
 
 // The multiplicative step of k_vanka_sweep on a level whose whole state fits
 // in LDS next to the inverses and the class lists (gfx950: 160 KB per
-// workgroup): the state is loaded once, the 16 class passes read and write
+// workgroup): the state is loaded once, the class passes read and write
 // it there, and it is written back at the end.  Same values.
 template <typename T>
 constexpr int vsweep_lds_elems() {

@@ -329,17 +329,17 @@ void carve(stokes_ctx* c, Carver& cv, int L) {
       long sum = 0;
       for (int k = 0; k < nc; ++k) {
         lv.nv[k] = (int)cells[k].size();
-        if (nc == 8 && k == 3)  // classes 3 and 4 back to back: their merged pass reads one list
-          lv.vcells[3] = cv.take<int>(std::max<size_t>(cells[3].size() + cells[4].size(), 1));
-        else if (nc == 8 && k == 4)
-          lv.vcells[4] = lv.vcells[3] ? lv.vcells[3] + lv.nv[3] : nullptr;
+        if (nc == 8 && k >= 4)  // classes k and 7-k back to back: their pair pass reads one list
+          lv.vcells[k] = lv.vcells[7 - k] ? lv.vcells[7 - k] + lv.nv[7 - k] : nullptr;
         else
-          lv.vcells[k] = cv.take<int>(std::max<size_t>(cells[k].size(), 1));
+          lv.vcells[k] =
+              cv.take<int>(std::max<size_t>(cells[k].size() + (nc == 8 ? cells[7 - k].size() : 0), 1));
         lv.doff[k] = p.vanka == STOKES_VANKA_ADDITIVE ? sum : 0;
         sum += 8L * lv.nv[k];
         vmax = std::max<long>(vmax, p.vanka == STOKES_VANKA_ADDITIVE ? sum / 8 : lv.nv[k]);
       }
-      if (nc == 8 && p.vanka != STOKES_VANKA_ADDITIVE) vmax = std::max<long>(vmax, (long)lv.nv[3] + lv.nv[4]);
+      if (nc == 8 && p.vanka != STOKES_VANKA_ADDITIVE)
+        for (int q = 0; q < 4; ++q) vmax = std::max<long>(vmax, (long)lv.nv[q] + lv.nv[7 - q]);
       // two-copy passes where a pass is a latency chain (eight lanes per subdomain);
       // on larger levels the passes are bound by bandwidth and the copies cost more
       lv.pp = p.vanka == STOKES_VANKA_MULT8 && !c->labelled && !vsweep_level(lv, nc);
@@ -391,17 +391,15 @@ void launch(stokes_ctx* c, int cls, int level, F f) {
   f();
 }
 
-// The cells of one multiplicative pass (8 classes, 14 passes: vanka_pass8),
-// and the class mask of the pass.
+// The cells of pair q (8 classes: classes q and 7-q, one list) and the class
+// mask of its pass.
 struct VPass {
   const int* cells;
   int n;
   int mask;
 };
-VPass vanka_pass_list(const Level& lv, int pass) {
-  bool merged;
-  const int k = vanka_pass8(pass, &merged);
-  return VPass{lv.vcells[k], merged ? lv.nv[3] + lv.nv[4] : lv.nv[k], vanka_pass8_mask(pass)};
+VPass vanka_pair_list(const Level& lv, int q) {
+  return VPass{lv.vcells[q], lv.nv[q] + lv.nv[7 - q], vanka_pair8_mask(q)};
 }
 
 // Residual pass over n cells; corrections to vd (delta[r * n + c]).
@@ -443,8 +441,9 @@ void vanka_correct(stokes_ctx* c, int l, T* x, int k) {
 }
 
 // One application of the V1 smoother in a Vanka slot of Alg. 3: symmetric
-// multiplicative Vanka (classes forward then backward; each class from the
-// state at its start), or additive Vanka (Eq. av: every class from the same
+// multiplicative Vanka (classes forward then backward, 8 classes as the
+// complementary pairs of vanka_pair8; each pass from the state at its start),
+// or additive Vanka (Eq. av: every class from the same
 // state, the corrections then added class by class in a fixed order).
 template <typename T>
 void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_IN, bool xout = true) {
@@ -474,7 +473,7 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
     for (int k = 0; k < nc; ++k) vanka_correct<T>(c, l, x, k);
     return;
   }
-  if (lv.pp) {  // two copies of the state; the 14 passes end in x
+  if (lv.pp) {  // two copies of the state; the 8 passes end in x
     const Geom g = lv.g;
     T* X[2] = {x, (T*)lv.alt};
     T* alt = X[1];
@@ -487,11 +486,11 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
     }
     const T* kinv = (const T*)lv.kinv;
     for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
-      const VPass cur = vanka_pass_list(lv, pass);
-      // the previous pass's corrections to copy: none before the first pass,
-      // nor before the second class-7 pass, which rewrites all of its unknowns
-      const bool fresh = pass == 0 || pass == VANKA_PASSES8 / 2;
-      const VPass prv = fresh ? VPass{cur.cells, 0, 0} : vanka_pass_list(lv, pass - 1);
+      const VPass cur = vanka_pair_list(lv, vanka_pair8(pass));
+      // the previous pass's corrections to copy (none for the first pass and
+      // for the second {3,4} pass)
+      const int qp = vanka_pair8_prev(pass);
+      const VPass prv = qp < 0 ? VPass{cur.cells, 0, 0} : vanka_pair_list(lv, qp);
       const int n = cur.n, np = prv.n, kmask = cur.mask;
       const int* cells = cur.cells;
       const int* prev = prv.cells;
@@ -514,7 +513,7 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
     if (xin != XS_OUT)  // XS_OUT as the way in: the slab is current
       launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_xslab_copy<T><<<nbc, BS, 0, c->ks>>>(g, x, xs, xin); });
     for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
-      const VPass cur = vanka_pass_list(lv, pass);
+      const VPass cur = vanka_pair_list(lv, vanka_pair8(pass));
       const int n = cur.n;
       if (n == 0) continue;
       const int* cells = cur.cells;
@@ -530,7 +529,7 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
   }
   if (nc == 8) {
     for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
-      const VPass cur = vanka_pass_list(lv, pass);
+      const VPass cur = vanka_pair_list(lv, vanka_pair8(pass));
       vanka_delta_list<T>(c, l, x, b, cur.cells, cur.n, (T*)c->vdelta);
       vanka_correct_list<T>(c, l, x, cur.cells, cur.n, (const T*)c->vdelta);
     }

@@ -71,20 +71,20 @@ def _iterations(n, coarse_net, seeds):
     return zero, warm
 
 
-# Over 200 held-out seeds (profiles/warmstart_eval.md) the guess saves 1.02
-# iterations on average at 128^3 and is never worse; at 256^3, from the 128^3
-# level, 0.92, and one iteration worse on 2 seeds of 200.  The seeds are fixed
+# Over 200 held-out seeds (profiles/warmstart_eval.md) the guess saves 0.86
+# iterations on average at 128^3, and is one iteration worse on 7 seeds of
+# 200; at 256^3, from the 128^3 level, 0.94, never worse.  The seeds are fixed
 # and the solver deterministic, so these are regression bars on the first
-# eight held-out seeds (observed: 5 iterations fewer at either size).
+# eight held-out seeds (observed: 6 iterations fewer at 128^3, 5 at 256^3).
 def test_fewer_iterations_at_128_with_the_guess():
     announce("warm start 128^3: iterations and time vs zero guess")
     zero, warm = _iterations(128, False, 8)
-    assert all(w <= z for z, w in zip(zero, warm))
+    assert all(w <= z + 1 for z, w in zip(zero, warm))
     assert sum(zero) - sum(warm) >= 4
 
 
 def test_fewer_iterations_at_256_with_the_guess_from_128():
     announce("warm start 256^3 (network on the 128^3 level): iterations and time vs zero guess")
     zero, warm = _iterations(256, True, 8)
-    assert all(w <= z + 1 for z, w in zip(zero, warm))
+    assert all(w <= z for z, w in zip(zero, warm))
     assert sum(zero) - sum(warm) >= 3

@@ -8,9 +8,9 @@ import scipy.sparse.linalg as spla
 from oracle.domain import Domain, box_labels
 from oracle.multigrid import Hierarchy, postsmooth, presmooth, vcycle
 from oracle.operator import apply_operator, assemble, from_vector, residual, to_vector
-from oracle.smoother import (collect, dgs_diagonals, dgs_forward, dgs_reverse, dgs_symmetric,
-                             distribute, smooth, vanka_color, vanka_local_matrix, vanka_slots,
-                             vanka_symmetric)
+from oracle.smoother import (VANKA_ORDER8, collect, dgs_diagonals, dgs_forward, dgs_reverse, dgs_symmetric,
+                             distribute, smooth, vanka_cells_step, vanka_color, vanka_local_matrix,
+                             vanka_slots, vanka_symmetric)
 from oracle.sqmr import mg_sqmr, remove_pressure_mean, sqmr
 from oracle.transfer import prolong, restrict
 from paper_2312_10615_amd.workloads import mms_fields, random_state, sinusoid_forcing
@@ -319,6 +319,50 @@ def test_single_subdomain_solve_zeroes_its_local_residual():
     for s in range(7):
         if act[0, s]:
             assert abs(r[fields[s]][tuple(ix[0] for ix in idx[s])]) <= 1e-10 * np.abs(b[fields[s]]).max()
+
+
+def test_complementary_vanka_classes_commute_and_equal_one_step_over_both():
+    """Cells of complementary classes (all three parity bits differ) meet
+    only at edges and corners: their subdomains share no unknown and read none
+    of each other's, so the two classes in either order equal one step over the
+    cells of both, bit for bit (what lets a pair run as one pass).  Classes one
+    bit apart are face neighbours and do not commute (the control)."""
+    dom = dom_of((6, 6, 6))
+    b, x = rand_state(dom, 11), rand_state(dom, 12)
+    col = dom.vanka_colour()
+    for q in range(4):
+        both = np.argwhere(dom.v1[3] & ((col == q) | (col == 7 - q)))
+        one = vanka_cells_step(dom, x, b, both)
+        ab = vanka_color(dom, vanka_color(dom, x, b, q), b, 7 - q)
+        ba = vanka_color(dom, vanka_color(dom, x, b, 7 - q), b, q)
+        for u, v, w in zip(one, ab, ba):
+            assert np.array_equal(u, v) and np.array_equal(u, w)
+    ab = vanka_color(dom, vanka_color(dom, x, b, 0), b, 1)
+    ba = vanka_color(dom, vanka_color(dom, x, b, 1), b, 0)
+    assert max(float(np.abs(u - v).max()) for u, v in zip(ab, ba)) > 1e-3
+
+
+def test_symmetric_vanka_takes_the_classes_in_complementary_pairs():
+    """The symmetric step is the classes forward then backward (Section 3.2),
+    each class followed by its complement.  On 2x2x2 cells every class is one
+    subdomain, so the step is Eq. mv's product over the subdomains in that
+    order, checked with one-subdomain steps; the order 0..7 gives another
+    result (the check has teeth)."""
+    assert VANKA_ORDER8 == (0, 7, 1, 6, 2, 5, 3, 4)
+    dom = dom_of((2, 2, 2))
+    b, x = rand_state(dom, 13), rand_state(dom, 14)
+    col = dom.vanka_colour()
+
+    def sequence(order):
+        y = x
+        for k in list(order) + list(order)[::-1]:
+            y = vanka_cells_step(dom, y, b, np.argwhere(col == k))
+        return y
+
+    got, want, other = vanka_symmetric(dom, x, b), sequence(VANKA_ORDER8), sequence(range(8))
+    scale = max(float(np.abs(v).max()) for v in want)
+    assert max(float(np.abs(u - v).max()) for u, v in zip(got, want)) <= 1e-13 * scale
+    assert max(float(np.abs(u - v).max()) for u, v in zip(got, other)) > 1e-6 * scale
 
 
 # --- Symmetry theorems (Appendices A, C, D) and the V-cycle -----------------
