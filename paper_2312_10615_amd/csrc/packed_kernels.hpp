@@ -627,13 +627,16 @@ static_assert(RR_TX * RR_TY == BS, "one coarse column per thread");
 __host__ __device__ inline long rr_plane(const Geom& f, const Geom& c) { return (long)(c.ny + 2) * c.sy; }
 __host__ __device__ inline long rr_elems(const Geom& f, const Geom& c) { return 4L * (f.nz + 2) * rr_plane(f, c); }
 
+// Tiles cover the coarse columns I = 1..nx, J = 1..ny (the ghost columns have
+// no unknown, and k_restrict_z writes 0 there without reading S), so a tile's
+// fine window starts at the lattice's first slot: for sides that are
+// multiples of 32 no window is clipped.
 // Workgroups: XCD x (blockIdx % NXCD) takes a run of consecutive fine planes
 // and goes through it strip by strip (a row of tiles), plane by plane, tile by
 // tile, so that the lines two neighbouring tiles share and the planes below
 // and above a stencil are read by the same XCD close in time (one L2).
-// Returns false for the padding blocks past the last plane or strip.
-__host__ __device__ inline int rr_cols_x(const Geom& c) { return (c.sy + RR_TX - 1) / RR_TX; }
-__host__ __device__ inline int rr_cols_y(const Geom& c) { return (c.ny + 2 + RR_TY - 1) / RR_TY; }
+__host__ __device__ inline int rr_cols_x(const Geom& c) { return (c.nx + RR_TX - 1) / RR_TX; }
+__host__ __device__ inline int rr_cols_y(const Geom& c) { return (c.ny + RR_TY - 1) / RR_TY; }
 __host__ __device__ inline int rr_run(const Geom& f) { return (f.nz + 2 + NXCD - 1) / NXCD; }
 __host__ __device__ inline long rr_blocks(const Geom& f, const Geom& c) {
   return (long)NXCD * rr_cols_x(c) * rr_cols_y(c) * rr_run(f);
@@ -648,7 +651,7 @@ __global__ __launch_bounds__(BS) void k_resid_restrict_xy(Geom f, Geom c, const 
   const int xt = l % cx, rest = l / cx;
   const int Kf = (blockIdx.x % NXCD) * run + rest % run, yt = rest / run;
   if (Kf > f.nz + 1 || yt >= rr_cols_y(c)) return;
-  const int I0 = xt * RR_TX, J0 = yt * RR_TY;
+  const int I0 = 1 + xt * RR_TX, J0 = 1 + yt * RR_TY;
   const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
   // the fine window clipped to the lattice; the rest of it holds 0
   const int ilo = max(fi0, 0), ihi = min(fi0 + RR_WX, f.nx + 2);
@@ -684,7 +687,7 @@ __global__ __launch_bounds__(BS) void k_resid_restrict_xy(Geom f, Geom c, const 
   __syncthreads();
   const int tI = threadIdx.x % RR_TX, tJ = threadIdx.x / RR_TX;
   const int I = I0 + tI, J = J0 + tJ;
-  if (I >= c.sy || J >= c.ny + 2) return;
+  if (I > c.nx || J > c.ny) return;
   const T wc[4] = {T(0.25), T(0.75), T(0.75), T(0.25)};
   const T wf[3] = {T(0.5), T(1), T(0.5)};
   const int li = 2 * tI, lj = 2 * tJ;  // window position of fine 2I-2, 2J-2
@@ -712,11 +715,17 @@ __global__ __launch_bounds__(BS) void k_resid_restrict_xy(Geom f, Geom c, const 
 
 // One thread per coarse slot (slab mapping).  Coarse plane K takes fine planes
 // 2K-2 .. 2K+1 (u_x, u_y: 1/4, 3/4, 3/4, 1/4), 2K-2 .. 2K (u_z: 1/2, 1, 1/2),
-// 2K-1 .. 2K (p: 1, 1); planes outside the lattice add nothing.
+// 2K-1 .. 2K (p: 1, 1); planes outside the lattice add nothing.  Ghost slots
+// (no unknown; S holds nothing for their columns) get 0.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_restrict_z(Geom f, Geom c, const T* __restrict__ S, T* __restrict__ bc) {
   int I, J, K;
   if (!slab_item(c, c.sy, I, J, K)) return;
+  const int s = c.at(c.idx(I, J, K)), Fc = c.field;
+  if (I < 1 || I > c.nx || J < 1 || J > c.ny || K < 1 || K > c.nz) {
+    bc[s] = bc[Fc + s] = bc[2 * Fc + s] = bc[3 * Fc + s] = T(0);
+    return;
+  }
   const T wc[4] = {T(0.25), T(0.75), T(0.75), T(0.25)};
   const T wf[3] = {T(0.5), T(1), T(0.5)};
   const long pl = rr_plane(f, c), comp = (long)(f.nz + 2) * pl;
@@ -732,7 +741,6 @@ __global__ __launch_bounds__(BS) void k_restrict_z(Geom f, Geom c, const T* __re
     if (kk < 3) a2 += wf[kk] * S[2 * comp + e];
     if (kk == 1 || kk == 2) a3 += S[3 * comp + e];
   }
-  const int s = c.at(c.idx(I, J, K)), Fc = c.field;
   bc[s] = c.ux_active(I, J, K) ? a0 * T(0.125) : T(0);
   bc[Fc + s] = c.uy_active(I, J, K) ? a1 * T(0.125) : T(0);
   bc[2 * Fc + s] = c.uz_active(I, J, K) ? a2 * T(0.125) : T(0);
