@@ -627,16 +627,19 @@ static_assert(RR_TX * RR_TY == BS, "one coarse column per thread");
 __host__ __device__ inline long rr_plane(const Geom& f, const Geom& c) { return (long)(c.ny + 2) * c.sy; }
 __host__ __device__ inline long rr_elems(const Geom& f, const Geom& c) { return 4L * (f.nz + 2) * rr_plane(f, c); }
 
-// Tiles cover the coarse columns I = 1..nx, J = 1..ny (the ghost columns have
-// no unknown, and k_restrict_z writes 0 there without reading S), so a tile's
-// fine window starts at the lattice's first slot: for sides that are
-// multiples of 32 no window is clipped.
+// Tiles cover the coarse columns I = 1..nx+e, J = 1..ny+e, e = 1 on a
+// labelled domain (whose faces with an exterior ghost cell, at I = nx+1 and so
+// on, are unknowns) and 0 on a box (the other ghost columns have no unknown,
+// and k_restrict_z writes 0 there without reading S), so a tile's fine window
+// starts at the lattice's first slot: for box sides that are multiples of 32
+// no window is clipped.
 // Workgroups: XCD x (blockIdx % NXCD) takes a run of consecutive fine planes
 // and goes through it strip by strip (a row of tiles), plane by plane, tile by
 // tile, so that the lines two neighbouring tiles share and the planes below
 // and above a stencil are read by the same XCD close in time (one L2).
-__host__ __device__ inline int rr_cols_x(const Geom& c) { return (c.nx + RR_TX - 1) / RR_TX; }
-__host__ __device__ inline int rr_cols_y(const Geom& c) { return (c.ny + RR_TY - 1) / RR_TY; }
+__host__ __device__ inline int rr_ext(const Geom& c) { return c.flags ? 1 : 0; }
+__host__ __device__ inline int rr_cols_x(const Geom& c) { return (c.nx + rr_ext(c) + RR_TX - 1) / RR_TX; }
+__host__ __device__ inline int rr_cols_y(const Geom& c) { return (c.ny + rr_ext(c) + RR_TY - 1) / RR_TY; }
 __host__ __device__ inline int rr_run(const Geom& f) { return (f.nz + 2 + NXCD - 1) / NXCD; }
 __host__ __device__ inline long rr_blocks(const Geom& f, const Geom& c) {
   return (long)NXCD * rr_cols_x(c) * rr_cols_y(c) * rr_run(f);
@@ -687,7 +690,7 @@ __global__ __launch_bounds__(BS) void k_resid_restrict_xy(Geom f, Geom c, const 
   __syncthreads();
   const int tI = threadIdx.x % RR_TX, tJ = threadIdx.x / RR_TX;
   const int I = I0 + tI, J = J0 + tJ;
-  if (I > c.nx || J > c.ny) return;
+  if (I > c.nx + rr_ext(c) || J > c.ny + rr_ext(c)) return;
   const T wc[4] = {T(0.25), T(0.75), T(0.75), T(0.25)};
   const T wf[3] = {T(0.5), T(1), T(0.5)};
   const int li = 2 * tI, lj = 2 * tJ;  // window position of fine 2I-2, 2J-2
@@ -715,14 +718,16 @@ __global__ __launch_bounds__(BS) void k_resid_restrict_xy(Geom f, Geom c, const 
 
 // One thread per coarse slot (slab mapping).  Coarse plane K takes fine planes
 // 2K-2 .. 2K+1 (u_x, u_y: 1/4, 3/4, 3/4, 1/4), 2K-2 .. 2K (u_z: 1/2, 1, 1/2),
-// 2K-1 .. 2K (p: 1, 1); planes outside the lattice add nothing.  Ghost slots
-// (no unknown; S holds nothing for their columns) get 0.
+// 2K-1 .. 2K (p: 1, 1); planes outside the lattice add nothing.  Slots
+// outside the columns and planes k_resid_restrict_xy covers (no unknown; S
+// holds nothing for their columns) get 0.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_restrict_z(Geom f, Geom c, const T* __restrict__ S, T* __restrict__ bc) {
   int I, J, K;
   if (!slab_item(c, c.sy, I, J, K)) return;
   const int s = c.at(c.idx(I, J, K)), Fc = c.field;
-  if (I < 1 || I > c.nx || J < 1 || J > c.ny || K < 1 || K > c.nz) {
+  const int e = rr_ext(c);
+  if (I < 1 || I > c.nx + e || J < 1 || J > c.ny + e || K < 1 || K > c.nz + e) {
     bc[s] = bc[Fc + s] = bc[2 * Fc + s] = bc[3 * Fc + s] = T(0);
     return;
   }
