@@ -79,8 +79,9 @@ def vcycle_model_bytes(n, s=S, levels=7):
     model: each dependent colour half-sweep streams its operands once).  Per
     level: two symmetric DGS (forward + reverse sweep, (16 n_u + 14 n_p) s
     each), four symmetric Vanka steps (~114 values per V1 cell each: 16 class
-    passes x 1/8 of the cells x ~57 values), residual + restriction and
-    prolongation + correction ((2 n + n/8) s each); the coarsest level's dense
+    steps, run as 8 passes of two classes, x 1/8 of the cells x ~57 values),
+    residual + restriction and prolongation + correction ((2 n + n/8) s
+    each); the coarsest level's dense
     solve reads its inverse once (8-byte values).  With 4-byte level values
     (the FP32 V-cycle) the conversions of s to FP32 and of the result back to
     FP64 add (8 + 4) bytes per unknown each."""
