@@ -407,6 +407,52 @@ __global__ __launch_bounds__(BS) void k_dgs_pr_v(Geom g, T* __restrict__ x, cons
 }
 
 // ---------------------------------------------------------------------------
+// A DGS sweep of a small level in one workgroup: each launch of the sweep
+// (a velocity colour, a pressure launch or stage) becomes one pass over the
+// level's packs, with a workgroup barrier in place of the launch boundary.
+// The packs and their arithmetic are the launches', so the values are the
+// same bit for bit.  On a level of a few thousand packs a pass costs the
+// workgroup a memory round trip or two, where a graph-replayed launch costs
+// several microseconds.
+// ---------------------------------------------------------------------------
+constexpr int DSWEEP_BS = 1024;
+constexpr int DSWEEP_MAX_PACKS = 4096;  // packs of one pass a level may have to run this way
+
+template <int V>
+__host__ __device__ inline int dgs_small_packs(const Geom& g) {
+  return pack_per_row<V>(g) * (g.ny + 2) * (g.nz + 2);
+}
+
+// dir 0: the forward sweep (velocities red, black; pressure launches t = 0..4
+// as k_dgs_pf_v); dir 1: the reverse sweep (pressure stages 3..0; velocities
+// black, red).
+template <typename T, typename TB, int V>
+__global__ __launch_bounds__(DSWEEP_BS) void k_dgs_small(Geom g, T* __restrict__ x, const TB* __restrict__ b,
+                                                         T* __restrict__ dscr, int dir) {
+  const int ppr = pack_per_row<V>(g), ry = g.ny + 2;
+  const int n = dgs_small_packs<V>(g);
+  auto pass = [&](int par, auto&& body) {
+    for (int l = threadIdx.x; l < n; l += DSWEEP_BS) {
+      const int r = l / ppr;
+      RowPack<V> rp;
+      if (row_pack_at<V>(g, par, l - r * ppr, r % ry, r / ry, rp)) body(rp);
+    }
+    __syncthreads();
+  };
+  if (dir == 0) {
+    for (int col = 0; col < 2; ++col)
+      pass(col ^ 1, [&](const RowPack<V>& rp) { dgs_u_pack<T, TB, V>(g, x, b, rp); });
+    for (int t = 0; t <= 4; ++t)
+      pass((t & 1) ^ 1, [&](const RowPack<V>& rp) { dgs_pf_stage_pack<T, TB, V>(g, x, b, dscr, rp, t); });
+  } else {
+    for (int st = 3; st >= 0; --st)
+      pass((st & 1) ^ 1, [&](const RowPack<V>& rp) { dgs_pr_stage_pack<T, TB, V>(g, x, b, rp, st); });
+    for (int col = 1; col >= 0; --col)
+      pass(col ^ 1, [&](const RowPack<V>& rp) { dgs_u_pack<T, TB, V>(g, x, b, rp); });
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The operator passes (the ApplyMode modes) with V slots per thread.  A thread
 // takes V consecutive slots of one parity in one row, every row and both
 // parities (ghost slots included: y gets 0 there).  The four rows are four

@@ -551,6 +551,10 @@ void dgs_forward(stokes_ctx* c, int l, T* x, const T* b) {
   constexpr int V = dgs_pack<T>();
   const Geom g = c->lev[l].g;
   T* dscr = (T*)c->lev[l].dscr;
+  if (dgs_small_packs<V>(g) <= DSWEEP_MAX_PACKS) {  // small level: the sweep in one workgroup
+    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_small<T, T, V><<<1, DSWEEP_BS, 0, c->ks>>>(g, x, b, dscr, 0); });
+    return;
+  }
   const int hg = dgs_grid<T>(g);
   for (int col = 0; col < 2; ++col)
     launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_u_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, col); });
@@ -565,6 +569,11 @@ template <typename T>
 void dgs_reverse(stokes_ctx* c, int l, T* x, const T* b) {
   constexpr int V = dgs_pack<T>();
   const Geom g = c->lev[l].g;
+  if (dgs_small_packs<V>(g) <= DSWEEP_MAX_PACKS) {  // small level: the sweep in one workgroup
+    T* dscr = (T*)c->lev[l].dscr;
+    launch(c, STOKES_KC_DGS_U, l, [=] { k_dgs_small<T, T, V><<<1, DSWEEP_BS, 0, c->ks>>>(g, x, b, dscr, 1); });
+    return;
+  }
   const int hg = dgs_grid<T>(g);
   for (int st = 3; st >= 0; --st)
     launch(c, STOKES_KC_DGS_PR, l, [=] { k_dgs_pr_v<T, T, V><<<hg, BS, 0, c->ks>>>(g, x, b, st); });
