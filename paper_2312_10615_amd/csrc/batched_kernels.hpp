@@ -237,7 +237,7 @@ __global__ __launch_bounds__(BS) void kb_vanka_pp(const BEnt* __restrict__ tab, 
   }
 }
 
-// alt = x on the boundary band of every box (k_vanka_band_copy), or on the
+// alt = x on the boundary band of every box (vanka_band_copy_item), or on the
 // whole state of a box with a side below 8
 template <typename T>
 __global__ __launch_bounds__(BS) void kb_vanka_band(const BEnt* __restrict__ tab, int nent, const BLev* __restrict__ lev,

@@ -500,8 +500,8 @@ __global__ __launch_bounds__(BS) void k_vanka_apply_xs(Geom g, T* x, T* xs, cons
 // with a V1 cell of one of the pass's classes).  The subdomains of one pass
 // share no unknown and W is never read, so every element of W has at most one
 // writer and no launch reads what it writes.  The values are those of the
-// delta/apply passes, bit for bit.  Before the first pass W is brought up to
-// date on the boundary band (k_vanka_band_copy); after the 8 passes the state
+// delta/apply passes, bit for bit.  The first pass also brings W up to date
+// on the boundary band (vanka_band_copy_item); after the 8 passes the state
 // is back in the first copy.
 // ---------------------------------------------------------------------------
 
@@ -526,63 +526,24 @@ __host__ __device__ inline int vanka_pair8_prev(int pass) {
 // bit mask of the two classes of pair q
 __host__ __device__ inline int vanka_pair8_mask(int q) { return (1 << q) | (1 << (7 - q)); }
 
-// Copy unknown r of previous-pass cell s from R to W unless a V1 cell of a
-// class in the pass's mask kmask owns it too.
-template <typename T>
-__device__ __forceinline__ void vanka_copy_dof(const Geom& g, const T* __restrict__ R, T* __restrict__ W, int s,
-                                               int r, int kmask) {
-  int I, J, K;
-  slot_ijk(g, s, I, J, K);
-  const VankaDof d = vanka_dof(g, s, I, J, K, r);
-  if (!d.active) return;
-  if (r < 6 && g.p_active(d.nI, d.nJ, d.nK) && !g.p_v2(d.nI, d.nJ, d.nK) &&
-      ((kmask >> Geom::vanka_colour(d.nI, d.nJ, d.nK)) & 1))
-    return;
-  W[d.e] = R[d.e];
-}
-
-// Eight lanes per cell of the pass (lanes [0, copy0), copy0 = 8 ncells
-// rounded up to whole waves), then eight lanes per previous-pass cell.
-template <typename T, typename TB>
-__global__ __launch_bounds__(BS) void k_vanka_pp8(Geom g, const T* __restrict__ R, T* __restrict__ W,
-                                                  const TB* __restrict__ b, const int* __restrict__ cells, int ncells,
-                                                  const T* __restrict__ kinv, const int* __restrict__ prev, int nprev,
-                                                  int kmask, int copy0) {
-  const int t = blockIdx.x * BS + threadIdx.x;
-  if (t < copy0) {  // whole waves: the shuffles see only this part's lanes
-    const int c = t >> 3, r = t & 7;
-    const bool valid = c < ncells;
-    const int s = valid ? cells[c] : 0;
-    int I = 1, J = 1, K = 1;
-    if (valid) slot_ijk(g, s, I, J, K);
-    // loads that need only the cell go out before the residual and its shuffles:
-    // this lane's row of the local inverse and the value it corrects
-    const T* km = kinv + g.vtype(I, J, K, g.vface_bits(I, J, K)) * 64 + r * 8;
-    T kr[7];
-#pragma unroll
-    for (int j = 0; j < 7; ++j) kr[j] = km[j];
-    const VankaDof dof = vanka_dof(g, s, I, J, K, r < 7 ? r : 6);
-    const bool wr = valid && r < 7 && dof.active;
-    const T old = wr ? R[dof.e] : T(0);
-    const T res = vanka_row_residual<T, TB>(g, R, b, s, I, J, K, r, valid);
-    const int base = (int)(threadIdx.x & 63) & ~7;
-    T acc = T(0);
-#pragma unroll
-    for (int j = 0; j < 7; ++j) {
-      const T rj = __shfl(res, base + j, 64);
-      acc += kr[j] * rj;
-    }
-    if (wr) W[dof.e] = old + acc;
-  } else {
-    const int u = t - copy0, c = u >> 3, r = u & 7;
-    if (c < nprev && r < 7) vanka_copy_dof<T>(g, R, W, prev[c], r, kmask);
-  }
+// Whether unknown f of slot (I, J, K) is an active unknown of a V1 cell of a
+// class in kmask: a pressure of its own cell, a face of either cell beside it
+// (the minus face of (I, J, K) and the plus face of the cell before it).
+__device__ __forceinline__ bool vanka_owned(const Geom& g, int f, int I, int J, int K, int kmask) {
+  auto v1 = [&](int i, int j, int k) {
+    return i >= 0 && j >= 0 && k >= 0 && g.p_active(i, j, k) && !g.p_v2(i, j, k) &&
+           ((kmask >> Geom::vanka_colour(i, j, k)) & 1);
+  };
+  if (f == 3) return v1(I, J, K);
+  const bool act = f == 0 ? g.ux_active(I, J, K) : f == 1 ? g.uy_active(I, J, K) : g.uz_active(I, J, K);
+  return act && (v1(I, J, K) || v1(I - (f == 0), J - (f == 1), K - (f == 2)));
 }
 
 // W = R on every slot within four cells of the boundary (padded I <= 3 or
 // I >= nx-2, and so on): every value a V1 cell's local residuals read, and
 // every unknown a Vanka pass writes.  Needs nx, ny, nz >= 8 (else copy the
-// whole state).  Threads: first the full rows (planes K <= 3 or K >= nz-2,
+// whole state).  With kmask, the unknowns of the V1 cells of those classes
+// are left out (the first pass of a step writes them in the same launch).  Threads: first the full rows (planes K <= 3 or K >= nz-2,
 // then rows J <= 3 or J >= ny-2 of the other planes), nx+2 slots each; then
 // the eight band slots of every remaining row.
 __host__ __device__ inline long vanka_band_slots(const Geom& g) {
@@ -591,7 +552,8 @@ __host__ __device__ inline long vanka_band_slots(const Geom& g) {
 }
 
 template <typename T>
-__device__ __forceinline__ void vanka_band_copy_item(const Geom& g, const T* __restrict__ R, T* __restrict__ W, long t) {
+__device__ __forceinline__ void vanka_band_copy_item(const Geom& g, const T* __restrict__ R, T* __restrict__ W, long t,
+                                                     int kmask = 0) {
   const long full = 8L * (g.ny + 2) + 8L * (g.nz - 6);
   const long nA = full * (g.nx + 2);
   int I, J, K;
@@ -618,12 +580,67 @@ __device__ __forceinline__ void vanka_band_copy_item(const Geom& g, const T* __r
   }
   const int e = g.at(g.idx(I, J, K));
 #pragma unroll
-  for (int f = 0; f < 4; ++f) W[f * g.field + e] = R[f * g.field + e];
+  for (int f = 0; f < 4; ++f)
+    if (!kmask || !vanka_owned(g, f, I, J, K, kmask)) W[f * g.field + e] = R[f * g.field + e];
 }
 
+
+// Copy unknown r of previous-pass cell s from R to W unless a V1 cell of a
+// class in the pass's mask kmask owns it too.
 template <typename T>
-__global__ __launch_bounds__(BS) void k_vanka_band_copy(Geom g, const T* __restrict__ R, T* __restrict__ W) {
-  vanka_band_copy_item<T>(g, R, W, (long)blockIdx.x * BS + threadIdx.x);
+__device__ __forceinline__ void vanka_copy_dof(const Geom& g, const T* __restrict__ R, T* __restrict__ W, int s,
+                                               int r, int kmask) {
+  int I, J, K;
+  slot_ijk(g, s, I, J, K);
+  const VankaDof d = vanka_dof(g, s, I, J, K, r);
+  if (!d.active) return;
+  if (r < 6 && g.p_active(d.nI, d.nJ, d.nK) && !g.p_v2(d.nI, d.nJ, d.nK) &&
+      ((kmask >> Geom::vanka_colour(d.nI, d.nJ, d.nK)) & 1))
+    return;
+  W[d.e] = R[d.e];
+}
+
+// Eight lanes per cell of the pass (lanes [0, copy0), copy0 = 8 ncells
+// rounded up to whole waves), then eight lanes per previous-pass cell, then
+// (the first pass of a step: nband > 0, no previous pass) one lane per slot
+// of the boundary band, which brings W up to date there except on the
+// unknowns this pass writes (vanka_band_copy_item in the same launch).
+template <typename T, typename TB>
+__global__ __launch_bounds__(BS) void k_vanka_pp8(Geom g, const T* __restrict__ R, T* __restrict__ W,
+                                                  const TB* __restrict__ b, const int* __restrict__ cells, int ncells,
+                                                  const T* __restrict__ kinv, const int* __restrict__ prev, int nprev,
+                                                  int kmask, int copy0, int nband) {
+  const int t = blockIdx.x * BS + threadIdx.x;
+  if (t < copy0) {  // whole waves: the shuffles see only this part's lanes
+    const int c = t >> 3, r = t & 7;
+    const bool valid = c < ncells;
+    const int s = valid ? cells[c] : 0;
+    int I = 1, J = 1, K = 1;
+    if (valid) slot_ijk(g, s, I, J, K);
+    // loads that need only the cell go out before the residual and its shuffles:
+    // this lane's row of the local inverse and the value it corrects
+    const T* km = kinv + g.vtype(I, J, K, g.vface_bits(I, J, K)) * 64 + r * 8;
+    T kr[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) kr[j] = km[j];
+    const VankaDof dof = vanka_dof(g, s, I, J, K, r < 7 ? r : 6);
+    const bool wr = valid && r < 7 && dof.active;
+    const T old = wr ? R[dof.e] : T(0);
+    const T res = vanka_row_residual<T, TB>(g, R, b, s, I, J, K, r, valid);
+    const int base = (int)(threadIdx.x & 63) & ~7;
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      const T rj = __shfl(res, base + j, 64);
+      acc += kr[j] * rj;
+    }
+    if (wr) W[dof.e] = old + acc;
+  } else if (t < copy0 + 8 * nprev) {
+    const int u = t - copy0, c = u >> 3, r = u & 7;
+    if (r < 7) vanka_copy_dof<T>(g, R, W, prev[c], r, kmask);
+  } else if (t < copy0 + 8 * nprev + nband) {
+    vanka_band_copy_item<T>(g, R, W, t - copy0 - 8 * nprev, kmask);
+  }
 }
 
 // A whole Vanka smoothing step on a small level in one workgroup: the class

@@ -477,10 +477,10 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
     const Geom g = lv.g;
     T* X[2] = {x, (T*)lv.alt};
     T* alt = X[1];
-    if (std::min(g.nx, std::min(g.ny, g.nz)) >= 8) {
-      const int nb = (int)((vanka_band_slots(g) + BS - 1) / BS);
-      launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_vanka_band_copy<T><<<nb, BS, 0, c->ks>>>(g, x, alt); });
-    } else {
+    // the second copy is brought up to date on the boundary band by the first
+    // pass's launch; a level with a side below 8 copies its whole state first
+    const bool band = std::min(g.nx, std::min(g.ny, g.nz)) >= 8;
+    if (!band) {
       const long n = 4L * g.field;
       launch(c, STOKES_KC_VANKA_APPLY, l, [=] { k_convert<T, T><<<RED_BLOCKS, BS, 0, c->ks>>>(x, alt, n); });
     }
@@ -496,11 +496,12 @@ void vanka_symmetric(stokes_ctx* c, int l, T* x, const T* b, XSlabCopy xin = XS_
       const int* prev = prv.cells;
       const T* R = X[pass & 1];
       T* W = X[(pass + 1) & 1];
-      if (n == 0 && np == 0) continue;
+      const int nband = band && pass == 0 ? (int)vanka_band_slots(g) : 0;
+      if (n == 0 && np == 0 && nband == 0) continue;
       const int copy0 = (8 * n + 63) / 64 * 64;
-      const int nb = (copy0 + 8 * np + BS - 1) / BS;
+      const int nb = (copy0 + 8 * np + nband + BS - 1) / BS;
       launch(c, STOKES_KC_VANKA_DELTA, l, [=] {
-        k_vanka_pp8<T, T><<<nb, BS, 0, c->ks>>>(g, R, W, b, cells, n, kinv, prev, np, kmask, copy0);
+        k_vanka_pp8<T, T><<<nb, BS, 0, c->ks>>>(g, R, W, b, cells, n, kinv, prev, np, kmask, copy0, nband);
       });
     }
     return;
