@@ -698,42 +698,50 @@ static_assert(VSWEEP_MAX_CLASS <= VSWEEP_BS, "a thread per subdomain");
 
 // One barrier-separated step of the one-workgroup passes: the subdomains of
 // class ka (na cells) and of class kb (nb cells, none when nb = 0), a thread
-// each; every subdomain's new values are formed before the first barrier and
-// written after it.
+// each, or two (thread t takes cells t and t + blockDim.x) when there are more
+// cells than threads.  Every subdomain's new values are formed from the
+// step-start state before the first barrier and written after it (the
+// subdomains of a step share no unknown; the two classes of a pair read none
+// of each other's, so the step has the values of the classes one after the
+// other).
 template <typename T, typename Lists>
 __device__ __forceinline__ void vsweep_step(const Geom& g, const Lists& a, const int* __restrict__ scell,
                                             T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ sk,
                                             int ka, int na, int kb, int nb) {
-  const int t = threadIdx.x;
-  const bool mine = t < na + nb;
-  T d[7], old[7];
-  int e[7];
-  bool act[7];
-  if (mine) {
-    const int s = t < na ? vsweep_cell(a, scell, ka, t) : vsweep_cell(a, scell, kb, t - na);
-    vanka_delta_vals<T, T>(g, x, b, s, sk, d);
-    int I, J, K;
-    slot_ijk(g, s, I, J, K);
+  T d[2][7], old[2][7];
+  int e[2][7];
+  bool act[2][7], mine[2];
 #pragma unroll
-    for (int r = 0; r < 7; ++r) {
-      const VankaDof v = vanka_dof(g, s, I, J, K, r);
-      e[r] = v.e;
-      act[r] = v.active;
-      old[r] = v.active ? x[v.e] : T(0);
+  for (int h = 0; h < 2; ++h) {
+    const int c = threadIdx.x + h * blockDim.x;
+    mine[h] = c < na + nb;
+    if (mine[h]) {
+      const int s = c < na ? vsweep_cell(a, scell, ka, c) : vsweep_cell(a, scell, kb, c - na);
+      vanka_delta_vals<T, T>(g, x, b, s, sk, d[h]);
+      int I, J, K;
+      slot_ijk(g, s, I, J, K);
+#pragma unroll
+      for (int r = 0; r < 7; ++r) {
+        const VankaDof v = vanka_dof(g, s, I, J, K, r);
+        e[h][r] = v.e;
+        act[h][r] = v.active;
+        old[h][r] = v.active ? x[v.e] : T(0);
+      }
     }
   }
   __syncthreads();
-  if (mine) {
 #pragma unroll
-    for (int r = 0; r < 7; ++r)
-      if (act[r]) x[e[r]] = old[r] + d[r];
-  }
+  for (int h = 0; h < 2; ++h)
+    if (mine[h]) {
+#pragma unroll
+      for (int r = 0; r < 7; ++r)
+        if (act[h][r]) x[e[h][r]] = old[h][r] + d[h][r];
+    }
   __syncthreads();
 }
 
-// 8 classes: the 8 pair passes (vanka_pair8), a pair in one step when a
-// thread each covers its cells, else its two classes one after the other
-// (the same values); 27 classes: 0..26 then 26..0.
+// 8 classes: the 8 pair passes (vanka_pair8), one step each (a pair holds at
+// most 2 VSWEEP_MAX_CLASS cells: two a thread); 27 classes: 0..26 then 26..0.
 template <typename T, typename Lists>
 __device__ __forceinline__ void vanka_sweep_passes1(const Geom& g, const Lists& a, T* __restrict__ x,
                                                     const T* __restrict__ b, const T* __restrict__ sk,
@@ -741,13 +749,8 @@ __device__ __forceinline__ void vanka_sweep_passes1(const Geom& g, const Lists& 
   vsweep_load_lists(a, scell);
   if (a.nc == 8) {
     for (int pass = 0; pass < VANKA_PASSES8; ++pass) {
-      const int q = vanka_pair8(pass), nq = a.count(q), nr = a.count(7 - q);
-      if (nq + nr <= (int)blockDim.x) {
-        vsweep_step<T>(g, a, scell, x, b, sk, q, nq, 7 - q, nr);
-      } else {
-        vsweep_step<T>(g, a, scell, x, b, sk, q, nq, q, 0);
-        vsweep_step<T>(g, a, scell, x, b, sk, 7 - q, nr, 7 - q, 0);
-      }
+      const int q = vanka_pair8(pass);
+      vsweep_step<T>(g, a, scell, x, b, sk, q, a.count(q), 7 - q, a.count(7 - q));
     }
     return;
   }

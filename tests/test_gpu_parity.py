@@ -47,8 +47,8 @@ def test_operator_apply_matches_oracle(dims, penalized):
 @pytest.mark.parametrize("dims,levels,nu,nb,sched", [((32, 32, 32), 0, 2, 1, "symmetric"), ((16, 24, 8), 0, 2, 1, "symmetric"),
                                                     ((8, 8, 8), 2, 1, 1, "split"), ((16, 16, 16), 0, 3, 2, "split"),
                                                     ((12, 20, 16), 3, 2, 1, "symmetric"),
-                                                    # classes of 271 cells: the one-workgroup step runs each
-                                                    # pair of more than 512 cells as its two classes in turn
+                                                    # classes of 271 cells: the one-workgroup step takes the
+                                                    # 542 cells of a class pair two a thread
                                                     ((20, 20, 20), 0, 2, 1, "symmetric"),
                                                     ((32, 32, 32), 0, 2, 2, "symmetric"),
                                                     # level-0 classes of ~20k cells: the x-slab Vanka step
